@@ -1,0 +1,202 @@
+/*
+ * qrkit.h - C ABI of the MI355X (gfx950) structured-QR Levenberg-Marquardt step solver.
+ *
+ * The operation (Svoboda, Cashman & Fitzgibbon, "QRkit", Section 1, Eqs. 1-2):
+ * given J, b, a positive diagonal D = diag(d) and a damping lambda >= 0, return
+ *
+ *     p = argmin_p || [J; sqrt(lambda) D] p - [b; 0] ||_2 = (J^T J + lambda D^2)^{-1} J^T b,
+ *
+ * computed by QR of the augmented matrix, so the condition number of J is never
+ * squared.  Two structures of J are supported:
+ *
+ *   block-angular  J = [ blkdiag(A_1, ..., A_K) | B ]   (Section 4.2, horizontal
+ *                  concatenation of a block-diagonal part, Section 4.1, and a dense
+ *                  part B).  The damping rows are permuted next to their blocks as in
+ *                  Section 5.2 (Backtrack LM, P_r [J; sqrt(lambda) D] = QR).
+ *   banded         row i of J holds w values at columns row_start[i] .. row_start[i]+w-1
+ *                  (the banded class of Section 4.4), factorised by Givens rotations.
+ *
+ * The paper's interface is compute(A); Q^T b; R.solve(Q^T b) (Section 5.1).  Because
+ * the step always knows b, "compute" and "Q^T b" are fused into qrk_factor_*: b rides
+ * through the factorisation as one more column and Q is never stored.
+ * "R.solve" (plus optional refinement) is qrk_solve.
+ *
+ * Conventions for every function below
+ *   - Array arguments are DEVICE pointers unless marked [host].  The caller owns
+ *     every buffer it passes.  The handle owns its workspace (R factors, coupling
+ *     rows, TSQR partials, refinement scratch, status word).
+ *   - A handle BORROWS the J, b and d buffers given to qrk_factor_*: qrk_solve with
+ *     sweeps > 0 and qrk_solve_adjoint read them again, so they must stay alive and
+ *     unchanged until the next factor call or qrk_destroy.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).  Calls
+ *     after create only enqueue work on that stream and never synchronise, except
+ *     qrk_status_get and qrk_get_factor.
+ *   - Argument errors are detected on the host before anything is enqueued and
+ *     return QRK_EINVAL.  Numerical conditions (tiny pivot, non-finite values) are
+ *     recorded in a device status word and reported by qrk_status_get; kernels never
+ *     trap.  The functions never throw.
+ *   - Handles are not thread-safe; distinct handles are independent.
+ *   - Row-major storage throughout.  "T" below is float for QRK_F32 handles and
+ *     double for QRK_F64 handles.
+ */
+#ifndef QRKIT_H
+#define QRKIT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  QRK_OK = 0,
+  QRK_EINVAL = 1,        /* bad argument or shape; nothing was enqueued            */
+  QRK_ENOMEM = 2,        /* device workspace allocation failed                     */
+  QRK_EHIP = 3,          /* a HIP runtime call failed                              */
+  QRK_ESINGULAR = 4,     /* a pivot of R is (numerically) zero; p is undefined     */
+  QRK_ENONFINITE = 5,    /* NaN or Inf met in the inputs or the factor             */
+  QRK_ENODEVICE = 6      /* no usable gfx950 device                                */
+} qrk_status;
+
+typedef enum { QRK_F32 = 0, QRK_F64 = 1 } qrk_dtype;
+
+/* How the dense-part trailing updates are multiplied (float32 handles only).
+ * QRK_PLAIN: fp32 products.  QRK_BF16X3: each fp32 operand x is split into
+ * hi = bf16(x), lo = bf16(x - hi) and a*b is formed as hi*hi' + hi*lo' + lo*hi'
+ * on the bf16 matrix cores with fp32 accumulation (about 16 significant bits). */
+typedef enum { QRK_PLAIN = 0, QRK_BF16X3 = 1 } qrk_mode;
+
+typedef struct qrk_handle_s* qrk_handle;
+
+/* Limits of this implementation. */
+#define QRK_MAX_BLOCK_COLS 8     /* n, columns per diagonal block                 */
+#define QRK_MAX_BLOCK_ROWS 56    /* m_i, rows per diagonal block                  */
+#define QRK_MAX_DENSE_COLS 127   /* nB, columns of the dense part B               */
+#define QRK_MAX_BAND 32          /* w, nonzeros per banded row                    */
+
+/* ------------------------------------------------------------------------------
+ * qrk_create_blockangular
+ *   Plan a solver for block-angular J with K blocks of n columns and a dense part of
+ *   nB columns.  row_off_host [host, int64, K+1]: block i owns rows
+ *   [row_off_host[i], row_off_host[i+1]) of J, of B and of b; row_off_host[0] = 0,
+ *   nondecreasing, 0 <= m_i = row_off[i+1]-row_off[i] <= QRK_MAX_BLOCK_ROWS.  The
+ *   row structure is copied; it is fixed for the life of the handle.
+ *   ldb >= nB is the row stride (in elements) of B.  Allocates all device
+ *   workspace, so later calls allocate nothing.
+ *   Returns QRK_EINVAL for K < 1, n outside 1..8, nB outside 0..127, ldb < nB, a bad
+ *   row_off_host, or mode == QRK_BF16X3 with dtype == QRK_F64.
+ * ------------------------------------------------------------------------------ */
+qrk_status qrk_create_blockangular(int32_t K, int32_t n, int32_t nB, const int64_t* row_off_host,
+                                   int64_t ldb, qrk_dtype dtype, qrk_mode mode, qrk_handle* out);
+
+/* ------------------------------------------------------------------------------
+ * qrk_factor_blockangular
+ *   Structured QR of P_r [J; sqrt(lambda) D] with b carried along (Sections 4.1, 4.2):
+ *     per block   [A_i; sqrt(lambda) D_i] = Q_i [R_i; 0]   (Householder, Section 2),
+ *                 Q_i^T [B_i | b_i; 0 | 0] -> coupling rows S_i | c_i and reduced rows;
+ *     dense part  QR of [all reduced rows; sqrt(lambda) D_B | 0] -> R_B | c_B
+ *                 (tall-skinny QR: per-workgroup leaves, then a reduction tree).
+ *   A [M x n] T, row r belongs to the block owning row r; B [M x ldb] T; b [M] T;
+ *   d [N = K*n + nB] double, d_j > 0; lambda >= 0 (finite).
+ *   Returns QRK_EINVAL on null pointers (B may be null iff nB == 0) or bad lambda.
+ * ------------------------------------------------------------------------------ */
+qrk_status qrk_factor_blockangular(qrk_handle h, const void* A, const void* B, const void* b,
+                                   const double* d, double lambda, void* stream);
+
+/* ------------------------------------------------------------------------------
+ * qrk_create_banded / qrk_factor_banded
+ *   Banded J (M x N, w values per row).  qrk_factor_banded starts from the upper
+ *   triangular R = diag(sqrt(lambda) d) and rotates each row of J into R in row order
+ *   with at most w Givens rotations; b rides along into c.  R has upper bandwidth w-1.
+ *   row_start [M] int32, nondecreasing, 0 <= row_start[i] <= N - w (checked on the
+ *   device; a violation sets QRK_EINVAL in the status word); vals [M x w] T;
+ *   b [M] T; d [N] double > 0; lambda >= 0.
+ *   create returns QRK_EINVAL for M < 0, N < 1, w outside 1..QRK_MAX_BAND, w > N.
+ * ------------------------------------------------------------------------------ */
+qrk_status qrk_create_banded(int64_t M, int64_t N, int32_t w, qrk_dtype dtype, qrk_handle* out);
+qrk_status qrk_factor_banded(qrk_handle h, const int32_t* row_start, const void* vals,
+                             const void* b, const double* d, double lambda, void* stream);
+
+/* ------------------------------------------------------------------------------
+ * qrk_solve
+ *   Back-substitution through the stored R (Section 4.2: R = [[blkdiag(R_i), S],
+ *   [0, R_B]] for block-angular J, banded R otherwise), then `sweeps` (0..8) sweeps of
+ *   corrected semi-normal-equation refinement against the same R:
+ *       r = b - J p,  g = J^T r - lambda D^2 p      (float64 on the device),
+ *       R^T R delta = g (two triangular solves),    p <- p + delta   (p in float64).
+ *   p [N] double (written).  Needs a preceding qrk_factor_* on this handle.
+ * ------------------------------------------------------------------------------ */
+qrk_status qrk_solve(qrk_handle h, double* p, int32_t sweeps, void* stream);
+
+/* ------------------------------------------------------------------------------
+ * qrk_solve_adjoint
+ *   For a loss L(p) of the step p (from qrk_solve on this handle) and g = dL/dp,
+ *   with u = (R^T R)^{-1} g (two triangular solves with the stored R; R^T R =
+ *   J^T J + lambda D^2) and r = b - J p:
+ *       dL/db = J u,   dL/dJ_ab = r_a u_b - (J u)_a p_b   (structural nonzeros only),
+ *       dL/dlambda = -u^T D^2 p,   dL/dd_j = -2 lambda u_j d_j p_j.
+ *   Block-angular handles: dA [M x n] T, dB [M x ldb] T, db [M] T.  Banded handles:
+ *   dA is dvals [M x w] T and dB must be NULL.  p, g [N] double.  dlambda [1] double,
+ *   dd [N] double.  Any output pointer may be NULL (not computed).
+ * ------------------------------------------------------------------------------ */
+qrk_status qrk_solve_adjoint(qrk_handle h, const double* p, const double* g, void* dA, void* dB,
+                             void* db, double* dlambda, double* dd, void* stream);
+
+/* ------------------------------------------------------------------------------
+ * qrk_colnorms_blockangular
+ *   d_j = ||J e_j||_2 in float64 (1 for an all-zero column), the LM choice
+ *   D = diag(J^T J)^(1/2) of Section 5.2.  A, B as for qrk_factor_blockangular; d [N].
+ * ------------------------------------------------------------------------------ */
+qrk_status qrk_colnorms_blockangular(qrk_handle h, const void* A, const void* B, double* d,
+                                     void* stream);
+
+/* ------------------------------------------------------------------------------
+ * qrk_get_factor (inspection; synchronises the stream)
+ *   Copies the stored factor into caller DEVICE buffers, any of which may be NULL.
+ *   Block-angular: Rblk [K x n x n] T (R_i, zeros below the diagonal);
+ *   S [K x n x (nB+1)] T (coupling rows S_i with c_i as last column);
+ *   RB [(nB+1) x (nB+1)] T (R_B with c_B as last column; entry [nB][nB] is +-the
+ *   residual norm || [J; sqrt(lambda) D] p - [b; 0] ||).
+ *   Banded: Rblk [N x w] T (row j holds R[j][j .. j+w-1]), S [N] T (c), RB unused.
+ * ------------------------------------------------------------------------------ */
+qrk_status qrk_get_factor(qrk_handle h, void* Rblk, void* S, void* RB, void* stream);
+
+/* ------------------------------------------------------------------------------
+ * qrk_status_get: synchronises `stream`, returns the worst numerical condition recorded
+ * since the last factor call (QRK_OK, QRK_ESINGULAR, QRK_ENONFINITE or QRK_EINVAL for a
+ * bad banded row_start) and clears nothing.  *detail_host [host, may be NULL] receives
+ * the raw status bits.
+ * ------------------------------------------------------------------------------ */
+qrk_status qrk_status_get(qrk_handle h, int32_t* detail_host, void* stream);
+
+/* Set the launch shape of the dense-part leaves (0 = library default): number of
+ * leaf workgroups and tree fan-in.  Used by the autotuner; returns QRK_EINVAL for
+ * out-of-range values. */
+qrk_status qrk_set_tsqr_shape(qrk_handle h, int32_t leaves, int32_t fanin);
+
+/* ------------------------------------------------------------------------------
+ * Phase timing (HIP events recorded on the call's stream around each phase).
+ * qrk_profile_enable(h, max_calls): max_calls > 0 creates the events for that many
+ * factor/solve calls (not capturable; call outside graph capture) and starts
+ * recording; 0 stops recording and frees the events.
+ * qrk_profile_read(h, ms_host, count_host, nphase): synchronises, then writes for each
+ * phase the summed milliseconds [host, double] and the number of recorded launches
+ * [host, int32] since enable/the previous read, and resets the sums.  Phases:
+ *   0 per-block QR, 1 dense-part leaves, 2 dense-part tree, 3 back-substitution,
+ *   4 refinement sweeps, 5 banded factorisation.
+ * ------------------------------------------------------------------------------ */
+#define QRK_NPHASES 6
+qrk_status qrk_profile_enable(qrk_handle h, int32_t max_calls);
+qrk_status qrk_profile_read(qrk_handle h, double* ms_host, int32_t* count_host, int32_t nphase);
+
+/* Device workspace held by the handle, in bytes. */
+int64_t qrk_workspace_bytes(qrk_handle h);
+
+void qrk_destroy(qrk_handle h);
+const char* qrk_strerror(qrk_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QRKIT_H */

@@ -1,0 +1,8 @@
+"""MI355X (gfx950) structured-QR Levenberg-Marquardt step solver.
+
+The hot path lives in libqrkit.so (HIP kernels behind the C ABI of include/qrkit.h);
+`qrkit` is its ctypes binding.
+"""
+from . import qrkit  # noqa: F401
+from .qrkit import (BandedSolver, BlockAngularSolver, QRKError, factor_banded,  # noqa: F401
+                    factor_blockangular)

@@ -1,0 +1,59 @@
+// Device-side helpers shared by the qrkit HIP kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qrk {
+
+// Status bits recorded in the handle's device status word.
+enum : int {
+  ST_SINGULAR = 1,
+  ST_NONFINITE = 2,
+  ST_BADINPUT = 4,
+};
+
+constexpr int kWave = 64;
+
+// Make LDS writes of one lane visible to the other lanes of the same wave.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_allreduce_sum(T v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_allreduce_max(T v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ bool is_finite(T x) {
+  return __builtin_isfinite(x);
+}
+
+template <typename T>
+struct Eps;
+template <>
+struct Eps<float> {
+  static constexpr double value = 5.9604644775390625e-08;  // 2^-24
+};
+template <>
+struct Eps<double> {
+  static constexpr double value = 1.1102230246251565e-16;  // 2^-53
+};
+
+__device__ __forceinline__ void set_status(int* status, int bits) {
+  if (status) atomicOr(status, bits);
+}
+
+}  // namespace qrk

@@ -1,0 +1,85 @@
+// Handle layout shared by the host-side translation units of libqrkit.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "qrkit.h"
+
+namespace qrk {
+
+enum HandleKind { KIND_BLOCKANGULAR = 0, KIND_BANDED = 1 };
+
+hipError_t launch_fill_int(int* ptr, int value, hipStream_t st);
+
+}  // namespace qrk
+
+struct qrk_handle_s {
+  qrk::HandleKind kind = qrk::KIND_BLOCKANGULAR;
+  qrk_dtype dtype = QRK_F32;
+  qrk_mode mode = QRK_PLAIN;
+
+  // shape
+  int64_t K = 0;       // blocks
+  int n = 0;           // columns per block
+  int nB = 0;          // dense columns
+  int64_t M = 0;       // rows of J
+  int64_t N = 0;       // columns of J
+  int64_t ldb = 0;
+  int max_rows = 0;    // max_i m_i + n
+  int w = 0;           // banded: values per row
+
+  // launch shape
+  int grid_blocks = 1;
+  int refine_grid = 1;
+  int leaves = 1;
+  int fanin = 8;
+  int64_t ldr = 0;
+
+  // owned device workspace
+  std::vector<void*> allocs;
+  int64_t ws_bytes = 0;
+  int64_t* row_off_d = nullptr;
+  void* Rblk = nullptr;   // [K][n][n]
+  void* Sc = nullptr;     // [K][n][nB+1]
+  void* Red = nullptr;    // [M][ldr]
+  void* RB = nullptr;     // [nB+1][nB+1]
+  void* part0 = nullptr;  // TSQR partial triangles
+  void* part1 = nullptr;
+  double* ybuf = nullptr;     // refinement: y_i per block
+  double* refpart = nullptr;  // refinement: per-workgroup partial sums
+  double* deltaB = nullptr;   // refinement: dense-part correction
+  double* ubuf = nullptr;     // adjoint: u = (R^T R)^{-1} g
+  double* Jubuf = nullptr;    // adjoint: J u
+  int* status = nullptr;
+  void* bandR = nullptr;      // banded: [N][w]
+  void* bandc = nullptr;      // banded: [N]
+
+  // phase timing: event pairs in a ring, summed on read
+  struct ProfRec {
+    int phase;
+    hipEvent_t start, stop;
+  };
+  std::vector<ProfRec> prof_pool;  // created at enable time
+  int prof_used = 0;
+  bool prof_on = false;
+  double prof_ms[QRK_NPHASES] = {0};
+  int prof_cnt[QRK_NPHASES] = {0};
+
+  // borrowed inputs of the last factor call
+  const void* A = nullptr;
+  const void* B = nullptr;
+  const void* b = nullptr;
+  const double* d = nullptr;
+  const int32_t* row_start = nullptr;
+  double lam = 0.0;
+  bool factored = false;
+};
+
+qrk_status banded_solve(qrk_handle h, double* p, int sweeps, hipStream_t st);
+
+// Phase timing helpers: prof_begin returns the record index (or -1 when off or full).
+int prof_begin(qrk_handle h, int phase, hipStream_t st);
+void prof_end(qrk_handle h, int rec, hipStream_t st);

@@ -1,0 +1,319 @@
+"""Python binding of libqrkit.so (ctypes; argument marshalling only).
+
+Every step of the LM step solve runs in the library's HIP kernels; torch supplies
+device memory and the current HIP stream.  There is no CPU fallback: if the library
+is missing or no gfx950 device is present, the calls raise.
+
+Names follow the C ABI of include/qrkit.h:
+    factor_blockangular / factor_banded   -> compute(A) and Q^T b  (paper Section 5.1)
+    Factor.solve                          -> R.solve(Q^T b), plus refinement sweeps
+    Factor.solve_adjoint                  -> gradients of a loss of p
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libqrkit.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "qrkit.h")
+
+QRK_OK, QRK_EINVAL, QRK_ENOMEM, QRK_EHIP, QRK_ESINGULAR, QRK_ENONFINITE, QRK_ENODEVICE = range(7)
+QRK_F32, QRK_F64 = 0, 1
+QRK_PLAIN, QRK_BF16X3 = 0, 1
+MAX_BLOCK_COLS, MAX_BLOCK_ROWS, MAX_DENSE_COLS, MAX_BAND = 8, 56, 127, 31
+
+_c_i32, _c_i64, _c_dbl, _c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+_c_i64p = ctypes.POINTER(ctypes.c_int64)
+_c_i32p = ctypes.POINTER(ctypes.c_int32)
+
+_SIGS = {
+    "qrk_create_blockangular": (_c_i32, [_c_i32, _c_i32, _c_i32, _c_i64p, _c_i64, _c_i32, _c_i32,
+                                         ctypes.POINTER(_c_vp)]),
+    "qrk_factor_blockangular": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_dbl, _c_vp]),
+    "qrk_create_banded": (_c_i32, [_c_i64, _c_i64, _c_i32, _c_i32, ctypes.POINTER(_c_vp)]),
+    "qrk_factor_banded": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_dbl, _c_vp]),
+    "qrk_solve": (_c_i32, [_c_vp, _c_vp, _c_i32, _c_vp]),
+    "qrk_solve_adjoint": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp]),
+    "qrk_colnorms_blockangular": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_vp]),
+    "qrk_get_factor": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_vp]),
+    "qrk_status_get": (_c_i32, [_c_vp, _c_i32p, _c_vp]),
+    "qrk_set_tsqr_shape": (_c_i32, [_c_vp, _c_i32, _c_i32]),
+    "qrk_workspace_bytes": (_c_i64, [_c_vp]),
+    "qrk_profile_enable": (_c_i32, [_c_vp, _c_i32]),
+    "qrk_profile_read": (_c_i32, [_c_vp, ctypes.POINTER(_c_dbl), _c_i32p, _c_i32]),
+    "qrk_destroy": (None, [_c_vp]),
+    "qrk_strerror": (ctypes.c_char_p, [_c_i32]),
+}
+
+_LIB = None
+
+
+def header_functions() -> list[str]:
+    """Names of every function declared in include/qrkit.h."""
+    with open(HEADER_PATH) as fh:
+        text = fh.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qrk_[a-z0-9_]+)\s*\(", text)))
+
+
+def lib() -> ctypes.CDLL:
+    """Load libqrkit.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1802_03773_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+class QRKError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = int(status)
+        msg = lib().qrk_strerror(int(status)).decode()
+        super().__init__(f"{what}: {msg} (status {status})" if what else msg)
+
+
+def _check(status: int, what: str):
+    if status != QRK_OK:
+        raise QRKError(status, what)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t, dtype, name, numel=None):
+    torch = _torch()
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name} has {t.numel()} elements, needs {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _torch_dtype(qdtype):
+    torch = _torch()
+    return torch.float32 if qdtype == QRK_F32 else torch.float64
+
+
+class Factor:
+    """A qrkit handle plus the borrowed inputs of its last factor call."""
+
+    def __init__(self, handle, kind: str, dtype: int, N: int):
+        self._h = handle
+        self.kind = kind
+        self.qdtype = dtype
+        self.N = N
+        self._keep = ()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h is not None and _LIB is not None:
+            _LIB.qrk_destroy(h)
+
+    def solve(self, sweeps: int = 0, out=None, stream=None):
+        """Back-substitution (plus `sweeps` float64-residual refinement sweeps); p float64 [N]."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty(self.N, dtype=torch.float64, device="cuda")
+        _check(lib().qrk_solve(self._h, _dev_ptr(out, torch.float64, "p", self.N), int(sweeps),
+                               _stream_ptr(stream)), "qrk_solve")
+        return out
+
+    def status(self, stream=None) -> tuple[int, int]:
+        detail = ctypes.c_int32(0)
+        st = lib().qrk_status_get(self._h, ctypes.byref(detail), _stream_ptr(stream))
+        return int(st), int(detail.value)
+
+    def raise_on_status(self, stream=None):
+        st, _ = self.status(stream)
+        _check(st, "device status")
+
+    def workspace_bytes(self) -> int:
+        return int(lib().qrk_workspace_bytes(self._h))
+
+    PHASES = ("block_qr", "dense_leaves", "dense_tree", "backsub", "refine", "banded")
+
+    def profile_enable(self, max_calls: int):
+        _check(lib().qrk_profile_enable(self._h, int(max_calls)), "qrk_profile_enable")
+
+    def profile_read(self) -> dict:
+        """{phase: (milliseconds summed, launches)} since enable or the previous read."""
+        n = len(self.PHASES)
+        ms = (_c_dbl * n)()
+        cnt = (_c_i32 * n)()
+        _check(lib().qrk_profile_read(self._h, ms, cnt, n), "qrk_profile_read")
+        return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(self.PHASES)}
+
+
+class BlockAngularSolver(Factor):
+    """Solver for J = [blkdiag(A_1..A_K) | B] (K blocks of n columns, nB dense columns)."""
+
+    def __init__(self, row_off, n: int, nB: int, ldb: Optional[int] = None, dtype="float32",
+                 mode: str = "plain"):
+        row_off = np.ascontiguousarray(np.asarray(row_off, dtype=np.int64))
+        K = int(row_off.shape[0] - 1)
+        qd = QRK_F32 if str(dtype).endswith("float32") else QRK_F64
+        qm = {"plain": QRK_PLAIN, "bf16x3": QRK_BF16X3}[mode]
+        ldb = nB if ldb is None else int(ldb)
+        h = _c_vp()
+        st = lib().qrk_create_blockangular(K, int(n), int(nB), row_off.ctypes.data_as(_c_i64p), ldb,
+                                           qd, qm, ctypes.byref(h))
+        _check(st, "qrk_create_blockangular")
+        super().__init__(h, "blockangular", qd, K * int(n) + int(nB))
+        self.K, self.n, self.nB, self.ldb, self.M = K, int(n), int(nB), ldb, int(row_off[-1])
+        self.row_off = row_off
+        self.mode = mode
+
+    def set_tsqr_shape(self, leaves: int = 0, fanin: int = 0):
+        _check(lib().qrk_set_tsqr_shape(self._h, int(leaves), int(fanin)), "qrk_set_tsqr_shape")
+
+    def factor(self, A, B, b, d, lam: float, stream=None):
+        torch = _torch()
+        td = _torch_dtype(self.qdtype)
+        pa = _dev_ptr(A, td, "A", self.M * self.n)
+        pB = _dev_ptr(B, td, "B", self.M * self.ldb) if self.nB > 0 else (
+            _dev_ptr(B, td, "B") if B is not None else None)
+        pb = _dev_ptr(b, td, "b", self.M)
+        pd = _dev_ptr(d, torch.float64, "d", self.N)
+        _check(lib().qrk_factor_blockangular(self._h, pa, pB, pb, pd, float(lam), _stream_ptr(stream)),
+               "qrk_factor_blockangular")
+        self._keep = (A, B, b, d)
+        self.lam = float(lam)
+        return self
+
+    def colnorms(self, A, B, out=None, stream=None):
+        torch = _torch()
+        td = _torch_dtype(self.qdtype)
+        if out is None:
+            out = torch.empty(self.N, dtype=torch.float64, device="cuda")
+        _check(lib().qrk_colnorms_blockangular(self._h, _dev_ptr(A, td, "A", self.M * self.n),
+                                               _dev_ptr(B, td, "B") if B is not None else None,
+                                               _dev_ptr(out, torch.float64, "d", self.N),
+                                               _stream_ptr(stream)), "qrk_colnorms_blockangular")
+        return out
+
+    def get_factor(self, stream=None):
+        """(Rblk [K,n,n], S [K,n,nB+1], RB [nB+1,nB+1]) copies of the stored factor."""
+        torch = _torch()
+        td = _torch_dtype(self.qdtype)
+        L = self.nB + 1
+        Rblk = torch.empty((self.K, self.n, self.n), dtype=td, device="cuda")
+        S = torch.empty((self.K, self.n, L), dtype=td, device="cuda")
+        RB = torch.empty((L, L), dtype=td, device="cuda")
+        _check(lib().qrk_get_factor(self._h, _dev_ptr(Rblk, td, "Rblk"), _dev_ptr(S, td, "S"),
+                                    _dev_ptr(RB, td, "RB"), _stream_ptr(stream)), "qrk_get_factor")
+        return Rblk, S, RB
+
+    def solve_adjoint(self, p, g, want=("dA", "dB", "db", "dlam", "dd"), stream=None):
+        torch = _torch()
+        td = _torch_dtype(self.qdtype)
+        out = {}
+        if "dA" in want:
+            out["dA"] = torch.empty((self.M, self.n), dtype=td, device="cuda")
+        if "dB" in want and self.nB > 0:
+            out["dB"] = torch.zeros((self.M, self.ldb), dtype=td, device="cuda")
+        if "db" in want:
+            out["db"] = torch.empty(self.M, dtype=td, device="cuda")
+        if "dlam" in want:
+            out["dlam"] = torch.empty(1, dtype=torch.float64, device="cuda")
+        if "dd" in want:
+            out["dd"] = torch.empty(self.N, dtype=torch.float64, device="cuda")
+
+        def ptr(k, dt):
+            return _dev_ptr(out[k], dt, k) if k in out else None
+
+        _check(lib().qrk_solve_adjoint(self._h, _dev_ptr(p, torch.float64, "p", self.N),
+                                       _dev_ptr(g, torch.float64, "g", self.N), ptr("dA", td),
+                                       ptr("dB", td), ptr("db", td), ptr("dlam", torch.float64),
+                                       ptr("dd", torch.float64), _stream_ptr(stream)),
+               "qrk_solve_adjoint")
+        return out
+
+
+class BandedSolver(Factor):
+    """Solver for banded J (M x N, w values per row at nondecreasing starts)."""
+
+    def __init__(self, M: int, N: int, w: int, dtype="float32"):
+        qd = QRK_F32 if str(dtype).endswith("float32") else QRK_F64
+        h = _c_vp()
+        _check(lib().qrk_create_banded(int(M), int(N), int(w), qd, ctypes.byref(h)), "qrk_create_banded")
+        super().__init__(h, "banded", qd, int(N))
+        self.M, self.w = int(M), int(w)
+
+    def factor(self, row_start, vals, b, d, lam: float, stream=None):
+        torch = _torch()
+        td = _torch_dtype(self.qdtype)
+        _check(lib().qrk_factor_banded(self._h, _dev_ptr(row_start, torch.int32, "row_start", self.M),
+                                       _dev_ptr(vals, td, "vals", self.M * self.w),
+                                       _dev_ptr(b, td, "b", self.M), _dev_ptr(d, torch.float64, "d", self.N),
+                                       float(lam), _stream_ptr(stream)), "qrk_factor_banded")
+        self._keep = (row_start, vals, b, d)
+        self.lam = float(lam)
+        return self
+
+    def get_factor(self, stream=None):
+        """(R band [N, w] with row j = R[j, j..j+w-1], c [N])."""
+        torch = _torch()
+        td = _torch_dtype(self.qdtype)
+        R = torch.empty((self.N, self.w), dtype=td, device="cuda")
+        c = torch.empty(self.N, dtype=td, device="cuda")
+        _check(lib().qrk_get_factor(self._h, _dev_ptr(R, td, "R"), _dev_ptr(c, td, "c"), None,
+                                    _stream_ptr(stream)), "qrk_get_factor")
+        return R, c
+
+    def solve_adjoint(self, p, g, stream=None):
+        torch = _torch()
+        td = _torch_dtype(self.qdtype)
+        out = dict(dvals=torch.empty((self.M, self.w), dtype=td, device="cuda"),
+                   db=torch.empty(self.M, dtype=td, device="cuda"),
+                   dlam=torch.empty(1, dtype=torch.float64, device="cuda"),
+                   dd=torch.empty(self.N, dtype=torch.float64, device="cuda"))
+        _check(lib().qrk_solve_adjoint(self._h, _dev_ptr(p, torch.float64, "p", self.N),
+                                       _dev_ptr(g, torch.float64, "g", self.N),
+                                       _dev_ptr(out["dvals"], td, "dvals"), None,
+                                       _dev_ptr(out["db"], td, "db"),
+                                       _dev_ptr(out["dlam"], torch.float64, "dlam"),
+                                       _dev_ptr(out["dd"], torch.float64, "dd"), _stream_ptr(stream)),
+               "qrk_solve_adjoint")
+        return out
+
+
+def factor_blockangular(row_off, A, B, b, d, lam, n: int, dtype="float32", mode="plain", stream=None):
+    """Convenience: create a block-angular solver and factor one instance."""
+    nB = 0 if B is None else int(B.shape[1])
+    s = BlockAngularSolver(row_off, n, nB, dtype=dtype, mode=mode)
+    return s.factor(A, B, b, d, lam, stream=stream)
+
+
+def factor_banded(row_start, vals, b, d, lam, N: int, dtype="float32", stream=None):
+    M, w = int(vals.shape[0]), int(vals.shape[1])
+    s = BandedSolver(M, N, w, dtype=dtype)
+    return s.factor(row_start, vals, b, d, lam, stream=stream)

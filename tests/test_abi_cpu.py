@@ -1,0 +1,79 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports every
+function declared in include/qrkit.h, and rejects bad arguments before touching the
+device."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_1802_03773_amd import qrkit
+
+pytestmark = pytest.mark.skipif(not __import__("os").path.exists(qrkit.LIB_PATH),
+                                reason="libqrkit.so not built")
+
+
+def test_every_declared_symbol_is_exported():
+    L = qrkit.lib()
+    names = qrkit.header_functions()
+    assert len(names) >= 12
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    assert set(qrkit._SIGS) == set(names)
+
+
+def test_strerror():
+    L = qrkit.lib()
+    assert L.qrk_strerror(0) == b"success"
+    assert L.qrk_strerror(1) == b"invalid argument"
+    assert L.qrk_strerror(99) == b"unknown status"
+
+
+def _create(K, n, nB, row_off, ldb, dtype=0, mode=0):
+    L = qrkit.lib()
+    h = ctypes.c_void_p()
+    ro = np.ascontiguousarray(np.asarray(row_off, np.int64))
+    st = L.qrk_create_blockangular(K, n, nB, ro.ctypes.data_as(qrkit._c_i64p), ldb, dtype, mode,
+                                   ctypes.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("args", [
+    (0, 3, 4, [0], 4),                      # K < 1
+    (2, 0, 4, [0, 1, 2], 4),                # n < 1
+    (2, 9, 4, [0, 1, 2], 4),                # n > 8
+    (2, 3, -1, [0, 1, 2], 4),               # nB < 0
+    (2, 3, 128, [0, 1, 2], 128),            # nB > 127
+    (2, 3, 4, [0, 1, 2], 3),                # ldb < nB
+    (2, 3, 4, [1, 2, 3], 4),                # row_off[0] != 0
+    (2, 3, 4, [0, 5, 3], 4),                # negative block
+    (2, 3, 4, [0, 57, 60], 4),              # block taller than the limit
+])
+def test_create_rejects_bad_shapes(args):
+    st, h = _create(*args)
+    assert st == qrkit.QRK_EINVAL and not h.value
+
+
+def test_create_rejects_bad_dtype_mode():
+    assert _create(2, 3, 4, [0, 2, 4], 4, dtype=5)[0] == qrkit.QRK_EINVAL
+    assert _create(2, 3, 4, [0, 2, 4], 4, mode=7)[0] == qrkit.QRK_EINVAL
+    # bf16x3 trailing updates exist only for float32 factors
+    assert _create(2, 3, 4, [0, 2, 4], 4, dtype=1, mode=1)[0] == qrkit.QRK_EINVAL
+
+
+def test_null_handle_calls_are_rejected():
+    L = qrkit.lib()
+    assert L.qrk_factor_blockangular(None, None, None, None, None, 0.1, None) == qrkit.QRK_EINVAL
+    assert L.qrk_solve(None, None, 0, None) == qrkit.QRK_EINVAL
+    assert L.qrk_status_get(None, None, None) == qrkit.QRK_EINVAL
+    assert L.qrk_get_factor(None, None, None, None, None) == qrkit.QRK_EINVAL
+    assert L.qrk_solve_adjoint(None, None, None, None, None, None, None, None, None) == qrkit.QRK_EINVAL
+    assert L.qrk_set_tsqr_shape(None, 0, 0) == qrkit.QRK_EINVAL
+    assert L.qrk_workspace_bytes(None) == 0
+    L.qrk_destroy(None)
+
+
+def test_banded_create_rejects_bad_shapes():
+    L = qrkit.lib()
+    h = ctypes.c_void_p()
+    for M, N, w in [(-1, 10, 3), (10, 0, 3), (10, 10, 0), (10, 10, 32), (10, 4, 5)]:
+        assert L.qrk_create_banded(M, N, w, 0, ctypes.byref(h)) == qrkit.QRK_EINVAL

@@ -1,0 +1,159 @@
+"""GPU parity of the block-angular LM step (HIP path through the C ABI) against the
+CPU oracle: the solution p, and the stored factor (R_i, S_i | c_i, R_B | c_B) up to row
+signs.  Tolerances: float64 path 1e-12 vs the longdouble-refined reference; float32
+unrefined 1e-5 at cond(J) <= 1e3; any path after refinement sweeps 1e-10."""
+import numpy as np
+import pytest
+
+from oracle import refine, structured
+from tests.gpu_util import gpu_solve_blockangular, log, rel_err, sign_fix_rows
+from workloads import generators as gen
+
+pytestmark = pytest.mark.gpu
+
+
+def _check_factor(inst, solver, f, tol):
+    Rblk, S, RB = [t.cpu().numpy().astype(np.float64) for t in solver.get_factor()]
+    K, n, nB = inst.K, inst.n, inst.nB
+    # per-block R_i and coupling rows S_i | c_i, up to the sign of each row
+    for i in range(0, K, max(1, K // 64)):
+        Rg, Sg = sign_fix_rows(Rblk[i], S[i])
+        Ro, So = sign_fix_rows(f.R_blk[i], np.concatenate([f.S[i], f.c_blk[i][:, None]], axis=1))
+        scale = max(np.abs(Ro).max(), 1e-300)
+        assert np.abs(Rg - Ro).max() <= tol * scale, f"R_{i}"
+        assert np.abs(Sg - So).max() <= tol * max(np.abs(So).max(), scale), f"S_{i}"
+    if nB:
+        Rg, cg = sign_fix_rows(RB[:nB, :nB], RB[:nB, nB])
+        Ro, co = sign_fix_rows(f.R_B, f.c_B)
+        assert np.abs(Rg - Ro).max() <= tol * np.abs(Ro).max()
+        assert np.abs(cg - co).max() <= tol * max(np.abs(co).max(), np.abs(Ro).max())
+    assert abs(abs(RB[nB, nB]) - f.resid) <= tol * max(1.0, f.resid) * 10
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_tiny_float64(seed):
+    log(f"tiny float64 seed={seed}")
+    inst = gen.tiny_blockangular(seed, dtype=np.float64)
+    p_ref, f = refine.reference_solution(inst)
+    p, st, solver, _ = gpu_solve_blockangular(inst, return_solver=True)
+    assert st[0] == 0
+    assert rel_err(p, p_ref) <= 1e-12
+    _check_factor(inst, solver, f, 1e-12)
+
+
+@pytest.mark.parametrize("seed", [0, 3])
+def test_tiny_float32_unrefined_and_refined(seed):
+    log(f"tiny float32 seed={seed}")
+    inst = gen.tiny_blockangular(seed, dtype=np.float32)
+    p_ref, f = refine.reference_solution(inst)
+    p0, st, solver, _ = gpu_solve_blockangular(inst, return_solver=True)
+    assert st[0] == 0
+    assert rel_err(p0, p_ref) <= 1e-5
+    _check_factor(inst, solver, f, 2e-5)
+    p2, st = gpu_solve_blockangular(inst, sweeps=2)
+    assert rel_err(p2, p_ref) <= 1e-10
+
+
+SHAPES = [
+    # (K, m (int or (lo, hi) ragged), n, nB, lam)
+    (1, 30, 3, 6, 1e-2),
+    (7, (0, 9), 2, 1, 1e-1),
+    (33, (1, 12), 1, 0, 1e-2),
+    (50, (3, 20), 3, 63, 1e-3),
+    (61, (3, 20), 3, 64, 1e-2),
+    (70, (0, 40), 4, 90, 1e-2),
+    (45, (10, 56), 8, 127, 1.0),
+    (200, 12, 3, 90, 1e-4),
+]
+
+
+def _ragged(seed, K, m):
+    if isinstance(m, tuple):
+        rng = np.random.default_rng(seed + 77)
+        return rng.integers(m[0], m[1] + 1, size=K)
+    return m
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_shapes(shape, dtype):
+    K, m, n, nB, lam = shape
+    log(f"shape K={K} m={m} n={n} nB={nB} lam={lam} dtype={np.dtype(dtype).name}")
+    inst = gen.make_blockangular(10 + K, K=K, m=_ragged(K, K, m), n=n, nB=nB, lam=lam, dtype=dtype)
+    p_ref, f = refine.reference_solution(inst)
+    p, st, solver, _ = gpu_solve_blockangular(inst, return_solver=True)
+    assert st[0] == 0, st
+    tol = 1e-11 if dtype == np.float64 else 1e-5
+    assert rel_err(p, p_ref) <= tol
+    _check_factor(inst, solver, f, 1e-11 if dtype == np.float64 else 5e-5)
+    p2, st = gpu_solve_blockangular(inst, sweeps=2)
+    assert rel_err(p2, p_ref) <= 1e-10
+
+
+def test_tsqr_launch_shapes_agree():
+    """Leaf counts and tree fan-ins change only the rounding of the result."""
+    inst = gen.make_blockangular(5, K=400, m=12, n=3, nB=30, lam=1e-2, dtype=np.float64)
+    p_ref, _ = refine.reference_solution(inst)
+    for leaves, fanin in [(1, 2), (3, 2), (17, 4), (64, 8), (400, 16), (1024, 64)]:
+        log(f"tsqr leaves={leaves} fanin={fanin}")
+        p, st = gpu_solve_blockangular(inst, leaves=leaves, fanin=fanin)
+        assert st[0] == 0
+        assert rel_err(p, p_ref) <= 1e-12
+
+
+def test_lambda_zero_gauss_newton():
+    inst = gen.make_blockangular(6, K=300, m=(np.arange(300) % 7) + 4, n=3, nB=20, lam=0.0,
+                                 dtype=np.float64)
+    log("lambda = 0")
+    p_ref, _ = refine.reference_solution(inst)
+    p, st = gpu_solve_blockangular(inst)
+    assert st[0] == 0
+    assert rel_err(p, p_ref) <= 1e-11
+
+
+def test_singular_block_is_reported():
+    """lam = 0 with a block of fewer rows than columns: R_i has a zero pivot."""
+    log("singular status")
+    m = np.full(20, 6)
+    m[7] = 2
+    inst = gen.make_blockangular(7, K=20, m=m, n=3, nB=4, lam=0.0, dtype=np.float64)
+    _, st = gpu_solve_blockangular(inst)
+    assert st[0] == 4  # QRK_ESINGULAR
+
+
+def test_nonfinite_input_is_reported():
+    log("non-finite status")
+    inst = gen.make_blockangular(8, K=20, m=6, n=3, nB=4, lam=1e-2, dtype=np.float32)
+    inst.B[13, 2] = np.nan
+    _, st = gpu_solve_blockangular(inst)
+    assert st[0] == 5  # QRK_ENONFINITE
+
+
+def test_deterministic_repeat():
+    log("determinism")
+    inst = gen.make_blockangular(9, K=5000, m=12, n=3, nB=90, lam=1e-2, dtype=np.float32, scale_k=3.0)
+    p1, _ = gpu_solve_blockangular(inst, sweeps=1)
+    p2, _ = gpu_solve_blockangular(inst, sweeps=1)
+    assert np.array_equal(p1, p2)
+
+
+@pytest.mark.parametrize("lam", [1e-2, 0.0])
+def test_scale_workload_full_size(lam):
+    """50,000 blocks of 12x3 with a 600,000 x 90 dense part (column scales 10^(3t)), in the
+    launch configuration the benchmark times: unrefined <= 1e-5, one sweep <= 1e-10."""
+    log(f"scale workload lam={lam}: generating")
+    inst = gen.scale_blockangular(100, lam=lam)
+    log("oracle")
+    p_ref, f = refine.reference_solution(inst, sweeps=2)
+    log("gpu")
+    p0, st, solver, dev = gpu_solve_blockangular(inst, return_solver=True)
+    assert st[0] == 0
+    e0 = rel_err(p0, p_ref)
+    log(f"unrefined rel err {e0:.3e}")
+    assert e0 <= 1e-5
+    p1 = solver.solve(sweeps=1).cpu().numpy()
+    e1 = rel_err(p1, p_ref)
+    log(f"1 sweep rel err {e1:.3e}")
+    assert e1 <= 1e-10
+    p2 = solver.solve(sweeps=2).cpu().numpy()
+    assert rel_err(p2, p_ref) <= 1e-10
