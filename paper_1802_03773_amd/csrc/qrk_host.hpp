@@ -42,12 +42,18 @@ struct qrk_handle_s {
   std::vector<void*> allocs;
   int64_t ws_bytes = 0;
   int64_t* row_off_d = nullptr;
+  int64_t* pack_blk = nullptr;  // packs of whole blocks with at most 64 rows: [npacks+1]
+  int64_t npacks = 0;
+  int solve_grid = 1;
   void* Rblk = nullptr;   // [K][n][n]
   void* Sc = nullptr;     // [K][n][nB+1]
   void* Red = nullptr;    // [M][ldr]
   void* RB = nullptr;     // [nB+1][nB+1]
-  void* part0 = nullptr;  // TSQR partial triangles
+  void* part0 = nullptr;  // TSQR partial triangles (float64 path)
   void* part1 = nullptr;
+  float* slots = nullptr; // TSQR tree slots (float32 matrix-core path)
+  int* counters = nullptr;
+  int max_leaves = 1;
   double* ybuf = nullptr;     // refinement: y_i per block
   double* refpart = nullptr;  // refinement: per-workgroup partial sums
   double* deltaB = nullptr;   // refinement: dense-part correction

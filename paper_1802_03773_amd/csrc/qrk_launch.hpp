@@ -23,6 +23,16 @@ template <typename T>
 hipError_t launch_tsqr_stream(const T* X, int64_t ldx, int64_t nrows, int L, int64_t rows_per_wg,
                               int grid, const double* dB, double sqrt_lam, T* Rout, hipStream_t st);
 
+// Float32 tall-skinny QR on the matrix cores: nleaves waves each stream a contiguous
+// share of the nrows x L rows of X (row stride ldx) into a triangle, then merge pairwise in
+// the same launch; the root goes to Rout (L x L row-major).  Leaf 0 starts from
+// diag(sqrt_lam * dB) when dB is not null.  slots holds 2*nleaves triangles of
+// tsqr_mfma_slot_floats(L) floats; counters holds 2*nleaves+2 ints (cleared here).
+int tsqr_mfma_slot_floats(int L);
+hipError_t launch_tsqr_mfma(const float* X, int64_t ldx, int64_t nrows, int L, int nleaves,
+                            const double* dB, double sqrt_lam, float* slots, int* counters,
+                            float* Rout, hipStream_t st);
+
 // R_B p_B = c_B (RB is L x L with c_B in column L-1); writes p[off .. off+nB) as double.
 template <typename T>
 hipError_t launch_backsub_dense(const T* RB, int L, double* p, int64_t off, int* status,
@@ -33,13 +43,14 @@ template <typename T>
 hipError_t launch_backsub_blocks(int64_t K, int n, int nB, const T* Rblk, const T* Sc, double* p,
                                  int* status, int grid, hipStream_t st);
 
-// Refinement, pass 1: per block r = b - J p, g_i = A_i^T r - lam d_i^2 p_i, y_i = R_i^{-T} g_i,
-// and per-workgroup partial sums of B_i^T r - S_i^T y_i (part[wg][nB]).
+// Refinement, pass 1: per pack of whole blocks (pack_blk[k] .. pack_blk[k+1], at most 64
+// rows): r = b - J p, g_i = A_i^T r - lam d_i^2 p_i, y_i = R_i^{-T} g_i, and per-workgroup
+// partial sums of B^T r - S_i^T y_i (part[wg][nB]).
 template <typename T>
-hipError_t launch_refine_residual(int64_t K, int n, int nB, const int64_t* row_off, const T* A,
-                                  const T* B, int64_t ldb, const T* b, const double* d, double lam,
-                                  const T* Rblk, const T* Sc, const double* p, double* y,
-                                  double* part, int grid, hipStream_t st);
+hipError_t launch_refine_residual(int64_t npacks, const int64_t* pack_blk, int64_t K, int n, int nB,
+                                  const int64_t* row_off, const T* A, const T* B, int64_t ldb, const T* b,
+                                  const double* d, double lam, const T* Rblk, const T* Sc,
+                                  const double* p, double* y, double* part, int grid, hipStream_t st);
 
 // Refinement, pass 2: g_B = sum(part) - lam d_B^2 p_B; y_B = R_B^{-T} g_B; dB = R_B^{-1} y_B;
 // p_B += dB; dB stored to delta_B.

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "qrk_launch.hpp"
@@ -50,6 +51,15 @@ qrk_status factor_ba(qrk_handle h, hipStream_t st) {
                         Rblk, Sc, Red, h->ldr, h->grid_blocks, st) != hipSuccess)
     return QRK_EHIP;
   prof_end(h, pr, st);
+  if constexpr (std::is_same<T, float>::value) {
+    // dense part on the matrix cores: leaves and the merge tree in one launch
+    pr = prof_begin(h, 1, st);
+    if (launch_tsqr_mfma(Red, h->ldr, h->M, L, h->leaves, h->d + h->K * h->n, sq, h->slots,
+                         h->counters, RB, st) != hipSuccess)
+      return QRK_EHIP;
+    prof_end(h, pr, st);
+    return QRK_OK;
+  }
   // dense part: leaves, then the reduction tree (ping-pong buffers, last level -> RB)
   int G = h->leaves;
   const int64_t rows_per = std::max<int64_t>(1, ceil_div(h->M, G));
@@ -85,13 +95,14 @@ qrk_status solve_ba(qrk_handle h, double* p, int sweeps, hipStream_t st) {
   const int64_t off = h->K * h->n;
   int pr = prof_begin(h, 3, st);
   if (launch_backsub_dense<T>(RB, L, p, off, h->status, st) != hipSuccess) return QRK_EHIP;
-  if (launch_backsub_blocks<T>(h->K, h->n, h->nB, Rblk, Sc, p, h->status, h->grid_blocks, st) !=
+  if (launch_backsub_blocks<T>(h->K, h->n, h->nB, Rblk, Sc, p, h->status, h->solve_grid, st) !=
       hipSuccess)
     return QRK_EHIP;
   prof_end(h, pr, st);
   pr = sweeps > 0 ? prof_begin(h, 4, st) : -1;
   for (int s = 0; s < sweeps; ++s) {
-    if (launch_refine_residual<T>(h->K, h->n, h->nB, h->row_off_d, static_cast<const T*>(h->A),
+    if (launch_refine_residual<T>(h->npacks, h->pack_blk, h->K, h->n, h->nB, h->row_off_d,
+                                  static_cast<const T*>(h->A),
                                   static_cast<const T*>(h->B), h->ldb, static_cast<const T*>(h->b),
                                   h->d, h->lam, Rblk, Sc, p, h->ybuf, h->refpart, h->refine_grid,
                                   st) != hipSuccess)
@@ -100,11 +111,18 @@ qrk_status solve_ba(qrk_handle h, double* p, int sweeps, hipStream_t st) {
                                h->deltaB, st) != hipSuccess)
       return QRK_EHIP;
     if (launch_refine_blocks<T>(h->K, h->n, h->nB, Rblk, Sc, h->ybuf, h->deltaB, p,
-                                h->grid_blocks, st) != hipSuccess)
+                                h->solve_grid, st) != hipSuccess)
       return QRK_EHIP;
   }
   prof_end(h, pr, st);
   return QRK_OK;
+}
+
+// Leaf count of the dense-part QR: float32 leaves are single waves (about 128 rows
+// each, at most 2048); float64 leaves are workgroups (about 256 rows, at most 1024).
+int default_leaves(qrk_handle h) {
+  const int64_t per = h->dtype == QRK_F32 ? 128 : 256;  // rows per leaf before the cap
+  return (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(h->M + h->nB, per), h->max_leaves));
 }
 
 void prof_free(qrk_handle h) {
@@ -196,18 +214,43 @@ qrk_status qrk_create_blockangular(int32_t K, int32_t n, int32_t nB, const int64
   const size_t es = dtype == QRK_F32 ? 4 : 8;
   const int L = nB + 1;
   h->ldr = ((L + 3) / 4) * 4;
+  // packs of consecutive whole blocks, at most 64 rows and 64 blocks each (refinement)
+  std::vector<int64_t> packs{0};
+  {
+    int64_t rows = 0;
+    int nbp = 0;
+    for (int32_t i = 0; i < K; ++i) {
+      const int64_t m = row_off_host[i + 1] - row_off_host[i];
+      if (nbp > 0 && (rows + m > 64 || nbp == 64)) {
+        packs.push_back(i);
+        rows = 0;
+        nbp = 0;
+      }
+      rows += m;
+      ++nbp;
+    }
+    packs.push_back(K);
+  }
+  h->npacks = (int64_t)packs.size() - 1;
   h->grid_blocks = (int)std::min<int64_t>(ceil_div(K, 4), 2048);
-  h->refine_grid = (int)std::min<int64_t>(ceil_div(K, 4), 1024);
-  h->leaves = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(h->M, 256), 1024));
+  h->solve_grid = (int)std::min<int64_t>(ceil_div(K, 16), 2048);
+  h->refine_grid = (int)std::min<int64_t>(ceil_div(h->npacks, 4), 1024);
+  h->max_leaves = 1024;  // float32: one leaf wave per SIMD of the 256-CU chip
+  h->leaves = default_leaves(h);
   h->fanin = 8;
   qrk_status s = QRK_OK;
   if ((s = dalloc(h, &h->row_off_d, sizeof(int64_t) * (K + 1))) != QRK_OK ||
+      (s = dalloc(h, &h->pack_blk, sizeof(int64_t) * packs.size())) != QRK_OK ||
       (s = dalloc(h, &h->Rblk, es * (size_t)K * n * n)) != QRK_OK ||
       (s = dalloc(h, &h->Sc, es * (size_t)K * n * L)) != QRK_OK ||
       (s = dalloc(h, &h->Red, es * (size_t)std::max<int64_t>(h->M, 1) * h->ldr)) != QRK_OK ||
       (s = dalloc(h, &h->RB, es * (size_t)L * L)) != QRK_OK ||
-      (s = dalloc(h, &h->part0, es * (size_t)1024 * L * L)) != QRK_OK ||
-      (s = dalloc(h, &h->part1, es * (size_t)1024 * L * L)) != QRK_OK ||
+      (s = dalloc(h, &h->part0, dtype == QRK_F64 ? es * (size_t)1024 * L * L : 0)) != QRK_OK ||
+      (s = dalloc(h, &h->part1, dtype == QRK_F64 ? es * (size_t)1024 * L * L : 0)) != QRK_OK ||
+      (s = dalloc(h, &h->slots, dtype == QRK_F32 ? sizeof(float) * (size_t)2 * h->max_leaves *
+                                                       tsqr_mfma_slot_floats(L)
+                                                 : 0)) != QRK_OK ||
+      (s = dalloc(h, &h->counters, sizeof(int) * (size_t)(2 * h->max_leaves + 2))) != QRK_OK ||
       (s = dalloc(h, &h->ybuf, sizeof(double) * (size_t)K * n)) != QRK_OK ||
       (s = dalloc(h, &h->refpart, sizeof(double) * (size_t)h->refine_grid * std::max(nB, 1))) != QRK_OK ||
       (s = dalloc(h, &h->deltaB, sizeof(double) * (size_t)std::max(nB, 1))) != QRK_OK ||
@@ -217,6 +260,8 @@ qrk_status qrk_create_blockangular(int32_t K, int32_t n, int32_t nB, const int64
     return s;
   }
   if (hipMemcpy(h->row_off_d, row_off_host, sizeof(int64_t) * (K + 1), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(h->pack_blk, packs.data(), sizeof(int64_t) * packs.size(), hipMemcpyHostToDevice) !=
           hipSuccess ||
       hipMemset(h->status, 0, sizeof(int) * 4) != hipSuccess) {
     free_all(h);
@@ -290,10 +335,9 @@ qrk_status qrk_status_get(qrk_handle h, int32_t* detail_host, void* stream) {
 }
 
 qrk_status qrk_set_tsqr_shape(qrk_handle h, int32_t leaves, int32_t fanin) {
-  if (!h || leaves < 0 || leaves > 1024 || fanin < 0 || fanin == 1 || fanin > 64) return QRK_EINVAL;
-  if (h->kind != KIND_BLOCKANGULAR) return QRK_EINVAL;
-  h->leaves = leaves ? leaves
-                     : (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(h->M, 256), 1024));
+  if (!h || leaves < 0 || fanin < 0 || fanin == 1 || fanin > 64) return QRK_EINVAL;
+  if (h->kind != KIND_BLOCKANGULAR || leaves > h->max_leaves) return QRK_EINVAL;
+  h->leaves = leaves ? leaves : default_leaves(h);
   h->fanin = fanin ? fanin : 8;
   return QRK_OK;
 }

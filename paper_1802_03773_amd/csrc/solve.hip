@@ -6,49 +6,108 @@
 // The two triangular solves run through the structure:
 //     R_i^T y_i = g_i;   R_B^T y_B = g_B - sum_i S_i^T y_i;
 //     R_B delta_B = y_B; R_i delta_i = y_i - S_i delta_B.
-// Sums over blocks are deterministic: per-wave partials in registers, per-workgroup
-// partials combined in a fixed order, then one workgroup adds the workgroup partials
-// in index order.
+// Sums over blocks are deterministic: per-wave partials in registers, workgroup partials
+// combined in a fixed order, then a fixed-order reduction of the workgroup partials.
 #include "qrk_device.hpp"
 #include "qrk_launch.hpp"
 
 namespace qrk {
 
+constexpr int kMaxDense = 128;  // nB + 1 <= 128
+
 // ---------------------------------------------------------------------------------
-// Dense part: R_B p_B = c_B, one workgroup (column-sweep back-substitution).
+// Dense triangle, one wave: forward (R_B^T y = g) and backward (R_B x = y) sweeps with
+// R_B staged in LDS.  Lane i holds rows i and i + 64 of the right-hand side.
 // ---------------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(128)
+__device__ __forceinline__ void stage_dense(const T* __restrict__ RB, int L, float* Rs, double* Rsd,
+                                            int tid, int nthreads) {
+  for (int e = tid; e < L * L; e += nthreads) {
+    if constexpr (sizeof(T) == 4)
+      Rs[e] = (float)RB[e];
+    else
+      Rsd[e] = (double)RB[e];
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ double rs_at(const float* Rs, const double* Rsd, int e) {
+  if constexpr (sizeof(T) == 4)
+    return (double)Rs[e];
+  else
+    return Rsd[e];
+}
+
+__device__ __forceinline__ double read_lane_d(double x, int lane) {
+  const long long b = __builtin_bit_cast(long long, x);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Forward: y = R^{-T} g (upper-triangular R, column sweep).  v0/v1 hold g for rows
+// lane and lane+64 on entry and y on exit.
+template <typename T>
+__device__ __forceinline__ void wave_fwd_T(const float* Rs, const double* Rsd, int L, int nB, int lane,
+                                           double& v0, double& v1) {
+  for (int k = 0; k < nB; ++k) {
+    const double gk = read_lane_d(k < 64 ? v0 : v1, k & 63);
+    const double yk = gk / rs_at<T>(Rs, Rsd, k * L + k);
+    if (lane == (k & 63)) {
+      if (k < 64) v0 = yk; else v1 = yk;
+    }
+    if (lane > k && lane < nB) v0 -= rs_at<T>(Rs, Rsd, k * L + lane) * yk;
+    if (lane + 64 > k && lane + 64 < nB) v1 -= rs_at<T>(Rs, Rsd, k * L + lane + 64) * yk;
+  }
+}
+
+// Backward: x = R^{-1} y.
+template <typename T>
+__device__ __forceinline__ void wave_bwd(const float* Rs, const double* Rsd, int L, int nB, int lane,
+                                         double& v0, double& v1) {
+  for (int k = nB - 1; k >= 0; --k) {
+    const double yk = read_lane_d(k < 64 ? v0 : v1, k & 63);
+    const double xk = yk / rs_at<T>(Rs, Rsd, k * L + k);
+    if (lane == (k & 63)) {
+      if (k < 64) v0 = xk; else v1 = xk;
+    }
+    if (lane < k) v0 -= rs_at<T>(Rs, Rsd, lane * L + k) * xk;
+    if (lane + 64 < k) v1 -= rs_at<T>(Rs, Rsd, (lane + 64) * L + k) * xk;
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// Dense part of the back-substitution: R_B p_B = c_B (one workgroup, one working wave).
+// ---------------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256)
 k_backsub_dense(const T* __restrict__ RB, int L, double* __restrict__ p, int64_t off,
                 int* __restrict__ status) {
-  __shared__ double pbuf[2];
-  __shared__ double dmax[2];
-  const int t = threadIdx.x;
+  __shared__ float Rs[sizeof(T) == 4 ? kMaxDense * kMaxDense : 1];
+  __shared__ double Rsd[sizeof(T) == 8 ? kMaxDense * kMaxDense : 1];
   const int nB = L - 1;
-  double rhs = (t < nB) ? (double)RB[(int64_t)t * L + nB] : 0.0;
-  double dg = (t < nB) ? fabs((double)RB[(int64_t)t * L + t]) : 0.0;
-  // max |R_jj| over the workgroup (two waves)
-  double wm = wave_allreduce_max(dg);
-  if ((t & 63) == 0) dmax[t >> 6] = wm;
+  stage_dense<T>(RB, L, Rs, Rsd, threadIdx.x, blockDim.x);
   __syncthreads();
-  const double rmax = (blockDim.x > 64) ? fmax(dmax[0], dmax[1]) : dmax[0];
-  const double tol = (double)nB * Eps<T>::value * rmax;
+  if (threadIdx.x >= 64) return;
+  const int lane = threadIdx.x;
+  double v0 = lane < nB ? rs_at<T>(Rs, Rsd, lane * L + nB) : 0.0;
+  double v1 = lane + 64 < nB ? rs_at<T>(Rs, Rsd, (lane + 64) * L + nB) : 0.0;
+  double dmax = 0.0;
+  for (int k = 0; k < nB; ++k) dmax = fmax(dmax, fabs(rs_at<T>(Rs, Rsd, k * L + k)));
   bool bad = false;
-  for (int i = nB - 1; i >= 0; --i) {
-    if (t == i) {
-      const double piv = (double)RB[(int64_t)i * L + i];
-      if (is_finite(piv) && !(fabs(piv) > tol)) bad = true;
-      pbuf[i & 1] = rhs / piv;
-    }
-    __syncthreads();
-    const double pi = pbuf[i & 1];
-    if (t < i) rhs -= (double)RB[(int64_t)t * L + i] * pi;
-    if (t == i) rhs = pi;
+  for (int k = lane; k < nB; k += 64) {
+    const double piv = rs_at<T>(Rs, Rsd, k * L + k);
+    if (is_finite(piv) && !(fabs(piv) > (double)nB * Eps<T>::value * dmax)) bad = true;
   }
+  wave_bwd<T>(Rs, Rsd, L, nB, lane, v0, v1);
   bool nonfinite = false;
-  if (t < nB) {
-    p[off + t] = rhs;
-    if (!is_finite(rhs)) nonfinite = true;
+  if (lane < nB) {
+    p[off + lane] = v0;
+    nonfinite |= !is_finite(v0);
+  }
+  if (lane + 64 < nB) {
+    p[off + lane + 64] = v1;
+    nonfinite |= !is_finite(v1);
   }
   if (bad) set_status(status, ST_SINGULAR);
   if (nonfinite) set_status(status, ST_NONFINITE);
@@ -57,13 +116,12 @@ k_backsub_dense(const T* __restrict__ RB, int L, double* __restrict__ p, int64_t
 template <typename T>
 hipError_t launch_backsub_dense(const T* RB, int L, double* p, int64_t off, int* status,
                                 hipStream_t st) {
-  if (L - 1 > 128) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_backsub_dense<T>), dim3(1), dim3(128), 0, st, RB, L, p, off, status);
+  if (L > kMaxDense) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_backsub_dense<T>), dim3(1), dim3(256), 0, st, RB, L, p, off, status);
   return hipGetLastError();
 }
 
-// Small triangular solves of one block, evaluated redundantly by every lane.
-// Rb is the block's n x n R (row-major).  rhs/out hold up to 8 entries.
+// Small triangular solves of one block (n <= 8), evaluated by one lane.
 template <typename T>
 __device__ __forceinline__ void block_backsub(const T* __restrict__ Rb, int n, const double* rhs,
                                               double* out) {
@@ -94,245 +152,293 @@ __device__ __forceinline__ void block_fwdsub_T(const T* __restrict__ Rb, int n, 
   }
 }
 
+__device__ __forceinline__ double sum16(double x) {
+#pragma unroll
+  for (int off = 8; off >= 1; off >>= 1) x += __shfl_xor(x, off, 16);
+  return x;
+}
+
 // ---------------------------------------------------------------------------------
-// Blocks: p_i = R_i^{-1} (c_i - S_i p_B), one wave per block.
+// Blocks: p_i (= | +=) R_i^{-1} (base_i - S_i v), 16 lanes per block, 16 blocks per
+// workgroup in flight.
+//   back-substitution: base_i = c_i (last column of S|c), v = p_B, p_i set;
+//   refinement:        base_i = y_i, v = delta_B, p_i incremented.
 // ---------------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool REFINE>
 __global__ void __launch_bounds__(256)
-k_backsub_blocks(int64_t K, int n, int nB, const T* __restrict__ Rblk, const T* __restrict__ Sc,
-                 double* __restrict__ p, int* __restrict__ status) {
+k_blocks_solve(int64_t K, int n, int nB, const T* __restrict__ Rblk, const T* __restrict__ Sc,
+               const double* __restrict__ v, const double* __restrict__ ybase,
+               double* __restrict__ p, int* __restrict__ status) {
   const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
+  const int l16 = lane & 15;
+  const int grp = threadIdx.x >> 4;  // 0..15
   const int L = nB + 1;
-  const int64_t base = K * n;
-  const double pb0 = (lane < nB) ? p[base + lane] : 0.0;
-  const double pb1 = (lane + 64 < nB) ? p[base + 64 + lane] : 0.0;
-  const int64_t nwaves = (int64_t)gridDim.x * 4;
+  double vj[8];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const int j = l16 + 16 * s;
+    vj[s] = (j < nB) ? v[j] : 0.0;
+  }
+  const int64_t stride = (int64_t)gridDim.x * 16;
   bool bad = false, nonfinite = false;
-  for (int64_t blk = (int64_t)blockIdx.x * 4 + wv; blk < K; blk += nwaves) {
+  // every group of a wave runs the same number of iterations (the wave's first group
+  // decides), so the 16-lane reductions always see all their lanes
+  const int64_t first = (int64_t)blockIdx.x * 16 + (grp & ~3);
+  for (int64_t base = first; base < K; base += stride) {
+    const int64_t blk = base + (grp & 3);
+    const bool active = blk < K;
     double rhs[8], out[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       rhs[k] = 0.0;
       out[k] = 0.0;
       if (k < n) {
-        const T* row = Sc + (blk * n + k) * L;
         double s = 0.0;
-        if (lane < nB) s += (double)row[lane] * pb0;
-        if (lane + 64 < nB) s += (double)row[64 + lane] * pb1;
-        s = wave_allreduce_sum(s);
-        rhs[k] = (double)row[nB] - s;
+        const T* row = Sc + ((active ? blk : 0) * n + k) * L;
+        if (active) {
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const int j = l16 + 16 * q;
+            if (j < nB) s += (double)row[j] * vj[q];
+          }
+        }
+        s = sum16(s);
+        if (active) rhs[k] = (REFINE ? ybase[blk * n + k] : (double)row[nB]) - s;
       }
     }
-    const T* Rb = Rblk + blk * n * n;
-    double dmax = 0.0;
+    if (active && l16 == 0) {
+      const T* Rb = Rblk + blk * n * n;
+      if (!REFINE) {
+        double dmax = 0.0;
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
-      if (k < n) dmax = fmax(dmax, fabs((double)Rb[k * n + k]));
+        for (int k = 0; k < 8; ++k)
+          if (k < n) dmax = fmax(dmax, fabs((double)Rb[k * n + k]));
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
-      if (k < n) {
-        const double piv = (double)Rb[k * n + k];
-        if (is_finite(piv) && !(fabs(piv) > (double)n * Eps<T>::value * dmax)) bad = true;
+        for (int k = 0; k < 8; ++k)
+          if (k < n) {
+            const double piv = (double)Rb[k * n + k];
+            if (is_finite(piv) && !(fabs(piv) > (double)n * Eps<T>::value * dmax)) bad = true;
+          }
       }
-    block_backsub(Rb, n, rhs, out);
+      block_backsub(Rb, n, rhs, out);
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
-      if (k < n && lane == k) {
-        p[blk * n + k] = out[k];
-        if (!is_finite(out[k])) nonfinite = true;
-      }
+      for (int k = 0; k < 8; ++k)
+        if (k < n) {
+          if (REFINE)
+            p[blk * n + k] += out[k];
+          else
+            p[blk * n + k] = out[k];
+          nonfinite |= !is_finite(out[k]);
+        }
+    }
   }
-  if (bad) set_status(status, ST_SINGULAR);
-  if (nonfinite) set_status(status, ST_NONFINITE);
+  if (status) {
+    if (bad) set_status(status, ST_SINGULAR);
+    if (nonfinite) set_status(status, ST_NONFINITE);
+  }
 }
 
 template <typename T>
 hipError_t launch_backsub_blocks(int64_t K, int n, int nB, const T* Rblk, const T* Sc, double* p,
                                  int* status, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((k_backsub_blocks<T>), dim3(grid), dim3(256), 0, st, K, n, nB, Rblk, Sc, p,
-                     status);
+  if (nB + 1 > kMaxDense || n > 8) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_blocks_solve<T, false>), dim3(grid), dim3(256), 0, st, K, n, nB, Rblk, Sc,
+                     p + K * n, (const double*)nullptr, p, status);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_refine_blocks(int64_t K, int n, int nB, const T* Rblk, const T* Sc, const double* y,
+                                const double* delta_B, double* p, int grid, hipStream_t st) {
+  if (nB + 1 > kMaxDense || n > 8) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_blocks_solve<T, true>), dim3(grid), dim3(256), 0, st, K, n, nB, Rblk, Sc,
+                     delta_B, y, p, (int*)nullptr);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------------
-// Refinement pass 1 (one wave per block, float64 arithmetic).
+// Refinement pass 1: one wave per pack of whole blocks (at most 64 rows), one row per lane.
+//   r = b - A_i p_i - B p_B;  g_i = A_i^T r - lam d_i^2 p_i;  y_i = R_i^{-T} g_i;
+//   per-workgroup partial of  B^T r - sum_i S_i^T y_i.
 // ---------------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_refine_residual(int64_t K, int n, int nB, const int64_t* __restrict__ row_off,
-                  const T* __restrict__ A, const T* __restrict__ B, int64_t ldb,
-                  const T* __restrict__ bvec, const double* __restrict__ d, double lam,
-                  const T* __restrict__ Rblk, const T* __restrict__ Sc,
-                  const double* __restrict__ p, double* __restrict__ y, double* __restrict__ part) {
-  __shared__ double red[4][128];
+k_refine_pass1(int64_t npacks, const int64_t* __restrict__ pack_blk, int n, int nB,
+               const int64_t* __restrict__ row_off, const T* __restrict__ A, const T* __restrict__ B,
+               int64_t ldb, const T* __restrict__ bvec, const double* __restrict__ d, double lam,
+               const T* __restrict__ Rblk, const T* __restrict__ Sc, const double* __restrict__ p,
+               double* __restrict__ y, double* __restrict__ part, int64_t Kn) {
+  __shared__ double pB[kMaxDense];
+  __shared__ double rr[4][64];
+  __shared__ double prod[4][64][8];
+  __shared__ double yv[4][64][8];
+  __shared__ int rowblk[4][64];
+  __shared__ double red[4][kMaxDense];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int L = nB + 1;
-  const int64_t base = K * n;
-  const double pb0 = (lane < nB) ? p[base + lane] : 0.0;
-  const double pb1 = (lane + 64 < nB) ? p[base + 64 + lane] : 0.0;
-  double t0 = 0.0, t1 = 0.0;  // partial sums of B^T r - S^T y for columns lane, lane+64
-  const int64_t nwaves = (int64_t)gridDim.x * 4;
-  for (int64_t blk = (int64_t)blockIdx.x * 4 + wv; blk < K; blk += nwaves) {
-    const int64_t r0 = row_off[blk];
-    const int m = (int)(row_off[blk + 1] - r0);
-    double pi[8], g[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      pi[k] = (k < n) ? p[blk * n + k] : 0.0;
-      g[k] = 0.0;
-    }
-    for (int r = 0; r < m; ++r) {
-      const int64_t row = r0 + r;
-      const double b0 = (lane < nB) ? (double)B[row * ldb + lane] : 0.0;
-      const double b1 = (lane + 64 < nB) ? (double)B[row * ldb + 64 + lane] : 0.0;
-      double s = wave_allreduce_sum(b0 * pb0 + b1 * pb1);
-      double aval[8];
-      double ap = 0.0;
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        aval[k] = (k < n) ? (double)A[row * n + k] : 0.0;
-        ap += aval[k] * pi[k];
-      }
-      const double res = (double)bvec[row] - ap - s;
-#pragma unroll
-      for (int k = 0; k < 8; ++k) g[k] += aval[k] * res;
-      t0 += b0 * res;
-      t1 += b1 * res;
-    }
-#pragma unroll
-    for (int k = 0; k < 8; ++k)
-      if (k < n) {
-        const double dk = d[blk * n + k];
-        g[k] -= lam * dk * dk * pi[k];
-      }
-    const T* Rb = Rblk + blk * n * n;
-    double yy[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) yy[k] = 0.0;
-    block_fwdsub_T(Rb, n, g, yy);
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      if (k < n) {
-        const T* row = Sc + (blk * n + k) * L;
-        if (lane < nB) t0 -= (double)row[lane] * yy[k];
-        if (lane + 64 < nB) t1 -= (double)row[64 + lane] * yy[k];
-        if (lane == k) y[blk * n + k] = yy[k];
-      }
-    }
-  }
-  // workgroup partial: waves combined in fixed order
-  red[wv][lane] = t0;
-  red[wv][64 + lane] = t1;
+  for (int j = threadIdx.x; j < nB; j += blockDim.x) pB[j] = p[Kn + j];
   __syncthreads();
-  if (threadIdx.x < 128 && threadIdx.x < nB) {
-    const int j = threadIdx.x;
-    const double s = ((red[0][j] + red[1][j]) + red[2][j]) + red[3][j];
-    part[(int64_t)blockIdx.x * nB + j] = s;
+  double t0 = 0.0, t1 = 0.0;  // partial B^T r - S^T y for columns lane, lane + 64
+  const int64_t nwaves = (int64_t)gridDim.x * 4;
+  for (int64_t pk = (int64_t)blockIdx.x * 4 + wv; pk < npacks; pk += nwaves) {
+    const int64_t b0 = pack_blk[pk];
+    const int nb = (int)(pack_blk[pk + 1] - b0);
+    const int64_t pr0 = row_off[b0];
+    const int prows = (int)(row_off[b0 + nb] - pr0);
+    if (lane < nb) {
+      const int lo = (int)(row_off[b0 + lane] - pr0), hi = (int)(row_off[b0 + lane + 1] - pr0);
+      for (int r = lo; r < hi; ++r) rowblk[wv][r] = lane;
+    }
+    wave_lds_sync();
+    if (lane < prows) {
+      const int64_t row = pr0 + lane;
+      const int64_t blk = b0 + rowblk[wv][lane];
+      double a[8], dot = 0.0;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        a[c] = (c < n) ? (double)A[row * n + c] : 0.0;
+        if (c < n) dot += a[c] * p[blk * n + c];
+      }
+      const T* Brow = B + row * ldb;
+      double d0 = 0.0, d1 = 0.0;
+      int j = 0;
+      for (; j + 1 < nB; j += 2) {
+        d0 += (double)Brow[j] * pB[j];
+        d1 += (double)Brow[j + 1] * pB[j + 1];
+      }
+      if (j < nB) d0 += (double)Brow[j] * pB[j];
+      const double r = (double)bvec[row] - dot - (d0 + d1);
+      rr[wv][lane] = r;
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (c < n) prod[wv][lane][c] = a[c] * r;
+    }
+    wave_lds_sync();
+    // B^T r over the pack's rows (coalesced across lanes)
+    for (int r = 0; r < prows; ++r) {
+      const T* Brow = B + (pr0 + r) * ldb;
+      const double rv = rr[wv][r];
+      if (lane < nB) t0 += (double)Brow[lane] * rv;
+      if (lane + 64 < nB) t1 += (double)Brow[lane + 64] * rv;
+    }
+    // per block: g_i, y_i
+    if (lane < nb) {
+      const int64_t blk = b0 + lane;
+      const int lo = (int)(row_off[blk] - pr0), hi = (int)(row_off[blk + 1] - pr0);
+      double g[8], yy[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        g[c] = 0.0;
+        yy[c] = 0.0;
+      }
+      for (int r = lo; r < hi; ++r)
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+          if (c < n) g[c] += prod[wv][r][c];
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (c < n) {
+          const double dc = d[blk * n + c];
+          g[c] -= lam * dc * dc * p[blk * n + c];
+        }
+      block_fwdsub_T(Rblk + blk * n * n, n, g, yy);
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (c < n) {
+          y[blk * n + c] = yy[c];
+          yv[wv][lane][c] = yy[c];
+        }
+    }
+    wave_lds_sync();
+    // S^T y over the pack's blocks
+    for (int k = 0; k < nb; ++k) {
+      const T* Srow = Sc + (b0 + k) * n * L;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        if (c < n) {
+          const double yc = yv[wv][k][c];
+          if (lane < nB) t0 -= (double)Srow[c * L + lane] * yc;
+          if (lane + 64 < nB) t1 -= (double)Srow[c * L + lane + 64] * yc;
+        }
+      }
+    }
+    wave_lds_sync();
   }
+  red[wv][lane] = t0;
+  red[wv][lane + 64] = t1;
+  __syncthreads();
+  for (int j = threadIdx.x; j < nB; j += blockDim.x)
+    part[(int64_t)blockIdx.x * nB + j] = ((red[0][j] + red[1][j]) + red[2][j]) + red[3][j];
 }
 
 template <typename T>
-hipError_t launch_refine_residual(int64_t K, int n, int nB, const int64_t* row_off, const T* A,
-                                  const T* B, int64_t ldb, const T* b, const double* d, double lam,
-                                  const T* Rblk, const T* Sc, const double* p, double* y,
-                                  double* part, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((k_refine_residual<T>), dim3(grid), dim3(256), 0, st, K, n, nB, row_off, A, B,
-                     ldb, b, d, lam, Rblk, Sc, p, y, part);
+hipError_t launch_refine_residual(int64_t npacks, const int64_t* pack_blk, int64_t K, int n, int nB,
+                                  const int64_t* row_off, const T* A, const T* B, int64_t ldb, const T* b,
+                                  const double* d, double lam, const T* Rblk, const T* Sc,
+                                  const double* p, double* y, double* part, int grid, hipStream_t st) {
+  if (nB + 1 > kMaxDense || n > 8) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_refine_pass1<T>), dim3(grid), dim3(256), 0, st, npacks, pack_blk, n, nB, row_off,
+                     A, B, ldb, b, d, lam, Rblk, Sc, p, y, part, K * n);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------------
-// Refinement pass 2 (one workgroup): dense-part correction.
+// Refinement pass 2 (one workgroup): g_B = sum of the partials (fixed order) - lam d_B^2 p_B,
+// then y_B = R_B^{-T} g_B and delta_B = R_B^{-1} y_B by one wave; p_B += delta_B.
 // ---------------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(128)
+__global__ void __launch_bounds__(1024)
 k_refine_dense(int nparts, int nB, const double* __restrict__ part, const T* __restrict__ RB,
                const double* __restrict__ dvec, double lam, double* __restrict__ p, int64_t off,
                double* __restrict__ delta_B) {
-  __shared__ double buf[2];
-  const int t = threadIdx.x;
+  __shared__ float Rs[sizeof(T) == 4 ? kMaxDense * kMaxDense : 1];
+  __shared__ double Rsd[sizeof(T) == 8 ? kMaxDense * kMaxDense : 1];
+  __shared__ double acc[8][kMaxDense];
   const int L = nB + 1;
-  double g = 0.0;
-  if (t < nB) {
-    for (int w = 0; w < nparts; ++w) g += part[(int64_t)w * nB + t];
-    const double dj = dvec[off + t];
-    g -= lam * dj * dj * p[off + t];
-  }
-  // R_B^T y = g (forward, column sweep): y_i = g_i / R_ii; g_t -= R_it y_i for t > i
-  for (int i = 0; i < nB; ++i) {
-    if (t == i) buf[i & 1] = g / (double)RB[(int64_t)i * L + i];
-    __syncthreads();
-    const double yi = buf[i & 1];
-    if (t > i && t < nB) g -= (double)RB[(int64_t)i * L + t] * yi;
-    if (t == i) g = yi;
-  }
+  const int t = threadIdx.x;
+  const int j = t & 127, q = t >> 7;
+  double s = 0.0;
+  if (j < nB)
+    for (int w = q; w < nparts; w += 8) s += part[(int64_t)w * nB + j];
+  acc[q][j] = s;
+  stage_dense<T>(RB, L, Rs, Rsd, t, blockDim.x);
   __syncthreads();
-  // R_B delta = y (backward, column sweep)
-  for (int i = nB - 1; i >= 0; --i) {
-    if (t == i) buf[i & 1] = g / (double)RB[(int64_t)i * L + i];
-    __syncthreads();
-    const double di = buf[i & 1];
-    if (t < i) g -= (double)RB[(int64_t)t * L + i] * di;
-    if (t == i) g = di;
+  if (t >= 64) return;
+  const int lane = t;
+  double v0 = 0.0, v1 = 0.0;
+  if (lane < nB) {
+    double g = 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) g += acc[k][lane];
+    const double dj = dvec[off + lane];
+    v0 = g - lam * dj * dj * p[off + lane];
   }
-  if (t < nB) {
-    delta_B[t] = g;
-    p[off + t] += g;
+  if (lane + 64 < nB) {
+    double g = 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) g += acc[k][lane + 64];
+    const double dj = dvec[off + lane + 64];
+    v1 = g - lam * dj * dj * p[off + lane + 64];
+  }
+  wave_fwd_T<T>(Rs, Rsd, L, nB, lane, v0, v1);
+  wave_bwd<T>(Rs, Rsd, L, nB, lane, v0, v1);
+  if (lane < nB) {
+    delta_B[lane] = v0;
+    p[off + lane] += v0;
+  }
+  if (lane + 64 < nB) {
+    delta_B[lane + 64] = v1;
+    p[off + lane + 64] += v1;
   }
 }
 
 template <typename T>
 hipError_t launch_refine_dense(int nparts, int nB, const double* part, const T* RB, const double* dvec,
                                double lam, double* p, int64_t off, double* delta_B, hipStream_t st) {
-  if (nB > 128) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_refine_dense<T>), dim3(1), dim3(128), 0, st, nparts, nB, part, RB, dvec, lam,
+  if (nB + 1 > kMaxDense) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_refine_dense<T>), dim3(1), dim3(1024), 0, st, nparts, nB, part, RB, dvec, lam,
                      p, off, delta_B);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------------
-// Refinement pass 3: delta_i = R_i^{-1}(y_i - S_i delta_B), p_i += delta_i.
-// ---------------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(256)
-k_refine_blocks(int64_t K, int n, int nB, const T* __restrict__ Rblk, const T* __restrict__ Sc,
-                const double* __restrict__ y, const double* __restrict__ delta_B,
-                double* __restrict__ p) {
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  const int L = nB + 1;
-  const double db0 = (lane < nB) ? delta_B[lane] : 0.0;
-  const double db1 = (lane + 64 < nB) ? delta_B[64 + lane] : 0.0;
-  const int64_t nwaves = (int64_t)gridDim.x * 4;
-  for (int64_t blk = (int64_t)blockIdx.x * 4 + wv; blk < K; blk += nwaves) {
-    double rhs[8], out[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      rhs[k] = 0.0;
-      out[k] = 0.0;
-      if (k < n) {
-        const T* row = Sc + (blk * n + k) * L;
-        double s = 0.0;
-        if (lane < nB) s += (double)row[lane] * db0;
-        if (lane + 64 < nB) s += (double)row[64 + lane] * db1;
-        s = wave_allreduce_sum(s);
-        rhs[k] = y[blk * n + k] - s;
-      }
-    }
-    block_backsub(Rblk + blk * n * n, n, rhs, out);
-#pragma unroll
-    for (int k = 0; k < 8; ++k)
-      if (k < n && lane == k) p[blk * n + k] += out[k];
-  }
-}
-
-template <typename T>
-hipError_t launch_refine_blocks(int64_t K, int n, int nB, const T* Rblk, const T* Sc, const double* y,
-                                const double* delta_B, double* p, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((k_refine_blocks<T>), dim3(grid), dim3(256), 0, st, K, n, nB, Rblk, Sc, y,
-                     delta_B, p);
   return hipGetLastError();
 }
 
@@ -340,10 +446,10 @@ hipError_t launch_refine_blocks(int64_t K, int n, int nB, const T* Rblk, const T
   template hipError_t launch_backsub_dense<T>(const T*, int, double*, int64_t, int*, hipStream_t);  \
   template hipError_t launch_backsub_blocks<T>(int64_t, int, int, const T*, const T*, double*, int*, \
                                                int, hipStream_t);                                   \
-  template hipError_t launch_refine_residual<T>(int64_t, int, int, const int64_t*, const T*,         \
-                                                const T*, int64_t, const T*, const double*, double,  \
-                                                const T*, const T*, const double*, double*, double*, \
-                                                int, hipStream_t);                                  \
+  template hipError_t launch_refine_residual<T>(int64_t, const int64_t*, int64_t, int, int,          \
+                                                const int64_t*, const T*, const T*, int64_t,         \
+                                                const T*, const double*, double, const T*, const T*, \
+                                                const double*, double*, double*, int, hipStream_t);  \
   template hipError_t launch_refine_dense<T>(int, int, const double*, const T*, const double*,       \
                                              double, double*, int64_t, double*, hipStream_t);       \
   template hipError_t launch_refine_blocks<T>(int64_t, int, int, const T*, const T*, const double*,  \

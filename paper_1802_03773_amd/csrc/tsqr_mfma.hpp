@@ -1,0 +1,370 @@
+// Tall-skinny QR of the reduced dense rows on the gfx950 matrix cores (float32).
+//
+// What is computed (QRkit Section 4.2): the triangle R' of qr(Q_1^perp^T A_2), i.e. of
+// all reduced rows of the block-angular step stacked with the damping rows
+// sqrt(lam) D_B, with the right-hand side carried as the last column.
+//
+// Organisation (communication-avoiding tall-skinny QR):
+//   * every wave is a leaf: it streams a contiguous range of rows, a tile of 16*NRB rows
+//     at a time, into its own running upper triangle R (a flat tree inside the wave);
+//   * the leaf triangles are then merged pairwise, QR([R_left; R_right]), in the same
+//     launch: the second wave of a pair to finish performs the merge (arrival counted
+//     with a device-scope atomic), so no wave ever waits for another;
+//   * the root is written out row-major (L x L).
+//
+// Merging a tile X into R uses blocked Householder with the compact WY form (paper
+// Section 2, compressed WY: Q = I - V T V^T; the paper writes I + Y T Y^T, the sign of
+// T differs), panels of 16 columns:
+//   panel   for each column j: reflector [1; w_j] acting on R's row j and the tile (the
+//           zeros of R below its diagonal are never touched), applied to the rest of the
+//           panel; the Gram entries w_k^T w_j come out of the same reductions and
+//           T[0:j, j] = -tau_j T[0:j, 0:j] (W[:, 0:j]^T w_j), T_jj = tau_j, is built
+//           alongside;
+//   update  Z = R[panel rows, trail] + W^T X_trail;  Z' = T^T Z;
+//           R[panel rows, trail] -= Z';  X_trail -= W Z'        (MFMA f32 16x16x4).
+//
+// Register layout: a 16x16 block M is one float4 per lane in the matrix-core
+// accumulator layout: lane l, component v holds M[4*(l>>4) + v][l & 15].  With that
+// layout the tile blocks are directly the operands of W^T X and T is directly the A
+// operand of T^T Z; only W and T are re-laid out through LDS, once per panel.
+#pragma once
+
+#include <type_traits>
+
+#include "qrk_device.hpp"
+
+namespace qrk {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
+__device__ __forceinline__ float f_of(unsigned u) { return __builtin_bit_cast(float, u); }
+__device__ __forceinline__ unsigned u_of(float x) { return __builtin_bit_cast(unsigned, x); }
+
+// A copy of x that the compiler cannot identify with x (an empty asm on a register;
+// no memory is touched).  The permlane swaps need two distinct operands.
+__device__ __forceinline__ unsigned opaque_copy(unsigned x) {
+  unsigned y = x;
+  asm volatile("" : "+v"(y));
+  return y;
+}
+
+// Sum over the four 16-lane rows of the wave (lanes l, l^16, l^32, l^48), in every lane.
+// permlane16_swap exchanges the odd rows of its first operand with the even rows of
+// the second, permlane32_swap the upper half of the first with the lower half of the
+// second; with both operands equal to x, the two results add up to x[l] + x[l^16]
+// (resp. x[l^32]).  IEEE addition is commutative, so all lanes get the same bits.
+__device__ __forceinline__ float sum_rows4(float x) {
+  auto a = __builtin_amdgcn_permlane16_swap(u_of(x), opaque_copy(u_of(x)), false, false);
+  x = f_of(a[0]) + f_of(a[1]);
+  auto b = __builtin_amdgcn_permlane32_swap(u_of(x), opaque_copy(u_of(x)), false, false);
+  return f_of(b[0]) + f_of(b[1]);
+}
+
+// Broadcast lane J of every 16-lane row to the whole row.
+template <int J>
+__device__ __forceinline__ float row_bcast(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x150 + J,
+                                                            0xF, 0xF, false));
+}
+
+__device__ __forceinline__ float read_lane(float x, int lane) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), lane));
+}
+
+__device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+constexpr int kWaveLds = 256 + 256 + 256 * 8;  // T staging, spare, W staging (up to 8 blocks)
+
+template <int NCB>
+struct Tri {
+  static constexpr int count = NCB * (NCB + 1) / 2;
+  static constexpr int idx(int p, int q) { return p * NCB - (p * (p - 1)) / 2 + (q - p); }
+};
+
+// Merge the tile X (NRB block rows) into the running triangle R.
+//   TRI = false: a dense tile of 16*NRB rows; panels before pstart are skipped (their
+//                tile columns are known to be zero).
+//   TRI = true : the tile is an upper-triangular NCB x NCB block triangle (NRB == NCB);
+//                in panel P only block rows 0..P are nonzero, which is used at compile
+//                time.
+template <int NCB, int NRB, bool TRI>
+__device__ __forceinline__ void merge_tile(f4 (&R)[Tri<NCB>::count], f4 (&X)[NRB][NCB], int pstart,
+                                           float* __restrict__ lds, int lane) {
+  const int g = lane >> 4;
+  const int c = lane & 15;
+  float* Tl = lds;            // [16][16]
+  float* Wl = lds + 512;      // [NRB][16][16]
+
+  static_for<0, NCB>([&](auto PP) {
+    constexpr int P = decltype(PP)::value;
+    constexpr int rp = Tri<NCB>::idx(P, P);
+    constexpr int RBN = TRI ? (P + 1 < NRB ? P + 1 : NRB) : NRB;  // active block rows
+    if (!TRI && P < pstart) return;
+
+    // ---- panel factorisation of [R[P][P]; X[:, P]] (and T alongside) -------------------
+    float trow[16];  // lane (g, c) builds row c of T
+    static_for<0, 16>([&](auto JJ) {
+      constexpr int j = decltype(JJ)::value;
+      float ps0 = 0.f, ps1 = 0.f;
+#pragma unroll
+      for (int rb = 0; rb < RBN; ++rb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          if (v & 1)
+            ps1 += X[rb][P][v] * X[rb][P][v];
+          else
+            ps0 += X[rb][P][v] * X[rb][P][v];
+        }
+      const float ps = sum_rows4(ps0 + ps1);
+      const float sigma = read_lane(ps, j);
+      const float alpha = read_lane(R[rp][j & 3], (j >> 2) * 16 + j);
+      float beta = alpha, tau = 0.f, scale = 0.f;
+      if (sigma != 0.f) {
+        const float nrm = __builtin_amdgcn_sqrtf(alpha * alpha + sigma);
+        beta = alpha >= 0.f ? -nrm : nrm;
+        tau = (beta - alpha) * __builtin_amdgcn_rcpf(beta);
+        scale = __builtin_amdgcn_rcpf(alpha - beta);
+      }
+      float wv[RBN][4];
+#pragma unroll
+      for (int rb = 0; rb < RBN; ++rb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) wv[rb][v] = row_bcast<j>(X[rb][P][v]) * scale;
+      float pd0 = (g == (j >> 2)) ? R[rp][j & 3] : 0.f, pd1 = 0.f;
+#pragma unroll
+      for (int rb = 0; rb < RBN; ++rb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          if (v & 1)
+            pd1 += wv[rb][v] * X[rb][P][v];
+          else
+            pd0 += wv[rb][v] * X[rb][P][v];
+        }
+      const float pd = sum_rows4(pd0 + pd1);  // lane c: R[j][c] + w_j^T x_c  (= w_c^T w_j for c < j)
+      const float s = tau * pd;
+      if (c > j) {
+#pragma unroll
+        for (int rb = 0; rb < RBN; ++rb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) X[rb][P][v] -= wv[rb][v] * s;
+        if (g == (j >> 2)) R[rp][j & 3] -= s;
+      } else if (c == j) {
+#pragma unroll
+        for (int rb = 0; rb < RBN; ++rb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) X[rb][P][v] = wv[rb][v];
+        if (g == (j >> 2)) R[rp][j & 3] = beta;
+      }
+      // T column j: T[c][j] = -tau_j sum_{k<j} T[c][k] (w_k^T w_j), T[j][j] = tau_j
+      float t = 0.f;
+      static_for<0, j>([&](auto KK) {
+        constexpr int k = decltype(KK)::value;
+        t += trow[k] * row_bcast<k>(pd);
+      });
+      trow[j] = (c < j) ? -tau * t : (c == j ? tau : 0.f);
+    });
+
+    // ---- re-lay out T (rows -> accumulator layout) and W (transposed) through LDS --------
+    if (g == 0) {
+#pragma unroll
+      for (int k = 0; k < 16; k += 4)
+        *reinterpret_cast<f4*>(Tl + c * 16 + k) = f4{trow[k], trow[k + 1], trow[k + 2], trow[k + 3]};
+    }
+#pragma unroll
+    for (int rb = 0; rb < RBN; ++rb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Wl[rb * 256 + (4 * g + v) * 16 + c] = X[rb][P][v];
+    wave_lds_sync();
+    f4 Td;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Td[v] = Tl[(4 * g + v) * 16 + c];
+    float Wt[RBN][4];  // -W[rb*16 + c][4g + v]
+#pragma unroll
+    for (int rb = 0; rb < RBN; ++rb) {
+      const f4 w4 = *reinterpret_cast<const f4*>(Wl + rb * 256 + c * 16 + 4 * g);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Wt[rb][v] = -w4[v];
+    }
+    wave_lds_sync();
+
+    // ---- trailing update on the matrix cores ----------------------------------------------
+    static_for<P + 1, NCB>([&](auto QQ) {
+      constexpr int q = decltype(QQ)::value;
+      constexpr int rq = Tri<NCB>::idx(P, q);
+      f4 Z0 = R[rq], Z1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int rb = 0; rb < RBN; ++rb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          if ((rb * 4 + v) & 1)
+            Z1 = mfma4(X[rb][P][v], X[rb][q][v], Z1);
+          else
+            Z0 = mfma4(X[rb][P][v], X[rb][q][v], Z0);
+        }
+      const f4 Z = Z0 + Z1;
+      f4 Zp = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Zp = mfma4(Td[v], Z[v], Zp);
+      R[rq] -= Zp;
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int rb = 0; rb < RBN; ++rb) X[rb][q] = mfma4(Wt[rb][v], Zp[v], X[rb][q]);
+    });
+  });
+}
+
+// A stored triangle is its NCB(NCB+1)/2 blocks, 1 KiB each, lane-contiguous.
+template <int NCB>
+__device__ __forceinline__ void store_tri(float* __restrict__ dst, const f4 (&R)[Tri<NCB>::count],
+                                          int lane) {
+#pragma unroll
+  for (int t = 0; t < Tri<NCB>::count; ++t) *reinterpret_cast<f4*>(dst + t * 256 + lane * 4) = R[t];
+}
+
+template <int NCB>
+__device__ __forceinline__ void load_tri(const float* __restrict__ src, f4 (&R)[Tri<NCB>::count],
+                                         int lane) {
+#pragma unroll
+  for (int t = 0; t < Tri<NCB>::count; ++t)
+    R[t] = __builtin_nontemporal_load(reinterpret_cast<const f4*>(src + t * 256 + lane * 4));
+}
+
+// R <- triangle of QR([R; stored triangle at src]).
+template <int NCB>
+__device__ __forceinline__ void merge_stored_tri(f4 (&R)[Tri<NCB>::count], const float* __restrict__ src,
+                                                 float* lds, int lane) {
+  f4 X[NCB][NCB];
+  static_for<0, NCB>([&](auto RB) {
+    constexpr int rb = decltype(RB)::value;
+    static_for<0, NCB>([&](auto QQ) {
+      constexpr int q = decltype(QQ)::value;
+      if constexpr (q >= rb)
+        X[rb][q] = __builtin_nontemporal_load(
+            reinterpret_cast<const f4*>(src + Tri<NCB>::idx(rb, q) * 256 + lane * 4));
+      else
+        X[rb][q] = f4{0.f, 0.f, 0.f, 0.f};
+    });
+  });
+  merge_tile<NCB, NCB, true>(R, X, 0, lds, lane);
+}
+
+template <int NCB, int NRB>
+__global__ void __launch_bounds__(256)
+k_tsqr_mfma(const float* __restrict__ Xg, int64_t ldx, int64_t nrows, int L, int64_t rows_per_leaf,
+            int nleaves, const double* __restrict__ dB, double sqrt_lam, float* __restrict__ slots,
+            int* __restrict__ counters, float* __restrict__ Rout) {
+  __shared__ float lds_all[4][kWaveLds];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int leaf = blockIdx.x * 4 + wv;
+  if (leaf >= nleaves) return;
+  float* lds = lds_all[wv];
+  const int g = lane >> 4;
+  const int c = lane & 15;
+  constexpr int NT = Tri<NCB>::count;
+  constexpr int SLOT = NT * 256;
+  constexpr int KT = 16 * NRB;
+
+  f4 R[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) R[t] = f4{0.f, 0.f, 0.f, 0.f};
+  if (leaf == 0 && dB != nullptr) {
+    static_for<0, NCB>([&](auto PP) {
+      constexpr int P = decltype(PP)::value;
+      const int col = 16 * P + c;
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (4 * g + v == c && col < L - 1) R[Tri<NCB>::idx(P, P)][v] = (float)(sqrt_lam * dB[col]);
+    });
+  }
+
+  // ---- leaf: stream this wave's rows -------------------------------------------------------
+  const int64_t r0 = (int64_t)leaf * rows_per_leaf;
+  const int64_t r1 = r0 + rows_per_leaf < nrows ? r0 + rows_per_leaf : nrows;
+  for (int64_t t = r0; t < r1; t += KT) {
+    f4 X[NRB][NCB];
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+      for (int q = 0; q < NCB; ++q) {
+        const int col = 16 * q + c;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t row = t + rb * 16 + 4 * g + v;
+          X[rb][q][v] = (row < r1 && col < L) ? Xg[row * ldx + col] : 0.f;
+        }
+      }
+    merge_tile<NCB, NRB, false>(R, X, 0, lds, lane);
+  }
+
+  // ---- pairwise merges up the tree, in the same launch --------------------------------------
+  int n = nleaves;
+  int slot = leaf;
+  int64_t base = 0;   // first slot of the current level
+  int64_t cbase = 0;  // first counter of the current level
+  while (n > 1) {
+    const int sib = slot ^ 1;
+    const int parent = slot >> 1;
+    const int nn = (n + 1) >> 1;
+    if (sib >= n) {  // no sibling at this level: carry the triangle up unchanged
+      base += n;
+      cbase += nn;
+      slot = parent;
+      n = nn;
+      continue;
+    }
+    store_tri<NCB>(slots + (base + slot) * SLOT, R, lane);
+    __threadfence();
+    int old = 0;
+    if (lane == 0) old = atomicAdd(&counters[cbase + parent], 1);
+    old = __builtin_amdgcn_readfirstlane(old);
+    if (old == 0) return;  // the sibling is still running; it will merge
+    __threadfence();
+    const int left = slot & ~1;
+    load_tri<NCB>(slots + (base + left) * SLOT, R, lane);
+    merge_stored_tri<NCB>(R, slots + (base + left + 1) * SLOT, lds, lane);
+    base += n;
+    cbase += nn;
+    slot = parent;
+    n = nn;
+  }
+
+  // ---- root: row-major L x L ----------------------------------------------------------------
+  static_for<0, NCB>([&](auto PP) {
+    constexpr int P = decltype(PP)::value;
+    static_for<0, NCB>([&](auto QQ) {
+      constexpr int q = decltype(QQ)::value;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * P + 4 * g + v;
+        const int col = 16 * q + c;
+        float val = 0.f;
+        if constexpr (q >= P) val = (col >= row) ? R[Tri<NCB>::idx(P, q)][v] : 0.f;
+        if (row < L && col < L) Rout[(int64_t)row * L + col] = val;
+      }
+    });
+  });
+}
+
+template <int NCB, int NRB>
+hipError_t launch_tsqr_mfma_ncb(const float* X, int64_t ldx, int64_t nrows, int L, int64_t rows_per_leaf,
+                                int nleaves, const double* dB, double sqrt_lam, float* slots,
+                                int* counters, float* Rout, hipStream_t st) {
+  const int grid = (nleaves + 3) / 4;
+  hipLaunchKernelGGL((k_tsqr_mfma<NCB, NRB>), dim3(grid), dim3(256), 0, st, X, ldx, nrows, L,
+                     rows_per_leaf, nleaves, dB, sqrt_lam, slots, counters, Rout);
+  return hipGetLastError();
+}
+
+}  // namespace qrk

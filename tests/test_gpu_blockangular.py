@@ -101,6 +101,19 @@ def test_tsqr_launch_shapes_agree():
         assert rel_err(p, p_ref) <= 1e-12
 
 
+@pytest.mark.parametrize("nB", [95, 100, 111, 112, 120, 127])
+def test_wide_dense_part_multi_leaf_trees(nB):
+    """7 and 8 column blocks of the dense part with forced multi-leaf reduction trees."""
+    inst = gen.make_blockangular(40 + nB, K=60, m=(np.arange(60) % 9) + 8, n=3, nB=nB, lam=1e-2,
+                                 dtype=np.float32)
+    p_ref, _ = refine.reference_solution(inst)
+    for leaves in [1, 2, 3, 5, 0]:
+        log(f"nB={nB} leaves={leaves}")
+        p, st = gpu_solve_blockangular(inst, leaves=leaves)
+        assert st[0] == 0, st
+        assert rel_err(p, p_ref) <= 1e-5
+
+
 def test_lambda_zero_gauss_newton():
     inst = gen.make_blockangular(6, K=300, m=(np.arange(300) % 7) + 4, n=3, nB=20, lam=0.0,
                                  dtype=np.float64)
