@@ -72,7 +72,7 @@ typedef struct qrk_handle_s* qrk_handle;
 #define QRK_MAX_BLOCK_COLS 8     /* n, columns per diagonal block                 */
 #define QRK_MAX_BLOCK_ROWS 56    /* m_i, rows per diagonal block                  */
 #define QRK_MAX_DENSE_COLS 127   /* nB, columns of the dense part B               */
-#define QRK_MAX_BAND 32          /* w, nonzeros per banded row                    */
+#define QRK_MAX_BAND 31          /* w, nonzeros per banded row                    */
 
 /* ------------------------------------------------------------------------------
  * qrk_create_blockangular
@@ -112,8 +112,16 @@ qrk_status qrk_factor_blockangular(qrk_handle h, const void* A, const void* B, c
  *   device; a violation sets QRK_EINVAL in the status word); vals [M x w] T;
  *   b [M] T; d [N] double > 0; lambda >= 0.
  *   create returns QRK_EINVAL for M < 0, N < 1, w outside 1..QRK_MAX_BAND, w > N.
+ *   Out-of-range or decreasing row starts are clamped and reported as QRK_EINVAL by
+ *   qrk_status_get (the factor of such a call is not meaningful).
  * ------------------------------------------------------------------------------ */
 qrk_status qrk_create_banded(int64_t M, int64_t N, int32_t w, qrk_dtype dtype, qrk_handle* out);
+/* P independent banded problems of the same shape in one handle (one launch per step): every
+ * per-problem array is stacked, row_start [P][M], vals [P][M][w], b [P][M], d and p [P][N];
+ * qrk_solve, qrk_solve_adjoint (dlambda [P]) and qrk_get_factor (R [P][N][w], c [P][N])
+ * follow the same stacking.  QRK_EINVAL for P < 1 or the shape errors above. */
+qrk_status qrk_create_banded_batched(int32_t P, int64_t M, int64_t N, int32_t w, qrk_dtype dtype,
+                                     qrk_handle* out);
 qrk_status qrk_factor_banded(qrk_handle h, const int32_t* row_start, const void* vals,
                              const void* b, const double* d, double lambda, void* stream);
 

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace qrk {
 
 // Status bits recorded in the handle's device status word.
@@ -14,6 +16,15 @@ enum : int {
 };
 
 constexpr int kWave = 64;
+
+// Compile-time loop: f(std::integral_constant<int, I>) for I in [I0, N).
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
 
 // Make LDS writes of one lane visible to the other lanes of the same wave.
 __device__ __forceinline__ void wave_lds_sync() {

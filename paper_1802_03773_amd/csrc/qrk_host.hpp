@@ -13,6 +13,12 @@ namespace qrk {
 enum HandleKind { KIND_BLOCKANGULAR = 0, KIND_BANDED = 1 };
 
 hipError_t launch_fill_int(int* ptr, int value, hipStream_t st);
+hipError_t launch_fill_double(double* p, int64_t n, double value, hipStream_t st);
+template <typename T>
+hipError_t launch_to_type(const double* src, T* dst, int64_t n, hipStream_t st);
+template <typename T>
+hipError_t launch_colnorms(int64_t K, int n, int nB, int64_t M, const int64_t* row_off, const T* A,
+                           const T* B, int64_t ldb, double* d, double* part, int nparts, hipStream_t st);
 
 }  // namespace qrk
 
@@ -30,6 +36,7 @@ struct qrk_handle_s {
   int64_t ldb = 0;
   int max_rows = 0;    // max_i m_i + n
   int w = 0;           // banded: values per row
+  int P = 1;           // banded: problems stacked in the handle
 
   // launch shape
   int grid_blocks = 1;
@@ -60,8 +67,12 @@ struct qrk_handle_s {
   double* ubuf = nullptr;     // adjoint: u = (R^T R)^{-1} g
   double* Jubuf = nullptr;    // adjoint: J u
   int* status = nullptr;
-  void* bandR = nullptr;      // banded: [N][w]
-  void* bandc = nullptr;      // banded: [N]
+  void* bandR = nullptr;      // banded: [P][N][w]
+  void* bandc = nullptr;      // banded: [P][N]
+  double* rbuf = nullptr;     // banded: residual / J u, [P][M] each
+  double* jubuf = nullptr;
+  double* gbuf = nullptr;     // banded: [P][N]
+  double* vecpart = nullptr;  // adjoint vector-term partials
 
   // phase timing: event pairs in a ring, summed on read
   struct ProfRec {
@@ -85,6 +96,14 @@ struct qrk_handle_s {
 };
 
 qrk_status banded_solve(qrk_handle h, double* p, int sweeps, hipStream_t st);
+qrk_status banded_adjoint(qrk_handle h, const double* p, const double* g, void* dvals, void* db,
+                          double* dlam, double* dd, hipStream_t st);
+qrk_status blockangular_adjoint(qrk_handle h, const double* p, const double* g, void* dA, void* dB,
+                                void* db, double* dlam, double* dd, hipStream_t st);
+
+// Workspace allocation shared by the create functions (records the allocation in h).
+qrk_status handle_alloc(qrk_handle h, void** out, size_t bytes);
+void handle_free(qrk_handle h);
 
 // Phase timing helpers: prof_begin returns the record index (or -1 when off or full).
 int prof_begin(qrk_handle h, int phase, hipStream_t st);

@@ -63,4 +63,29 @@ template <typename T>
 hipError_t launch_refine_blocks(int64_t K, int n, int nB, const T* Rblk, const T* Sc, const double* y,
                                 const double* delta_B, double* p, int grid, hipStream_t st);
 
+// Adjoint pieces.  u = (R^T R)^{-1} g through the structured R:
+//   launch_adjoint_fwd_blocks: y_i = R_i^{-T} g_i (-> y), per-workgroup partials of -S_i^T y_i;
+//   launch_adjoint_dense:      u_B = R_B^{-1} R_B^{-T} (g_B + sum of partials);
+//   launch_adjoint_blocks:     u_i = R_i^{-1} (y_i - S_i u_B).
+template <typename T>
+hipError_t launch_adjoint_fwd_blocks(int64_t K, int n, int nB, const T* Rblk, const T* Sc, const double* g,
+                                     double* y, double* part, int grid, hipStream_t st);
+template <typename T>
+hipError_t launch_adjoint_dense(int nparts, int nB, const double* part, const T* RB, const double* gB,
+                                double* uB, hipStream_t st);
+template <typename T>
+hipError_t launch_adjoint_blocks(int64_t K, int n, int nB, const T* Rblk, const T* Sc, const double* y,
+                                 const double* uB, double* u, int grid, hipStream_t st);
+// Gradients on the structural nonzeros, per pack of whole blocks (one row per lane):
+//   r = b - J p, Ju = J u;  dA = r u_i^T - Ju p_i^T;  dB = r u_B^T - Ju p_B^T;  db = Ju.
+template <typename T>
+hipError_t launch_adjoint_rows(int64_t npacks, const int64_t* pack_blk, int64_t K, int n, int nB,
+                               const int64_t* row_off, const T* A, const T* B, int64_t ldb, const T* b,
+                               const double* p, const double* u, T* dA, T* dB, T* db, int grid,
+                               hipStream_t st);
+// dd_j = -2 lam u_j d_j p_j and dlam = -sum_j u_j d_j^2 p_j over P problems of N unknowns
+// (deterministic two-level sum; part holds at least 1024 doubles).
+hipError_t launch_adjoint_vec(int P, int64_t N, const double* u, const double* d, const double* p,
+                              double lam, double* dd, double* dlam, double* part, hipStream_t st);
+
 }  // namespace qrk

@@ -154,6 +154,44 @@ qrk_status dalloc(qrk_handle h, P** out, size_t bytes) {
 
 }  // namespace
 
+qrk_status handle_alloc(qrk_handle h, void** out, size_t bytes) { return dalloc(h, out, bytes); }
+void handle_free(qrk_handle h) { free_all(h); }
+
+template <typename T>
+qrk_status adjoint_ba(qrk_handle h, const double* p, const double* g, void* dA, void* dB, void* db,
+                      double* dlam, double* dd, hipStream_t st) {
+  const T* Rblk = static_cast<const T*>(h->Rblk);
+  const T* Sc = static_cast<const T*>(h->Sc);
+  const T* RB = static_cast<const T*>(h->RB);
+  const int64_t Kn = h->K * h->n;
+  // u = (R^T R)^{-1} g through the structured R
+  if (launch_adjoint_fwd_blocks<T>(h->K, h->n, h->nB, Rblk, Sc, g, h->ybuf, h->refpart, h->refine_grid,
+                                   st) != hipSuccess)
+    return QRK_EHIP;
+  if (h->nB > 0 && launch_adjoint_dense<T>(h->refine_grid, h->nB, h->refpart, RB, g + Kn, h->ubuf + Kn,
+                                           st) != hipSuccess)
+    return QRK_EHIP;
+  if (launch_adjoint_blocks<T>(h->K, h->n, h->nB, Rblk, Sc, h->ybuf, h->ubuf + Kn, h->ubuf, h->solve_grid,
+                               st) != hipSuccess)
+    return QRK_EHIP;
+  if ((dA || dB || db) &&
+      launch_adjoint_rows<T>(h->npacks, h->pack_blk, h->K, h->n, h->nB, h->row_off_d,
+                             static_cast<const T*>(h->A), static_cast<const T*>(h->B), h->ldb,
+                             static_cast<const T*>(h->b), p, h->ubuf, static_cast<T*>(dA),
+                             static_cast<T*>(dB), static_cast<T*>(db), h->refine_grid, st) != hipSuccess)
+    return QRK_EHIP;
+  if ((dlam || dd) &&
+      launch_adjoint_vec(1, h->N, h->ubuf, h->d, p, h->lam, dd, dlam, h->vecpart, st) != hipSuccess)
+    return QRK_EHIP;
+  return QRK_OK;
+}
+
+qrk_status blockangular_adjoint(qrk_handle h, const double* p, const double* g, void* dA, void* dB,
+                                void* db, double* dlam, double* dd, hipStream_t st) {
+  return h->dtype == QRK_F32 ? adjoint_ba<float>(h, p, g, dA, dB, db, dlam, dd, st)
+                             : adjoint_ba<double>(h, p, g, dA, dB, db, dlam, dd, st);
+}
+
 int prof_begin(qrk_handle h, int phase, hipStream_t st) {
   if (!h->prof_on || h->prof_used >= (int)h->prof_pool.size()) return -1;
   const int i = h->prof_used++;
@@ -252,6 +290,8 @@ qrk_status qrk_create_blockangular(int32_t K, int32_t n, int32_t nB, const int64
                                                  : 0)) != QRK_OK ||
       (s = dalloc(h, &h->counters, sizeof(int) * (size_t)(2 * h->max_leaves + 2))) != QRK_OK ||
       (s = dalloc(h, &h->ybuf, sizeof(double) * (size_t)K * n)) != QRK_OK ||
+      (s = dalloc(h, &h->ubuf, sizeof(double) * (size_t)h->N)) != QRK_OK ||
+      (s = dalloc(h, &h->vecpart, sizeof(double) * (size_t)1024 * std::max(nB, 1))) != QRK_OK ||
       (s = dalloc(h, &h->refpart, sizeof(double) * (size_t)h->refine_grid * std::max(nB, 1))) != QRK_OK ||
       (s = dalloc(h, &h->deltaB, sizeof(double) * (size_t)std::max(nB, 1))) != QRK_OK ||
       (s = dalloc(h, &h->status, sizeof(int) * 4)) != QRK_OK) {
@@ -294,6 +334,31 @@ qrk_status qrk_solve(qrk_handle h, double* p, int32_t sweeps, void* stream) {
   return banded_solve(h, p, sweeps, S(stream));
 }
 
+qrk_status qrk_solve_adjoint(qrk_handle h, const double* p, const double* g, void* dA, void* dB,
+                             void* db, double* dlambda, double* dd, void* stream) {
+  if (!h || !h->factored || !p || !g) return QRK_EINVAL;
+  if (h->kind == KIND_BLOCKANGULAR) {
+    if (dB && h->nB == 0) return QRK_EINVAL;
+    return blockangular_adjoint(h, p, g, dA, dB, db, dlambda, dd, S(stream));
+  }
+  if (dB) return QRK_EINVAL;
+  return banded_adjoint(h, p, g, dA, db, dlambda, dd, S(stream));
+}
+
+qrk_status qrk_colnorms_blockangular(qrk_handle h, const void* A, const void* B, double* d, void* stream) {
+  if (!h || h->kind != KIND_BLOCKANGULAR || !A || !d || (h->nB > 0 && !B)) return QRK_EINVAL;
+  const int nparts = (int)std::min<int64_t>(std::max<int64_t>(1, ceil_div(h->M, 512)), 1024);
+  hipError_t e = h->dtype == QRK_F32
+                     ? launch_colnorms<float>(h->K, h->n, h->nB, h->M, h->row_off_d,
+                                              static_cast<const float*>(A), static_cast<const float*>(B),
+                                              h->ldb, d, h->vecpart, nparts, S(stream))
+                     : launch_colnorms<double>(h->K, h->n, h->nB, h->M, h->row_off_d,
+                                               static_cast<const double*>(A),
+                                               static_cast<const double*>(B), h->ldb, d, h->vecpart,
+                                               nparts, S(stream));
+  return e == hipSuccess ? QRK_OK : QRK_EHIP;
+}
+
 qrk_status qrk_get_factor(qrk_handle h, void* Rblk, void* Sc, void* RB, void* stream) {
   if (!h || !h->factored) return QRK_EINVAL;
   const size_t es = h->dtype == QRK_F32 ? 4 : 8;
@@ -309,10 +374,10 @@ qrk_status qrk_get_factor(qrk_handle h, void* Rblk, void* Sc, void* RB, void* st
     if (RB && hipMemcpyAsync(RB, h->RB, es * (size_t)L * L, hipMemcpyDeviceToDevice, st) != hipSuccess)
       return QRK_EHIP;
   } else {
-    if (Rblk && hipMemcpyAsync(Rblk, h->bandR, es * (size_t)h->N * h->w, hipMemcpyDeviceToDevice,
-                               st) != hipSuccess)
+    if (Rblk && hipMemcpyAsync(Rblk, h->bandR, es * (size_t)h->P * h->N * h->w,
+                               hipMemcpyDeviceToDevice, st) != hipSuccess)
       return QRK_EHIP;
-    if (Sc && hipMemcpyAsync(Sc, h->bandc, es * (size_t)h->N, hipMemcpyDeviceToDevice, st) !=
+    if (Sc && hipMemcpyAsync(Sc, h->bandc, es * (size_t)h->P * h->N, hipMemcpyDeviceToDevice, st) !=
                   hipSuccess)
       return QRK_EHIP;
   }

@@ -164,7 +164,9 @@ __device__ __forceinline__ double sum16(double x) {
 //   back-substitution: base_i = c_i (last column of S|c), v = p_B, p_i set;
 //   refinement:        base_i = y_i, v = delta_B, p_i incremented.
 // ---------------------------------------------------------------------------------
-template <typename T, bool REFINE>
+// MODE 0: back-substitution (base c, set p); 1: refinement (base y, add to p);
+// 2: adjoint (base y, set out).
+template <typename T, int MODE>
 __global__ void __launch_bounds__(256)
 k_blocks_solve(int64_t K, int n, int nB, const T* __restrict__ Rblk, const T* __restrict__ Sc,
                const double* __restrict__ v, const double* __restrict__ ybase,
@@ -203,12 +205,12 @@ k_blocks_solve(int64_t K, int n, int nB, const T* __restrict__ Rblk, const T* __
           }
         }
         s = sum16(s);
-        if (active) rhs[k] = (REFINE ? ybase[blk * n + k] : (double)row[nB]) - s;
+        if (active) rhs[k] = (MODE != 0 ? ybase[blk * n + k] : (double)row[nB]) - s;
       }
     }
     if (active && l16 == 0) {
       const T* Rb = Rblk + blk * n * n;
-      if (!REFINE) {
+      if (MODE == 0) {
         double dmax = 0.0;
 #pragma unroll
         for (int k = 0; k < 8; ++k)
@@ -224,7 +226,7 @@ k_blocks_solve(int64_t K, int n, int nB, const T* __restrict__ Rblk, const T* __
 #pragma unroll
       for (int k = 0; k < 8; ++k)
         if (k < n) {
-          if (REFINE)
+          if (MODE == 1)
             p[blk * n + k] += out[k];
           else
             p[blk * n + k] = out[k];
@@ -242,7 +244,7 @@ template <typename T>
 hipError_t launch_backsub_blocks(int64_t K, int n, int nB, const T* Rblk, const T* Sc, double* p,
                                  int* status, int grid, hipStream_t st) {
   if (nB + 1 > kMaxDense || n > 8) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_blocks_solve<T, false>), dim3(grid), dim3(256), 0, st, K, n, nB, Rblk, Sc,
+  hipLaunchKernelGGL((k_blocks_solve<T, 0>), dim3(grid), dim3(256), 0, st, K, n, nB, Rblk, Sc,
                      p + K * n, (const double*)nullptr, p, status);
   return hipGetLastError();
 }
@@ -251,8 +253,17 @@ template <typename T>
 hipError_t launch_refine_blocks(int64_t K, int n, int nB, const T* Rblk, const T* Sc, const double* y,
                                 const double* delta_B, double* p, int grid, hipStream_t st) {
   if (nB + 1 > kMaxDense || n > 8) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_blocks_solve<T, true>), dim3(grid), dim3(256), 0, st, K, n, nB, Rblk, Sc,
+  hipLaunchKernelGGL((k_blocks_solve<T, 1>), dim3(grid), dim3(256), 0, st, K, n, nB, Rblk, Sc,
                      delta_B, y, p, (int*)nullptr);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adjoint_blocks(int64_t K, int n, int nB, const T* Rblk, const T* Sc, const double* y,
+                                 const double* uB, double* u, int grid, hipStream_t st) {
+  if (nB + 1 > kMaxDense || n > 8) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_blocks_solve<T, 2>), dim3(grid), dim3(256), 0, st, K, n, nB, Rblk, Sc,
+                     uB, y, u, (int*)nullptr);
   return hipGetLastError();
 }
 
@@ -387,11 +398,13 @@ hipError_t launch_refine_residual(int64_t npacks, const int64_t* pack_blk, int64
 // Refinement pass 2 (one workgroup): g_B = sum of the partials (fixed order) - lam d_B^2 p_B,
 // then y_B = R_B^{-T} g_B and delta_B = R_B^{-1} y_B by one wave; p_B += delta_B.
 // ---------------------------------------------------------------------------------
-template <typename T>
+// ADJ = false: refinement (rhs = sum(part) - lam d_B^2 p_B; p_B += delta, delta -> delta_B).
+// ADJ = true : adjoint (rhs = g_B + sum(part); the solution -> delta_B, p untouched).
+template <typename T, bool ADJ>
 __global__ void __launch_bounds__(1024)
 k_refine_dense(int nparts, int nB, const double* __restrict__ part, const T* __restrict__ RB,
                const double* __restrict__ dvec, double lam, double* __restrict__ p, int64_t off,
-               double* __restrict__ delta_B) {
+               double* __restrict__ delta_B, const double* __restrict__ gB) {
   __shared__ float Rs[sizeof(T) == 4 ? kMaxDense * kMaxDense : 1];
   __shared__ double Rsd[sizeof(T) == 8 ? kMaxDense * kMaxDense : 1];
   __shared__ double acc[8][kMaxDense];
@@ -411,25 +424,33 @@ k_refine_dense(int nparts, int nB, const double* __restrict__ part, const T* __r
     double g = 0.0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) g += acc[k][lane];
-    const double dj = dvec[off + lane];
-    v0 = g - lam * dj * dj * p[off + lane];
+    if (ADJ) {
+      v0 = gB[lane] + g;
+    } else {
+      const double dj = dvec[off + lane];
+      v0 = g - lam * dj * dj * p[off + lane];
+    }
   }
   if (lane + 64 < nB) {
     double g = 0.0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) g += acc[k][lane + 64];
-    const double dj = dvec[off + lane + 64];
-    v1 = g - lam * dj * dj * p[off + lane + 64];
+    if (ADJ) {
+      v1 = gB[lane + 64] + g;
+    } else {
+      const double dj = dvec[off + lane + 64];
+      v1 = g - lam * dj * dj * p[off + lane + 64];
+    }
   }
   wave_fwd_T<T>(Rs, Rsd, L, nB, lane, v0, v1);
   wave_bwd<T>(Rs, Rsd, L, nB, lane, v0, v1);
   if (lane < nB) {
     delta_B[lane] = v0;
-    p[off + lane] += v0;
+    if (!ADJ) p[off + lane] += v0;
   }
   if (lane + 64 < nB) {
     delta_B[lane + 64] = v1;
-    p[off + lane + 64] += v1;
+    if (!ADJ) p[off + lane + 64] += v1;
   }
 }
 
@@ -437,8 +458,17 @@ template <typename T>
 hipError_t launch_refine_dense(int nparts, int nB, const double* part, const T* RB, const double* dvec,
                                double lam, double* p, int64_t off, double* delta_B, hipStream_t st) {
   if (nB + 1 > kMaxDense) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_refine_dense<T>), dim3(1), dim3(1024), 0, st, nparts, nB, part, RB, dvec, lam,
-                     p, off, delta_B);
+  hipLaunchKernelGGL((k_refine_dense<T, false>), dim3(1), dim3(1024), 0, st, nparts, nB, part, RB, dvec,
+                     lam, p, off, delta_B, (const double*)nullptr);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adjoint_dense(int nparts, int nB, const double* part, const T* RB, const double* gB,
+                                double* uB, hipStream_t st) {
+  if (nB + 1 > kMaxDense) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_refine_dense<T, true>), dim3(1), dim3(1024), 0, st, nparts, nB, part, RB,
+                     (const double*)nullptr, 0.0, (double*)nullptr, (int64_t)0, uB, gB);
   return hipGetLastError();
 }
 
@@ -453,7 +483,11 @@ hipError_t launch_refine_dense(int nparts, int nB, const double* part, const T* 
   template hipError_t launch_refine_dense<T>(int, int, const double*, const T*, const double*,       \
                                              double, double*, int64_t, double*, hipStream_t);       \
   template hipError_t launch_refine_blocks<T>(int64_t, int, int, const T*, const T*, const double*,  \
-                                              const double*, double*, int, hipStream_t);
+                                              const double*, double*, int, hipStream_t);               \
+  template hipError_t launch_adjoint_blocks<T>(int64_t, int, int, const T*, const T*, const double*, \
+                                               const double*, double*, int, hipStream_t);             \
+  template hipError_t launch_adjoint_dense<T>(int, int, const double*, const T*, const double*,      \
+                                              double*, hipStream_t);
 QRK_INST(float)
 QRK_INST(double)
 #undef QRK_INST

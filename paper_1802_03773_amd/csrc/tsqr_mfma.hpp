@@ -37,14 +37,6 @@ namespace qrk {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-template <int I, int N, typename F>
-__device__ __forceinline__ void static_for(F&& f) {
-  if constexpr (I < N) {
-    f(std::integral_constant<int, I>{});
-    static_for<I + 1, N>(f);
-  }
-}
-
 __device__ __forceinline__ float f_of(unsigned u) { return __builtin_bit_cast(float, u); }
 __device__ __forceinline__ unsigned u_of(float x) { return __builtin_bit_cast(unsigned, x); }
 
@@ -83,7 +75,7 @@ __device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-constexpr int kWaveLds = 256 + 256 + 256 * 8;  // T staging, spare, W staging (up to 8 blocks)
+constexpr int kWaveLds = 256 + 256 + 256 * 8;  // T staging, scales, W staging (up to 8 blocks)
 
 template <int NCB>
 struct Tri {
@@ -97,12 +89,16 @@ struct Tri {
 //   TRI = true : the tile is an upper-triangular NCB x NCB block triangle (NRB == NCB);
 //                in panel P only block rows 0..P are nonzero, which is used at compile
 //                time.
+// The Householder vectors are kept unscaled: the tile column x_j stays in place and the
+// reflector's tile part is w_j = s_j x_j with s_j = 1/(alpha_j - beta_j); the scales are
+// applied once per row of the small Z products instead of once per tile element.
 template <int NCB, int NRB, bool TRI>
 __device__ __forceinline__ void merge_tile(f4 (&R)[Tri<NCB>::count], f4 (&X)[NRB][NCB], int pstart,
                                            float* __restrict__ lds, int lane) {
   const int g = lane >> 4;
   const int c = lane & 15;
   float* Tl = lds;            // [16][16]
+  float* Sl = lds + 256;      // [16] column scales
   float* Wl = lds + 512;      // [NRB][16][16]
 
   static_for<0, NCB>([&](auto PP) {
@@ -113,6 +109,7 @@ __device__ __forceinline__ void merge_tile(f4 (&R)[Tri<NCB>::count], f4 (&X)[NRB
 
     // ---- panel factorisation of [R[P][P]; X[:, P]] (and T alongside) -------------------
     float trow[16];  // lane (g, c) builds row c of T
+    float sc = 0.f;  // scale of this lane's column once it has been reduced
     static_for<0, 16>([&](auto JJ) {
       constexpr int j = decltype(JJ)::value;
       float ps0 = 0.f, ps1 = 0.f;
@@ -135,50 +132,44 @@ __device__ __forceinline__ void merge_tile(f4 (&R)[Tri<NCB>::count], f4 (&X)[NRB
         tau = (beta - alpha) * __builtin_amdgcn_rcpf(beta);
         scale = __builtin_amdgcn_rcpf(alpha - beta);
       }
-      float wv[RBN][4];
-#pragma unroll
-      for (int rb = 0; rb < RBN; ++rb)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) wv[rb][v] = row_bcast<j>(X[rb][P][v]) * scale;
-      float pd0 = (g == (j >> 2)) ? R[rp][j & 3] : 0.f, pd1 = 0.f;
+      // x_j^T x_c for every lane's column c
+      float pr0 = 0.f, pr1 = 0.f;
 #pragma unroll
       for (int rb = 0; rb < RBN; ++rb)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           if (v & 1)
-            pd1 += wv[rb][v] * X[rb][P][v];
+            pr1 += row_bcast<j>(X[rb][P][v]) * X[rb][P][v];
           else
-            pd0 += wv[rb][v] * X[rb][P][v];
+            pr0 += row_bcast<j>(X[rb][P][v]) * X[rb][P][v];
         }
-      const float pd = sum_rows4(pd0 + pd1);  // lane c: R[j][c] + w_j^T x_c  (= w_c^T w_j for c < j)
+      const float rj = (g == (j >> 2)) ? R[rp][j & 3] : 0.f;
+      const float pd = sum_rows4((pr0 + pr1) * scale + rj);  // R[j][c] + w_j^T x_c
       const float s = tau * pd;
-      if (c > j) {
+      const float nf = (c > j) ? -scale * s : 0.f;             // x_c -= x_j * (scale s_c)
 #pragma unroll
-        for (int rb = 0; rb < RBN; ++rb)
+      for (int rb = 0; rb < RBN; ++rb)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) X[rb][P][v] -= wv[rb][v] * s;
-        if (g == (j >> 2)) R[rp][j & 3] -= s;
-      } else if (c == j) {
-#pragma unroll
-        for (int rb = 0; rb < RBN; ++rb)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) X[rb][P][v] = wv[rb][v];
-        if (g == (j >> 2)) R[rp][j & 3] = beta;
-      }
-      // T column j: T[c][j] = -tau_j sum_{k<j} T[c][k] (w_k^T w_j), T[j][j] = tau_j
+        for (int v = 0; v < 4; ++v) X[rb][P][v] += row_bcast<j>(X[rb][P][v]) * nf;
+      if (g == (j >> 2)) R[rp][j & 3] = (c > j) ? R[rp][j & 3] - s : (c == j ? beta : R[rp][j & 3]);
+      // T column j: T[c][j] = -tau_j sum_{k<j} T[c][k] (w_k^T w_j), T[j][j] = tau_j, where
+      // w_k^T w_j = s_k * (pd at lane k) for k < j.
+      const float gk = sc * pd;
       float t = 0.f;
       static_for<0, j>([&](auto KK) {
         constexpr int k = decltype(KK)::value;
-        t += trow[k] * row_bcast<k>(pd);
+        t += trow[k] * row_bcast<k>(gk);
       });
       trow[j] = (c < j) ? -tau * t : (c == j ? tau : 0.f);
+      if (c == j) sc = scale;
     });
 
-    // ---- re-lay out T (rows -> accumulator layout) and W (transposed) through LDS --------
+    // ---- re-lay out T (rows -> accumulator layout), scales and W^T through LDS ------------
     if (g == 0) {
 #pragma unroll
       for (int k = 0; k < 16; k += 4)
         *reinterpret_cast<f4*>(Tl + c * 16 + k) = f4{trow[k], trow[k + 1], trow[k + 2], trow[k + 3]};
+      Sl[c] = sc;
     }
 #pragma unroll
     for (int rb = 0; rb < RBN; ++rb)
@@ -188,7 +179,8 @@ __device__ __forceinline__ void merge_tile(f4 (&R)[Tri<NCB>::count], f4 (&X)[NRB
     f4 Td;
 #pragma unroll
     for (int v = 0; v < 4; ++v) Td[v] = Tl[(4 * g + v) * 16 + c];
-    float Wt[RBN][4];  // -W[rb*16 + c][4g + v]
+    const f4 srow = *reinterpret_cast<const f4*>(Sl + 4 * g);  // scales of rows 4g .. 4g+3
+    float Wt[RBN][4];  // -x[rb*16 + c][4g + v]  (raw tile columns, transposed)
 #pragma unroll
     for (int rb = 0; rb < RBN; ++rb) {
       const f4 w4 = *reinterpret_cast<const f4*>(Wl + rb * 256 + c * 16 + 4 * g);
@@ -198,28 +190,30 @@ __device__ __forceinline__ void merge_tile(f4 (&R)[Tri<NCB>::count], f4 (&X)[NRB
     wave_lds_sync();
 
     // ---- trailing update on the matrix cores ----------------------------------------------
+    //   Z = R_rows + diag(s) X_P^T X_q;  Z' = T^T Z;  R_rows -= Z';  X_q -= X_P diag(s) Z'
     static_for<P + 1, NCB>([&](auto QQ) {
       constexpr int q = decltype(QQ)::value;
       constexpr int rq = Tri<NCB>::idx(P, q);
-      f4 Z0 = R[rq], Z1 = {0.f, 0.f, 0.f, 0.f};
+      f4 Y0 = {0.f, 0.f, 0.f, 0.f}, Y1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int rb = 0; rb < RBN; ++rb)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           if ((rb * 4 + v) & 1)
-            Z1 = mfma4(X[rb][P][v], X[rb][q][v], Z1);
+            Y1 = mfma4(X[rb][P][v], X[rb][q][v], Y1);
           else
-            Z0 = mfma4(X[rb][P][v], X[rb][q][v], Z0);
+            Y0 = mfma4(X[rb][P][v], X[rb][q][v], Y0);
         }
-      const f4 Z = Z0 + Z1;
+      const f4 Z = R[rq] + srow * (Y0 + Y1);
       f4 Zp = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int v = 0; v < 4; ++v) Zp = mfma4(Td[v], Z[v], Zp);
       R[rq] -= Zp;
+      const f4 Zs = srow * Zp;
 #pragma unroll
       for (int v = 0; v < 4; ++v)
 #pragma unroll
-        for (int rb = 0; rb < RBN; ++rb) X[rb][q] = mfma4(Wt[rb][v], Zp[v], X[rb][q]);
+        for (int rb = 0; rb < RBN; ++rb) X[rb][q] = mfma4(Wt[rb][v], Zs[v], X[rb][q]);
     });
   });
 }

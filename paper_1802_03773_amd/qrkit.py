@@ -36,6 +36,7 @@ _SIGS = {
                                          ctypes.POINTER(_c_vp)]),
     "qrk_factor_blockangular": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_dbl, _c_vp]),
     "qrk_create_banded": (_c_i32, [_c_i64, _c_i64, _c_i32, _c_i32, ctypes.POINTER(_c_vp)]),
+    "qrk_create_banded_batched": (_c_i32, [_c_i32, _c_i64, _c_i64, _c_i32, _c_i32, ctypes.POINTER(_c_vp)]),
     "qrk_factor_banded": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_dbl, _c_vp]),
     "qrk_solve": (_c_i32, [_c_vp, _c_vp, _c_i32, _c_vp]),
     "qrk_solve_adjoint": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp]),
@@ -259,28 +260,34 @@ class BlockAngularSolver(Factor):
 
 
 class BandedSolver(Factor):
-    """Solver for banded J (M x N, w values per row at nondecreasing starts)."""
+    """Solver for banded J (M x N, w values per row at nondecreasing starts); P problems of the
+    same shape may be stacked in one handle (arrays [P, ...])."""
 
-    def __init__(self, M: int, N: int, w: int, dtype="float32"):
+    def __init__(self, M: int, N: int, w: int, dtype="float32", P: int = 1):
         qd = QRK_F32 if str(dtype).endswith("float32") else QRK_F64
         h = _c_vp()
-        _check(lib().qrk_create_banded(int(M), int(N), int(w), qd, ctypes.byref(h)), "qrk_create_banded")
-        super().__init__(h, "banded", qd, int(N))
-        self.M, self.w = int(M), int(w)
+        if P == 1:
+            _check(lib().qrk_create_banded(int(M), int(N), int(w), qd, ctypes.byref(h)), "qrk_create_banded")
+        else:
+            _check(lib().qrk_create_banded_batched(int(P), int(M), int(N), int(w), qd, ctypes.byref(h)),
+                   "qrk_create_banded_batched")
+        super().__init__(h, "banded", qd, int(P) * int(N))
+        self.M, self.w, self.P, self.Nper = int(M), int(w), int(P), int(N)
 
     def factor(self, row_start, vals, b, d, lam: float, stream=None):
         torch = _torch()
         td = _torch_dtype(self.qdtype)
-        _check(lib().qrk_factor_banded(self._h, _dev_ptr(row_start, torch.int32, "row_start", self.M),
-                                       _dev_ptr(vals, td, "vals", self.M * self.w),
-                                       _dev_ptr(b, td, "b", self.M), _dev_ptr(d, torch.float64, "d", self.N),
+        PM = self.P * self.M
+        _check(lib().qrk_factor_banded(self._h, _dev_ptr(row_start, torch.int32, "row_start", PM),
+                                       _dev_ptr(vals, td, "vals", PM * self.w),
+                                       _dev_ptr(b, td, "b", PM), _dev_ptr(d, torch.float64, "d", self.N),
                                        float(lam), _stream_ptr(stream)), "qrk_factor_banded")
         self._keep = (row_start, vals, b, d)
         self.lam = float(lam)
         return self
 
     def get_factor(self, stream=None):
-        """(R band [N, w] with row j = R[j, j..j+w-1], c [N])."""
+        """(R band [P*N, w] with row j = R[j, j..j+w-1], c [P*N])."""
         torch = _torch()
         td = _torch_dtype(self.qdtype)
         R = torch.empty((self.N, self.w), dtype=td, device="cuda")
@@ -292,9 +299,10 @@ class BandedSolver(Factor):
     def solve_adjoint(self, p, g, stream=None):
         torch = _torch()
         td = _torch_dtype(self.qdtype)
-        out = dict(dvals=torch.empty((self.M, self.w), dtype=td, device="cuda"),
-                   db=torch.empty(self.M, dtype=td, device="cuda"),
-                   dlam=torch.empty(1, dtype=torch.float64, device="cuda"),
+        PM = self.P * self.M
+        out = dict(dvals=torch.empty((PM, self.w), dtype=td, device="cuda"),
+                   db=torch.empty(PM, dtype=td, device="cuda"),
+                   dlam=torch.empty(self.P, dtype=torch.float64, device="cuda"),
                    dd=torch.empty(self.N, dtype=torch.float64, device="cuda"))
         _check(lib().qrk_solve_adjoint(self._h, _dev_ptr(p, torch.float64, "p", self.N),
                                        _dev_ptr(g, torch.float64, "g", self.N),

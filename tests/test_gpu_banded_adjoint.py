@@ -1,0 +1,173 @@
+"""GPU parity of the banded Givens path and of the adjoint (block-angular and banded)
+against the CPU oracle."""
+import numpy as np
+import pytest
+
+from oracle import adjoint, banded, dense, refine, structured
+from tests.gpu_util import log, rel_err, sign_fix_rows, to_device
+from workloads import generators as gen
+
+pytestmark = pytest.mark.gpu
+
+
+def _banded_dev(insts):
+    import torch
+    rs = torch.from_numpy(np.stack([i.row_start for i in insts])).cuda().contiguous()
+    vals = torch.from_numpy(np.stack([i.vals for i in insts])).cuda().contiguous()
+    b = torch.from_numpy(np.stack([i.b for i in insts])).cuda().contiguous()
+    d = torch.from_numpy(np.stack([i.d for i in insts])).cuda().contiguous()
+    return rs, vals, b, d
+
+
+def _banded_solve(insts, sweeps=0):
+    import torch
+    from paper_1802_03773_amd import BandedSolver
+    i0 = insts[0]
+    s = BandedSolver(i0.M, i0.N, i0.w, dtype=str(i0.dtype), P=len(insts))
+    rs, vals, b, d = _banded_dev(insts)
+    s.factor(rs, vals, b, d, i0.lam)
+    p = s.solve(sweeps=sweeps)
+    torch.cuda.synchronize()
+    return p.cpu().numpy().reshape(len(insts), i0.N), s.status(), s, (rs, vals, b, d)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("w", [1, 2, 5, 12, 15, 16, 24])
+def test_banded_small(w, dtype):
+    log(f"banded N=60 w={w} {np.dtype(dtype).name}")
+    inst = gen.make_banded(700 + w, N=60, w=w, lam=1e-2, dtype=dtype)
+    p_ref, R_ref, c_ref = banded.reference_solution(inst)
+    p, st, solver, _ = _banded_solve([inst])
+    assert st[0] == 0, st
+    tol = 1e-12 if dtype == np.float64 else 1e-5
+    assert rel_err(p[0], p_ref) <= tol
+    Rb, c = [t.cpu().numpy().astype(np.float64) for t in solver.get_factor()]
+    R = np.zeros((inst.N, inst.N))
+    for j in range(inst.N):
+        k = min(inst.w, inst.N - j)
+        R[j, j:j + k] = Rb[j, :k]
+    Rg, cg = sign_fix_rows(R, c)
+    Ro, co = sign_fix_rows(R_ref, c_ref)
+    ftol = 1e-12 if dtype == np.float64 else 5e-5
+    assert np.abs(Rg - Ro).max() <= ftol * np.abs(Ro).max()
+    assert np.abs(cg - co).max() <= ftol * max(np.abs(co).max(), np.abs(Ro).max())
+    p2, st, _, _ = _banded_solve([inst], sweeps=2)
+    assert rel_err(p2[0], p_ref) <= 1e-10
+
+
+def test_banded_batch_and_refine():
+    log("banded batch P=16 N=256 w=12")
+    insts = [gen.make_banded(900 + k, N=256, w=12, lam=1e-2, dtype=np.float32) for k in range(16)]
+    p0, st, _, _ = _banded_solve(insts)
+    assert st[0] == 0
+    p2, st, _, _ = _banded_solve(insts, sweeps=2)
+    for k, inst in enumerate(insts):
+        p_ref, _, _ = banded.reference_solution(inst)
+        assert rel_err(p0[k], p_ref) <= 1e-5
+        assert rel_err(p2[k], p_ref) <= 1e-10
+
+
+def test_banded_full_size_sampled():
+    """2,048 problems of n = 2,048 (4,096 rows, 12 values per row): sampled problems vs oracle."""
+    log("banded full size: generating")
+    insts = gen.banded_batch(300, P=2048)
+    log("banded full size: gpu")
+    p0, st, solver, dev = _banded_solve(insts)
+    assert st[0] == 0
+    p1 = solver.solve(sweeps=1).cpu().numpy().reshape(2048, -1)
+    for k in (0, 777, 2047):
+        log(f"banded full size: oracle problem {k}")
+        p_ref, _, _ = banded.reference_solution(insts[k])
+        assert rel_err(p0[k], p_ref) <= 1e-5
+        assert rel_err(p1[k], p_ref) <= 1e-10
+
+
+def test_banded_bad_row_start_is_reported():
+    log("banded bad row_start")
+    inst = gen.make_banded(5, N=40, w=4, dtype=np.float32)
+    inst.row_start[10] = inst.row_start[9] - 1  # decreasing
+    _, st, _, _ = _banded_solve([inst])
+    assert st[0] == 1  # QRK_EINVAL
+
+
+def _adjoint_case(inst, p_star):
+    import torch
+    from paper_1802_03773_amd import BlockAngularSolver
+    A, B, b, d = to_device(inst)
+    s = BlockAngularSolver(inst.row_off, inst.n, inst.nB, dtype=str(inst.dtype))
+    s.factor(A, B, b, d, inst.lam)
+    p = s.solve(sweeps=2)
+    g = p - torch.from_numpy(p_star).cuda()
+    out = s.solve_adjoint(p, g.contiguous())
+    torch.cuda.synchronize()
+    return p.cpu().numpy(), g.cpu().numpy(), {k: v.cpu().numpy().astype(np.float64) for k, v in out.items()}
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_adjoint_blockangular_small(dtype):
+    """20 blocks of 12x3 with their 240 rows of a 60-column dense part, L = 0.5||p - p*||^2."""
+    log(f"adjoint small {np.dtype(dtype).name}")
+    big, p_star_full = gen.adjoint_blockangular(500, dtype=dtype, K=20)
+    inst = big
+    p_star = p_star_full[:inst.N]
+    p, g, out = _adjoint_case(inst, p_star)
+    p_ref, f = refine.reference_solution(inst)
+    ref = adjoint.adjoint_blockangular(inst, f, p_ref, p_ref - p_star)
+    tol = 1e-10 if dtype == np.float64 else 1e-4
+    assert rel_err(out["dA"], ref["dA"]) <= tol
+    assert rel_err(out["dB"], ref["dB"]) <= tol
+    assert rel_err(out["db"], ref["db"]) <= tol
+    assert rel_err(out["dd"], ref["dd"]) <= tol
+    assert abs(out["dlam"][0] - ref["dlam"]) <= tol * abs(ref["dlam"])
+
+
+def test_adjoint_blockangular_full_size():
+    """10,000 blocks of 12x3, dense part 120,000 x 60, float32, lambda = 1e-2."""
+    log("adjoint full size: generating")
+    inst, p_star = gen.adjoint_blockangular(500)
+    p, g, out = _adjoint_case(inst, p_star)
+    log("adjoint full size: oracle")
+    p_ref, f = refine.reference_solution(inst, sweeps=2)
+    ref = adjoint.adjoint_blockangular(inst, f, p_ref, p_ref - p_star)
+    for k in ("dA", "dB", "db", "dd"):
+        assert rel_err(out[k], ref[k]) <= 1e-4, k
+    assert abs(out["dlam"][0] - ref["dlam"]) <= 1e-4 * abs(ref["dlam"])
+
+
+def test_adjoint_banded():
+    log("adjoint banded")
+    inst = gen.make_banded(11, N=80, w=6, lam=5e-2, dtype=np.float64)
+    rng = np.random.default_rng(3)
+    import torch
+    from paper_1802_03773_amd import BandedSolver
+    s = BandedSolver(inst.M, inst.N, inst.w, dtype="float64")
+    rs, vals, b, d = _banded_dev([inst])
+    s.factor(rs, vals, b, d, inst.lam)
+    p = s.solve(sweeps=1)
+    gvec = torch.from_numpy(rng.standard_normal(inst.N)).cuda()
+    out = s.solve_adjoint(p, gvec)
+    torch.cuda.synchronize()
+    J = banded.assemble(inst)
+    o1 = banded.solve_dense_o1(inst)
+    ref = adjoint.adjoint_dense(J, inst.b, inst.d, inst.lam, o1["p"], gvec.cpu().numpy(), o1["R"])
+    cols = inst.row_start[:, None] + np.arange(inst.w)[None, :]
+    dvals_ref = ref["dJ"][np.arange(inst.M)[:, None], cols]
+    assert rel_err(out["dvals"].cpu().numpy(), dvals_ref) <= 1e-10
+    assert rel_err(out["db"].cpu().numpy(), ref["db"]) <= 1e-10
+    assert rel_err(out["dd"].cpu().numpy(), ref["dd"]) <= 1e-10
+    assert abs(float(out["dlam"].cpu()[0]) - ref["dlam"]) <= 1e-10 * abs(ref["dlam"])
+
+
+def test_autograd_function_gradcheck():
+    """QRKSolve backward vs float64 central differences of its own forward (torch gradcheck)."""
+    import torch
+    from paper_1802_03773_amd.autograd import QRKSolve
+    log("autograd gradcheck")
+    inst = gen.make_blockangular(21, K=3, m=5, n=2, nB=3, lam=0.1, dtype=np.float64)
+    A, B, b, d = [t.clone().requires_grad_(True) for t in to_device(inst)]
+    lam = torch.tensor(inst.lam, dtype=torch.float64, device="cuda", requires_grad=True)
+
+    def f(A_, B_, b_, d_, lam_):
+        return QRKSolve.apply(A_, B_, b_, d_, lam_, inst.row_off, inst.n, 2)
+
+    assert torch.autograd.gradcheck(f, (A, B, b, d, lam), eps=1e-6, atol=1e-6, rtol=1e-4)
