@@ -8,7 +8,7 @@
 // cross-lane reduction: each Householder vector is broadcast once through LDS and each
 // lane updates its own columns.  B_i rows are read with consecutive lanes on consecutive
 // columns (coalesced) and the reduced rows are written the same way.
-#include "qrk_device.hpp"
+#include "blockqr.hpp"
 #include "qrk_launch.hpp"
 
 namespace qrk {
@@ -23,134 +23,12 @@ k_blockqr(int64_t K, int n, int nB, const int64_t* __restrict__ row_off,
   __shared__ T tbuf[4];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
-  const int L = nB + 1;
-  T* v = vbuf[wv];
   const int64_t nwaves = (int64_t)gridDim.x * 4;
-
   for (int64_t blk = (int64_t)blockIdx.x * 4 + wv; blk < K; blk += nwaves) {
     const int64_t r0 = row_off[blk];
-    const int m = (int)(row_off[blk + 1] - r0);
-    const int rows = m + n;
-
-    T a[ROWS];
-    T c[SLOTS][ROWS];
-    const T dl = (lane < n) ? (T)(sqrt_lam * d[blk * n + lane]) : T(0);
-#pragma unroll
-    for (int r = 0; r < ROWS; ++r) {
-      T x = T(0);
-      if (lane < n) {
-        if (r < m)
-          x = A[(r0 + r) * n + lane];
-        else if (r == m + lane)
-          x = dl;
-      }
-      a[r] = x;
-    }
-#pragma unroll
-    for (int s = 0; s < SLOTS; ++s) {
-      const int col = s * 64 + lane;
-#pragma unroll
-      for (int r = 0; r < ROWS; ++r) {
-        T x = T(0);
-        if (r < m) {
-          if (col < nB)
-            x = B[(r0 + r) * ldb + col];
-          else if (col == nB)
-            x = bvec[r0 + r];
-        }
-        c[s][r] = x;
-      }
-    }
-
-    for (int k = 0; k < n; ++k) {
-      // Each lane forms the reflector of its own column; lane k's is the one used.
-      T alpha = T(0), sig0 = T(0), sig1 = T(0);
-#pragma unroll
-      for (int r = 0; r < ROWS; ++r) {
-        if (r == k) alpha = a[r];
-        if (r > k && r < rows) {
-          if (r & 1)
-            sig1 += a[r] * a[r];
-          else
-            sig0 += a[r] * a[r];
-        }
-      }
-      const T sigma = sig0 + sig1;
-      T beta = alpha, tau = T(0), scale = T(0);
-      if (sigma != T(0)) {
-        const T nrm = sqrt(alpha * alpha + sigma);
-        beta = alpha >= T(0) ? -nrm : nrm;
-        tau = (beta - alpha) / beta;
-        scale = T(1) / (alpha - beta);
-      }
-      if (lane == k) {
-#pragma unroll
-        for (int r = 0; r < ROWS; ++r)
-          v[r] = (r == k) ? T(1) : ((r > k && r < rows) ? a[r] * scale : T(0));
-        tbuf[wv] = tau;
-      }
-      wave_lds_sync();
-      T vr[ROWS];
-#pragma unroll
-      for (int r = 0; r < ROWS; ++r) vr[r] = v[r];
-      const T tk = tbuf[wv];
-      wave_lds_sync();
-      if (tk != T(0)) {
-        T w0 = T(0), w1 = T(0);
-#pragma unroll
-        for (int r = 0; r < ROWS; ++r) {
-          if (r & 1)
-            w1 += vr[r] * a[r];
-          else
-            w0 += vr[r] * a[r];
-        }
-        const T w = (w0 + w1) * tk;
-#pragma unroll
-        for (int r = 0; r < ROWS; ++r) a[r] -= vr[r] * w;
-#pragma unroll
-        for (int s = 0; s < SLOTS; ++s) {
-          T u0 = T(0), u1 = T(0);
-#pragma unroll
-          for (int r = 0; r < ROWS; ++r) {
-            if (r & 1)
-              u1 += vr[r] * c[s][r];
-            else
-              u0 += vr[r] * c[s][r];
-          }
-          const T u = (u0 + u1) * tk;
-#pragma unroll
-          for (int r = 0; r < ROWS; ++r) c[s][r] -= vr[r] * u;
-        }
-      }
-      if (lane == k) {
-#pragma unroll
-        for (int r = 0; r < ROWS; ++r) {
-          if (r == k) a[r] = beta;
-          if (r > k) a[r] = T(0);
-        }
-      }
-    }
-
-    // R_i: lane j < n holds column j.
-    if (lane < n) {
-#pragma unroll
-      for (int r = 0; r < 8; ++r)
-        if (r < n) Rblk[(blk * n + r) * n + lane] = (r <= lane) ? a[r] : T(0);
-    }
-    // Coupling rows (top n) and reduced rows (the other m).
-#pragma unroll
-    for (int s = 0; s < SLOTS; ++s) {
-      const int col = s * 64 + lane;
-      if (col < L) {
-#pragma unroll
-        for (int r = 0; r < ROWS; ++r) {
-          if (r < n)
-            Sc[(blk * n + r) * L + col] = c[s][r];
-          else if (r < rows)
-            Red[(r0 + r - n) * ldr + col] = c[s][r];
-        }
-      }
-    }
+    block_qr_wave<T, ROWS, SLOTS>(blk, n, nB, row_off, A, B, ldb, bvec, d, sqrt_lam, Rblk, Sc, vbuf[wv],
+                                  &tbuf[wv], lane,
+                                  [&](int r, int col, T val) { Red[(r0 + r) * ldr + col] = val; });
   }
 }
 

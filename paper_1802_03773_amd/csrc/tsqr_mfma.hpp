@@ -126,7 +126,12 @@ __device__ __forceinline__ void merge_tile(f4 (&R)[Tri<NCB>::count], f4 (&X)[NRB
       const float sigma = read_lane(ps, j);
       const float alpha = read_lane(R[rp][j & 3], (j >> 2) * 16 + j);
       float beta = alpha, tau = 0.f, scale = 0.f;
-      if (sigma != 0.f) {
+      // sigma below the smallest normal float counts as zero (identity reflector).  A leaf
+      // that starts from a zero triangle reflects the roundoff left in the columns beyond the
+      // rank of its first tiles; that residue shrinks by about eps per tile height and can
+      // reach the subnormal range, where the hardware square root returns 0 and the scale
+      // 1 / (alpha - beta) would be infinite.
+      if (sigma >= 0x1p-126f) {
         const float nrm = __builtin_amdgcn_sqrtf(alpha * alpha + sigma);
         beta = alpha >= 0.f ? -nrm : nrm;
         tau = (beta - alpha) * __builtin_amdgcn_rcpf(beta);

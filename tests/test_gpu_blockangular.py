@@ -114,6 +114,27 @@ def test_wide_dense_part_multi_leaf_trees(nB):
         assert rel_err(p, p_ref) <= 1e-5
 
 
+@pytest.mark.parametrize("lam", [1e-2, 0.0])
+@pytest.mark.parametrize("nB", [47, 90, 127])
+def test_few_rows_per_leaf(nB, lam):
+    """Leaves of 33 and 12 rows: each leaf triangle starts from zero and has rank far below
+    the column count, so the columns beyond that rank are reflected on roundoff that shrinks
+    by about eps per leaf height and underflows to subnormal floats (lam = 0 starts leaf 0
+    from zero as well)."""
+    K = 40
+    m = np.where(np.arange(K) % 2 == 0, 10, 56)
+    inst = gen.make_blockangular(90 + nB, K=K, m=m, n=8, nB=nB, lam=lam, dtype=np.float32)
+    p_ref, _ = refine.reference_solution(inst)
+    for leaves in [1, 3, 40, 110, 0]:
+        log(f"few rows per leaf nB={nB} lam={lam} leaves={leaves}")
+        p, st = gpu_solve_blockangular(inst, leaves=leaves)
+        assert st[0] == 0, st
+        assert np.isfinite(p).all()
+        assert rel_err(p, p_ref) <= 1e-4
+        p1, st = gpu_solve_blockangular(inst, leaves=leaves, sweeps=2)
+        assert rel_err(p1, p_ref) <= 1e-10
+
+
 def test_lambda_zero_gauss_newton():
     inst = gen.make_blockangular(6, K=300, m=(np.arange(300) % 7) + 4, n=3, nB=20, lam=0.0,
                                  dtype=np.float64)
