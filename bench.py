@@ -27,6 +27,35 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP32_VECTOR_TFLOPS = 157.3
 PEAK_FP64_VECTOR_TFLOPS = 78.6
 
+# HBM bytes per launch of a phase's kernel, from two rocprofv3 PMC runs of this script
+# (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, factors read off a 256 MiB device copy; the runs
+# and figures are in profiles/blockangular_scale_pmc_traffic.md).  A figure holds only for the
+# workload it was taken on and while the kernel's sources hash to the recorded digest.
+MEASURED_TRAFFIC = {
+    "dense_leaves": {
+        "bytes": (131152.1 * 2.0 + 43062.3) * 1024.0,
+        "lam": 1e-2,
+        "mode": "plain",
+        "sources": ["paper_1802_03773_amd/csrc/tsqr_mfma.hpp", "paper_1802_03773_amd/csrc/tsqr_mfma.hip",
+                    "paper_1802_03773_amd/csrc/tsqr_mfma_ncb6.hip", "paper_1802_03773_amd/csrc/qrk_device.hpp"],
+        "sha256": "1c4e1db8aa262da03997741089b9f2711e7f04b12c467dae2d5876468e75b812",
+    },
+}
+
+
+def measured_traffic(phase, lam, mode):
+    """Bytes per launch for `phase` if a PMC figure matches this workload and these sources."""
+    import hashlib
+    rec = MEASURED_TRAFFIC.get(phase)
+    if rec is None or rec["lam"] != lam or rec["mode"] != mode:
+        return None
+    root = os.path.dirname(os.path.abspath(__file__))
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(root, src), "rb") as f:
+            h.update(f.read())
+    return rec["bytes"] if h.hexdigest() == rec["sha256"] else None
+
 
 def _parse():
     ap = argparse.ArgumentParser()
@@ -184,7 +213,7 @@ def main():
     dom = phase_out[dominant]
     roofline = {"kernel": dominant, "bound": dom.get("bound"), "achieved": dom.get("achieved"),
                 "peak": dom.get("peak"), "unit": dom.get("unit"), "frac": dom.get("frac"),
-                "traffic": None}
+                "traffic": measured_traffic(dominant, args.lam, args.mode)}
 
     if args.copy_calibration:
         x = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda")  # 256 MiB
