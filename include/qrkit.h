@@ -104,6 +104,37 @@ qrk_status qrk_factor_blockangular(qrk_handle h, const void* A, const void* B, c
                                    const double* d, double lambda, void* stream);
 
 /* ------------------------------------------------------------------------------
+ * qrk_create_blockangular_batched / qrk_factor_blockangular_batched
+ *   P independent block-angular problems with the same block width n, factored and solved
+ *   together: every phase of qrk_factor_blockangular / qrk_solve runs over all problems in
+ *   the same launches (the per-problem dense-part merge trees proceed independently inside
+ *   one launch per 16-column-block count).  Problem p has K_host[p] >= 1 blocks and
+ *   0 <= nB_host[p] <= 127 dense columns; N_p = K_host[p] n + nB_host[p].
+ *   row_off_host [host, int64, sum_p K_p + 1]: global row offsets of all blocks, problem
+ *   after problem (row_off_host[0] = 0, nondecreasing, m_i <= QRK_MAX_BLOCK_ROWS); problem p
+ *   owns the rows of its blocks.  Stacked device arrays, problem after problem:
+ *     A [M_tot x n] T and b [M_tot] T (global rows);
+ *     B: problem p's M_p x nB_p block, row-major with row stride nB_p, starting at element
+ *        sum_{q<p} M_q nB_q;
+ *     d [sum_p N_p] double;  lambda_dev [P] double, >= 0, read by the kernels when they
+ *        run (a captured graph picks up new values at each replay; not validated);
+ *     p (qrk_solve) [sum_p N_p] double.
+ *   qrk_status_get reports the worst condition over the batch (detail = OR of the bits);
+ *   qrk_status_get_problems gives the bits of every problem.  qrk_solve_adjoint,
+ *   qrk_colnorms_blockangular and qrk_get_factor are single-problem only (QRK_EINVAL).
+ *   create returns QRK_EINVAL for P < 1, n outside 1..8, a bad K_host / nB_host /
+ *   row_off_host, or mode == QRK_BF16X3 with dtype == QRK_F64.
+ * ------------------------------------------------------------------------------ */
+qrk_status qrk_create_blockangular_batched(int32_t P, int32_t n, const int32_t* K_host, const int32_t* nB_host,
+                                           const int64_t* row_off_host, qrk_dtype dtype, qrk_mode mode,
+                                           qrk_handle* out);
+qrk_status qrk_factor_blockangular_batched(qrk_handle h, const void* A, const void* B, const void* b,
+                                           const double* d, const double* lambda_dev, void* stream);
+/* Status bits (1 singular, 2 non-finite, 4 bad input) of each of the P problems of a
+ * handle into bits_host [host, int32, P]; synchronises `stream`. */
+qrk_status qrk_status_get_problems(qrk_handle h, int32_t* bits_host, void* stream);
+
+/* ------------------------------------------------------------------------------
  * qrk_create_banded / qrk_factor_banded
  *   Banded J (M x N, w values per row).  qrk_factor_banded starts from the upper
  *   triangular R = diag(sqrt(lambda) d) and rotates each row of J into R in row order
@@ -177,10 +208,23 @@ qrk_status qrk_get_factor(qrk_handle h, void* Rblk, void* S, void* RB, void* str
  * ------------------------------------------------------------------------------ */
 qrk_status qrk_status_get(qrk_handle h, int32_t* detail_host, void* stream);
 
-/* Set the launch shape of the dense-part leaves (0 = library default): number of
- * leaf workgroups and tree fan-in.  Used by the autotuner; returns QRK_EINVAL for
- * out-of-range values. */
+/* Set the launch shape of the dense-part leaves of a single-problem handle (0 = library
+ * default): number of leaves (at most 1024) and, for float64 handles, the tree fan-in.
+ * Not capturable (it may reallocate the merge-tree workspace).  QRK_EINVAL for
+ * out-of-range values or a batched handle. */
 qrk_status qrk_set_tsqr_shape(qrk_handle h, int32_t leaves, int32_t fanin);
+
+/* ------------------------------------------------------------------------------
+ * qrk_autotune_blockangular (float32 handles; not capturable; synchronises `stream`)
+ *   Times the factorisation of the inputs of the last qrk_factor_* call on this handle
+ *   for a few dense-part leaf shapes (rows per leaf scaled by 1/2, 1, 2 and 4 from the
+ *   library default, capped at 1024 leaves per problem) and keeps the fastest; the
+ *   handle is left factored with the chosen shape.  Choices are remembered in the
+ *   process by batch shape (sum of rows, P, n, widest dense part), so a later handle of
+ *   the same shape starts from the remembered choice.  *scale_host [host, may be NULL]
+ *   receives the chosen scale.  QRK_EINVAL before any factor call.
+ * ------------------------------------------------------------------------------ */
+qrk_status qrk_autotune_blockangular(qrk_handle h, double* scale_host, void* stream);
 
 /* ------------------------------------------------------------------------------
  * Phase timing (HIP events recorded on the call's stream around each phase).

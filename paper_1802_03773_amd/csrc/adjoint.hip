@@ -8,13 +8,14 @@
 // refinement; this file holds the pieces that differ: the forward pass over the blocks
 // with a given g, the row pass that writes the gradients on the structural nonzeros, and
 // the vector terms.
+#include "qrk_batch.hpp"
 #include "qrk_device.hpp"
 #include "qrk_launch.hpp"
 
 namespace qrk {
 
 // y_i = R_i^{-T} g_i (one wave per block, redundantly in every lane) and per-workgroup
-// partials of -sum_i S_i^T y_i (lanes over the dense columns).
+// partials of -sum_i S_i^T y_i (lanes over the dense columns; row stride kMaxDense).
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_adj_fwd_blocks(int64_t K, int n, int nB, const T* __restrict__ Rblk, const T* __restrict__ Sc,
@@ -53,7 +54,7 @@ k_adj_fwd_blocks(int64_t K, int n, int nB, const T* __restrict__ Rblk, const T* 
   red[wv][lane + 64] = t1;
   __syncthreads();
   for (int j = threadIdx.x; j < nB; j += blockDim.x)
-    part[(int64_t)blockIdx.x * nB + j] = ((red[0][j] + red[1][j]) + red[2][j]) + red[3][j];
+    part[(int64_t)blockIdx.x * kMaxDense + j] = ((red[0][j] + red[1][j]) + red[2][j]) + red[3][j];
 }
 
 template <typename T>

@@ -15,26 +15,26 @@
 
 namespace qrk {
 
+// A, B, bvec point at the block's first row (of A, of B_p with row stride ldb, of b), d at
+// its first damping entry, Rb and Scb at its R_i (n x n) and S_i | c_i (n x (nB+1)).
 template <typename T, int ROWS, int SLOTS, typename Emit>
-__device__ __forceinline__ void block_qr_wave(int64_t blk, int n, int nB, const int64_t* __restrict__ row_off,
-                                              const T* __restrict__ A, const T* __restrict__ B, int64_t ldb,
-                                              const T* __restrict__ bvec, const double* __restrict__ d,
-                                              double sqrt_lam, T* __restrict__ Rblk, T* __restrict__ Sc,
-                                              T* __restrict__ v, T* __restrict__ tb, int lane, Emit&& emit) {
+__device__ __forceinline__ void block_qr_wave(int n, int nB, int m, const T* __restrict__ A,
+                                              const T* __restrict__ B, int64_t ldb, const T* __restrict__ bvec,
+                                              const double* __restrict__ d, double sqrt_lam, T* __restrict__ Rb,
+                                              T* __restrict__ Scb, T* __restrict__ v, T* __restrict__ tb,
+                                              int lane, Emit&& emit) {
   const int L = nB + 1;
-  const int64_t r0 = row_off[blk];
-  const int m = (int)(row_off[blk + 1] - r0);
   const int rows = m + n;
 
   T a[ROWS];
   T c[SLOTS][ROWS];
-  const T dl = (lane < n) ? (T)(sqrt_lam * d[blk * n + (lane < n ? lane : 0)]) : T(0);
+  const T dl = (lane < n) ? (T)(sqrt_lam * d[lane < n ? lane : 0]) : T(0);
 #pragma unroll
   for (int r = 0; r < ROWS; ++r) {
     T x = T(0);
     if (lane < n) {
       if (r < m)
-        x = A[(r0 + r) * n + lane];
+        x = A[r * n + lane];
       else if (r == m + lane)
         x = dl;
     }
@@ -48,9 +48,9 @@ __device__ __forceinline__ void block_qr_wave(int64_t blk, int n, int nB, const 
       T x = T(0);
       if (r < m) {
         if (col < nB)
-          x = B[(r0 + r) * ldb + col];
+          x = B[r * ldb + col];
         else if (col == nB)
-          x = bvec[r0 + r];
+          x = bvec[r];
       }
       c[s][r] = x;
     }
@@ -129,7 +129,7 @@ __device__ __forceinline__ void block_qr_wave(int64_t blk, int n, int nB, const 
   if (lane < n) {
 #pragma unroll
     for (int r = 0; r < 8; ++r)
-      if (r < n) Rblk[(blk * n + r) * n + lane] = (r <= lane) ? a[r] : T(0);
+      if (r < n) Rb[r * n + lane] = (r <= lane) ? a[r] : T(0);
   }
   // Coupling rows (top n) and reduced rows (the other m).
 #pragma unroll
@@ -139,7 +139,7 @@ __device__ __forceinline__ void block_qr_wave(int64_t blk, int n, int nB, const 
 #pragma unroll
       for (int r = 0; r < ROWS; ++r) {
         if (r < n)
-          Sc[(blk * n + r) * L + col] = c[s][r];
+          Scb[r * L + col] = c[s][r];
         else if (r < rows)
           emit(r - n, col, c[s][r]);
       }

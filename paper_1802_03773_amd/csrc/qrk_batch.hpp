@@ -1,0 +1,52 @@
+// Layout of a batch of independent block-angular problems inside one handle.
+//
+// All problems share the block width n.  Problem p owns K_p consecutive blocks of the
+// global block list, M_p consecutive rows of A and b, and N_p = K_p n + nB_p consecutive
+// unknowns of d and p; its coupled columns B_p are a row-major M_p x ldb_p array starting
+// at element boff of B.  The handle's workspace (S|c, reduced rows, R_B|c_B, merge-tree
+// slots and counters, refinement partials) is carved per problem the same way.  A single
+// problem is the batch of one with every offset zero.
+#pragma once
+
+#include <stdint.h>
+
+namespace qrk {
+
+constexpr int kMaxDense = 128;  // nB + 1 <= 128
+
+struct ProbDesc {
+  int64_t koff, K;        // first global block, blocks
+  int64_t moff, M;        // first global row, rows
+  int64_t noff;           // first unknown (index into d and p)
+  int64_t boff, ldb;      // B_p at element boff of B, row stride ldb
+  int64_t soff;           // S_p|c_p (K x n x L, row stride L) at element soff
+  int64_t redoff, ldr;    // reduced rows (M x ldr) at element redoff
+  int64_t rboff;          // R_B|c_B (L x L, row-major) at element rboff
+  int64_t slot0, ctr0;    // merge tree: first slot float, first arrival counter
+  int64_t rows_per_leaf;  // dense-part QR: rows per leaf
+  int64_t pack0, npacks;  // packs of whole blocks (global index of the first)
+  int32_t nB, L;          // coupled columns, L = nB + 1
+  int32_t leaves;         // dense-part QR leaves
+  int32_t wg0, nwg;       // refinement workgroups [wg0, wg0 + nwg)
+  int32_t pad;
+};
+
+// Device view of a handle's batch, passed to the launchers.
+struct BatchView {
+  int P = 1;                           // problems
+  int n = 1;                           // block width
+  int64_t Ktot = 0;                    // blocks over all problems
+  int max_L = 1;                       // max_p nB_p + 1
+  int max_rows = 0;                    // max_i m_i + n
+  const ProbDesc* probs = nullptr;     // [P]
+  const int32_t* blk_prob = nullptr;   // [Ktot] problem of each block
+  const int64_t* row_off = nullptr;    // [Ktot + 1] global row offsets
+  const int64_t* pack_blk = nullptr;   // [npacks + 1] global block index of each pack start
+  const int32_t* wg_prob = nullptr;    // [nwg] problem of each refinement workgroup
+  int nwg = 1;
+  const double* lam = nullptr;         // [P] damping, read on the device
+  int grid_blocks = 1;                 // block-QR launch
+  int solve_grid = 1;                  // block-solve launches
+};
+
+}  // namespace qrk

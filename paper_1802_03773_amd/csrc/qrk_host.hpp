@@ -6,6 +6,7 @@
 
 #include <vector>
 
+#include "qrk_batch.hpp"
 #include "qrkit.h"
 
 namespace qrk {
@@ -27,7 +28,7 @@ struct qrk_handle_s {
   qrk_dtype dtype = QRK_F32;
   qrk_mode mode = QRK_PLAIN;
 
-  // shape
+  // shape (block-angular: totals over the batch; nB, ldb and ldr are those of problem 0)
   int64_t K = 0;       // blocks
   int n = 0;           // columns per block
   int nB = 0;          // dense columns
@@ -36,7 +37,26 @@ struct qrk_handle_s {
   int64_t ldb = 0;
   int max_rows = 0;    // max_i m_i + n
   int w = 0;           // banded: values per row
-  int P = 1;           // banded: problems stacked in the handle
+  int P = 1;           // problems stacked in the handle
+
+  // block-angular batch layout (a single problem is the batch of one)
+  std::vector<qrk::ProbDesc> probs_h;
+  qrk::ProbDesc* probs_d = nullptr;
+  int32_t* blk_prob = nullptr;   // [K]
+  int32_t* wg_prob = nullptr;    // [nwg]
+  int32_t* leaf_prob = nullptr;  // [leaf_cap]
+  int32_t* leaf_idx = nullptr;   // [leaf_cap]
+  int64_t leaf_cap = 0;
+  int64_t slot_cap = 0;          // floats
+  int64_t ctr_cap = 0;           // ints
+  int64_t nctr = 1;              // counters in use
+  int cls_begin[9] = {0};        // float32 leaves grouped by 16-column-block count
+  int cls_count[9] = {0};
+  int nwg = 1;                   // refinement workgroups over the batch
+  int max_L = 1;
+  double leaf_scale = 1.0;       // multiplies the default rows per leaf (autotuner)
+  double* lam_d = nullptr;       // owned damping of a single-problem factor call
+  const double* lam_ptr = nullptr;  // damping the kernels read ([P], device)
 
   // launch shape
   int grid_blocks = 1;

@@ -7,7 +7,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
 #include <type_traits>
 #include <vector>
 
@@ -32,6 +35,25 @@ qrk_status check_device() {
   return QRK_OK;
 }
 
+BatchView view(qrk_handle h) {
+  BatchView bv;
+  bv.P = h->P;
+  bv.n = h->n;
+  bv.Ktot = h->K;
+  bv.max_L = h->max_L;
+  bv.max_rows = h->max_rows;
+  bv.probs = h->probs_d;
+  bv.blk_prob = h->blk_prob;
+  bv.row_off = h->row_off_d;
+  bv.pack_blk = h->pack_blk;
+  bv.wg_prob = h->wg_prob;
+  bv.nwg = h->nwg;
+  bv.lam = h->lam_ptr;
+  bv.grid_blocks = h->grid_blocks;
+  bv.solve_grid = h->solve_grid;
+  return bv;
+}
+
 template <typename T>
 qrk_status factor_ba(qrk_handle h, hipStream_t st) {
   const T* A = static_cast<const T*>(h->A);
@@ -41,48 +63,52 @@ qrk_status factor_ba(qrk_handle h, hipStream_t st) {
   T* Sc = static_cast<T*>(h->Sc);
   T* Red = static_cast<T*>(h->Red);
   T* RB = static_cast<T*>(h->RB);
-  T* P0 = static_cast<T*>(h->part0);
-  T* P1 = static_cast<T*>(h->part1);
-  const int L = h->nB + 1;
-  const double sq = std::sqrt(h->lam);
-  if (launch_fill_int(h->status, 0, st) != hipSuccess) return QRK_EHIP;
+  if (launch_zero_ints(h->status, h->P, st) != hipSuccess) return QRK_EHIP;
   int pr = prof_begin(h, 0, st);
-  if (launch_blockqr<T>(h->K, h->n, h->nB, h->max_rows, h->row_off_d, A, B, h->ldb, b, h->d, sq,
-                        Rblk, Sc, Red, h->ldr, h->grid_blocks, st) != hipSuccess)
+  if (launch_blockqr<T>(h->K, h->n, h->max_L, h->max_rows, h->probs_d, h->blk_prob, h->row_off_d, A, B, b, h->d,
+                        h->lam_ptr, Rblk, Sc, Red, h->grid_blocks, st) != hipSuccess)
     return QRK_EHIP;
   prof_end(h, pr, st);
   if constexpr (std::is_same<T, float>::value) {
-    // dense part on the matrix cores: leaves and the merge tree in one launch
+    // dense parts on the matrix cores: leaves and merge trees, one launch per column-block count
     pr = prof_begin(h, 1, st);
-    if (launch_tsqr_mfma(Red, h->ldr, h->M, L, h->leaves, h->d + h->K * h->n, sq, h->slots,
-                         h->counters, RB, st) != hipSuccess)
+    if (launch_tsqr_mfma(h->cls_begin, h->cls_count, h->leaf_prob, h->leaf_idx, h->probs_d, h->n, Red, h->d,
+                         h->lam_ptr, h->slots, h->counters, h->nctr, RB, st) != hipSuccess)
       return QRK_EHIP;
     prof_end(h, pr, st);
     return QRK_OK;
   }
-  // dense part: leaves, then the reduction tree (ping-pong buffers, last level -> RB)
-  int G = h->leaves;
-  const int64_t rows_per = std::max<int64_t>(1, ceil_div(h->M, G));
-  T* out = (G == 1) ? RB : P0;
-  pr = prof_begin(h, 1, st);
-  if (launch_tsqr_stream<T>(Red, h->ldr, h->M, L, rows_per, G, h->d + h->K * h->n, sq, out, st) !=
-      hipSuccess)
-    return QRK_EHIP;
-  prof_end(h, pr, st);
-  T* cur = out;
-  T* other = P1;
-  pr = prof_begin(h, 2, st);
-  while (G > 1) {
-    const int Gn = (int)ceil_div(G, h->fanin);
-    T* dst = (Gn == 1) ? RB : other;
-    if (launch_tsqr_stream<T>(cur, L, (int64_t)G * L, L, (int64_t)h->fanin * L, Gn, nullptr, 0.0,
-                              dst, st) != hipSuccess)
+  // float64 dense parts, problem by problem: leaves, then the reduction tree (ping-pong
+  // buffers, last level -> the problem's R_B)
+  T* P0 = static_cast<T*>(h->part0);
+  T* P1 = static_cast<T*>(h->part1);
+  for (int q = 0; q < h->P; ++q) {
+    const ProbDesc& D = h->probs_h[q];
+    const int L = D.L;
+    int G = D.leaves;
+    const int64_t rows_per = std::max<int64_t>(1, ceil_div(D.M, G));
+    T* root = RB + D.rboff;
+    T* out = (G == 1) ? root : P0;
+    pr = prof_begin(h, 1, st);
+    if (launch_tsqr_stream<T>(Red + D.redoff, D.ldr, D.M, L, rows_per, G, h->d + D.noff + D.K * h->n,
+                              h->lam_ptr + q, out, st) != hipSuccess)
       return QRK_EHIP;
-    other = cur;
-    cur = dst;
-    G = Gn;
+    prof_end(h, pr, st);
+    T* cur = out;
+    T* other = P1;
+    pr = prof_begin(h, 2, st);
+    while (G > 1) {
+      const int Gn = (int)ceil_div(G, h->fanin);
+      T* dst = (Gn == 1) ? root : other;
+      if (launch_tsqr_stream<T>(cur, L, (int64_t)G * L, L, (int64_t)h->fanin * L, Gn, nullptr, nullptr, dst, st) !=
+          hipSuccess)
+        return QRK_EHIP;
+      other = cur;
+      cur = dst;
+      G = Gn;
+    }
+    prof_end(h, pr, st);
   }
-  prof_end(h, pr, st);
   return QRK_OK;
 }
 
@@ -91,38 +117,22 @@ qrk_status solve_ba(qrk_handle h, double* p, int sweeps, hipStream_t st) {
   const T* Rblk = static_cast<const T*>(h->Rblk);
   const T* Sc = static_cast<const T*>(h->Sc);
   const T* RB = static_cast<const T*>(h->RB);
-  const int L = h->nB + 1;
-  const int64_t off = h->K * h->n;
+  const BatchView bv = view(h);
   int pr = prof_begin(h, 3, st);
-  if (launch_backsub_dense<T>(RB, L, p, off, h->status, st) != hipSuccess) return QRK_EHIP;
-  if (launch_backsub_blocks<T>(h->K, h->n, h->nB, Rblk, Sc, p, h->status, h->solve_grid, st) !=
-      hipSuccess)
-    return QRK_EHIP;
+  if (launch_backsub_dense<T>(bv, RB, p, h->status, st) != hipSuccess) return QRK_EHIP;
+  if (launch_backsub_blocks<T>(bv, Rblk, Sc, p, h->status, st) != hipSuccess) return QRK_EHIP;
   prof_end(h, pr, st);
   pr = sweeps > 0 ? prof_begin(h, 4, st) : -1;
   for (int s = 0; s < sweeps; ++s) {
-    if (launch_refine_residual<T>(h->npacks, h->pack_blk, h->K, h->n, h->nB, h->row_off_d,
-                                  static_cast<const T*>(h->A),
-                                  static_cast<const T*>(h->B), h->ldb, static_cast<const T*>(h->b),
-                                  h->d, h->lam, Rblk, Sc, p, h->ybuf, h->refpart, h->refine_grid,
-                                  st) != hipSuccess)
-      return QRK_EHIP;
-    if (launch_refine_dense<T>(h->refine_grid, h->nB, h->refpart, RB, h->d, h->lam, p, off,
-                               h->deltaB, st) != hipSuccess)
-      return QRK_EHIP;
-    if (launch_refine_blocks<T>(h->K, h->n, h->nB, Rblk, Sc, h->ybuf, h->deltaB, p,
-                                h->solve_grid, st) != hipSuccess)
+    if (launch_refine_residual<T>(bv, static_cast<const T*>(h->A), static_cast<const T*>(h->B),
+                                  static_cast<const T*>(h->b), h->d, Rblk, Sc, p, h->ybuf, h->refpart, st) !=
+            hipSuccess ||
+        launch_refine_dense<T>(bv, h->refpart, RB, h->d, p, h->deltaB, st) != hipSuccess ||
+        launch_refine_blocks<T>(bv, Rblk, Sc, h->ybuf, h->deltaB, p, st) != hipSuccess)
       return QRK_EHIP;
   }
   prof_end(h, pr, st);
   return QRK_OK;
-}
-
-// Leaf count of the dense-part QR: float32 leaves are single waves (about 128 rows
-// each, at most 2048); float64 leaves are workgroups (about 256 rows, at most 1024).
-int default_leaves(qrk_handle h) {
-  const int64_t per = h->dtype == QRK_F32 ? 128 : 256;  // rows per leaf before the cap
-  return (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(h->M + h->nB, per), h->max_leaves));
 }
 
 void prof_free(qrk_handle h) {
@@ -152,6 +162,114 @@ qrk_status dalloc(qrk_handle h, P** out, size_t bytes) {
   return QRK_OK;
 }
 
+void dfree(qrk_handle h, void* ptr) {
+  if (!ptr) return;
+  for (size_t i = 0; i < h->allocs.size(); ++i)
+    if (h->allocs[i] == ptr) {
+      (void)hipFree(ptr);
+      h->allocs.erase(h->allocs.begin() + (long)i);
+      return;
+    }
+}
+
+// Slots and arrival counters a merge tree over `leaves` leaves touches: level k has n_k
+// nodes (n_0 = leaves, n_{k+1} = ceil(n_k / 2)); its stored triangles sit at slots
+// [sum_{j<k} n_j, sum_{j<=k} n_j) and its counters at [sum_{j<k} n_{j+1}, ...).
+struct TreeSize {
+  int64_t slots, counters;
+};
+TreeSize tree_size(int64_t leaves) {
+  TreeSize t{0, 0};
+  for (int64_t nl = leaves; nl > 1; nl = (nl + 1) / 2) {
+    t.slots += nl;
+    t.counters += (nl + 1) / 2;
+  }
+  t.slots = std::max<int64_t>(t.slots, 1);
+  t.counters = std::max<int64_t>(t.counters, 1);
+  return t;
+}
+
+// Dense-part leaves of every problem.  float32: leaves are single waves; per 16-column-block
+// class c the default is about max(128, rows_c / 4096) rows per leaf (rows_c: the class's
+// reduced plus damping rows), scaled by leaf_scale, at most 1024 leaves per problem; a
+// single-problem handle may fix the count (h->leaves > 0).  Leaves are listed class by class
+// for the per-class launches, and each problem's merge tree gets the slots and arrival
+// counters of tree_size.  float64: leaves are workgroups of about 256 rows.
+qrk_status assign_leaves(qrk_handle h) {
+  std::vector<ProbDesc>& pd = h->probs_h;
+  const int P = h->P;
+  if (h->dtype == QRK_F64) {
+    for (auto& D : pd) {
+      const int64_t def = std::max<int64_t>(1, std::min<int64_t>(ceil_div(D.M + D.nB, 256), 1024));
+      D.leaves = (int)(h->leaves > 0 ? h->leaves : def);
+      D.rows_per_leaf = std::max<int64_t>(1, ceil_div(D.M, D.leaves));
+    }
+  } else {
+    double rows_cls[9] = {0};
+    for (auto& D : pd) rows_cls[(D.L + 15) / 16] += (double)(D.M + D.nB);
+    for (auto& D : pd) {
+      const int c = (D.L + 15) / 16;
+      const double per = std::max(128.0, rows_cls[c] / 4096.0) * h->leaf_scale;
+      const int64_t def = std::max<int64_t>(
+          1, std::min<int64_t>((int64_t)std::ceil((double)(D.M + D.nB) / std::max(per, 1.0)), 1024));
+      D.leaves = (int)(h->leaves > 0 ? h->leaves : def);
+      D.rows_per_leaf = std::max<int64_t>(1, ceil_div(D.M, D.leaves));
+    }
+    std::vector<int32_t> lp, li;
+    for (int c = 1; c <= 8; ++c) {
+      h->cls_begin[c] = (int)lp.size();
+      for (int q = 0; q < P; ++q)
+        if ((pd[q].L + 15) / 16 == c)
+          for (int k = 0; k < pd[q].leaves; ++k) {
+            lp.push_back(q);
+            li.push_back(k);
+          }
+      h->cls_count[c] = (int)lp.size() - h->cls_begin[c];
+    }
+    int64_t slot = 0, ctr = 0;
+    for (auto& D : pd) {
+      D.slot0 = slot;
+      D.ctr0 = ctr;
+      const TreeSize ts = tree_size(D.leaves);
+      slot += ts.slots * tsqr_mfma_slot_floats(D.L);
+      ctr += ts.counters;
+    }
+    h->nctr = ctr;
+    const int64_t nleaf = (int64_t)lp.size();
+    qrk_status s;
+    if (nleaf > h->leaf_cap) {
+      dfree(h, h->leaf_prob);
+      dfree(h, h->leaf_idx);
+      h->leaf_prob = h->leaf_idx = nullptr;
+      h->leaf_cap = 0;
+      if ((s = dalloc(h, &h->leaf_prob, sizeof(int32_t) * nleaf)) != QRK_OK ||
+          (s = dalloc(h, &h->leaf_idx, sizeof(int32_t) * nleaf)) != QRK_OK)
+        return s;
+      h->leaf_cap = nleaf;
+    }
+    if (slot > h->slot_cap) {
+      dfree(h, h->slots);
+      h->slots = nullptr;
+      h->slot_cap = 0;
+      if ((s = dalloc(h, &h->slots, sizeof(float) * slot)) != QRK_OK) return s;
+      h->slot_cap = slot;
+    }
+    if (ctr > h->ctr_cap) {
+      dfree(h, h->counters);
+      h->counters = nullptr;
+      h->ctr_cap = 0;
+      if ((s = dalloc(h, &h->counters, sizeof(int) * ctr)) != QRK_OK) return s;
+      h->ctr_cap = ctr;
+    }
+    if (hipMemcpy(h->leaf_prob, lp.data(), sizeof(int32_t) * nleaf, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->leaf_idx, li.data(), sizeof(int32_t) * nleaf, hipMemcpyHostToDevice) != hipSuccess)
+      return QRK_EHIP;
+  }
+  if (hipMemcpy(h->probs_d, pd.data(), sizeof(ProbDesc) * P, hipMemcpyHostToDevice) != hipSuccess)
+    return QRK_EHIP;
+  return QRK_OK;
+}
+
 }  // namespace
 
 qrk_status handle_alloc(qrk_handle h, void** out, size_t bytes) { return dalloc(h, out, bytes); }
@@ -163,22 +281,17 @@ qrk_status adjoint_ba(qrk_handle h, const double* p, const double* g, void* dA, 
   const T* Rblk = static_cast<const T*>(h->Rblk);
   const T* Sc = static_cast<const T*>(h->Sc);
   const T* RB = static_cast<const T*>(h->RB);
-  const int64_t Kn = h->K * h->n;
+  const BatchView bv = view(h);
   // u = (R^T R)^{-1} g through the structured R
-  if (launch_adjoint_fwd_blocks<T>(h->K, h->n, h->nB, Rblk, Sc, g, h->ybuf, h->refpart, h->refine_grid,
-                                   st) != hipSuccess)
+  if (launch_adjoint_fwd_blocks<T>(h->K, h->n, h->nB, Rblk, Sc, g, h->ybuf, h->refpart, h->nwg, st) != hipSuccess)
     return QRK_EHIP;
-  if (h->nB > 0 && launch_adjoint_dense<T>(h->refine_grid, h->nB, h->refpart, RB, g + Kn, h->ubuf + Kn,
-                                           st) != hipSuccess)
-    return QRK_EHIP;
-  if (launch_adjoint_blocks<T>(h->K, h->n, h->nB, Rblk, Sc, h->ybuf, h->ubuf + Kn, h->ubuf, h->solve_grid,
-                               st) != hipSuccess)
-    return QRK_EHIP;
+  if (h->nB > 0 && launch_adjoint_dense<T>(bv, h->refpart, RB, g, h->ubuf, st) != hipSuccess) return QRK_EHIP;
+  if (launch_adjoint_blocks<T>(bv, Rblk, Sc, h->ybuf, h->ubuf, st) != hipSuccess) return QRK_EHIP;
   if ((dA || dB || db) &&
       launch_adjoint_rows<T>(h->npacks, h->pack_blk, h->K, h->n, h->nB, h->row_off_d,
                              static_cast<const T*>(h->A), static_cast<const T*>(h->B), h->ldb,
                              static_cast<const T*>(h->b), p, h->ubuf, static_cast<T*>(dA),
-                             static_cast<T*>(dB), static_cast<T*>(db), h->refine_grid, st) != hipSuccess)
+                             static_cast<T*>(dB), static_cast<T*>(db), h->nwg, st) != hipSuccess)
     return QRK_EHIP;
   if ((dlam || dd) &&
       launch_adjoint_vec(1, h->N, h->ubuf, h->d, p, h->lam, dd, dlam, h->vecpart, st) != hipSuccess)
@@ -204,6 +317,179 @@ void prof_end(qrk_handle h, int rec, hipStream_t st) {
   if (rec >= 0) (void)hipEventRecord(h->prof_pool[rec].stop, st);
 }
 
+// Leaf-shape choices of the autotuner, remembered in the process by batch shape.
+struct TuneKey {
+  int64_t rows;
+  int P, n, max_L, dtype;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(rows, P, n, max_L, dtype) < std::tie(o.rows, o.P, o.n, o.max_L, o.dtype);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, double> g_tune;
+
+TuneKey tune_key(qrk_handle h) { return TuneKey{h->M, h->P, h->n, h->max_L, (int)h->dtype}; }
+
+double remembered_leaf_scale(qrk_handle h) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(tune_key(h));
+  return it == g_tune.end() ? 1.0 : it->second;
+}
+
+// Validate a batch description and build the handle: per-problem descriptors, the
+// block -> problem map, packs of whole blocks (at most 64 rows and 64 blocks, never across
+// problems), refinement workgroups per problem (in proportion to the packs, at most 1024 in
+// all), dense-part leaves, and all workspace.  ldb_single >= 0: one problem whose B has that
+// row stride; -1: B packed problem after problem with row stride nB_p.
+qrk_status create_ba(int32_t P, int32_t n, const int32_t* Kp, const int32_t* nBp, const int64_t* row_off_host,
+                     int64_t ldb_single, qrk_dtype dtype, qrk_mode mode, qrk_handle* out) {
+  if (P < 1 || !Kp || !nBp || !row_off_host) return QRK_EINVAL;
+  if (n < 1 || n > QRK_MAX_BLOCK_COLS || (dtype != QRK_F32 && dtype != QRK_F64)) return QRK_EINVAL;
+  if (mode != QRK_PLAIN && mode != QRK_BF16X3) return QRK_EINVAL;
+  if (mode == QRK_BF16X3 && dtype != QRK_F32) return QRK_EINVAL;
+  int64_t Ktot = 0;
+  for (int32_t q = 0; q < P; ++q) {
+    if (Kp[q] < 1 || nBp[q] < 0 || nBp[q] > QRK_MAX_DENSE_COLS) return QRK_EINVAL;
+    Ktot += Kp[q];
+  }
+  if (row_off_host[0] != 0) return QRK_EINVAL;
+  int max_m = 0;
+  for (int64_t i = 0; i < Ktot; ++i) {
+    const int64_t m = row_off_host[i + 1] - row_off_host[i];
+    if (m < 0 || m > QRK_MAX_BLOCK_ROWS) return QRK_EINVAL;
+    max_m = std::max<int>(max_m, (int)m);
+  }
+  qrk_status ds = check_device();
+  if (ds != QRK_OK) return ds;
+
+  qrk_handle h = new (std::nothrow) qrk_handle_s();
+  if (!h) return QRK_ENOMEM;
+  h->kind = KIND_BLOCKANGULAR;
+  h->dtype = dtype;
+  h->mode = mode;
+  h->P = P;
+  h->K = Ktot;
+  h->n = n;
+  h->nB = nBp[0];
+  h->M = row_off_host[Ktot];
+  h->max_rows = max_m + n;
+  h->ldb = ldb_single >= 0 ? ldb_single : nBp[0];
+  h->ldr = ((nBp[0] + 1 + 3) / 4) * 4;
+  const size_t es = dtype == QRK_F32 ? 4 : 8;
+
+  // per-problem descriptors and packs
+  std::vector<ProbDesc>& pd = h->probs_h;
+  pd.resize(P);
+  std::vector<int64_t> packs{0};
+  std::vector<int32_t> blk_prob((size_t)Ktot);
+  int64_t koff = 0, noff = 0, boff = 0, soff = 0, redoff = 0, rboff = 0;
+  for (int32_t q = 0; q < P; ++q) {
+    ProbDesc& D = pd[q];
+    std::memset(&D, 0, sizeof(D));
+    D.koff = koff;
+    D.K = Kp[q];
+    D.moff = row_off_host[koff];
+    D.M = row_off_host[koff + D.K] - D.moff;
+    D.noff = noff;
+    D.nB = nBp[q];
+    D.L = D.nB + 1;
+    D.boff = boff;
+    D.ldb = ldb_single >= 0 ? ldb_single : D.nB;
+    D.soff = soff;
+    D.ldr = ((D.L + 3) / 4) * 4;
+    D.redoff = redoff;
+    D.rboff = rboff;
+    D.pack0 = (int64_t)packs.size() - 1;
+    int64_t rows = 0;
+    int nbp = 0;
+    for (int64_t i = koff; i < koff + D.K; ++i) {
+      blk_prob[(size_t)i] = q;
+      const int64_t m = row_off_host[i + 1] - row_off_host[i];
+      if (nbp > 0 && (rows + m > 64 || nbp == 64)) {
+        packs.push_back(i);
+        rows = 0;
+        nbp = 0;
+      }
+      rows += m;
+      ++nbp;
+    }
+    packs.push_back(koff + D.K);
+    D.npacks = (int64_t)packs.size() - 1 - D.pack0;
+    h->max_L = std::max(h->max_L, (int)D.L);
+    koff += D.K;
+    noff += D.K * n + D.nB;
+    boff += D.M * D.ldb;
+    soff += D.K * n * D.L;
+    redoff += D.M * D.ldr;
+    rboff += (int64_t)D.L * D.L;
+  }
+  h->N = noff;
+  h->npacks = (int64_t)packs.size() - 1;
+  // refinement workgroups, in proportion to each problem's packs
+  const int64_t target = std::min<int64_t>(ceil_div(h->npacks, 4), 1024);
+  std::vector<int32_t> wg_prob;
+  for (int32_t q = 0; q < P; ++q) {
+    ProbDesc& D = pd[q];
+    int64_t w = (int64_t)std::llround((double)D.npacks * (double)target / (double)h->npacks);
+    w = std::max<int64_t>(1, std::min<int64_t>(w, ceil_div(D.npacks, 4)));
+    D.wg0 = (int32_t)wg_prob.size();
+    D.nwg = (int32_t)w;
+    for (int64_t k = 0; k < w; ++k) wg_prob.push_back(q);
+  }
+  h->nwg = (int)wg_prob.size();
+  h->refine_grid = h->nwg;
+  h->grid_blocks = (int)std::min<int64_t>(ceil_div(Ktot, 4), 2048);
+  h->solve_grid = (int)std::min<int64_t>(ceil_div(Ktot, 16), 2048);
+  h->max_leaves = 1024;
+  h->leaves = 0;
+  h->fanin = 8;
+  h->leaf_scale = remembered_leaf_scale(h);
+
+  qrk_status s = QRK_OK;
+  const int Lm = h->max_L;
+  if ((s = dalloc(h, &h->row_off_d, sizeof(int64_t) * (Ktot + 1))) != QRK_OK ||
+      (s = dalloc(h, &h->pack_blk, sizeof(int64_t) * packs.size())) != QRK_OK ||
+      (s = dalloc(h, &h->blk_prob, sizeof(int32_t) * Ktot)) != QRK_OK ||
+      (s = dalloc(h, &h->wg_prob, sizeof(int32_t) * wg_prob.size())) != QRK_OK ||
+      (s = dalloc(h, &h->probs_d, sizeof(ProbDesc) * P)) != QRK_OK ||
+      (s = dalloc(h, &h->Rblk, es * (size_t)Ktot * n * n)) != QRK_OK ||
+      (s = dalloc(h, &h->Sc, es * (size_t)soff)) != QRK_OK ||
+      (s = dalloc(h, &h->Red, es * (size_t)std::max<int64_t>(redoff, 1))) != QRK_OK ||
+      (s = dalloc(h, &h->RB, es * (size_t)rboff)) != QRK_OK ||
+      (s = dalloc(h, &h->part0, dtype == QRK_F64 ? es * (size_t)1024 * Lm * Lm : 0)) != QRK_OK ||
+      (s = dalloc(h, &h->part1, dtype == QRK_F64 ? es * (size_t)1024 * Lm * Lm : 0)) != QRK_OK ||
+      (s = dalloc(h, &h->ybuf, sizeof(double) * (size_t)Ktot * n)) != QRK_OK ||
+      (s = dalloc(h, &h->ubuf, sizeof(double) * (size_t)h->N)) != QRK_OK ||
+      (s = dalloc(h, &h->vecpart, sizeof(double) * (size_t)1024 * std::max(Lm - 1, 1))) != QRK_OK ||
+      (s = dalloc(h, &h->refpart, sizeof(double) * (size_t)h->nwg * kMaxDense)) != QRK_OK ||
+      (s = dalloc(h, &h->deltaB, sizeof(double) * (size_t)P * kMaxDense)) != QRK_OK ||
+      (s = dalloc(h, &h->lam_d, sizeof(double) * (size_t)P)) != QRK_OK ||
+      (s = dalloc(h, &h->status, sizeof(int) * (size_t)std::max(P, 4))) != QRK_OK) {
+    free_all(h);
+    delete h;
+    return s;
+  }
+  h->lam_ptr = h->lam_d;
+  if (hipMemcpy(h->row_off_d, row_off_host, sizeof(int64_t) * (Ktot + 1), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(h->pack_blk, packs.data(), sizeof(int64_t) * packs.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(h->blk_prob, blk_prob.data(), sizeof(int32_t) * Ktot, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(h->wg_prob, wg_prob.data(), sizeof(int32_t) * wg_prob.size(), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemset(h->status, 0, sizeof(int) * (size_t)std::max(P, 4)) != hipSuccess ||
+      hipMemset(h->lam_d, 0, sizeof(double) * (size_t)P) != hipSuccess) {
+    free_all(h);
+    delete h;
+    return QRK_EHIP;
+  }
+  if ((s = assign_leaves(h)) != QRK_OK) {
+    free_all(h);
+    delete h;
+    return s;
+  }
+  *out = h;
+  return QRK_OK;
+}
+
 extern "C" {
 
 const char* qrk_strerror(qrk_status s) {
@@ -223,105 +509,43 @@ qrk_status qrk_create_blockangular(int32_t K, int32_t n, int32_t nB, const int64
                                    int64_t ldb, qrk_dtype dtype, qrk_mode mode, qrk_handle* out) {
   if (!out) return QRK_EINVAL;
   *out = nullptr;
-  if (K < 1 || n < 1 || n > QRK_MAX_BLOCK_COLS || nB < 0 || nB > QRK_MAX_DENSE_COLS) return QRK_EINVAL;
-  if (!row_off_host || ldb < nB || (dtype != QRK_F32 && dtype != QRK_F64)) return QRK_EINVAL;
-  if (mode != QRK_PLAIN && mode != QRK_BF16X3) return QRK_EINVAL;
-  if (mode == QRK_BF16X3 && dtype != QRK_F32) return QRK_EINVAL;
-  if (row_off_host[0] != 0) return QRK_EINVAL;
-  int max_m = 0;
-  for (int32_t i = 0; i < K; ++i) {
-    const int64_t m = row_off_host[i + 1] - row_off_host[i];
-    if (m < 0 || m > QRK_MAX_BLOCK_ROWS) return QRK_EINVAL;
-    max_m = std::max<int>(max_m, (int)m);
-  }
-  qrk_status ds = check_device();
-  if (ds != QRK_OK) return ds;
+  if (ldb < nB) return QRK_EINVAL;
+  return create_ba(1, n, &K, &nB, row_off_host, ldb, dtype, mode, out);
+}
 
-  qrk_handle h = new (std::nothrow) qrk_handle_s();
-  if (!h) return QRK_ENOMEM;
-  h->kind = KIND_BLOCKANGULAR;
-  h->dtype = dtype;
-  h->mode = mode;
-  h->K = K;
-  h->n = n;
-  h->nB = nB;
-  h->M = row_off_host[K];
-  h->N = (int64_t)K * n + nB;
-  h->ldb = ldb;
-  h->max_rows = max_m + n;
-  const size_t es = dtype == QRK_F32 ? 4 : 8;
-  const int L = nB + 1;
-  h->ldr = ((L + 3) / 4) * 4;
-  // packs of consecutive whole blocks, at most 64 rows and 64 blocks each (refinement)
-  std::vector<int64_t> packs{0};
-  {
-    int64_t rows = 0;
-    int nbp = 0;
-    for (int32_t i = 0; i < K; ++i) {
-      const int64_t m = row_off_host[i + 1] - row_off_host[i];
-      if (nbp > 0 && (rows + m > 64 || nbp == 64)) {
-        packs.push_back(i);
-        rows = 0;
-        nbp = 0;
-      }
-      rows += m;
-      ++nbp;
-    }
-    packs.push_back(K);
-  }
-  h->npacks = (int64_t)packs.size() - 1;
-  h->grid_blocks = (int)std::min<int64_t>(ceil_div(K, 4), 2048);
-  h->solve_grid = (int)std::min<int64_t>(ceil_div(K, 16), 2048);
-  h->refine_grid = (int)std::min<int64_t>(ceil_div(h->npacks, 4), 1024);
-  h->max_leaves = 1024;  // float32: one leaf wave per SIMD of the 256-CU chip
-  h->leaves = default_leaves(h);
-  h->fanin = 8;
-  qrk_status s = QRK_OK;
-  if ((s = dalloc(h, &h->row_off_d, sizeof(int64_t) * (K + 1))) != QRK_OK ||
-      (s = dalloc(h, &h->pack_blk, sizeof(int64_t) * packs.size())) != QRK_OK ||
-      (s = dalloc(h, &h->Rblk, es * (size_t)K * n * n)) != QRK_OK ||
-      (s = dalloc(h, &h->Sc, es * (size_t)K * n * L)) != QRK_OK ||
-      (s = dalloc(h, &h->Red, es * (size_t)std::max<int64_t>(h->M, 1) * h->ldr)) != QRK_OK ||
-      (s = dalloc(h, &h->RB, es * (size_t)L * L)) != QRK_OK ||
-      (s = dalloc(h, &h->part0, dtype == QRK_F64 ? es * (size_t)1024 * L * L : 0)) != QRK_OK ||
-      (s = dalloc(h, &h->part1, dtype == QRK_F64 ? es * (size_t)1024 * L * L : 0)) != QRK_OK ||
-      (s = dalloc(h, &h->slots, dtype == QRK_F32 ? sizeof(float) * (size_t)2 * h->max_leaves *
-                                                       tsqr_mfma_slot_floats(L)
-                                                 : 0)) != QRK_OK ||
-      (s = dalloc(h, &h->counters, sizeof(int) * (size_t)(2 * h->max_leaves + 2))) != QRK_OK ||
-      (s = dalloc(h, &h->ybuf, sizeof(double) * (size_t)K * n)) != QRK_OK ||
-      (s = dalloc(h, &h->ubuf, sizeof(double) * (size_t)h->N)) != QRK_OK ||
-      (s = dalloc(h, &h->vecpart, sizeof(double) * (size_t)1024 * std::max(nB, 1))) != QRK_OK ||
-      (s = dalloc(h, &h->refpart, sizeof(double) * (size_t)h->refine_grid * std::max(nB, 1))) != QRK_OK ||
-      (s = dalloc(h, &h->deltaB, sizeof(double) * (size_t)std::max(nB, 1))) != QRK_OK ||
-      (s = dalloc(h, &h->status, sizeof(int) * 4)) != QRK_OK) {
-    free_all(h);
-    delete h;
-    return s;
-  }
-  if (hipMemcpy(h->row_off_d, row_off_host, sizeof(int64_t) * (K + 1), hipMemcpyHostToDevice) !=
-          hipSuccess ||
-      hipMemcpy(h->pack_blk, packs.data(), sizeof(int64_t) * packs.size(), hipMemcpyHostToDevice) !=
-          hipSuccess ||
-      hipMemset(h->status, 0, sizeof(int) * 4) != hipSuccess) {
-    free_all(h);
-    delete h;
-    return QRK_EHIP;
-  }
-  *out = h;
-  return QRK_OK;
+qrk_status qrk_create_blockangular_batched(int32_t P, int32_t n, const int32_t* K_host, const int32_t* nB_host,
+                                           const int64_t* row_off_host, qrk_dtype dtype, qrk_mode mode,
+                                           qrk_handle* out) {
+  if (!out) return QRK_EINVAL;
+  *out = nullptr;
+  return create_ba(P, n, K_host, nB_host, row_off_host, -1, dtype, mode, out);
 }
 
 qrk_status qrk_factor_blockangular(qrk_handle h, const void* A, const void* B, const void* b,
                                    const double* d, double lambda, void* stream) {
-  if (!h || h->kind != KIND_BLOCKANGULAR) return QRK_EINVAL;
+  if (!h || h->kind != KIND_BLOCKANGULAR || h->P != 1) return QRK_EINVAL;
   if (!A || !b || !d || (h->nB > 0 && !B)) return QRK_EINVAL;
   if (!(lambda >= 0.0) || !std::isfinite(lambda)) return QRK_EINVAL;
+  if (launch_fill_double(h->lam_d, 1, lambda, S(stream)) != hipSuccess) return QRK_EHIP;
   h->A = A;
   h->B = B;
   h->b = b;
   h->d = d;
   h->lam = lambda;
+  h->lam_ptr = h->lam_d;
+  h->factored = true;
+  return h->dtype == QRK_F32 ? factor_ba<float>(h, S(stream)) : factor_ba<double>(h, S(stream));
+}
+
+qrk_status qrk_factor_blockangular_batched(qrk_handle h, const void* A, const void* B, const void* b,
+                                           const double* d, const double* lambda_dev, void* stream) {
+  if (!h || h->kind != KIND_BLOCKANGULAR || !A || !b || !d || !lambda_dev) return QRK_EINVAL;
+  if (h->max_L > 1 && !B) return QRK_EINVAL;
+  h->A = A;
+  h->B = B;
+  h->b = b;
+  h->d = d;
+  h->lam_ptr = lambda_dev;
   h->factored = true;
   return h->dtype == QRK_F32 ? factor_ba<float>(h, S(stream)) : factor_ba<double>(h, S(stream));
 }
@@ -338,7 +562,7 @@ qrk_status qrk_solve_adjoint(qrk_handle h, const double* p, const double* g, voi
                              void* db, double* dlambda, double* dd, void* stream) {
   if (!h || !h->factored || !p || !g) return QRK_EINVAL;
   if (h->kind == KIND_BLOCKANGULAR) {
-    if (dB && h->nB == 0) return QRK_EINVAL;
+    if (h->P != 1 || (dB && h->nB == 0)) return QRK_EINVAL;
     return blockangular_adjoint(h, p, g, dA, dB, db, dlambda, dd, S(stream));
   }
   if (dB) return QRK_EINVAL;
@@ -346,7 +570,7 @@ qrk_status qrk_solve_adjoint(qrk_handle h, const double* p, const double* g, voi
 }
 
 qrk_status qrk_colnorms_blockangular(qrk_handle h, const void* A, const void* B, double* d, void* stream) {
-  if (!h || h->kind != KIND_BLOCKANGULAR || !A || !d || (h->nB > 0 && !B)) return QRK_EINVAL;
+  if (!h || h->kind != KIND_BLOCKANGULAR || h->P != 1 || !A || !d || (h->nB > 0 && !B)) return QRK_EINVAL;
   const int nparts = (int)std::min<int64_t>(std::max<int64_t>(1, ceil_div(h->M, 512)), 1024);
   hipError_t e = h->dtype == QRK_F32
                      ? launch_colnorms<float>(h->K, h->n, h->nB, h->M, h->row_off_d,
@@ -364,6 +588,7 @@ qrk_status qrk_get_factor(qrk_handle h, void* Rblk, void* Sc, void* RB, void* st
   const size_t es = h->dtype == QRK_F32 ? 4 : 8;
   hipStream_t st = S(stream);
   if (h->kind == KIND_BLOCKANGULAR) {
+    if (h->P != 1) return QRK_EINVAL;
     const int L = h->nB + 1;
     if (Rblk && hipMemcpyAsync(Rblk, h->Rblk, es * (size_t)h->K * h->n * h->n,
                                hipMemcpyDeviceToDevice, st) != hipSuccess)
@@ -386,11 +611,14 @@ qrk_status qrk_get_factor(qrk_handle h, void* Rblk, void* Sc, void* RB, void* st
 
 qrk_status qrk_status_get(qrk_handle h, int32_t* detail_host, void* stream) {
   if (!h) return QRK_EINVAL;
-  int bits = 0;
+  const int nw = h->kind == KIND_BLOCKANGULAR ? h->P : 1;
+  std::vector<int> words((size_t)nw, 0);
   hipStream_t st = S(stream);
-  if (hipMemcpyAsync(&bits, h->status, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+  if (hipMemcpyAsync(words.data(), h->status, sizeof(int) * (size_t)nw, hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return QRK_EHIP;
+  int bits = 0;
+  for (int w : words) bits |= w;
   if (detail_host) *detail_host = bits;
   // a zero pivot also makes p non-finite, so singularity is reported first
   if (bits & ST_BADINPUT) return QRK_EINVAL;
@@ -399,12 +627,71 @@ qrk_status qrk_status_get(qrk_handle h, int32_t* detail_host, void* stream) {
   return QRK_OK;
 }
 
+qrk_status qrk_status_get_problems(qrk_handle h, int32_t* bits_host, void* stream) {
+  if (!h || !bits_host) return QRK_EINVAL;
+  const int nw = h->kind == KIND_BLOCKANGULAR ? h->P : 1;
+  hipStream_t st = S(stream);
+  if (hipMemcpyAsync(bits_host, h->status, sizeof(int) * (size_t)nw, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return QRK_EHIP;
+  return QRK_OK;
+}
+
 qrk_status qrk_set_tsqr_shape(qrk_handle h, int32_t leaves, int32_t fanin) {
   if (!h || leaves < 0 || fanin < 0 || fanin == 1 || fanin > 64) return QRK_EINVAL;
-  if (h->kind != KIND_BLOCKANGULAR || leaves > h->max_leaves) return QRK_EINVAL;
-  h->leaves = leaves ? leaves : default_leaves(h);
+  if (h->kind != KIND_BLOCKANGULAR || h->P != 1 || leaves > h->max_leaves) return QRK_EINVAL;
+  h->leaves = leaves;
   h->fanin = fanin ? fanin : 8;
-  return QRK_OK;
+  return assign_leaves(h);
+}
+
+qrk_status qrk_autotune_blockangular(qrk_handle h, double* scale_host, void* stream) {
+  if (!h || h->kind != KIND_BLOCKANGULAR || !h->factored || h->dtype != QRK_F32) return QRK_EINVAL;
+  hipStream_t st = S(stream);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return QRK_EHIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return QRK_EHIP;
+  }
+  const int fixed = h->leaves;
+  h->leaves = 0;
+  const bool prof = h->prof_on;
+  h->prof_on = false;
+  double best_ms = 1e300, best = 1.0;
+  qrk_status s = QRK_OK;
+  for (double scale : {0.5, 1.0, 2.0, 4.0}) {
+    h->leaf_scale = scale;
+    if ((s = assign_leaves(h)) != QRK_OK) break;
+    float ms_min = 1e30f;
+    for (int rep = 0; rep < 3 && s == QRK_OK; ++rep) {  // the first run warms up
+      if (hipEventRecord(e0, st) != hipSuccess) s = QRK_EHIP;
+      if (s == QRK_OK) s = factor_ba<float>(h, st);
+      if (s == QRK_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+        s = QRK_EHIP;
+      float ms = 0.f;
+      if (s == QRK_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) s = QRK_EHIP;
+      if (rep > 0) ms_min = std::min(ms_min, ms);
+    }
+    if (s != QRK_OK) break;
+    if (ms_min < best_ms) {
+      best_ms = ms_min;
+      best = scale;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h->prof_on = prof;
+  h->leaf_scale = best;
+  h->leaves = fixed;
+  if (s == QRK_OK) s = assign_leaves(h);
+  if (s == QRK_OK) s = factor_ba<float>(h, st);
+  if (s == QRK_OK) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[tune_key(h)] = best;
+  }
+  if (scale_host) *scale_host = best;
+  return s;
 }
 
 qrk_status qrk_profile_enable(qrk_handle h, int32_t max_calls) {

@@ -8,12 +8,13 @@
 //     R_B delta_B = y_B; R_i delta_i = y_i - S_i delta_B.
 // Sums over blocks are deterministic: per-wave partials in registers, workgroup partials
 // combined in a fixed order, then a fixed-order reduction of the workgroup partials.
+// Every kernel serves a batch of independent problems (ProbDesc); a single problem is the
+// batch of one.
+#include "qrk_batch.hpp"
 #include "qrk_device.hpp"
 #include "qrk_launch.hpp"
 
 namespace qrk {
-
-constexpr int kMaxDense = 128;  // nB + 1 <= 128
 
 // ---------------------------------------------------------------------------------
 // Dense triangle, one wave: forward (R_B^T y = g) and backward (R_B x = y) sweeps with
@@ -76,17 +77,22 @@ __device__ __forceinline__ void wave_bwd(const float* Rs, const double* Rsd, int
   }
 }
 
+
 // ---------------------------------------------------------------------------------
-// Dense part of the back-substitution: R_B p_B = c_B (one workgroup, one working wave).
+// Dense part of the back-substitution: R_B p_B = c_B, one workgroup (one working wave)
+// per problem.
 // ---------------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_backsub_dense(const T* __restrict__ RB, int L, double* __restrict__ p, int64_t off,
+k_backsub_dense(const ProbDesc* __restrict__ probs, int n, const T* __restrict__ RBall, double* __restrict__ p,
                 int* __restrict__ status) {
   __shared__ float Rs[sizeof(T) == 4 ? kMaxDense * kMaxDense : 1];
   __shared__ double Rsd[sizeof(T) == 8 ? kMaxDense * kMaxDense : 1];
-  const int nB = L - 1;
-  stage_dense<T>(RB, L, Rs, Rsd, threadIdx.x, blockDim.x);
+  const int pi = blockIdx.x;
+  const ProbDesc& P = probs[pi];
+  const int L = P.L, nB = P.nB;
+  const int64_t off = P.noff + P.K * n;
+  stage_dense<T>(RBall + P.rboff, L, Rs, Rsd, threadIdx.x, blockDim.x);
   __syncthreads();
   if (threadIdx.x >= 64) return;
   const int lane = threadIdx.x;
@@ -109,15 +115,14 @@ k_backsub_dense(const T* __restrict__ RB, int L, double* __restrict__ p, int64_t
     p[off + lane + 64] = v1;
     nonfinite |= !is_finite(v1);
   }
-  if (bad) set_status(status, ST_SINGULAR);
-  if (nonfinite) set_status(status, ST_NONFINITE);
+  if (bad) set_status(status + pi, ST_SINGULAR);
+  if (nonfinite) set_status(status + pi, ST_NONFINITE);
 }
 
 template <typename T>
-hipError_t launch_backsub_dense(const T* RB, int L, double* p, int64_t off, int* status,
-                                hipStream_t st) {
-  if (L > kMaxDense) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_backsub_dense<T>), dim3(1), dim3(256), 0, st, RB, L, p, off, status);
+hipError_t launch_backsub_dense(const BatchView& bv, const T* RB, double* p, int* status, hipStream_t st) {
+  if (bv.max_L > kMaxDense) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_backsub_dense<T>), dim3(bv.P), dim3(256), 0, st, bv.probs, bv.n, RB, p, status);
   return hipGetLastError();
 }
 
@@ -159,36 +164,50 @@ __device__ __forceinline__ double sum16(double x) {
 }
 
 // ---------------------------------------------------------------------------------
-// Blocks: p_i (= | +=) R_i^{-1} (base_i - S_i v), 16 lanes per block, 16 blocks per
-// workgroup in flight.
-//   back-substitution: base_i = c_i (last column of S|c), v = p_B, p_i set;
-//   refinement:        base_i = y_i, v = delta_B, p_i incremented.
+// Blocks: x_i (= | +=) R_i^{-1} (base_i - S_i v), 16 lanes per block, 16 blocks per
+// workgroup in flight; v is the dense-part vector of the block's problem.
+//   MODE 0 back-substitution: base_i = c_i (last column of S|c), v = p_B, p_i set;
+//   MODE 1 refinement:        base_i = y_i, v = delta_B, p_i incremented;
+//   MODE 2 adjoint:           base_i = y_i, v = u_B, u_i set.
 // ---------------------------------------------------------------------------------
-// MODE 0: back-substitution (base c, set p); 1: refinement (base y, add to p);
-// 2: adjoint (base y, set out).
 template <typename T, int MODE>
 __global__ void __launch_bounds__(256)
-k_blocks_solve(int64_t K, int n, int nB, const T* __restrict__ Rblk, const T* __restrict__ Sc,
-               const double* __restrict__ v, const double* __restrict__ ybase,
-               double* __restrict__ p, int* __restrict__ status) {
+k_blocks_solve(int64_t Ktot, int n, const ProbDesc* __restrict__ probs, const int32_t* __restrict__ blk_prob,
+               const T* __restrict__ Rblk, const T* __restrict__ Sc, const double* __restrict__ vbuf,
+               const double* __restrict__ ybase, double* __restrict__ x, int* __restrict__ status) {
   const int lane = threadIdx.x & 63;
   const int l16 = lane & 15;
   const int grp = threadIdx.x >> 4;  // 0..15
-  const int L = nB + 1;
+  int cur = -1;                      // problem whose dense vector vj holds
+  int nB = 0, L = 1;
+  int64_t koff = 0, noff = 0, soff = 0;
   double vj[8];
 #pragma unroll
-  for (int s = 0; s < 8; ++s) {
-    const int j = l16 + 16 * s;
-    vj[s] = (j < nB) ? v[j] : 0.0;
-  }
+  for (int s = 0; s < 8; ++s) vj[s] = 0.0;
   const int64_t stride = (int64_t)gridDim.x * 16;
-  bool bad = false, nonfinite = false;
   // every group of a wave runs the same number of iterations (the wave's first group
   // decides), so the 16-lane reductions always see all their lanes
   const int64_t first = (int64_t)blockIdx.x * 16 + (grp & ~3);
-  for (int64_t base = first; base < K; base += stride) {
+  for (int64_t base = first; base < Ktot; base += stride) {
     const int64_t blk = base + (grp & 3);
-    const bool active = blk < K;
+    const bool active = blk < Ktot;
+    const int pi = active ? blk_prob[blk] : cur;
+    if (pi != cur) {  // uniform within the 16-lane group
+      const ProbDesc& P = probs[pi];
+      nB = P.nB;
+      L = P.L;
+      koff = P.koff;
+      noff = P.noff;
+      soff = P.soff;
+      const double* v = MODE == 1 ? vbuf + (int64_t)pi * kMaxDense : vbuf + P.noff + P.K * n;
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const int j = l16 + 16 * s;
+        vj[s] = (j < nB) ? v[j] : 0.0;
+      }
+      cur = pi;
+    }
+    const int64_t lb = active ? blk - koff : 0;
     double rhs[8], out[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -196,7 +215,7 @@ k_blocks_solve(int64_t K, int n, int nB, const T* __restrict__ Rblk, const T* __
       out[k] = 0.0;
       if (k < n) {
         double s = 0.0;
-        const T* row = Sc + ((active ? blk : 0) * n + k) * L;
+        const T* row = Sc + soff + (lb * n + k) * L;
         if (active) {
 #pragma unroll
           for (int q = 0; q < 8; ++q) {
@@ -210,6 +229,7 @@ k_blocks_solve(int64_t K, int n, int nB, const T* __restrict__ Rblk, const T* __
     }
     if (active && l16 == 0) {
       const T* Rb = Rblk + blk * n * n;
+      bool bad = false, nonfinite = false;
       if (MODE == 0) {
         double dmax = 0.0;
 #pragma unroll
@@ -223,47 +243,48 @@ k_blocks_solve(int64_t K, int n, int nB, const T* __restrict__ Rblk, const T* __
           }
       }
       block_backsub(Rb, n, rhs, out);
+      double* xo = x + noff + lb * n;
 #pragma unroll
       for (int k = 0; k < 8; ++k)
         if (k < n) {
           if (MODE == 1)
-            p[blk * n + k] += out[k];
+            xo[k] += out[k];
           else
-            p[blk * n + k] = out[k];
+            xo[k] = out[k];
           nonfinite |= !is_finite(out[k]);
         }
+      if (MODE == 0 && status) {
+        if (bad) set_status(status + pi, ST_SINGULAR);
+        if (nonfinite) set_status(status + pi, ST_NONFINITE);
+      }
     }
   }
-  if (status) {
-    if (bad) set_status(status, ST_SINGULAR);
-    if (nonfinite) set_status(status, ST_NONFINITE);
-  }
 }
 
 template <typename T>
-hipError_t launch_backsub_blocks(int64_t K, int n, int nB, const T* Rblk, const T* Sc, double* p,
-                                 int* status, int grid, hipStream_t st) {
-  if (nB + 1 > kMaxDense || n > 8) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_blocks_solve<T, 0>), dim3(grid), dim3(256), 0, st, K, n, nB, Rblk, Sc,
-                     p + K * n, (const double*)nullptr, p, status);
+hipError_t launch_backsub_blocks(const BatchView& bv, const T* Rblk, const T* Sc, double* p, int* status,
+                                 hipStream_t st) {
+  if (bv.max_L > kMaxDense || bv.n > 8) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_blocks_solve<T, 0>), dim3(bv.solve_grid), dim3(256), 0, st, bv.Ktot, bv.n, bv.probs,
+                     bv.blk_prob, Rblk, Sc, (const double*)p, (const double*)nullptr, p, status);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_refine_blocks(int64_t K, int n, int nB, const T* Rblk, const T* Sc, const double* y,
-                                const double* delta_B, double* p, int grid, hipStream_t st) {
-  if (nB + 1 > kMaxDense || n > 8) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_blocks_solve<T, 1>), dim3(grid), dim3(256), 0, st, K, n, nB, Rblk, Sc,
-                     delta_B, y, p, (int*)nullptr);
+hipError_t launch_refine_blocks(const BatchView& bv, const T* Rblk, const T* Sc, const double* y,
+                                const double* delta_B, double* p, hipStream_t st) {
+  if (bv.max_L > kMaxDense || bv.n > 8) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_blocks_solve<T, 1>), dim3(bv.solve_grid), dim3(256), 0, st, bv.Ktot, bv.n, bv.probs,
+                     bv.blk_prob, Rblk, Sc, delta_B, y, p, (int*)nullptr);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_adjoint_blocks(int64_t K, int n, int nB, const T* Rblk, const T* Sc, const double* y,
-                                 const double* uB, double* u, int grid, hipStream_t st) {
-  if (nB + 1 > kMaxDense || n > 8) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_blocks_solve<T, 2>), dim3(grid), dim3(256), 0, st, K, n, nB, Rblk, Sc,
-                     uB, y, u, (int*)nullptr);
+hipError_t launch_adjoint_blocks(const BatchView& bv, const T* Rblk, const T* Sc, const double* y, double* u,
+                                 hipStream_t st) {
+  if (bv.max_L > kMaxDense || bv.n > 8) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_blocks_solve<T, 2>), dim3(bv.solve_grid), dim3(256), 0, st, bv.Ktot, bv.n, bv.probs,
+                     bv.blk_prob, Rblk, Sc, (const double*)u, y, u, (int*)nullptr);
   return hipGetLastError();
 }
 
@@ -271,14 +292,17 @@ hipError_t launch_adjoint_blocks(int64_t K, int n, int nB, const T* Rblk, const 
 // Refinement pass 1: one wave per pack of whole blocks (at most 64 rows), one row per lane.
 //   r = b - A_i p_i - B p_B;  g_i = A_i^T r - lam d_i^2 p_i;  y_i = R_i^{-T} g_i;
 //   per-workgroup partial of  B^T r - sum_i S_i^T y_i.
+// Workgroup w serves problem wg_prob[w] only; its packs are that problem's packs
+// lw*4 + wave, lw*4 + wave + 4*nwg, ... (lw = w - wg0), its partial goes to part[w].
 // ---------------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_refine_pass1(int64_t npacks, const int64_t* __restrict__ pack_blk, int n, int nB,
-               const int64_t* __restrict__ row_off, const T* __restrict__ A, const T* __restrict__ B,
-               int64_t ldb, const T* __restrict__ bvec, const double* __restrict__ d, double lam,
-               const T* __restrict__ Rblk, const T* __restrict__ Sc, const double* __restrict__ p,
-               double* __restrict__ y, double* __restrict__ part, int64_t Kn) {
+k_refine_pass1(const ProbDesc* __restrict__ probs, const int32_t* __restrict__ wg_prob,
+               const int64_t* __restrict__ pack_blk, int n, const int64_t* __restrict__ row_off,
+               const T* __restrict__ A, const T* __restrict__ B, const T* __restrict__ bvec,
+               const double* __restrict__ d, const double* __restrict__ lamv, const T* __restrict__ Rblk,
+               const T* __restrict__ Sc, const double* __restrict__ p, double* __restrict__ y,
+               double* __restrict__ part) {
   __shared__ double pB[kMaxDense];
   __shared__ double rr[4][64];
   __shared__ double prod[4][64][8];
@@ -287,12 +311,18 @@ k_refine_pass1(int64_t npacks, const int64_t* __restrict__ pack_blk, int n, int 
   __shared__ double red[4][kMaxDense];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
-  const int L = nB + 1;
-  for (int j = threadIdx.x; j < nB; j += blockDim.x) pB[j] = p[Kn + j];
+  const int pi = wg_prob[blockIdx.x];
+  const ProbDesc& P = probs[pi];
+  const int nB = P.nB, L = P.L;
+  const int64_t koff = P.koff, noff = P.noff, moff = P.moff, soff = P.soff, ldb = P.ldb;
+  const T* Bp = B + P.boff;
+  const double lam = lamv[pi];
+  for (int j = threadIdx.x; j < nB; j += blockDim.x) pB[j] = p[noff + P.K * n + j];
   __syncthreads();
   double t0 = 0.0, t1 = 0.0;  // partial B^T r - S^T y for columns lane, lane + 64
-  const int64_t nwaves = (int64_t)gridDim.x * 4;
-  for (int64_t pk = (int64_t)blockIdx.x * 4 + wv; pk < npacks; pk += nwaves) {
+  const int64_t lw = blockIdx.x - P.wg0;
+  const int64_t pend = P.pack0 + P.npacks;
+  for (int64_t pk = P.pack0 + lw * 4 + wv; pk < pend; pk += (int64_t)P.nwg * 4) {
     const int64_t b0 = pack_blk[pk];
     const int nb = (int)(pack_blk[pk + 1] - b0);
     const int64_t pr0 = row_off[b0];
@@ -304,14 +334,14 @@ k_refine_pass1(int64_t npacks, const int64_t* __restrict__ pack_blk, int n, int 
     wave_lds_sync();
     if (lane < prows) {
       const int64_t row = pr0 + lane;
-      const int64_t blk = b0 + rowblk[wv][lane];
+      const int64_t lb = b0 - koff + rowblk[wv][lane];
       double a[8], dot = 0.0;
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
         a[c] = (c < n) ? (double)A[row * n + c] : 0.0;
-        if (c < n) dot += a[c] * p[blk * n + c];
+        if (c < n) dot += a[c] * p[noff + lb * n + c];
       }
-      const T* Brow = B + row * ldb;
+      const T* Brow = Bp + (row - moff) * ldb;
       double d0 = 0.0, d1 = 0.0;
       int j = 0;
       for (; j + 1 < nB; j += 2) {
@@ -328,7 +358,7 @@ k_refine_pass1(int64_t npacks, const int64_t* __restrict__ pack_blk, int n, int 
     wave_lds_sync();
     // B^T r over the pack's rows (coalesced across lanes)
     for (int r = 0; r < prows; ++r) {
-      const T* Brow = B + (pr0 + r) * ldb;
+      const T* Brow = Bp + (pr0 + r - moff) * ldb;
       const double rv = rr[wv][r];
       if (lane < nB) t0 += (double)Brow[lane] * rv;
       if (lane + 64 < nB) t1 += (double)Brow[lane + 64] * rv;
@@ -336,6 +366,7 @@ k_refine_pass1(int64_t npacks, const int64_t* __restrict__ pack_blk, int n, int 
     // per block: g_i, y_i
     if (lane < nb) {
       const int64_t blk = b0 + lane;
+      const int64_t lb = blk - koff;
       const int lo = (int)(row_off[blk] - pr0), hi = (int)(row_off[blk + 1] - pr0);
       double g[8], yy[8];
 #pragma unroll
@@ -350,8 +381,8 @@ k_refine_pass1(int64_t npacks, const int64_t* __restrict__ pack_blk, int n, int 
 #pragma unroll
       for (int c = 0; c < 8; ++c)
         if (c < n) {
-          const double dc = d[blk * n + c];
-          g[c] -= lam * dc * dc * p[blk * n + c];
+          const double dc = d[noff + lb * n + c];
+          g[c] -= lam * dc * dc * p[noff + lb * n + c];
         }
       block_fwdsub_T(Rblk + blk * n * n, n, g, yy);
 #pragma unroll
@@ -364,7 +395,7 @@ k_refine_pass1(int64_t npacks, const int64_t* __restrict__ pack_blk, int n, int 
     wave_lds_sync();
     // S^T y over the pack's blocks
     for (int k = 0; k < nb; ++k) {
-      const T* Srow = Sc + (b0 + k) * n * L;
+      const T* Srow = Sc + soff + (b0 - koff + k) * n * L;
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
         if (c < n) {
@@ -380,52 +411,59 @@ k_refine_pass1(int64_t npacks, const int64_t* __restrict__ pack_blk, int n, int 
   red[wv][lane + 64] = t1;
   __syncthreads();
   for (int j = threadIdx.x; j < nB; j += blockDim.x)
-    part[(int64_t)blockIdx.x * nB + j] = ((red[0][j] + red[1][j]) + red[2][j]) + red[3][j];
+    part[(int64_t)blockIdx.x * kMaxDense + j] = ((red[0][j] + red[1][j]) + red[2][j]) + red[3][j];
 }
 
 template <typename T>
-hipError_t launch_refine_residual(int64_t npacks, const int64_t* pack_blk, int64_t K, int n, int nB,
-                                  const int64_t* row_off, const T* A, const T* B, int64_t ldb, const T* b,
-                                  const double* d, double lam, const T* Rblk, const T* Sc,
-                                  const double* p, double* y, double* part, int grid, hipStream_t st) {
-  if (nB + 1 > kMaxDense || n > 8) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_refine_pass1<T>), dim3(grid), dim3(256), 0, st, npacks, pack_blk, n, nB, row_off,
-                     A, B, ldb, b, d, lam, Rblk, Sc, p, y, part, K * n);
+hipError_t launch_refine_residual(const BatchView& bv, const T* A, const T* B, const T* b, const double* d,
+                                  const T* Rblk, const T* Sc, const double* p, double* y, double* part,
+                                  hipStream_t st) {
+  if (bv.max_L > kMaxDense || bv.n > 8) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_refine_pass1<T>), dim3(bv.nwg), dim3(256), 0, st, bv.probs, bv.wg_prob, bv.pack_blk,
+                     bv.n, bv.row_off, A, B, b, d, bv.lam, Rblk, Sc, p, y, part);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------------
-// Refinement pass 2 (one workgroup): g_B = sum of the partials (fixed order) - lam d_B^2 p_B,
-// then y_B = R_B^{-T} g_B and delta_B = R_B^{-1} y_B by one wave; p_B += delta_B.
+// Refinement pass 2 (one workgroup per problem): g_B = sum of the problem's workgroup
+// partials (fixed order) - lam d_B^2 p_B, then y_B = R_B^{-T} g_B and delta_B = R_B^{-1} y_B
+// by one wave; p_B += delta_B.
+// ADJ = false: refinement (delta_B -> delta[pi * kMaxDense ..]).
+// ADJ = true : adjoint (rhs = g_B + sum of partials; the solution -> u_B in out, laid out
+//              like p; p untouched).
 // ---------------------------------------------------------------------------------
-// ADJ = false: refinement (rhs = sum(part) - lam d_B^2 p_B; p_B += delta, delta -> delta_B).
-// ADJ = true : adjoint (rhs = g_B + sum(part); the solution -> delta_B, p untouched).
 template <typename T, bool ADJ>
 __global__ void __launch_bounds__(1024)
-k_refine_dense(int nparts, int nB, const double* __restrict__ part, const T* __restrict__ RB,
-               const double* __restrict__ dvec, double lam, double* __restrict__ p, int64_t off,
-               double* __restrict__ delta_B, const double* __restrict__ gB) {
+k_refine_dense(const ProbDesc* __restrict__ probs, int n, const double* __restrict__ part,
+               const T* __restrict__ RBall, const double* __restrict__ dvec, const double* __restrict__ lamv,
+               double* __restrict__ p, double* __restrict__ out, const double* __restrict__ gvec) {
   __shared__ float Rs[sizeof(T) == 4 ? kMaxDense * kMaxDense : 1];
   __shared__ double Rsd[sizeof(T) == 8 ? kMaxDense * kMaxDense : 1];
   __shared__ double acc[8][kMaxDense];
-  const int L = nB + 1;
+  const int pi = blockIdx.x;
+  const ProbDesc& P = probs[pi];
+  const int nB = P.nB, L = P.L;
+  const int64_t off = P.noff + P.K * n;
+  const double* pp = part + (int64_t)P.wg0 * kMaxDense;
+  const int nparts = P.nwg;
   const int t = threadIdx.x;
   const int j = t & 127, q = t >> 7;
   double s = 0.0;
   if (j < nB)
-    for (int w = q; w < nparts; w += 8) s += part[(int64_t)w * nB + j];
+    for (int w = q; w < nparts; w += 8) s += pp[(int64_t)w * kMaxDense + j];
   acc[q][j] = s;
-  stage_dense<T>(RB, L, Rs, Rsd, t, blockDim.x);
+  stage_dense<T>(RBall + P.rboff, L, Rs, Rsd, t, blockDim.x);
   __syncthreads();
   if (t >= 64) return;
   const int lane = t;
+  const double lam = ADJ ? 0.0 : lamv[pi];
   double v0 = 0.0, v1 = 0.0;
   if (lane < nB) {
     double g = 0.0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) g += acc[k][lane];
     if (ADJ) {
-      v0 = gB[lane] + g;
+      v0 = gvec[off + lane] + g;
     } else {
       const double dj = dvec[off + lane];
       v0 = g - lam * dj * dj * p[off + lane];
@@ -436,7 +474,7 @@ k_refine_dense(int nparts, int nB, const double* __restrict__ part, const T* __r
 #pragma unroll
     for (int k = 0; k < 8; ++k) g += acc[k][lane + 64];
     if (ADJ) {
-      v1 = gB[lane + 64] + g;
+      v1 = gvec[off + lane + 64] + g;
     } else {
       const double dj = dvec[off + lane + 64];
       v1 = g - lam * dj * dj * p[off + lane + 64];
@@ -444,49 +482,49 @@ k_refine_dense(int nparts, int nB, const double* __restrict__ part, const T* __r
   }
   wave_fwd_T<T>(Rs, Rsd, L, nB, lane, v0, v1);
   wave_bwd<T>(Rs, Rsd, L, nB, lane, v0, v1);
+  double* o = ADJ ? out + off : out + (int64_t)pi * kMaxDense;
   if (lane < nB) {
-    delta_B[lane] = v0;
+    o[lane] = v0;
     if (!ADJ) p[off + lane] += v0;
   }
   if (lane + 64 < nB) {
-    delta_B[lane + 64] = v1;
+    o[lane + 64] = v1;
     if (!ADJ) p[off + lane + 64] += v1;
   }
 }
 
 template <typename T>
-hipError_t launch_refine_dense(int nparts, int nB, const double* part, const T* RB, const double* dvec,
-                               double lam, double* p, int64_t off, double* delta_B, hipStream_t st) {
-  if (nB + 1 > kMaxDense) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_refine_dense<T, false>), dim3(1), dim3(1024), 0, st, nparts, nB, part, RB, dvec,
-                     lam, p, off, delta_B, (const double*)nullptr);
+hipError_t launch_refine_dense(const BatchView& bv, const double* part, const T* RB, const double* dvec,
+                               double* p, double* delta_B, hipStream_t st) {
+  if (bv.max_L > kMaxDense) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_refine_dense<T, false>), dim3(bv.P), dim3(1024), 0, st, bv.probs, bv.n, part, RB, dvec,
+                     bv.lam, p, delta_B, (const double*)nullptr);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_adjoint_dense(int nparts, int nB, const double* part, const T* RB, const double* gB,
-                                double* uB, hipStream_t st) {
-  if (nB + 1 > kMaxDense) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_refine_dense<T, true>), dim3(1), dim3(1024), 0, st, nparts, nB, part, RB,
-                     (const double*)nullptr, 0.0, (double*)nullptr, (int64_t)0, uB, gB);
+hipError_t launch_adjoint_dense(const BatchView& bv, const double* part, const T* RB, const double* g, double* u,
+                                hipStream_t st) {
+  if (bv.max_L > kMaxDense) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_refine_dense<T, true>), dim3(bv.P), dim3(1024), 0, st, bv.probs, bv.n, part, RB,
+                     (const double*)nullptr, bv.lam, (double*)nullptr, u, g);
   return hipGetLastError();
 }
 
-#define QRK_INST(T)                                                                                \
-  template hipError_t launch_backsub_dense<T>(const T*, int, double*, int64_t, int*, hipStream_t);  \
-  template hipError_t launch_backsub_blocks<T>(int64_t, int, int, const T*, const T*, double*, int*, \
-                                               int, hipStream_t);                                   \
-  template hipError_t launch_refine_residual<T>(int64_t, const int64_t*, int64_t, int, int,          \
-                                                const int64_t*, const T*, const T*, int64_t,         \
-                                                const T*, const double*, double, const T*, const T*, \
-                                                const double*, double*, double*, int, hipStream_t);  \
-  template hipError_t launch_refine_dense<T>(int, int, const double*, const T*, const double*,       \
-                                             double, double*, int64_t, double*, hipStream_t);       \
-  template hipError_t launch_refine_blocks<T>(int64_t, int, int, const T*, const T*, const double*,  \
-                                              const double*, double*, int, hipStream_t);               \
-  template hipError_t launch_adjoint_blocks<T>(int64_t, int, int, const T*, const T*, const double*, \
-                                               const double*, double*, int, hipStream_t);             \
-  template hipError_t launch_adjoint_dense<T>(int, int, const double*, const T*, const double*,      \
+#define QRK_INST(T)                                                                                      \
+  template hipError_t launch_backsub_dense<T>(const BatchView&, const T*, double*, int*, hipStream_t);     \
+  template hipError_t launch_backsub_blocks<T>(const BatchView&, const T*, const T*, double*, int*,        \
+                                               hipStream_t);                                             \
+  template hipError_t launch_refine_residual<T>(const BatchView&, const T*, const T*, const T*,             \
+                                                const double*, const T*, const T*, const double*, double*, \
+                                                double*, hipStream_t);                                   \
+  template hipError_t launch_refine_dense<T>(const BatchView&, const double*, const T*, const double*,     \
+                                             double*, double*, hipStream_t);                             \
+  template hipError_t launch_refine_blocks<T>(const BatchView&, const T*, const T*, const double*,         \
+                                              const double*, double*, hipStream_t);                      \
+  template hipError_t launch_adjoint_blocks<T>(const BatchView&, const T*, const T*, const double*, double*, \
+                                               hipStream_t);                                             \
+  template hipError_t launch_adjoint_dense<T>(const BatchView&, const double*, const T*, const double*,     \
                                               double*, hipStream_t);
 QRK_INST(float)
 QRK_INST(double)

@@ -3,7 +3,7 @@
 // workgroup streams a contiguous range of rows into its own running triangle (a flat
 // tree inside the workgroup), and the triangles are then merged by the same kernel
 // level by level.  The damping rows sqrt(lam) D_B are already triangular, so they are
-// simply the starting triangle of workgroup 0.
+// simply the starting triangle of workgroup 0 (sqrt(lam) d_B, lam read on the device).
 //
 // Merge of a tile of KT rows into the running triangle R (Householder, Section 2):
 // for column j, the reflector acting on [R_jj; tile column j] has the form [1; w] so
@@ -18,7 +18,7 @@ namespace qrk {
 template <typename T, int KT, int NT>
 __global__ void __launch_bounds__(NT)
 k_tsqr_stream(const T* __restrict__ X, int64_t ldx, int64_t nrows, int L, int64_t rows_per_wg,
-              const double* __restrict__ dB, double sqrt_lam, T* __restrict__ Rout) {
+              const double* __restrict__ dB, const double* __restrict__ lam, T* __restrict__ Rout) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int ldc = L + 1;
   T* Rc = reinterpret_cast<T*>(smem_raw);                       // [L][ldc], column-major per thread
@@ -31,7 +31,7 @@ k_tsqr_stream(const T* __restrict__ X, int64_t ldx, int64_t nrows, int L, int64_
 
   if (own) {
     for (int j = 0; j < L; ++j) Rmy[j] = T(0);
-    if (dB != nullptr && blockIdx.x == 0 && c < L - 1) Rmy[c] = (T)(sqrt_lam * dB[c]);
+    if (dB != nullptr && blockIdx.x == 0 && c < L - 1) Rmy[c] = (T)(sqrt(*lam) * dB[c]);
   }
   __syncthreads();
 
@@ -101,13 +101,13 @@ k_tsqr_stream(const T* __restrict__ X, int64_t ldx, int64_t nrows, int L, int64_
 
 template <typename T>
 hipError_t launch_tsqr_stream(const T* X, int64_t ldx, int64_t nrows, int L, int64_t rows_per_wg,
-                              int grid, const double* dB, double sqrt_lam, T* Rout, hipStream_t st) {
+                              int grid, const double* dB, const double* lam, T* Rout, hipStream_t st) {
   constexpr int KT = 32;
   const int rc_elems = ((L * (L + 1) + 3) / 4) * 4;
   const size_t smem = sizeof(T) * (size_t)(rc_elems + 2 * KT + 4);
   if (L <= 64) {
     hipLaunchKernelGGL((k_tsqr_stream<T, KT, 64>), dim3(grid), dim3(64), smem, st, X, ldx, nrows, L,
-                       rows_per_wg, dB, sqrt_lam, Rout);
+                       rows_per_wg, dB, lam, Rout);
   } else if (L <= 128) {
     if (smem > 65536) {
       hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tsqr_stream<T, KT, 128>),
@@ -115,7 +115,7 @@ hipError_t launch_tsqr_stream(const T* X, int64_t ldx, int64_t nrows, int L, int
       if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL((k_tsqr_stream<T, KT, 128>), dim3(grid), dim3(128), smem, st, X, ldx, nrows,
-                       L, rows_per_wg, dB, sqrt_lam, Rout);
+                       L, rows_per_wg, dB, lam, Rout);
   } else {
     return hipErrorInvalidValue;
   }
@@ -123,8 +123,8 @@ hipError_t launch_tsqr_stream(const T* X, int64_t ldx, int64_t nrows, int L, int
 }
 
 template hipError_t launch_tsqr_stream<float>(const float*, int64_t, int64_t, int, int64_t, int,
-                                              const double*, double, float*, hipStream_t);
+                                              const double*, const double*, float*, hipStream_t);
 template hipError_t launch_tsqr_stream<double>(const double*, int64_t, int64_t, int, int64_t, int,
-                                               const double*, double, double*, hipStream_t);
+                                               const double*, const double*, double*, hipStream_t);
 
 }  // namespace qrk

@@ -1,4 +1,5 @@
-// Dispatch of the float32 tall-skinny QR on the matrix cores (see tsqr_mfma.hpp).
+// Dispatch of the float32 tall-skinny QR on the matrix cores (see tsqr_mfma.hpp): one launch
+// per column-block count present in the batch.
 #include "qrk_launch.hpp"
 #include "tsqr_mfma.hpp"
 
@@ -6,13 +7,19 @@ namespace qrk {
 
 // One instantiation per column-block count lives in tsqr_mfma_ncb<N>.hip.
 template <int NCB>
-hipError_t launch_tsqr_mfma_n(const float* X, int64_t ldx, int64_t nrows, int L, int64_t rows_per_leaf,
-                              int nleaves, const double* dB, double sqrt_lam, float* slots,
-                              int* counters, float* Rout, hipStream_t st);
+hipError_t launch_tsqr_mfma_n(int leaf_begin, int nleaves_cls, const int32_t* leaf_prob, const int32_t* leaf_idx,
+                              const ProbDesc* probs, int n, const float* Red, const double* d, const double* lam,
+                              float* slots, int* counters, float* RB, hipStream_t st);
 
-__global__ void k_zero_ints(int* __restrict__ p, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_zero_ints(int* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
+}
+
+hipError_t launch_zero_ints(int* p, int64_t n, hipStream_t st) {
+  if (n < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_ints, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n);
+  return hipGetLastError();
 }
 
 int tsqr_mfma_slot_floats(int L) {
@@ -20,25 +27,23 @@ int tsqr_mfma_slot_floats(int L) {
   return ncb * (ncb + 1) / 2 * 256;
 }
 
-hipError_t launch_tsqr_mfma(const float* X, int64_t ldx, int64_t nrows, int L, int nleaves,
-                            const double* dB, double sqrt_lam, float* slots, int* counters,
-                            float* Rout, hipStream_t st) {
-  if (L < 1 || L > 128 || nleaves < 1) return hipErrorInvalidValue;
-  const int nctr = 2 * nleaves + 2;
-  hipLaunchKernelGGL(k_zero_ints, dim3((nctr + 255) / 256), dim3(256), 0, st, counters, nctr);
-  int64_t rows_per_leaf = (nrows + nleaves - 1) / nleaves;
-  if (rows_per_leaf < 1) rows_per_leaf = 1;
-  switch ((L + 15) / 16) {
-    case 1: return launch_tsqr_mfma_n<1>(X, ldx, nrows, L, rows_per_leaf, nleaves, dB, sqrt_lam, slots, counters, Rout, st);
-    case 2: return launch_tsqr_mfma_n<2>(X, ldx, nrows, L, rows_per_leaf, nleaves, dB, sqrt_lam, slots, counters, Rout, st);
-    case 3: return launch_tsqr_mfma_n<3>(X, ldx, nrows, L, rows_per_leaf, nleaves, dB, sqrt_lam, slots, counters, Rout, st);
-    case 4: return launch_tsqr_mfma_n<4>(X, ldx, nrows, L, rows_per_leaf, nleaves, dB, sqrt_lam, slots, counters, Rout, st);
-    case 5: return launch_tsqr_mfma_n<5>(X, ldx, nrows, L, rows_per_leaf, nleaves, dB, sqrt_lam, slots, counters, Rout, st);
-    case 6: return launch_tsqr_mfma_n<6>(X, ldx, nrows, L, rows_per_leaf, nleaves, dB, sqrt_lam, slots, counters, Rout, st);
-    case 7: return launch_tsqr_mfma_n<7>(X, ldx, nrows, L, rows_per_leaf, nleaves, dB, sqrt_lam, slots, counters, Rout, st);
-    case 8: return launch_tsqr_mfma_n<8>(X, ldx, nrows, L, rows_per_leaf, nleaves, dB, sqrt_lam, slots, counters, Rout, st);
+hipError_t launch_tsqr_mfma(const int* cls_begin, const int* cls_count, const int32_t* leaf_prob,
+                            const int32_t* leaf_idx, const ProbDesc* probs, int n, const float* Red,
+                            const double* d, const double* lam, float* slots, int* counters, int64_t nctr,
+                            float* RB, hipStream_t st) {
+  if (nctr < 1) return hipErrorInvalidValue;
+  hipError_t e = launch_zero_ints(counters, nctr, st);
+  for (int c = 8; c >= 1 && e == hipSuccess; --c) {  // widest (slowest) problems first
+    const int b = cls_begin[c], k = cls_count[c];
+    if (k == 0) continue;
+#define QRK_TS(N)                                                                                            \
+  case N:                                                                                                    \
+    e = launch_tsqr_mfma_n<N>(b, k, leaf_prob, leaf_idx, probs, n, Red, d, lam, slots, counters, RB, st); \
+    break;
+    switch (c) { QRK_TS(1) QRK_TS(2) QRK_TS(3) QRK_TS(4) QRK_TS(5) QRK_TS(6) QRK_TS(7) QRK_TS(8) }
+#undef QRK_TS
   }
-  return hipErrorInvalidValue;
+  return e;
 }
 
 }  // namespace qrk

@@ -4,13 +4,16 @@
 // all reduced rows of the block-angular step stacked with the damping rows
 // sqrt(lam) D_B, with the right-hand side carried as the last column.
 //
-// Organisation (communication-avoiding tall-skinny QR):
-//   * every wave is a leaf: it streams a contiguous range of rows, a tile of 16*NRB rows
-//     at a time, into its own running upper triangle R (a flat tree inside the wave);
-//   * the leaf triangles are then merged pairwise, QR([R_left; R_right]), in the same
-//     launch: the second wave of a pair to finish performs the merge (arrival counted
-//     with a device-scope atomic), so no wave ever waits for another;
-//   * the root is written out row-major (L x L).
+// Organisation (communication-avoiding tall-skinny QR, for a batch of problems with the
+// same number of 16-column blocks at once):
+//   * every wave is a leaf of one problem: it streams a contiguous range of that problem's
+//     rows, a tile of 16*NRB rows at a time, into its own running upper triangle R (a flat
+//     tree inside the wave);
+//   * the leaf triangles of each problem are then merged pairwise, QR([R_left; R_right]),
+//     in the same launch: the second wave of a pair to finish performs the merge (arrival
+//     counted with a device-scope atomic), so no wave ever waits for another, and the trees
+//     of different problems proceed independently;
+//   * each problem's root is written out row-major (L x L).
 //
 // Merging a tile X into R uses blocked Householder with the compact WY form (paper
 // Section 2, compressed WY: Q = I - V T V^T; the paper writes I + Y T Y^T, the sign of
@@ -31,6 +34,7 @@
 
 #include <type_traits>
 
+#include "qrk_batch.hpp"
 #include "qrk_device.hpp"
 
 namespace qrk {
@@ -258,16 +262,31 @@ __device__ __forceinline__ void merge_stored_tri(f4 (&R)[Tri<NCB>::count], const
   merge_tile<NCB, NCB, true>(R, X, 0, lds, lane);
 }
 
+// One launch per column-block count NCB: wave w is global leaf leaf_begin + w.  Leaf li of
+// problem p streams rows [li * rows_per_leaf, ...) of the problem's reduced rows into its
+// triangle (leaf 0 starts from diag(sqrt(lam_p) d_B)); the leaves of each problem are then
+// merged pairwise in the same launch (the problem's own slots and arrival counters) and the
+// root is written row-major to the problem's R_B | c_B.
 template <int NCB, int NRB>
 __global__ void __launch_bounds__(256)
-k_tsqr_mfma(const float* __restrict__ Xg, int64_t ldx, int64_t nrows, int L, int64_t rows_per_leaf,
-            int nleaves, const double* __restrict__ dB, double sqrt_lam, float* __restrict__ slots,
-            int* __restrict__ counters, float* __restrict__ Rout) {
+k_tsqr_mfma(int leaf_begin, int nleaves_cls, const int32_t* __restrict__ leaf_prob,
+            const int32_t* __restrict__ leaf_idx, const ProbDesc* __restrict__ probs, int n,
+            const float* __restrict__ Red, const double* __restrict__ d, const double* __restrict__ lamv,
+            float* __restrict__ slots, int* __restrict__ counters, float* __restrict__ RBall) {
   __shared__ float lds_all[4][kWaveLds];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
-  const int leaf = blockIdx.x * 4 + wv;
-  if (leaf >= nleaves) return;
+  const int wl = blockIdx.x * 4 + wv;
+  if (wl >= nleaves_cls) return;
+  const int pi = leaf_prob[leaf_begin + wl];
+  const int leaf = leaf_idx[leaf_begin + wl];
+  const ProbDesc& P = probs[pi];
+  const float* Xg = Red + P.redoff;
+  const int64_t ldx = P.ldr;
+  const int64_t nrows = P.M;
+  const int L = P.L;
+  const int nleaves = P.leaves;
+  const int64_t rows_per_leaf = P.rows_per_leaf;
   float* lds = lds_all[wv];
   const int g = lane >> 4;
   const int c = lane & 15;
@@ -278,13 +297,15 @@ k_tsqr_mfma(const float* __restrict__ Xg, int64_t ldx, int64_t nrows, int L, int
   f4 R[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) R[t] = f4{0.f, 0.f, 0.f, 0.f};
-  if (leaf == 0 && dB != nullptr) {
+  if (leaf == 0) {
+    const double* dB = d + P.noff + P.K * n;
+    const double sqrt_lam = sqrt(lamv[pi]);
     static_for<0, NCB>([&](auto PP) {
-      constexpr int P = decltype(PP)::value;
-      const int col = 16 * P + c;
+      constexpr int Q = decltype(PP)::value;
+      const int col = 16 * Q + c;
 #pragma unroll
       for (int v = 0; v < 4; ++v)
-        if (4 * g + v == c && col < L - 1) R[Tri<NCB>::idx(P, P)][v] = (float)(sqrt_lam * dB[col]);
+        if (4 * g + v == c && col < L - 1) R[Tri<NCB>::idx(Q, Q)][v] = (float)(sqrt_lam * dB[col]);
     });
   }
 
@@ -307,49 +328,52 @@ k_tsqr_mfma(const float* __restrict__ Xg, int64_t ldx, int64_t nrows, int L, int
     merge_tile<NCB, NRB, false>(R, X, 0, lds, lane);
   }
 
-  // ---- pairwise merges up the tree, in the same launch --------------------------------------
-  int n = nleaves;
+  // ---- pairwise merges up the problem's tree, in the same launch ----------------------------
+  float* pslots = slots + P.slot0;
+  int* pctr = counters + P.ctr0;
+  int nl = nleaves;
   int slot = leaf;
   int64_t base = 0;   // first slot of the current level
   int64_t cbase = 0;  // first counter of the current level
-  while (n > 1) {
+  while (nl > 1) {
     const int sib = slot ^ 1;
     const int parent = slot >> 1;
-    const int nn = (n + 1) >> 1;
-    if (sib >= n) {  // no sibling at this level: carry the triangle up unchanged
-      base += n;
+    const int nn = (nl + 1) >> 1;
+    if (sib >= nl) {  // no sibling at this level: carry the triangle up unchanged
+      base += nl;
       cbase += nn;
       slot = parent;
-      n = nn;
+      nl = nn;
       continue;
     }
-    store_tri<NCB>(slots + (base + slot) * SLOT, R, lane);
+    store_tri<NCB>(pslots + (base + slot) * SLOT, R, lane);
     __threadfence();
     int old = 0;
-    if (lane == 0) old = atomicAdd(&counters[cbase + parent], 1);
+    if (lane == 0) old = atomicAdd(&pctr[cbase + parent], 1);
     old = __builtin_amdgcn_readfirstlane(old);
     if (old == 0) return;  // the sibling is still running; it will merge
     __threadfence();
     const int left = slot & ~1;
-    load_tri<NCB>(slots + (base + left) * SLOT, R, lane);
-    merge_stored_tri<NCB>(R, slots + (base + left + 1) * SLOT, lds, lane);
-    base += n;
+    load_tri<NCB>(pslots + (base + left) * SLOT, R, lane);
+    merge_stored_tri<NCB>(R, pslots + (base + left + 1) * SLOT, lds, lane);
+    base += nl;
     cbase += nn;
     slot = parent;
-    n = nn;
+    nl = nn;
   }
 
   // ---- root: row-major L x L ----------------------------------------------------------------
+  float* Rout = RBall + P.rboff;
   static_for<0, NCB>([&](auto PP) {
-    constexpr int P = decltype(PP)::value;
+    constexpr int Q = decltype(PP)::value;
     static_for<0, NCB>([&](auto QQ) {
       constexpr int q = decltype(QQ)::value;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = 16 * P + 4 * g + v;
+        const int row = 16 * Q + 4 * g + v;
         const int col = 16 * q + c;
         float val = 0.f;
-        if constexpr (q >= P) val = (col >= row) ? R[Tri<NCB>::idx(P, q)][v] : 0.f;
+        if constexpr (q >= Q) val = (col >= row) ? R[Tri<NCB>::idx(Q, q)][v] : 0.f;
         if (row < L && col < L) Rout[(int64_t)row * L + col] = val;
       }
     });
@@ -357,12 +381,12 @@ k_tsqr_mfma(const float* __restrict__ Xg, int64_t ldx, int64_t nrows, int L, int
 }
 
 template <int NCB, int NRB>
-hipError_t launch_tsqr_mfma_ncb(const float* X, int64_t ldx, int64_t nrows, int L, int64_t rows_per_leaf,
-                                int nleaves, const double* dB, double sqrt_lam, float* slots,
-                                int* counters, float* Rout, hipStream_t st) {
-  const int grid = (nleaves + 3) / 4;
-  hipLaunchKernelGGL((k_tsqr_mfma<NCB, NRB>), dim3(grid), dim3(256), 0, st, X, ldx, nrows, L,
-                     rows_per_leaf, nleaves, dB, sqrt_lam, slots, counters, Rout);
+hipError_t launch_tsqr_mfma_ncb(int leaf_begin, int nleaves_cls, const int32_t* leaf_prob, const int32_t* leaf_idx,
+                                const ProbDesc* probs, int n, const float* Red, const double* d, const double* lam,
+                                float* slots, int* counters, float* RB, hipStream_t st) {
+  const int grid = (nleaves_cls + 3) / 4;
+  hipLaunchKernelGGL((k_tsqr_mfma<NCB, NRB>), dim3(grid), dim3(256), 0, st, leaf_begin, nleaves_cls, leaf_prob,
+                     leaf_idx, probs, n, Red, d, lam, slots, counters, RB);
   return hipGetLastError();
 }
 

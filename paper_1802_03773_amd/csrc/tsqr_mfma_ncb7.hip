@@ -5,17 +5,17 @@
 namespace qrk {
 
 template <int NCB>
-hipError_t launch_tsqr_mfma_n(const float* X, int64_t ldx, int64_t nrows, int L, int64_t rows_per_leaf,
-                              int nleaves, const double* dB, double sqrt_lam, float* slots,
-                              int* counters, float* Rout, hipStream_t st);
+hipError_t launch_tsqr_mfma_n(int leaf_begin, int nleaves_cls, const int32_t* leaf_prob, const int32_t* leaf_idx,
+                              const ProbDesc* probs, int n, const float* Red, const double* d, const double* lam,
+                              float* slots, int* counters, float* RB, hipStream_t st);
 
 template <>
-hipError_t launch_tsqr_mfma_n<7>(const float* X, int64_t ldx, int64_t nrows, int L,
-                                 int64_t rows_per_leaf, int nleaves, const double* dB,
-                                 double sqrt_lam, float* slots, int* counters, float* Rout,
+hipError_t launch_tsqr_mfma_n<7>(int leaf_begin, int nleaves_cls, const int32_t* leaf_prob,
+                                 const int32_t* leaf_idx, const ProbDesc* probs, int n, const float* Red,
+                                 const double* d, const double* lam, float* slots, int* counters, float* RB,
                                  hipStream_t st) {
-  return launch_tsqr_mfma_ncb<7, 4>(X, ldx, nrows, L, rows_per_leaf, nleaves, dB, sqrt_lam, slots,
-                                      counters, Rout, st);
+  return launch_tsqr_mfma_ncb<7, 4>(leaf_begin, nleaves_cls, leaf_prob, leaf_idx, probs, n, Red, d, lam, slots,
+                                     counters, RB, st);
 }
 
 }  // namespace qrk

@@ -35,6 +35,11 @@ _SIGS = {
     "qrk_create_blockangular": (_c_i32, [_c_i32, _c_i32, _c_i32, _c_i64p, _c_i64, _c_i32, _c_i32,
                                          ctypes.POINTER(_c_vp)]),
     "qrk_factor_blockangular": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_dbl, _c_vp]),
+    "qrk_create_blockangular_batched": (_c_i32, [_c_i32, _c_i32, _c_i32p, _c_i32p, _c_i64p, _c_i32, _c_i32,
+                                                 ctypes.POINTER(_c_vp)]),
+    "qrk_factor_blockangular_batched": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp]),
+    "qrk_status_get_problems": (_c_i32, [_c_vp, _c_i32p, _c_vp]),
+    "qrk_autotune_blockangular": (_c_i32, [_c_vp, ctypes.POINTER(_c_dbl), _c_vp]),
     "qrk_create_banded": (_c_i32, [_c_i64, _c_i64, _c_i32, _c_i32, ctypes.POINTER(_c_vp)]),
     "qrk_create_banded_batched": (_c_i32, [_c_i32, _c_i64, _c_i64, _c_i32, _c_i32, ctypes.POINTER(_c_vp)]),
     "qrk_factor_banded": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_dbl, _c_vp]),
@@ -196,6 +201,13 @@ class BlockAngularSolver(Factor):
     def set_tsqr_shape(self, leaves: int = 0, fanin: int = 0):
         _check(lib().qrk_set_tsqr_shape(self._h, int(leaves), int(fanin)), "qrk_set_tsqr_shape")
 
+    def autotune(self, stream=None) -> float:
+        """Time a few dense-part leaf shapes on the last factor call's inputs; keep the best."""
+        scale = _c_dbl(0.0)
+        _check(lib().qrk_autotune_blockangular(self._h, ctypes.byref(scale), _stream_ptr(stream)),
+               "qrk_autotune_blockangular")
+        return float(scale.value)
+
     def factor(self, A, B, b, d, lam: float, stream=None):
         torch = _torch()
         td = _torch_dtype(self.qdtype)
@@ -257,6 +269,59 @@ class BlockAngularSolver(Factor):
                                        ptr("dd", torch.float64), _stream_ptr(stream)),
                "qrk_solve_adjoint")
         return out
+
+
+class BlockAngularBatch(Factor):
+    """P independent block-angular problems with the same block width n, factored and solved
+    in the same launches.  Problem p: K[p] blocks, nB[p] dense columns.  Stacked arrays,
+    problem after problem: A [M_tot, n], b [M_tot]; B flat, problem p's M_p x nB[p] rows
+    packed with row stride nB[p]; d and p [sum_p N_p]; lam [P] float64 on the device."""
+
+    def __init__(self, K, nB, row_off, n: int, dtype="float32", mode: str = "plain"):
+        K = np.ascontiguousarray(np.asarray(K, dtype=np.int32))
+        nB = np.ascontiguousarray(np.asarray(nB, dtype=np.int32))
+        row_off = np.ascontiguousarray(np.asarray(row_off, dtype=np.int64))
+        if K.shape != nB.shape or row_off.shape[0] != int(K.sum()) + 1:
+            raise ValueError("K, nB and row_off do not describe the same batch")
+        qd = QRK_F32 if str(dtype).endswith("float32") else QRK_F64
+        qm = {"plain": QRK_PLAIN, "bf16x3": QRK_BF16X3}[mode]
+        h = _c_vp()
+        _check(lib().qrk_create_blockangular_batched(int(K.shape[0]), int(n), K.ctypes.data_as(_c_i32p),
+                                                     nB.ctypes.data_as(_c_i32p), row_off.ctypes.data_as(_c_i64p),
+                                                     qd, qm, ctypes.byref(h)), "qrk_create_blockangular_batched")
+        self.P, self.n = int(K.shape[0]), int(n)
+        self.K, self.nB, self.row_off = K, nB, row_off
+        koff = np.concatenate([[0], np.cumsum(K)])
+        self.M_p = row_off[koff[1:]] - row_off[koff[:-1]]
+        self.N_p = K.astype(np.int64) * self.n + nB
+        self.M = int(row_off[-1])
+        self.B_elems = int(np.sum(self.M_p * nB))
+        super().__init__(h, "blockangular_batch", qd, int(self.N_p.sum()))
+        self.mode = mode
+
+    def factor(self, A, B, b, d, lam, stream=None):
+        torch = _torch()
+        td = _torch_dtype(self.qdtype)
+        pB = _dev_ptr(B, td, "B", self.B_elems) if self.B_elems > 0 else (
+            _dev_ptr(B, td, "B") if B is not None else None)
+        _check(lib().qrk_factor_blockangular_batched(
+            self._h, _dev_ptr(A, td, "A", self.M * self.n), pB, _dev_ptr(b, td, "b", self.M),
+            _dev_ptr(d, torch.float64, "d", self.N), _dev_ptr(lam, torch.float64, "lam", self.P),
+            _stream_ptr(stream)), "qrk_factor_blockangular_batched")
+        self._keep = (A, B, b, d, lam)
+        return self
+
+    def autotune(self, stream=None) -> float:
+        scale = _c_dbl(0.0)
+        _check(lib().qrk_autotune_blockangular(self._h, ctypes.byref(scale), _stream_ptr(stream)),
+               "qrk_autotune_blockangular")
+        return float(scale.value)
+
+    def status_problems(self, stream=None) -> np.ndarray:
+        bits = np.zeros(self.P, dtype=np.int32)
+        _check(lib().qrk_status_get_problems(self._h, bits.ctypes.data_as(_c_i32p), _stream_ptr(stream)),
+               "qrk_status_get_problems")
+        return bits
 
 
 class BandedSolver(Factor):

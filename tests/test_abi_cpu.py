@@ -77,3 +77,50 @@ def test_banded_create_rejects_bad_shapes():
     h = ctypes.c_void_p()
     for M, N, w in [(-1, 10, 3), (10, 0, 3), (10, 10, 0), (10, 10, 32), (10, 4, 5)]:
         assert L.qrk_create_banded(M, N, w, 0, ctypes.byref(h)) == qrkit.QRK_EINVAL
+
+
+def _create_batched(P, n, K, nB, row_off, dtype=0, mode=0):
+    L = qrkit.lib()
+    h = ctypes.c_void_p()
+    Ka = np.ascontiguousarray(np.asarray(K, np.int32))
+    nBa = np.ascontiguousarray(np.asarray(nB, np.int32))
+    ro = np.ascontiguousarray(np.asarray(row_off, np.int64))
+    st = L.qrk_create_blockangular_batched(P, n, Ka.ctypes.data_as(qrkit._c_i32p), nBa.ctypes.data_as(qrkit._c_i32p),
+                                           ro.ctypes.data_as(qrkit._c_i64p), dtype, mode, ctypes.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("args", [
+    (0, 3, [1], [4], [0, 2]),                       # P < 1
+    (2, 0, [1, 1], [4, 4], [0, 2, 4]),              # n < 1
+    (2, 3, [1, 0], [4, 4], [0, 2, 4]),              # a problem without blocks
+    (2, 3, [1, 1], [4, 128], [0, 2, 4]),            # nB > 127
+    (2, 3, [1, 1], [-1, 4], [0, 2, 4]),             # nB < 0
+    (2, 3, [1, 1], [4, 4], [1, 2, 4]),              # row_off[0] != 0
+    (2, 3, [1, 1], [4, 4], [0, 4, 2]),              # negative block
+    (2, 3, [1, 1], [4, 4], [0, 60, 62]),            # block taller than the limit
+])
+def test_batched_create_rejects_bad_shapes(args):
+    st, h = _create_batched(*args)
+    assert st == qrkit.QRK_EINVAL and not h.value
+
+
+def test_batched_calls_reject_null_handle():
+    L = qrkit.lib()
+    assert L.qrk_factor_blockangular_batched(None, None, None, None, None, None, None) == qrkit.QRK_EINVAL
+    assert L.qrk_status_get_problems(None, None, None) == qrkit.QRK_EINVAL
+    assert L.qrk_autotune_blockangular(None, None, None) == qrkit.QRK_EINVAL
+    assert _create_batched(2, 3, [1, 1], [4, 4], [0, 2, 4], dtype=1, mode=1)[0] == qrkit.QRK_EINVAL
+
+
+def test_stack_batch_layout():
+    """The batched layout: global row offsets, packed B per problem, stacked d."""
+    from workloads import generators as gen
+    insts = [gen.make_blockangular(s, K=k, m=5, n=2, nB=nb, lam=0.1, dtype=np.float32)
+             for s, k, nb in [(1, 3, 4), (2, 2, 0), (3, 4, 7)]]
+    st = gen.stack_batch(insts)
+    assert list(st["K"]) == [3, 2, 4] and list(st["nB"]) == [4, 0, 7]
+    assert st["row_off"].tolist() == list(range(0, 46, 5))
+    assert st["B"].size == 15 * 4 + 20 * 7
+    assert np.array_equal(st["B"][60:].reshape(20, 7), insts[2].B)
+    assert st["d"].size == sum(i.N for i in insts)

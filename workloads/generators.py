@@ -214,6 +214,26 @@ def ragged_batch(seed: int = 200, P: int = 512, kmin: int = 500, kmax: int = 800
     return out
 
 
+def stack_batch(insts):
+    """Stack block-angular problems (same n and dtype) into the batched layout: K [P], nB [P],
+    global row offsets [sum K + 1], A [M_tot, n], B flat (each problem's M_p x nB_p rows packed
+    with row stride nB_p), b [M_tot], d [sum N_p] and lam [P].  Pure data layout."""
+    n = insts[0].n
+    K = np.array([i.K for i in insts], dtype=np.int32)
+    nB = np.array([i.nB for i in insts], dtype=np.int32)
+    row_off = [np.zeros(1, dtype=np.int64)]
+    base = 0
+    for i in insts:
+        row_off.append(i.row_off[1:] + base)
+        base += i.M
+    B = [np.ascontiguousarray(i.B[:, :i.nB]).reshape(-1) for i in insts]
+    return dict(n=n, K=K, nB=nB, row_off=np.concatenate(row_off),
+                A=np.concatenate([i.A for i in insts], axis=0),
+                B=np.concatenate(B) if B else np.zeros(0, dtype=insts[0].A.dtype),
+                b=np.concatenate([i.b for i in insts]), d=np.concatenate([i.d for i in insts]),
+                lam=np.array([i.lam for i in insts], dtype=np.float64))
+
+
 @dataclasses.dataclass
 class Banded:
     """Banded J: row i holds w values at columns row_start[i] .. row_start[i]+w-1."""
