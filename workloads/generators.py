@@ -289,3 +289,36 @@ def banded_batch(seed: int = 300, P: int = 2048, N: int = 2048, w: int = 12,
     rng = _rng(seed)
     seeds = rng.integers(0, 2**63 - 1, size=P)
     return [make_banded(int(s), N=N, w=w, lam=lam, dtype=dtype) for s in seeds]
+
+
+def lm_blockangular(seed: int = 310, K: int = 200, m=12, n: int = 3, nB: int = 30, c: float = 0.1,
+                    noise: float = 0.01, x_noise: float = 0.1, dtype=np.float32):
+    """Synthetic LM workload on a block-angular J0: x_true ~ N(0,1), y = J0 (x_true + c x_true^3)
+    + noise N(0,1), start x0 = x_true + x_noise N(0,1).  Returns (inst0, y, x0, x_true); inst0
+    holds A0, B0 (its b, d, lam are unused)."""
+    inst0 = make_blockangular(seed, K=K, m=m, n=n, nB=nB, lam=0.0, dtype=dtype)
+    rng = _rng(seed + 1)
+    x_true = rng.standard_normal(inst0.N)
+    u = x_true + c * x_true ** 3
+    blk = np.repeat(np.arange(K), np.diff(inst0.row_off))
+    ub = u[:K * n].reshape(K, n)
+    y = (inst0.A.astype(np.float64) * ub[blk]).sum(axis=1)
+    if nB:
+        y = y + inst0.B.astype(np.float64) @ u[K * n:]
+    y = (y + noise * rng.standard_normal(inst0.M)).astype(dtype)
+    x0 = x_true + x_noise * rng.standard_normal(inst0.N)
+    return inst0, y, x0, x_true
+
+
+def lm_banded(seed: int = 320, N: int = 2048, w: int = 12, c: float = 0.1, noise: float = 0.01,
+              x_noise: float = 0.1, dtype=np.float32):
+    """The same synthetic LM workload on a banded J0 (make_banded's pattern)."""
+    inst0 = make_banded(seed, N=N, w=w, lam=0.0, dtype=dtype)
+    rng = _rng(seed + 1)
+    x_true = rng.standard_normal(N)
+    u = x_true + c * x_true ** 3
+    cols = inst0.row_start.astype(np.int64)[:, None] + np.arange(w)[None, :]
+    y = (inst0.vals.astype(np.float64) * u[cols]).sum(axis=1)
+    y = (y + noise * rng.standard_normal(inst0.M)).astype(dtype)
+    x0 = x_true + x_noise * rng.standard_normal(N)
+    return inst0, y, x0, x_true
