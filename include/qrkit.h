@@ -227,6 +227,37 @@ qrk_status qrk_set_tsqr_shape(qrk_handle h, int32_t leaves, int32_t fanin);
 qrk_status qrk_autotune_blockangular(qrk_handle h, double* scale_host, void* stream);
 
 /* ------------------------------------------------------------------------------
+ * Levenberg-Marquardt driver (Backtrack LM of Section 5.2) for the synthetic model
+ *     f(x) = J0 phi(x) - y,   phi(t) = t + c t^3 elementwise,   J(x) = J0 diag(phi'(x)),
+ * on every problem of a block-angular handle (single or batched; J(x) keeps J0's pattern).
+ * One iteration, per problem, entirely on the device:
+ *     J(x), b = -f(x) (stored in the handle's type), d = column norms of J(x) (1 for a zero
+ *     column), F = |f|^2/2;  p = the handle's factor + solve with `sweeps` refinement sweeps;
+ *     pred = p^T (lambda D^2 p - J^T f)/2;  F_new = |f(x + p)|^2/2;  rho = (F - F_new)/pred;
+ *     rho > 0: x += p, lambda *= max(1/3, 1 - (2 rho - 1)^3), nu = 2; else lambda *= nu,
+ *     nu *= 2  (Nielsen's rule; the paper names the rule it adapts but not its constants).
+ * qrk_lm_create_blockangular: A0, B0, y [device, the handle's type and layouts, borrowed
+ *   for the life of the driver]; c finite; 0 <= sweeps <= 8; max_log >= 0 iterations of
+ *   log kept.  The driver uses the handle's factor workspace (do not factor on the handle
+ *   while a run is in flight).  Allocates its state (J(x), -f, x, p, d, damping, log).
+ * qrk_lm_reset: x0 [device, N] and lambda0 [device, P] doubles; nu = 2; clears the log and
+ *   the iteration counter.  Stream-ordered.
+ * qrk_lm_run: `iters` iterations on `stream`.  use_graph = 0 enqueues them one by one;
+ *   use_graph != 0 captures one iteration into a HIP graph on the driver's own stream at
+ *   the first such call (not capturable itself) and replays it `iters` times on `stream`.
+ * qrk_lm_get: copies x [device, N], lambda [device, P] and the log [device,
+ *   max_log x P x 4: F, F_new, lambda after, accepted (0/1)] (any may be NULL); with
+ *   iters_host != NULL synchronises `stream` and returns the number of iterations run.
+ * ------------------------------------------------------------------------------ */
+typedef struct qrk_lm_s* qrk_lm;
+qrk_status qrk_lm_create_blockangular(qrk_handle h, const void* A0, const void* B0, const void* y, double c,
+                                      int32_t sweeps, int32_t max_log, qrk_lm* out);
+qrk_status qrk_lm_reset(qrk_lm lm, const double* x0, const double* lambda0, void* stream);
+qrk_status qrk_lm_run(qrk_lm lm, int32_t iters, int32_t use_graph, void* stream);
+qrk_status qrk_lm_get(qrk_lm lm, double* x, double* lambda, double* log, int32_t* iters_host, void* stream);
+void qrk_lm_destroy(qrk_lm lm);
+
+/* ------------------------------------------------------------------------------
  * Phase timing (HIP events recorded on the call's stream around each phase).
  * qrk_profile_enable(h, max_calls): max_calls > 0 creates the events for that many
  * factor/solve calls (not capturable; call outside graph capture) and starts

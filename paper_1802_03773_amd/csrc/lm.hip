@@ -1,0 +1,316 @@
+// Levenberg-Marquardt iteration kernels (Backtrack LM of QRkit Section 5.2, Nielsen's
+// gain-ratio damping rule) for the synthetic model f(x) = J0 phi(x) - y with the elementwise
+// phi(t) = t + c t^3, whose Jacobian J(x) = J0 diag(phi'(x)) keeps the pattern of J0.
+// Every kernel serves a batch of independent problems; all state (x, lambda, nu, costs) is
+// on the device, so one iteration can be captured into a graph and replayed.
+//
+// Per iteration, per problem:
+//   eval at x      : J(x) (stored), b = -f(x) (stored), d = column norms of J(x) (1 for a zero
+//                    column), J^T f, F = |f|^2 / 2
+//   factor + solve : p from the structured QR (libqrkit's factor and solve kernels)
+//   pred           : 1/2 p^T (lam D^2 p - J^T f)         (= L(0) - L(p), L(h) = |f + J h|^2 / 2)
+//   eval at x + p  : F_new = |f(x + p)|^2 / 2
+//   accept         : rho = (F - F_new) / pred; rho > 0: x += p, lam *= max(1/3, 1 - (2 rho - 1)^3),
+//                    nu = 2; else lam *= nu, nu *= 2
+// Sums are deterministic (fixed-order per wave, per workgroup and per problem).
+#include "qrk_batch.hpp"
+#include "qrk_device.hpp"
+#include "qrk_lm.hpp"
+
+namespace qrk {
+
+__device__ __forceinline__ double lm_phi(double t, double c) { return t + c * t * t * t; }
+__device__ __forceinline__ double lm_dphi(double t, double c) { return 1.0 + 3.0 * c * t * t; }
+
+// ---------------------------------------------------------------------------------------
+// Block-angular model evaluation: workgroup w serves the packs of problem wg_prob[w] (the
+// refinement's assignment), one wave per pack of whole blocks, one row per lane.
+// JAC: writes A = A0 diag(phi'(u_blk)), B = B0 diag(phi'(u_B)), b = -f, the block columns'
+//      d and J^T f, and per-workgroup partials of sum_r B_rj^2, sum_r B_rj f_r and sum_r f_r^2.
+// !JAC: only the partial of sum_r f_r^2, at u = x + p.
+// ---------------------------------------------------------------------------------------
+template <typename T, bool JAC>
+__global__ void __launch_bounds__(256)
+k_lmba_eval(const ProbDesc* __restrict__ probs, const int32_t* __restrict__ wg_prob,
+            const int64_t* __restrict__ pack_blk, int n, const int64_t* __restrict__ row_off,
+            const T* __restrict__ A0, const T* __restrict__ B0, const T* __restrict__ y, double c,
+            const double* __restrict__ x, const double* __restrict__ pstep, T* __restrict__ A,
+            T* __restrict__ B, T* __restrict__ b, double* __restrict__ d, double* __restrict__ gJ,
+            double* __restrict__ part, double* __restrict__ fpart) {
+  __shared__ double phB[kMaxDense], dphB[kMaxDense];
+  __shared__ double rr[4][64];
+  __shared__ double av[4][64][8];
+  __shared__ int rowblk[4][64];
+  __shared__ double red2[4][kMaxDense], redf[4][kMaxDense];
+  __shared__ double fred[4];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int pi = wg_prob[blockIdx.x];
+  const ProbDesc& P = probs[pi];
+  const int nB = P.nB;
+  const int64_t koff = P.koff, noff = P.noff, moff = P.moff, ldb = P.ldb;
+  const int64_t offB = noff + P.K * n;
+  const T* B0p = B0 + P.boff;
+  T* Bp = B + P.boff;
+  for (int j = threadIdx.x; j < nB; j += blockDim.x) {
+    const double u = x[offB + j] + (JAC ? 0.0 : pstep[offB + j]);
+    phB[j] = lm_phi(u, c);
+    dphB[j] = lm_dphi(u, c);
+  }
+  __syncthreads();
+  double s2a = 0.0, s2b = 0.0, sfa = 0.0, sfb = 0.0;  // columns lane, lane + 64
+  double fsq = 0.0;
+  const int64_t lw = blockIdx.x - P.wg0;
+  const int64_t pend = P.pack0 + P.npacks;
+  for (int64_t pk = P.pack0 + lw * 4 + wv; pk < pend; pk += (int64_t)P.nwg * 4) {
+    const int64_t b0 = pack_blk[pk];
+    const int nb = (int)(pack_blk[pk + 1] - b0);
+    const int64_t pr0 = row_off[b0];
+    const int prows = (int)(row_off[b0 + nb] - pr0);
+    if (lane < nb) {
+      const int lo = (int)(row_off[b0 + lane] - pr0), hi = (int)(row_off[b0 + lane + 1] - pr0);
+      for (int r = lo; r < hi; ++r) rowblk[wv][r] = lane;
+    }
+    wave_lds_sync();
+    if (lane < prows) {
+      const int64_t row = pr0 + lane;
+      const int64_t lb = b0 - koff + rowblk[wv][lane];
+      double f = 0.0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        if (k < n) {
+          const double u = x[noff + lb * n + k] + (JAC ? 0.0 : pstep[noff + lb * n + k]);
+          const double a0 = (double)A0[row * n + k];
+          f += a0 * lm_phi(u, c);
+          if (JAC) {
+            const T a = (T)(a0 * lm_dphi(u, c));
+            A[row * n + k] = a;
+            av[wv][lane][k] = (double)a;
+          }
+        }
+      }
+      const T* Brow = B0p + (row - moff) * ldb;
+      double f0 = 0.0, f1 = 0.0;
+      int j = 0;
+      for (; j + 1 < nB; j += 2) {
+        f0 += (double)Brow[j] * phB[j];
+        f1 += (double)Brow[j + 1] * phB[j + 1];
+      }
+      if (j < nB) f0 += (double)Brow[j] * phB[j];
+      f += (f0 + f1) - (double)y[row];
+      rr[wv][lane] = f;
+      fsq += f * f;
+      if (JAC) b[row] = (T)(-f);
+    }
+    wave_lds_sync();
+    if (JAC) {
+      // B rows of the pack, coalesced across lanes: scale, store, accumulate column sums
+      for (int r = 0; r < prows; ++r) {
+        const int64_t roff = (pr0 + r - moff) * ldb;
+        const double fr = rr[wv][r];
+        if (lane < nB) {
+          const T v = (T)((double)B0p[roff + lane] * dphB[lane]);
+          Bp[roff + lane] = v;
+          s2a += (double)v * (double)v;
+          sfa += (double)v * fr;
+        }
+        if (lane + 64 < nB) {
+          const T v = (T)((double)B0p[roff + lane + 64] * dphB[lane + 64]);
+          Bp[roff + lane + 64] = v;
+          s2b += (double)v * (double)v;
+          sfb += (double)v * fr;
+        }
+      }
+      // block columns: lane per block
+      if (lane < nb) {
+        const int64_t lb = b0 - koff + lane;
+        const int lo = (int)(row_off[b0 + lane] - pr0), hi = (int)(row_off[b0 + lane + 1] - pr0);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          if (k < n) {
+            double sq = 0.0, gf = 0.0;
+            for (int r = lo; r < hi; ++r) {
+              const double a = av[wv][r][k];
+              sq += a * a;
+              gf += a * rr[wv][r];
+            }
+            d[noff + lb * n + k] = sq > 0.0 ? sqrt(sq) : 1.0;
+            gJ[noff + lb * n + k] = gf;
+          }
+        }
+      }
+    }
+    wave_lds_sync();
+  }
+  // fixed-order reductions: across the wave (butterfly), then the four waves in order
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) fsq += __shfl_xor(fsq, off, 64);
+  if (lane == 0) fred[wv] = fsq;
+  if (JAC) {
+    red2[wv][lane] = s2a;
+    red2[wv][lane + 64] = s2b;
+    redf[wv][lane] = sfa;
+    redf[wv][lane + 64] = sfb;
+  }
+  __syncthreads();
+  if (JAC) {
+    double* pw = part + (int64_t)blockIdx.x * 2 * kMaxDense;
+    for (int j = threadIdx.x; j < nB; j += blockDim.x) {
+      pw[j] = ((red2[0][j] + red2[1][j]) + red2[2][j]) + red2[3][j];
+      pw[kMaxDense + j] = ((redf[0][j] + redf[1][j]) + redf[2][j]) + redf[3][j];
+    }
+  }
+  if (threadIdx.x == 0) fpart[blockIdx.x] = ((fred[0] + fred[1]) + fred[2]) + fred[3];
+}
+
+// Per problem (one workgroup each): the dense columns' d and J^T f from the workgroup
+// partials (JAC), and F = sum f^2 / 2 into Fout[p].
+template <bool JAC>
+__global__ void __launch_bounds__(128)
+k_lmba_reduce(const ProbDesc* __restrict__ probs, int n, const double* __restrict__ part,
+              const double* __restrict__ fpart, double* __restrict__ d, double* __restrict__ gJ,
+              double* __restrict__ Fout) {
+  const int pi = blockIdx.x;
+  const ProbDesc& P = probs[pi];
+  const int j = threadIdx.x;
+  const int64_t offB = P.noff + P.K * n;
+  if (JAC && j < P.nB) {
+    double s2 = 0.0, sf = 0.0;
+    for (int w = P.wg0; w < P.wg0 + P.nwg; ++w) {
+      s2 += part[(int64_t)w * 2 * kMaxDense + j];
+      sf += part[(int64_t)w * 2 * kMaxDense + kMaxDense + j];
+    }
+    d[offB + j] = s2 > 0.0 ? sqrt(s2) : 1.0;
+    gJ[offB + j] = sf;
+  }
+  if (j == 0) {
+    double s = 0.0;
+    for (int w = P.wg0; w < P.wg0 + P.nwg; ++w) s += fpart[w];
+    Fout[pi] = 0.5 * s;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Problem-generic pieces (unknowns of problem p: [noff[p], noff[p+1])).
+// ---------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_lm_pred(const int64_t* __restrict__ noff, const double* __restrict__ p, const double* __restrict__ d,
+          const double* __restrict__ gJ, const double* __restrict__ lam, double* __restrict__ pred) {
+  __shared__ double red[256];
+  const int pi = blockIdx.x;
+  const int64_t a = noff[pi], e = noff[pi + 1];
+  const double l = lam[pi];
+  double s = 0.0;
+  for (int64_t j = a + threadIdx.x; j < e; j += blockDim.x) s += p[j] * (l * d[j] * d[j] * p[j] - gJ[j]);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h >= 1; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) pred[pi] = 0.5 * red[0];
+}
+
+// One workgroup: gain ratio, damping update and accept flag of every problem, the iteration
+// log ([iter][p] = F, F_new, lam after, accepted) and the iteration counter.
+__global__ void __launch_bounds__(256)
+k_lm_accept(int P, const double* __restrict__ F, const double* __restrict__ Fnew, const double* __restrict__ pred,
+            double* __restrict__ lam, double* __restrict__ nu, int* __restrict__ acc, int* __restrict__ iter,
+            double* __restrict__ log, int max_log) {
+  const int it = *iter;
+  for (int pi = threadIdx.x; pi < P; pi += blockDim.x) {
+    const double f0 = F[pi], f1 = Fnew[pi], pr = pred[pi];
+    double rho = -1.0;
+    if (pr > 0.0 && is_finite(f1) && is_finite(pr)) rho = (f0 - f1) / pr;
+    double l = lam[pi], v = nu[pi];
+    const bool ok = rho > 0.0;
+    if (ok) {
+      const double t = 2.0 * rho - 1.0;
+      l *= fmax(1.0 / 3.0, 1.0 - t * t * t);
+      v = 2.0;
+    } else {
+      l *= v;
+      v *= 2.0;
+    }
+    lam[pi] = l;
+    nu[pi] = v;
+    acc[pi] = ok ? 1 : 0;
+    if (it < max_log) {
+      double* r = log + ((int64_t)it * P + pi) * 4;
+      r[0] = f0;
+      r[1] = f1;
+      r[2] = l;
+      r[3] = ok ? 1.0 : 0.0;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *iter = it + 1;
+}
+
+__global__ void __launch_bounds__(256)
+k_lm_step(const int64_t* __restrict__ noff, const int* __restrict__ acc, const double* __restrict__ p,
+          double* __restrict__ x) {
+  const int pi = blockIdx.x;
+  if (!acc[pi]) return;
+  for (int64_t j = noff[pi] + threadIdx.x; j < noff[pi + 1]; j += blockDim.x) x[j] += p[j];
+}
+
+__global__ void k_lm_init(int P, double* __restrict__ nu, int* __restrict__ iter) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < P) nu[i] = 2.0;
+  if (i == 0) *iter = 0;
+}
+
+// ---------------------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------------------
+template <typename T>
+hipError_t launch_lmba_eval(const BatchView& bv, bool jac, const T* A0, const T* B0, const T* y, double c,
+                            const double* x, const double* p, T* A, T* B, T* b, double* d, double* gJ,
+                            double* part, double* fpart, double* Fout, hipStream_t st) {
+  if (bv.max_L > kMaxDense || bv.n > 8) return hipErrorInvalidValue;
+  if (jac)
+    hipLaunchKernelGGL((k_lmba_eval<T, true>), dim3(bv.nwg), dim3(256), 0, st, bv.probs, bv.wg_prob, bv.pack_blk,
+                       bv.n, bv.row_off, A0, B0, y, c, x, p, A, B, b, d, gJ, part, fpart);
+  else
+    hipLaunchKernelGGL((k_lmba_eval<T, false>), dim3(bv.nwg), dim3(256), 0, st, bv.probs, bv.wg_prob,
+                       bv.pack_blk, bv.n, bv.row_off, A0, B0, y, c, x, p, A, B, b, d, gJ, part, fpart);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (jac)
+    hipLaunchKernelGGL((k_lmba_reduce<true>), dim3(bv.P), dim3(128), 0, st, bv.probs, bv.n, part, fpart, d, gJ,
+                       Fout);
+  else
+    hipLaunchKernelGGL((k_lmba_reduce<false>), dim3(bv.P), dim3(128), 0, st, bv.probs, bv.n, part, fpart, d, gJ,
+                       Fout);
+  return hipGetLastError();
+}
+
+hipError_t launch_lm_control(int P, const int64_t* noff, const double* p, const double* d, const double* gJ,
+                             double* lam, double* nu, const double* F, const double* Fnew, double* pred, int* acc,
+                             int* iter, double* log, int max_log, double* x, hipStream_t st, int stage) {
+  if (stage == 0) {
+    hipLaunchKernelGGL(k_lm_pred, dim3(P), dim3(256), 0, st, noff, p, d, gJ, lam, pred);
+  } else {
+    hipLaunchKernelGGL(k_lm_accept, dim3(1), dim3(256), 0, st, P, F, Fnew, pred, lam, nu, acc, iter, log, max_log);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_lm_step, dim3(P), dim3(256), 0, st, noff, acc, p, x);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_lm_init(int P, double* nu, int* iter, hipStream_t st) {
+  hipLaunchKernelGGL(k_lm_init, dim3((P + 255) / 256), dim3(256), 0, st, P, nu, iter);
+  return hipGetLastError();
+}
+
+#define QRK_INST(T)                                                                                      \
+  template hipError_t launch_lmba_eval<T>(const BatchView&, bool, const T*, const T*, const T*, double,    \
+                                          const double*, const double*, T*, T*, T*, double*, double*,      \
+                                          double*, double*, double*, hipStream_t);
+QRK_INST(float)
+QRK_INST(double)
+#undef QRK_INST
+
+}  // namespace qrk

@@ -121,6 +121,12 @@ qrk_status banded_adjoint(qrk_handle h, const double* p, const double* g, void* 
 qrk_status blockangular_adjoint(qrk_handle h, const double* p, const double* g, void* dA, void* dB,
                                 void* db, double* dlam, double* dd, hipStream_t st);
 
+// Block-angular factor / solve on the handle's current (borrowed) inputs and damping, and
+// the batch view the kernels take; shared with the LM driver.
+qrk_status blockangular_factor(qrk_handle h, hipStream_t st);
+qrk_status blockangular_solve(qrk_handle h, double* p, int sweeps, hipStream_t st);
+qrk::BatchView blockangular_view(qrk_handle h);
+
 // Workspace allocation shared by the create functions (records the allocation in h).
 qrk_status handle_alloc(qrk_handle h, void** out, size_t bytes);
 void handle_free(qrk_handle h);

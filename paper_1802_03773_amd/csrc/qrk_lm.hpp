@@ -1,0 +1,29 @@
+// Launchers of the Levenberg-Marquardt iteration kernels (lm.hip), internal to libqrkit.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "qrk_batch.hpp"
+
+namespace qrk {
+
+// Block-angular model evaluation and its per-problem reduction.  jac = true at x: J(x) into
+// A and B (the handle's B layout), b = -f, d and J^T f (block and dense columns), F = |f|^2/2
+// into Fout.  jac = false at x + p: F_new into Fout only.  part [nwg][2][kMaxDense] and
+// fpart [nwg] are scratch.
+template <typename T>
+hipError_t launch_lmba_eval(const BatchView& bv, bool jac, const T* A0, const T* B0, const T* y, double c,
+                            const double* x, const double* p, T* A, T* B, T* b, double* d, double* gJ,
+                            double* part, double* fpart, double* Fout, hipStream_t st);
+
+// stage 0: pred = p^T (lam D^2 p - J^T f) / 2 per problem.  stage 1: gain ratio, damping
+// update, accept flags, log row of this iteration, iteration counter, x += p where accepted.
+hipError_t launch_lm_control(int P, const int64_t* noff, const double* p, const double* d, const double* gJ,
+                             double* lam, double* nu, const double* F, const double* Fnew, double* pred, int* acc,
+                             int* iter, double* log, int max_log, double* x, hipStream_t st, int stage);
+
+// nu = 2 for every problem, iteration counter = 0.
+hipError_t launch_lm_init(int P, double* nu, int* iter, hipStream_t st);
+
+}  // namespace qrk

@@ -273,6 +273,16 @@ qrk_status assign_leaves(qrk_handle h) {
 }  // namespace
 
 qrk_status handle_alloc(qrk_handle h, void** out, size_t bytes) { return dalloc(h, out, bytes); }
+
+qrk_status blockangular_factor(qrk_handle h, hipStream_t st) {
+  return h->dtype == QRK_F32 ? factor_ba<float>(h, st) : factor_ba<double>(h, st);
+}
+
+qrk_status blockangular_solve(qrk_handle h, double* p, int sweeps, hipStream_t st) {
+  return h->dtype == QRK_F32 ? solve_ba<float>(h, p, sweeps, st) : solve_ba<double>(h, p, sweeps, st);
+}
+
+BatchView blockangular_view(qrk_handle h) { return view(h); }
 void handle_free(qrk_handle h) { free_all(h); }
 
 template <typename T>

@@ -40,6 +40,12 @@ _SIGS = {
     "qrk_factor_blockangular_batched": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp]),
     "qrk_status_get_problems": (_c_i32, [_c_vp, _c_i32p, _c_vp]),
     "qrk_autotune_blockangular": (_c_i32, [_c_vp, ctypes.POINTER(_c_dbl), _c_vp]),
+    "qrk_lm_create_blockangular": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_dbl, _c_i32, _c_i32,
+                                            ctypes.POINTER(_c_vp)]),
+    "qrk_lm_reset": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp]),
+    "qrk_lm_run": (_c_i32, [_c_vp, _c_i32, _c_i32, _c_vp]),
+    "qrk_lm_get": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_i32p, _c_vp]),
+    "qrk_lm_destroy": (None, [_c_vp]),
     "qrk_create_banded": (_c_i32, [_c_i64, _c_i64, _c_i32, _c_i32, ctypes.POINTER(_c_vp)]),
     "qrk_create_banded_batched": (_c_i32, [_c_i32, _c_i64, _c_i64, _c_i32, _c_i32, ctypes.POINTER(_c_vp)]),
     "qrk_factor_banded": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_dbl, _c_vp]),
@@ -390,3 +396,51 @@ def factor_banded(row_start, vals, b, d, lam, N: int, dtype="float32", stream=No
     M, w = int(vals.shape[0]), int(vals.shape[1])
     s = BandedSolver(M, N, w, dtype=dtype)
     return s.factor(row_start, vals, b, d, lam, stream=stream)
+
+
+class LMDriver:
+    """Backtrack-LM iterations on f(x) = J0 phi(x) - y (phi(t) = t + c t^3) over every problem of
+    a block-angular solver or batch, run by the library (optionally as a replayed HIP graph)."""
+
+    def __init__(self, solver, A0, B0, y, c: float, sweeps: int = 1, max_log: int = 64):
+        torch = _torch()
+        td = _torch_dtype(solver.qdtype)
+        self.solver, self.P = solver, int(getattr(solver, "P", 1))
+        self.max_log = int(max_log)
+        h = _c_vp()
+        _check(lib().qrk_lm_create_blockangular(solver.handle, _dev_ptr(A0, td, "A0"),
+                                                _dev_ptr(B0, td, "B0") if B0 is not None else None,
+                                                _dev_ptr(y, td, "y"), float(c), int(sweeps), self.max_log,
+                                                ctypes.byref(h)), "qrk_lm_create_blockangular")
+        self._lm = h
+        self._keep = (A0, B0, y)
+        self.N = solver.N
+        del torch
+
+    def __del__(self):
+        h, self._lm = getattr(self, "_lm", None), None
+        if h is not None and _LIB is not None:
+            _LIB.qrk_lm_destroy(h)
+
+    def reset(self, x0, lam0, stream=None):
+        torch = _torch()
+        self._x0 = x0.to(torch.float64).contiguous()
+        self._lam0 = lam0.to(torch.float64).contiguous()
+        _check(lib().qrk_lm_reset(self._lm, _dev_ptr(self._x0, torch.float64, "x0", self.N),
+                                  _dev_ptr(self._lam0, torch.float64, "lam0", self.P), _stream_ptr(stream)),
+               "qrk_lm_reset")
+
+    def run(self, iters: int, graph: bool = False, stream=None):
+        _check(lib().qrk_lm_run(self._lm, int(iters), int(bool(graph)), _stream_ptr(stream)), "qrk_lm_run")
+
+    def get(self, stream=None):
+        """(x [N], lam [P], log [max_log, P, 4] = F, F_new, lam after, accepted; iterations run)."""
+        torch = _torch()
+        x = torch.empty(self.N, dtype=torch.float64, device="cuda")
+        lam = torch.empty(self.P, dtype=torch.float64, device="cuda")
+        log = torch.empty((max(self.max_log, 1), self.P, 4), dtype=torch.float64, device="cuda")
+        it = _c_i32(0)
+        _check(lib().qrk_lm_get(self._lm, _dev_ptr(x, torch.float64, "x"), _dev_ptr(lam, torch.float64, "lam"),
+                                _dev_ptr(log, torch.float64, "log"), ctypes.byref(it), _stream_ptr(stream)),
+               "qrk_lm_get")
+        return x, lam, log[:self.max_log], int(it.value)
