@@ -30,10 +30,12 @@ hipError_t launch_tsqr_stream(const T* X, int64_t ldx, int64_t nrows, int L, int
 // 16-column blocks (leaf_prob / leaf_idx: problem and index within it); one launch per c.
 // Each problem's leaves merge pairwise in the same launch (its slots from slot0, counters
 // from ctr0; nctr counters in all, cleared here) and its root goes to RB + rboff.
+// bf16x3: the trailing updates' two large products are formed as three bf16 products each
+// (hi hi' + hi lo' + lo hi', fp32 accumulation).
 int tsqr_mfma_slot_floats(int L);
 // p[0 .. n) = 0 (a kernel, so it may be captured into a graph).
 hipError_t launch_zero_ints(int* p, int64_t n, hipStream_t st);
-hipError_t launch_tsqr_mfma(const int* cls_begin, const int* cls_count, const int32_t* leaf_prob,
+hipError_t launch_tsqr_mfma(bool bf16x3, const int* cls_begin, const int* cls_count, const int32_t* leaf_prob,
                             const int32_t* leaf_idx, const ProbDesc* probs, int n, const float* Red,
                             const double* d, const double* lam, float* slots, int* counters, int64_t nctr,
                             float* RB, hipStream_t st);

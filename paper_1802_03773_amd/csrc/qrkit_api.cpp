@@ -72,7 +72,7 @@ qrk_status factor_ba(qrk_handle h, hipStream_t st) {
   if constexpr (std::is_same<T, float>::value) {
     // dense parts on the matrix cores: leaves and merge trees, one launch per column-block count
     pr = prof_begin(h, 1, st);
-    if (launch_tsqr_mfma(h->cls_begin, h->cls_count, h->leaf_prob, h->leaf_idx, h->probs_d, h->n, Red, h->d,
+    if (launch_tsqr_mfma(h->mode == QRK_BF16X3, h->cls_begin, h->cls_count, h->leaf_prob, h->leaf_idx, h->probs_d, h->n, Red, h->d,
                          h->lam_ptr, h->slots, h->counters, h->nctr, RB, st) != hipSuccess)
       return QRK_EHIP;
     prof_end(h, pr, st);

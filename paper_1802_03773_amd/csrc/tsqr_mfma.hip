@@ -7,7 +7,7 @@ namespace qrk {
 
 // One instantiation per column-block count lives in tsqr_mfma_ncb<N>.hip.
 template <int NCB>
-hipError_t launch_tsqr_mfma_n(int leaf_begin, int nleaves_cls, const int32_t* leaf_prob, const int32_t* leaf_idx,
+hipError_t launch_tsqr_mfma_n(bool bf16x3, int leaf_begin, int nleaves_cls, const int32_t* leaf_prob, const int32_t* leaf_idx,
                               const ProbDesc* probs, int n, const float* Red, const double* d, const double* lam,
                               float* slots, int* counters, float* RB, hipStream_t st);
 
@@ -27,7 +27,7 @@ int tsqr_mfma_slot_floats(int L) {
   return ncb * (ncb + 1) / 2 * 256;
 }
 
-hipError_t launch_tsqr_mfma(const int* cls_begin, const int* cls_count, const int32_t* leaf_prob,
+hipError_t launch_tsqr_mfma(bool bf16x3, const int* cls_begin, const int* cls_count, const int32_t* leaf_prob,
                             const int32_t* leaf_idx, const ProbDesc* probs, int n, const float* Red,
                             const double* d, const double* lam, float* slots, int* counters, int64_t nctr,
                             float* RB, hipStream_t st) {
@@ -38,7 +38,7 @@ hipError_t launch_tsqr_mfma(const int* cls_begin, const int* cls_count, const in
     if (k == 0) continue;
 #define QRK_TS(N)                                                                                            \
   case N:                                                                                                    \
-    e = launch_tsqr_mfma_n<N>(b, k, leaf_prob, leaf_idx, probs, n, Red, d, lam, slots, counters, RB, st); \
+    e = launch_tsqr_mfma_n<N>(bf16x3, b, k, leaf_prob, leaf_idx, probs, n, Red, d, lam, slots, counters, RB, st); \
     break;
     switch (c) { QRK_TS(1) QRK_TS(2) QRK_TS(3) QRK_TS(4) QRK_TS(5) QRK_TS(6) QRK_TS(7) QRK_TS(8) }
 #undef QRK_TS

@@ -79,6 +79,30 @@ __device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// bf16 operands of the 16x16x32 matrix-core product: lane l supplies A[l%16][8(l/16) + e] and
+// B[8(l/16) + e][l%16], e = 0..7.  Any fixed assignment of a lane's eight K slots to tile rows
+// (or panel columns) gives the same sum as long as A and B use the same one.
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ f4 mfma_bf(bf8 a, bf8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// BF16x3 split of eight floats: hi = bf16(x), lo = bf16(x - hi) (round to nearest even).
+struct BfPair {
+  bf8 hi, lo;
+};
+__device__ __forceinline__ BfPair bf_split(const float (&x)[8]) {
+  BfPair r;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const __bf16 h = (__bf16)x[e];
+    r.hi[e] = h;
+    r.lo[e] = (__bf16)(x[e] - (float)h);
+  }
+  return r;
+}
+
 constexpr int kWaveLds = 256 + 256 + 256 * 8;  // T staging, scales, W staging (up to 8 blocks)
 
 template <int NCB>
@@ -96,7 +120,7 @@ struct Tri {
 // The Householder vectors are kept unscaled: the tile column x_j stays in place and the
 // reflector's tile part is w_j = s_j x_j with s_j = 1/(alpha_j - beta_j); the scales are
 // applied once per row of the small Z products instead of once per tile element.
-template <int NCB, int NRB, bool TRI>
+template <int NCB, int NRB, bool TRI, bool BF = false>
 __device__ __forceinline__ void merge_tile(f4 (&R)[Tri<NCB>::count], f4 (&X)[NRB][NCB], int pstart,
                                            float* __restrict__ lds, int lane) {
   const int g = lane >> 4;
@@ -200,29 +224,91 @@ __device__ __forceinline__ void merge_tile(f4 (&R)[Tri<NCB>::count], f4 (&X)[NRB
 
     // ---- trailing update on the matrix cores ----------------------------------------------
     //   Z = R_rows + diag(s) X_P^T X_q;  Z' = T^T Z;  R_rows -= Z';  X_q -= X_P diag(s) Z'
+    // BF: X_P^T X_q and X_P (s Z') as three bf16 products each (hi hi' + hi lo' + lo hi'),
+    // fp32 accumulation.  For X_P^T X_q, chunk h covers block rows 2h and 2h+1: lane (g, c)
+    // gives K slots 8g + v and 8g + 4 + v the tile rows 16(2h) + 4g + v and 16(2h+1) + 4g + v of
+    // column c (the panel's for A, column block q's for B).  For X_P (s Z') the K slots 8g + v
+    // are panel columns 4g + v and the slots 8g + 4 .. 8g + 7 are zero.
+    constexpr int NCH = (RBN + 1) / 2;
+    BfPair Pbf[BF ? NCH : 1];
+    BfPair Wbf[BF ? RBN : 1];
+    if constexpr (BF) {
+#pragma unroll
+      for (int h = 0; h < NCH; ++h) {
+        float t[8];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          t[v] = X[2 * h][P][v];
+          t[4 + v] = (2 * h + 1 < RBN) ? X[2 * h + 1 < RBN ? 2 * h + 1 : 0][P][v] : 0.f;
+        }
+        Pbf[h] = bf_split(t);
+      }
+#pragma unroll
+      for (int rb = 0; rb < RBN; ++rb) {
+        float t[8];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          t[v] = Wt[rb][v];
+          t[4 + v] = 0.f;
+        }
+        Wbf[rb] = bf_split(t);
+      }
+    }
     static_for<P + 1, NCB>([&](auto QQ) {
       constexpr int q = decltype(QQ)::value;
       constexpr int rq = Tri<NCB>::idx(P, q);
       f4 Y0 = {0.f, 0.f, 0.f, 0.f}, Y1 = {0.f, 0.f, 0.f, 0.f};
+      if constexpr (BF) {
 #pragma unroll
-      for (int rb = 0; rb < RBN; ++rb)
+        for (int h = 0; h < NCH; ++h) {
+          float t[8];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          if ((rb * 4 + v) & 1)
-            Y1 = mfma4(X[rb][P][v], X[rb][q][v], Y1);
-          else
-            Y0 = mfma4(X[rb][P][v], X[rb][q][v], Y0);
+          for (int v = 0; v < 4; ++v) {
+            t[v] = X[2 * h][q][v];
+            t[4 + v] = (2 * h + 1 < RBN) ? X[2 * h + 1 < RBN ? 2 * h + 1 : 0][q][v] : 0.f;
+          }
+          const BfPair qb = bf_split(t);
+          Y0 = mfma_bf(Pbf[h].hi, qb.hi, Y0);
+          Y1 = mfma_bf(Pbf[h].hi, qb.lo, Y1);
+          Y1 = mfma_bf(Pbf[h].lo, qb.hi, Y1);
         }
+      } else {
+#pragma unroll
+        for (int rb = 0; rb < RBN; ++rb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            if ((rb * 4 + v) & 1)
+              Y1 = mfma4(X[rb][P][v], X[rb][q][v], Y1);
+            else
+              Y0 = mfma4(X[rb][P][v], X[rb][q][v], Y0);
+          }
+      }
       const f4 Z = R[rq] + srow * (Y0 + Y1);
       f4 Zp = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int v = 0; v < 4; ++v) Zp = mfma4(Td[v], Z[v], Zp);
       R[rq] -= Zp;
       const f4 Zs = srow * Zp;
+      if constexpr (BF) {
+        float t[8];
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
+        for (int v = 0; v < 4; ++v) {
+          t[v] = Zs[v];
+          t[4 + v] = 0.f;
+        }
+        const BfPair zb = bf_split(t);
 #pragma unroll
-        for (int rb = 0; rb < RBN; ++rb) X[rb][q] = mfma4(Wt[rb][v], Zs[v], X[rb][q]);
+        for (int rb = 0; rb < RBN; ++rb) {
+          X[rb][q] = mfma_bf(Wbf[rb].hi, zb.hi, X[rb][q]);
+          X[rb][q] = mfma_bf(Wbf[rb].hi, zb.lo, X[rb][q]);
+          X[rb][q] = mfma_bf(Wbf[rb].lo, zb.hi, X[rb][q]);
+        }
+      } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+          for (int rb = 0; rb < RBN; ++rb) X[rb][q] = mfma4(Wt[rb][v], Zs[v], X[rb][q]);
+      }
     });
   });
 }
@@ -244,7 +330,7 @@ __device__ __forceinline__ void load_tri(const float* __restrict__ src, f4 (&R)[
 }
 
 // R <- triangle of QR([R; stored triangle at src]).
-template <int NCB>
+template <int NCB, bool BF = false>
 __device__ __forceinline__ void merge_stored_tri(f4 (&R)[Tri<NCB>::count], const float* __restrict__ src,
                                                  float* lds, int lane) {
   f4 X[NCB][NCB];
@@ -259,7 +345,7 @@ __device__ __forceinline__ void merge_stored_tri(f4 (&R)[Tri<NCB>::count], const
         X[rb][q] = f4{0.f, 0.f, 0.f, 0.f};
     });
   });
-  merge_tile<NCB, NCB, true>(R, X, 0, lds, lane);
+  merge_tile<NCB, NCB, true, BF>(R, X, 0, lds, lane);
 }
 
 // One launch per column-block count NCB: wave w is global leaf leaf_begin + w.  Leaf li of
@@ -267,7 +353,7 @@ __device__ __forceinline__ void merge_stored_tri(f4 (&R)[Tri<NCB>::count], const
 // triangle (leaf 0 starts from diag(sqrt(lam_p) d_B)); the leaves of each problem are then
 // merged pairwise in the same launch (the problem's own slots and arrival counters) and the
 // root is written row-major to the problem's R_B | c_B.
-template <int NCB, int NRB>
+template <int NCB, int NRB, bool BF>
 __global__ void __launch_bounds__(256)
 k_tsqr_mfma(int leaf_begin, int nleaves_cls, const int32_t* __restrict__ leaf_prob,
             const int32_t* __restrict__ leaf_idx, const ProbDesc* __restrict__ probs, int n,
@@ -325,7 +411,7 @@ k_tsqr_mfma(int leaf_begin, int nleaves_cls, const int32_t* __restrict__ leaf_pr
           X[rb][q][v] = (row < r1 && col < L) ? Xg[row * ldx + col] : 0.f;
         }
       }
-    merge_tile<NCB, NRB, false>(R, X, 0, lds, lane);
+    merge_tile<NCB, NRB, false, BF>(R, X, 0, lds, lane);
   }
 
   // ---- pairwise merges up the problem's tree, in the same launch ----------------------------
@@ -355,7 +441,7 @@ k_tsqr_mfma(int leaf_begin, int nleaves_cls, const int32_t* __restrict__ leaf_pr
     __threadfence();
     const int left = slot & ~1;
     load_tri<NCB>(pslots + (base + left) * SLOT, R, lane);
-    merge_stored_tri<NCB>(R, pslots + (base + left + 1) * SLOT, lds, lane);
+    merge_stored_tri<NCB, BF>(R, pslots + (base + left + 1) * SLOT, lds, lane);
     base += nl;
     cbase += nn;
     slot = parent;
@@ -381,12 +467,17 @@ k_tsqr_mfma(int leaf_begin, int nleaves_cls, const int32_t* __restrict__ leaf_pr
 }
 
 template <int NCB, int NRB>
-hipError_t launch_tsqr_mfma_ncb(int leaf_begin, int nleaves_cls, const int32_t* leaf_prob, const int32_t* leaf_idx,
-                                const ProbDesc* probs, int n, const float* Red, const double* d, const double* lam,
-                                float* slots, int* counters, float* RB, hipStream_t st) {
+hipError_t launch_tsqr_mfma_ncb(bool bf16x3, int leaf_begin, int nleaves_cls, const int32_t* leaf_prob,
+                                const int32_t* leaf_idx, const ProbDesc* probs, int n, const float* Red,
+                                const double* d, const double* lam, float* slots, int* counters, float* RB,
+                                hipStream_t st) {
   const int grid = (nleaves_cls + 3) / 4;
-  hipLaunchKernelGGL((k_tsqr_mfma<NCB, NRB>), dim3(grid), dim3(256), 0, st, leaf_begin, nleaves_cls, leaf_prob,
-                     leaf_idx, probs, n, Red, d, lam, slots, counters, RB);
+  if (bf16x3)
+    hipLaunchKernelGGL((k_tsqr_mfma<NCB, NRB, true>), dim3(grid), dim3(256), 0, st, leaf_begin, nleaves_cls,
+                       leaf_prob, leaf_idx, probs, n, Red, d, lam, slots, counters, RB);
+  else
+    hipLaunchKernelGGL((k_tsqr_mfma<NCB, NRB, false>), dim3(grid), dim3(256), 0, st, leaf_begin, nleaves_cls,
+                       leaf_prob, leaf_idx, probs, n, Red, d, lam, slots, counters, RB);
   return hipGetLastError();
 }
 
