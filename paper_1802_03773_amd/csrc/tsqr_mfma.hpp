@@ -151,20 +151,20 @@ __device__ __forceinline__ void merge_tile(f4 (&R)[Tri<NCB>::count], f4 (&X)[NRB
             ps0 += X[rb][P][v] * X[rb][P][v];
         }
       const float ps = sum_rows4(ps0 + ps1);
-      const float sigma = read_lane(ps, j);
+      const float sigma = row_bcast<j>(ps);  // every row of the wave holds column j's sum
       const float alpha = read_lane(R[rp][j & 3], (j >> 2) * 16 + j);
-      float beta = alpha, tau = 0.f, scale = 0.f;
       // sigma below the smallest normal float counts as zero (identity reflector).  A leaf
       // that starts from a zero triangle reflects the roundoff left in the columns beyond the
       // rank of its first tiles; that residue shrinks by about eps per tile height and can
       // reach the subnormal range, where the hardware square root returns 0 and the scale
-      // 1 / (alpha - beta) would be infinite.
-      if (sigma >= 0x1p-126f) {
-        const float nrm = __builtin_amdgcn_sqrtf(alpha * alpha + sigma);
-        beta = alpha >= 0.f ? -nrm : nrm;
-        tau = (beta - alpha) * __builtin_amdgcn_rcpf(beta);
-        scale = __builtin_amdgcn_rcpf(alpha - beta);
-      }
+      // 1 / (alpha - beta) would be infinite.  Selects, not a branch: the whole panel stays
+      // one straight-line block the scheduler can interleave with the matrix-core updates.
+      const bool refl = sigma >= 0x1p-126f;
+      const float nrm = __builtin_amdgcn_sqrtf(alpha * alpha + sigma);
+      const float bneg = alpha >= 0.f ? -nrm : nrm;
+      const float beta = refl ? bneg : alpha;
+      const float tau = refl ? (bneg - alpha) * __builtin_amdgcn_rcpf(bneg) : 0.f;
+      const float scale = refl ? __builtin_amdgcn_rcpf(alpha - bneg) : 0.f;
       // x_j^T x_c for every lane's column c
       float pr0 = 0.f, pr1 = 0.f;
 #pragma unroll
