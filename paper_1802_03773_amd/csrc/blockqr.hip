@@ -8,7 +8,8 @@
 // n), so Q_i^T is applied without any cross-lane reduction: each Householder vector is
 // broadcast once through LDS and each lane updates its own columns.  B_i rows are read with
 // consecutive lanes on consecutive columns (coalesced) and the reduced rows are written the
-// same way, into the problem's slice of the reduced-row buffer.
+// same way, into the problem's slice of the reduced-row buffer.  blk_prob == nullptr: a
+// single problem.
 #include "blockqr.hpp"
 #include "qrk_batch.hpp"
 #include "qrk_launch.hpp"
@@ -27,7 +28,7 @@ k_blockqr(int64_t Ktot, int n, const ProbDesc* __restrict__ probs, const int32_t
   const int wv = threadIdx.x >> 6;
   const int64_t nwaves = (int64_t)gridDim.x * 4;
   for (int64_t blk = (int64_t)blockIdx.x * 4 + wv; blk < Ktot; blk += nwaves) {
-    const int pi = __builtin_amdgcn_readfirstlane(blk_prob[blk]);
+    const int pi = blk_prob == nullptr ? 0 : __builtin_amdgcn_readfirstlane(blk_prob[blk]);
     const ProbDesc& P = probs[pi];
     const int64_t r0 = row_off[blk];
     const int m = (int)(row_off[blk + 1] - r0);
@@ -43,14 +44,15 @@ k_blockqr(int64_t Ktot, int n, const ProbDesc* __restrict__ probs, const int32_t
 }
 
 template <typename T>
-hipError_t launch_blockqr(int64_t Ktot, int n, int max_L, int max_rows, const ProbDesc* probs,
+hipError_t launch_blockqr(int64_t Ktot, int n, int max_L, int max_rows, int probs_count, const ProbDesc* probs,
                           const int32_t* blk_prob, const int64_t* row_off, const T* A, const T* B,
                           const T* b, const double* d, const double* lam, T* Rblk, T* Sc, T* Red, int grid,
                           hipStream_t st) {
   const int slots = max_L <= 64 ? 1 : 2;
+  const bool single = probs_count == 1;
   dim3 blk(256), grd(grid);
 #define QRK_BQR(R, S)                                                                                 \
-  hipLaunchKernelGGL((k_blockqr<T, R, S>), grd, blk, 0, st, Ktot, n, probs, blk_prob, row_off, A, B, b, \
+  hipLaunchKernelGGL((k_blockqr<T, R, S>), grd, blk, 0, st, Ktot, n, probs, single ? nullptr : blk_prob, row_off, A, B, b, \
                      d, lam, Rblk, Sc, Red)
   if (max_rows <= 16) {
     if (slots == 1) QRK_BQR(16, 1); else QRK_BQR(16, 2);
@@ -66,7 +68,7 @@ hipError_t launch_blockqr(int64_t Ktot, int n, int max_L, int max_rows, const Pr
 }
 
 #define QRK_INST(T)                                                                                   \
-  template hipError_t launch_blockqr<T>(int64_t, int, int, int, const ProbDesc*, const int32_t*,       \
+  template hipError_t launch_blockqr<T>(int64_t, int, int, int, int, const ProbDesc*, const int32_t*,  \
                                         const int64_t*, const T*, const T*, const T*, const double*,   \
                                         const double*, T*, T*, T*, int, hipStream_t);
 QRK_INST(float)

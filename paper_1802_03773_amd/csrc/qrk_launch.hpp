@@ -13,7 +13,7 @@ namespace qrk {
 // S_i | c_i (Sc, the problem's slice, row stride L_p) and the m_i reduced rows of every
 // block into the problem's slice of Red (row stride ldr_p).  max_rows <= 64.
 template <typename T>
-hipError_t launch_blockqr(int64_t Ktot, int n, int max_L, int max_rows, const ProbDesc* probs,
+hipError_t launch_blockqr(int64_t Ktot, int n, int max_L, int max_rows, int probs_count, const ProbDesc* probs,
                           const int32_t* blk_prob, const int64_t* row_off, const T* A, const T* B,
                           const T* b, const double* d, const double* lam, T* Rblk, T* Sc, T* Red, int grid,
                           hipStream_t st);

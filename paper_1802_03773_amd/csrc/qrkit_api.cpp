@@ -65,7 +65,7 @@ qrk_status factor_ba(qrk_handle h, hipStream_t st) {
   T* RB = static_cast<T*>(h->RB);
   if (launch_zero_ints(h->status, h->P, st) != hipSuccess) return QRK_EHIP;
   int pr = prof_begin(h, 0, st);
-  if (launch_blockqr<T>(h->K, h->n, h->max_L, h->max_rows, h->probs_d, h->blk_prob, h->row_off_d, A, B, b, h->d,
+  if (launch_blockqr<T>(h->K, h->n, h->max_L, h->max_rows, h->P, h->probs_d, h->blk_prob, h->row_off_d, A, B, b, h->d,
                         h->lam_ptr, Rblk, Sc, Red, h->grid_blocks, st) != hipSuccess)
     return QRK_EHIP;
   prof_end(h, pr, st);

@@ -169,6 +169,7 @@ __device__ __forceinline__ double sum16(double x) {
 //   MODE 0 back-substitution: base_i = c_i (last column of S|c), v = p_B, p_i set;
 //   MODE 1 refinement:        base_i = y_i, v = delta_B, p_i incremented;
 //   MODE 2 adjoint:           base_i = y_i, v = u_B, u_i set.
+// blk_prob == nullptr: a single problem (every block belongs to problem 0).
 // ---------------------------------------------------------------------------------
 template <typename T, int MODE>
 __global__ void __launch_bounds__(256)
@@ -191,7 +192,7 @@ k_blocks_solve(int64_t Ktot, int n, const ProbDesc* __restrict__ probs, const in
   for (int64_t base = first; base < Ktot; base += stride) {
     const int64_t blk = base + (grp & 3);
     const bool active = blk < Ktot;
-    const int pi = active ? blk_prob[blk] : cur;
+    const int pi = blk_prob == nullptr ? 0 : (active ? blk_prob[blk] : cur);
     if (pi != cur) {  // uniform within the 16-lane group
       const ProbDesc& P = probs[pi];
       nB = P.nB;
@@ -266,7 +267,7 @@ hipError_t launch_backsub_blocks(const BatchView& bv, const T* Rblk, const T* Sc
                                  hipStream_t st) {
   if (bv.max_L > kMaxDense || bv.n > 8) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_blocks_solve<T, 0>), dim3(bv.solve_grid), dim3(256), 0, st, bv.Ktot, bv.n, bv.probs,
-                     bv.blk_prob, Rblk, Sc, (const double*)p, (const double*)nullptr, p, status);
+                     bv.P == 1 ? nullptr : bv.blk_prob, Rblk, Sc, (const double*)p, (const double*)nullptr, p, status);
   return hipGetLastError();
 }
 
@@ -275,7 +276,7 @@ hipError_t launch_refine_blocks(const BatchView& bv, const T* Rblk, const T* Sc,
                                 const double* delta_B, double* p, hipStream_t st) {
   if (bv.max_L > kMaxDense || bv.n > 8) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_blocks_solve<T, 1>), dim3(bv.solve_grid), dim3(256), 0, st, bv.Ktot, bv.n, bv.probs,
-                     bv.blk_prob, Rblk, Sc, delta_B, y, p, (int*)nullptr);
+                     bv.P == 1 ? nullptr : bv.blk_prob, Rblk, Sc, delta_B, y, p, (int*)nullptr);
   return hipGetLastError();
 }
 
@@ -284,7 +285,7 @@ hipError_t launch_adjoint_blocks(const BatchView& bv, const T* Rblk, const T* Sc
                                  hipStream_t st) {
   if (bv.max_L > kMaxDense || bv.n > 8) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_blocks_solve<T, 2>), dim3(bv.solve_grid), dim3(256), 0, st, bv.Ktot, bv.n, bv.probs,
-                     bv.blk_prob, Rblk, Sc, (const double*)u, y, u, (int*)nullptr);
+                     bv.P == 1 ? nullptr : bv.blk_prob, Rblk, Sc, (const double*)u, y, u, (int*)nullptr);
   return hipGetLastError();
 }
 
@@ -448,9 +449,21 @@ k_refine_dense(const ProbDesc* __restrict__ probs, int n, const double* __restri
   const int nparts = P.nwg;
   const int t = threadIdx.x;
   const int j = t & 127, q = t >> 7;
+  // partials of group q: w = q, q + 8, ...; loaded 16 at a time so the loads overlap, then
+  // added in order
   double s = 0.0;
-  if (j < nB)
-    for (int w = q; w < nparts; w += 8) s += pp[(int64_t)w * kMaxDense + j];
+  if (j < nB) {
+    for (int w0 = q; w0 < nparts; w0 += 8 * 16) {
+      double buf[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int w = w0 + 8 * u;
+        buf[u] = w < nparts ? pp[(int64_t)w * kMaxDense + j] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) s += buf[u];
+    }
+  }
   acc[q][j] = s;
   stage_dense<T>(RBall + P.rboff, L, Rs, Rsd, t, blockDim.x);
   __syncthreads();
