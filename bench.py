@@ -31,23 +31,22 @@ PEAK_FP64_VECTOR_TFLOPS = 78.6
 # (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, factors read off a 256 MiB device copy; the runs
 # and figures are in profiles/blockangular_scale_pmc_traffic.md).  A figure holds only for the
 # workload it was taken on and while the kernel's sources hash to the recorded digest.
+_TSQR_SOURCES = ["paper_1802_03773_amd/csrc/tsqr_mfma.hpp", "paper_1802_03773_amd/csrc/tsqr_mfma.hip",
+                 "paper_1802_03773_amd/csrc/tsqr_mfma_ncb6.hip", "paper_1802_03773_amd/csrc/qrk_device.hpp"]
+_TSQR_DIGEST = "15269bfcacf69cdc72b50c88cb2d11cabc9d96efb3f64e53ab9e76c4906001fc"
 MEASURED_TRAFFIC = {
-    "dense_leaves": {
-        "bytes": (131152.1 * 2.0 + 43062.3) * 1024.0,
-        "lam": 1e-2,
-        "mode": "plain",
-        "sources": ["paper_1802_03773_amd/csrc/tsqr_mfma.hpp", "paper_1802_03773_amd/csrc/tsqr_mfma.hip",
-                    "paper_1802_03773_amd/csrc/tsqr_mfma_ncb6.hip", "paper_1802_03773_amd/csrc/qrk_device.hpp"],
-        "sha256": "1c4e1db8aa262da03997741089b9f2711e7f04b12c467dae2d5876468e75b812",
-    },
+    ("dense_leaves", "plain"): {"bytes": (131342.3 * 2.000 + 43062.3) * 1024.0, "lam": 1e-2,
+                                "sources": _TSQR_SOURCES, "sha256": _TSQR_DIGEST},
+    ("dense_leaves", "bf16x3"): {"bytes": (131284.2 * 2.000 + 43062.3) * 1024.0, "lam": 1e-2,
+                                 "sources": _TSQR_SOURCES, "sha256": _TSQR_DIGEST},
 }
 
 
 def measured_traffic(phase, lam, mode):
     """Bytes per launch for `phase` if a PMC figure matches this workload and these sources."""
     import hashlib
-    rec = MEASURED_TRAFFIC.get(phase)
-    if rec is None or rec["lam"] != lam or rec["mode"] != mode:
+    rec = MEASURED_TRAFFIC.get((phase, mode))
+    if rec is None or rec["lam"] != lam:
         return None
     root = os.path.dirname(os.path.abspath(__file__))
     h = hashlib.sha256()
