@@ -229,7 +229,8 @@ qrk_status qrk_autotune_blockangular(qrk_handle h, double* scale_host, void* str
 /* ------------------------------------------------------------------------------
  * Levenberg-Marquardt driver (Backtrack LM of Section 5.2) for the synthetic model
  *     f(x) = J0 phi(x) - y,   phi(t) = t + c t^3 elementwise,   J(x) = J0 diag(phi'(x)),
- * on every problem of a block-angular handle (single or batched; J(x) keeps J0's pattern).
+ * on every problem of a block-angular handle (single or batched) or of a banded handle (P
+ * stacked problems); J(x) keeps J0's pattern.
  * One iteration, per problem, entirely on the device:
  *     J(x), b = -f(x) (stored in the handle's type), d = column norms of J(x) (1 for a zero
  *     column), F = |f|^2/2;  p = the handle's factor + solve with `sweeps` refinement sweeps;
@@ -240,7 +241,10 @@ qrk_status qrk_autotune_blockangular(qrk_handle h, double* scale_host, void* str
  *   for the life of the driver]; c finite; 0 <= sweeps <= 8; max_log >= 0 iterations of
  *   log kept.  The driver uses the handle's factor workspace (do not factor on the handle
  *   while a run is in flight).  Allocates its state (J(x), -f, x, p, d, damping, log).
- * qrk_lm_reset: x0 [device, N] and lambda0 [device, P] doubles; nu = 2; clears the log and
+ * qrk_lm_create_banded: row_start [device, P x M int32, nondecreasing, <= N - w], vals0
+ *   [device, P x M x w] and y [device, P x M] in the handle's type, borrowed; the other
+ *   arguments as above.  QRK_EINVAL for M < 1.
+ * qrk_lm_reset: x0 [device, N (all problems: P x N for banded handles)] and lambda0 [device, P] doubles; nu = 2; clears the log and
  *   the iteration counter.  Stream-ordered.
  * qrk_lm_run: `iters` iterations on `stream`.  use_graph = 0 enqueues them one by one;
  *   use_graph != 0 captures one iteration into a HIP graph on the driver's own stream at
@@ -252,6 +256,8 @@ qrk_status qrk_autotune_blockangular(qrk_handle h, double* scale_host, void* str
 typedef struct qrk_lm_s* qrk_lm;
 qrk_status qrk_lm_create_blockangular(qrk_handle h, const void* A0, const void* B0, const void* y, double c,
                                       int32_t sweeps, int32_t max_log, qrk_lm* out);
+qrk_status qrk_lm_create_banded(qrk_handle h, const int32_t* row_start, const void* vals0, const void* y, double c,
+                                int32_t sweeps, int32_t max_log, qrk_lm* out);
 qrk_status qrk_lm_reset(qrk_lm lm, const double* x0, const double* lambda0, void* stream);
 qrk_status qrk_lm_run(qrk_lm lm, int32_t iters, int32_t use_graph, void* stream);
 qrk_status qrk_lm_get(qrk_lm lm, double* x, double* lambda, double* log, int32_t* iters_host, void* stream);

@@ -56,11 +56,12 @@ template <typename T, int G>
 __global__ void __launch_bounds__(256)
 k_banded_givens(int P, int64_t M, int64_t N, int w, const int32_t* __restrict__ row_start,
                 const T* __restrict__ vals, const T* __restrict__ bvec, const double* __restrict__ d,
-                double sqrt_lam, T* __restrict__ Rb, T* __restrict__ cb, int* __restrict__ status) {
+                const double* __restrict__ lam, T* __restrict__ Rb, T* __restrict__ cb, int* __restrict__ status) {
   constexpr int W = G - 1;
   const int lane = threadIdx.x % G;
   const int64_t prob = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
   if (prob >= P) return;
+  const double sqrt_lam = sqrt(lam[prob]);
   const int32_t* rs = row_start + prob * M;
   const T* V = vals + prob * M * w;
   const T* bb = bvec + prob * M;
@@ -228,10 +229,11 @@ template <typename T, int G>
 __global__ void __launch_bounds__(256)
 k_banded_jt(int P, int64_t M, int64_t N, int w, const int32_t* __restrict__ row_start,
             const T* __restrict__ vals, const double* __restrict__ r, const double* __restrict__ d,
-            double lam, const double* __restrict__ v, double* __restrict__ g) {
+            const double* __restrict__ lamv, const double* __restrict__ v, double* __restrict__ g) {
   const int lane = threadIdx.x % G;
   const int64_t prob = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
   if (prob >= P) return;
+  const double lam = lamv[prob];
   const int32_t* rs = row_start + prob * M;
   double acc = 0.0;  // lane l accumulates column s + l
   int64_t s = 0;
@@ -284,10 +286,10 @@ k_banded_dvals(int P, int64_t M, int64_t N, int w, const int32_t* __restrict__ r
 
 template <typename T>
 hipError_t launch_banded_givens(int P, int64_t M, int64_t N, int w, const int32_t* row_start,
-                                const T* vals, const T* b, const double* d, double sqrt_lam, T* Rb,
+                                const T* vals, const T* b, const double* d, const double* lam, T* Rb,
                                 T* cb, int* status, hipStream_t st) {
   if (w < 1 || w > 31) return hipErrorInvalidValue;
-  QRK_G_DISPATCH(k_banded_givens, T, P, M, N, w, row_start, vals, b, d, sqrt_lam, Rb, cb, status);
+  QRK_G_DISPATCH(k_banded_givens, T, P, M, N, w, row_start, vals, b, d, lam, Rb, cb, status);
   return hipGetLastError();
 }
 
@@ -340,7 +342,7 @@ hipError_t launch_banded_apply(int P, int64_t M, int64_t N, int w, const int32_t
 
 template <typename T>
 hipError_t launch_banded_jt(int P, int64_t M, int64_t N, int w, const int32_t* row_start, const T* vals,
-                            const double* r, const double* d, double lam, const double* v, double* g,
+                            const double* r, const double* d, const double* lam, const double* v, double* g,
                             hipStream_t st) {
   QRK_G_DISPATCH(k_banded_jt, T, P, M, N, w, row_start, vals, r, d, lam, v, g);
   return hipGetLastError();
@@ -358,7 +360,7 @@ hipError_t launch_banded_dvals(int P, int64_t M, int64_t N, int w, const int32_t
 
 #define QRK_BINST(T)                                                                                     \
   template hipError_t launch_banded_givens<T>(int, int64_t, int64_t, int, const int32_t*, const T*,        \
-                                              const T*, const double*, double, T*, T*, int*, hipStream_t); \
+                                              const T*, const double*, const double*, T*, T*, int*, hipStream_t); \
   template hipError_t launch_banded_backsub<T>(int, int64_t, int, const T*, const T*, double*, int*,       \
                                                hipStream_t);                                              \
   template hipError_t launch_banded_solve_add<T>(int, int64_t, int, const T*, const double*, double*,      \
@@ -368,7 +370,7 @@ hipError_t launch_banded_dvals(int P, int64_t M, int64_t N, int w, const int32_t
   template hipError_t launch_banded_apply<T>(int, int64_t, int64_t, int, const int32_t*, const T*,         \
                                              const T*, const double*, double*, hipStream_t);              \
   template hipError_t launch_banded_jt<T>(int, int64_t, int64_t, int, const int32_t*, const T*,            \
-                                          const double*, const double*, double, const double*, double*,   \
+                                          const double*, const double*, const double*, const double*, double*, \
                                           hipStream_t);                                                   \
   template hipError_t launch_banded_dvals<T>(int, int64_t, int64_t, int, const int32_t*, const double*,    \
                                              const double*, const double*, const double*, T*, hipStream_t);

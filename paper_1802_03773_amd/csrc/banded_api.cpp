@@ -32,7 +32,7 @@ qrk_status banded_solve_t(qrk_handle h, double* p, int sweeps, hipStream_t st) {
     if (launch_banded_apply<T>(h->P, h->M, h->N, h->w, h->row_start, static_cast<const T*>(h->A),
                                static_cast<const T*>(h->b), p, h->rbuf, st) != hipSuccess ||
         launch_banded_jt<T>(h->P, h->M, h->N, h->w, h->row_start, static_cast<const T*>(h->A), h->rbuf,
-                            h->d, h->lam, p, h->gbuf, st) != hipSuccess ||
+                            h->d, h->lam_ptr, p, h->gbuf, st) != hipSuccess ||
         launch_banded_fwd<T>(h->P, h->N, h->w, R, h->gbuf, h->gbuf, st) != hipSuccess ||
         launch_banded_solve_add<T>(h->P, h->N, h->w, R, h->gbuf, p, st) != hipSuccess)
       return QRK_EHIP;
@@ -100,6 +100,7 @@ qrk_status create_banded(int32_t P, int64_t M, int64_t N, int32_t w, qrk_dtype d
       (s = handle_alloc(h, reinterpret_cast<void**>(&h->ubuf), sizeof(double) * PN)) != QRK_OK ||
       (s = handle_alloc(h, reinterpret_cast<void**>(&h->vecpart),
                         sizeof(double) * (size_t)(P > 1024 ? P : 1024))) != QRK_OK ||
+      (s = handle_alloc(h, reinterpret_cast<void**>(&h->lam_d), sizeof(double) * (size_t)P)) != QRK_OK ||
       (s = handle_alloc(h, reinterpret_cast<void**>(&h->status), sizeof(int) * 4)) != QRK_OK) {
     handle_free(h);
     delete h;
@@ -149,22 +150,33 @@ qrk_status qrk_factor_banded(qrk_handle h, const int32_t* row_start, const void*
   h->lam = lambda;
   h->factored = true;
   hipStream_t st = S(stream);
+  if (launch_fill_double(h->lam_d, h->P, lambda, st) != hipSuccess) return QRK_EHIP;
+  h->lam_ptr = h->lam_d;
+  return banded_factor(h, st);
+}
+
+}  // extern "C"
+
+// Givens QR of every problem of a banded handle with its current (borrowed) inputs and
+// the damping at h->lam_ptr ([P], device).
+qrk_status banded_factor(qrk_handle h, hipStream_t st) {
   if (launch_fill_int(h->status, 0, st) != hipSuccess) return QRK_EHIP;
-  const double sq = std::sqrt(lambda);
+  const int32_t* row_start = h->row_start;
+  const void* vals = h->A;
+  const void* b = h->b;
+  const double* d = h->d;
   int pr = prof_begin(h, 5, st);
   hipError_t e = h->dtype == QRK_F32
                      ? launch_banded_givens<float>(h->P, h->M, h->N, h->w, row_start,
                                                    static_cast<const float*>(vals),
-                                                   static_cast<const float*>(b), d, sq,
+                                                   static_cast<const float*>(b), d, h->lam_ptr,
                                                    static_cast<float*>(h->bandR),
                                                    static_cast<float*>(h->bandc), h->status, st)
                      : launch_banded_givens<double>(h->P, h->M, h->N, h->w, row_start,
                                                     static_cast<const double*>(vals),
-                                                    static_cast<const double*>(b), d, sq,
+                                                    static_cast<const double*>(b), d, h->lam_ptr,
                                                     static_cast<double*>(h->bandR),
                                                     static_cast<double*>(h->bandc), h->status, st);
   prof_end(h, pr, st);
   return e == hipSuccess ? QRK_OK : QRK_EHIP;
 }
-
-}  // extern "C"

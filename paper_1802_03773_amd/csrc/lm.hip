@@ -191,6 +191,91 @@ k_lmba_reduce(const ProbDesc* __restrict__ probs, int n, const double* __restric
 }
 
 // ---------------------------------------------------------------------------------------
+// Banded model evaluation (P problems of M rows, N unknowns, w values per row starting at the
+// nondecreasing column row_start[i]).  Rows: one thread per row, grid (ceil(M/256), P);
+// JAC writes J(x) = vals0 diag(phi'(x)), b = -f and f, at x; !JAC evaluates at x + p.  Both
+// write per-workgroup partials of sum f^2.  Columns: one thread per column, summing over the
+// rows that cover it (found by binary search on row_start) in row order.
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ int64_t lm_row_start(const int32_t* rs, int64_t i, int64_t N, int w) {
+  int64_t s = rs[i];
+  return s < 0 ? 0 : (s > N - w ? N - w : s);
+}
+
+template <typename T, bool JAC>
+__global__ void __launch_bounds__(256)
+k_lmbd_rows(int64_t M, int64_t N, int w, const int32_t* __restrict__ row_start, const T* __restrict__ vals0,
+            const T* __restrict__ y, double c, const double* __restrict__ x, const double* __restrict__ pstep,
+            T* __restrict__ vals, T* __restrict__ b, double* __restrict__ f, double* __restrict__ fpart) {
+  __shared__ double red[256];
+  const int64_t prob = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double fi = 0.0;
+  if (i < M) {
+    const int64_t row = prob * M + i;
+    const int64_t s = lm_row_start(row_start + prob * M, i, N, w);
+    for (int k = 0; k < w; ++k) {
+      const int64_t col = prob * N + s + k;
+      const double u = x[col] + (JAC ? 0.0 : pstep[col]);
+      const double v0 = (double)vals0[row * w + k];
+      fi += v0 * lm_phi(u, c);
+      if (JAC) vals[row * w + k] = (T)(v0 * lm_dphi(u, c));
+    }
+    fi -= (double)y[row];
+    if (JAC) {
+      b[row] = (T)(-fi);
+      f[row] = fi;
+    }
+  }
+  red[threadIdx.x] = fi * fi;
+  __syncthreads();
+  for (int h = 128; h >= 1; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) fpart[prob * gridDim.x + blockIdx.x] = red[0];
+}
+
+__global__ void k_lmbd_fsum(int nblk, const double* __restrict__ fpart, double* __restrict__ Fout) {
+  const int prob = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int k = 0; k < nblk; ++k) s += fpart[(int64_t)prob * nblk + k];
+  Fout[prob] = 0.5 * s;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_lmbd_cols(int64_t M, int64_t N, int w, const int32_t* __restrict__ row_start, const T* __restrict__ vals,
+            const double* __restrict__ f, double* __restrict__ d, double* __restrict__ gJ) {
+  const int64_t prob = blockIdx.y;
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= N) return;
+  const int32_t* rs = row_start + prob * M;
+  // rows with j - w + 1 <= s_i <= j
+  int64_t lo = 0, hi = M;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) / 2;
+    if (lm_row_start(rs, mid, N, w) < j - w + 1) lo = mid + 1; else hi = mid;
+  }
+  int64_t e = lo, eh = M;
+  while (e < eh) {
+    const int64_t mid = (e + eh) / 2;
+    if (lm_row_start(rs, mid, N, w) <= j) e = mid + 1; else eh = mid;
+  }
+  double sq = 0.0, gf = 0.0;
+  for (int64_t i = lo; i < e; ++i) {
+    const int64_t k = j - lm_row_start(rs, i, N, w);
+    if (k < 0 || k >= w) continue;
+    const double v = (double)vals[(prob * M + i) * w + k];
+    sq += v * v;
+    gf += v * f[prob * M + i];
+  }
+  d[prob * N + j] = sq > 0.0 ? sqrt(sq) : 1.0;
+  gJ[prob * N + j] = gf;
+}
+
+// ---------------------------------------------------------------------------------------
 // Problem-generic pieces (unknowns of problem p: [noff[p], noff[p+1])).
 // ---------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(256)
@@ -305,10 +390,37 @@ hipError_t launch_lm_init(int P, double* nu, int* iter, hipStream_t st) {
   return hipGetLastError();
 }
 
+
+template <typename T>
+hipError_t launch_lmbd_eval(int P, int64_t M, int64_t N, int w, bool jac, const int32_t* row_start, const T* vals0,
+                            const T* y, double c, const double* x, const double* p, T* vals, T* b, double* f,
+                            double* d, double* gJ, double* fpart, double* Fout, hipStream_t st) {
+  const int nblk = (int)((M + 255) / 256);
+  if (P < 1 || nblk < 1) return hipErrorInvalidValue;
+  dim3 grd(nblk, P);
+  if (jac)
+    hipLaunchKernelGGL((k_lmbd_rows<T, true>), grd, dim3(256), 0, st, M, N, w, row_start, vals0, y, c, x, p, vals, b,
+                       f, fpart);
+  else
+    hipLaunchKernelGGL((k_lmbd_rows<T, false>), grd, dim3(256), 0, st, M, N, w, row_start, vals0, y, c, x, p, vals,
+                       b, f, fpart);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_lmbd_fsum, dim3(P), dim3(64), 0, st, nblk, fpart, Fout);
+  e = hipGetLastError();
+  if (e != hipSuccess || !jac) return e;
+  hipLaunchKernelGGL((k_lmbd_cols<T>), dim3((unsigned)((N + 255) / 256), P), dim3(256), 0, st, M, N, w, row_start,
+                     vals, f, d, gJ);
+  return hipGetLastError();
+}
+
 #define QRK_INST(T)                                                                                      \
   template hipError_t launch_lmba_eval<T>(const BatchView&, bool, const T*, const T*, const T*, double,    \
                                           const double*, const double*, T*, T*, T*, double*, double*,      \
-                                          double*, double*, double*, hipStream_t);
+                                          double*, double*, double*, hipStream_t);                         \
+  template hipError_t launch_lmbd_eval<T>(int, int64_t, int64_t, int, bool, const int32_t*, const T*, const T*,  \
+                                          double, const double*, const double*, T*, T*, double*, double*, double*, \
+                                          double*, double*, hipStream_t);
 QRK_INST(float)
 QRK_INST(double)
 #undef QRK_INST

@@ -1,4 +1,4 @@
-// Host side of the Levenberg-Marquardt driver: state ownership, one iteration as a sequence
+// Host side of the Levenberg-Marquardt driver (block-angular and banded handles): state ownership, one iteration as a sequence
 // of stream-ordered launches (model evaluation, the structured factor and solve, gain ratio
 // and damping update), and its capture into a HIP graph that is replayed per iteration.
 #include <hip/hip_runtime.h>
@@ -17,8 +17,9 @@ using namespace qrk;
 
 struct qrk_lm_s {
   qrk_handle h = nullptr;
-  const void* A0 = nullptr;
+  const void* A0 = nullptr;  // block-angular: A0; banded: vals0
   const void* B0 = nullptr;
+  const int32_t* row_start = nullptr;  // banded
   const void* y = nullptr;
   double c = 0.0;
   int sweeps = 1;
@@ -29,6 +30,7 @@ struct qrk_lm_s {
   double *x = nullptr, *p = nullptr, *d = nullptr, *gJ = nullptr;
   double *F = nullptr, *Fnew = nullptr, *pred = nullptr, *lam = nullptr, *nu = nullptr;
   double *part = nullptr, *fpart = nullptr, *log = nullptr;
+  double* f = nullptr;  // banded: f(x) per row
   int *acc = nullptr, *iter = nullptr;
   int64_t* noff = nullptr;
   std::vector<void*> allocs;
@@ -40,6 +42,9 @@ struct qrk_lm_s {
 namespace {
 
 inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Unknowns over all problems (banded handles keep N per problem).
+int64_t lm_unknowns(qrk_lm lm) { return lm->h->kind == KIND_BANDED ? (int64_t)lm->h->P * lm->h->N : lm->h->N; }
 
 template <typename P>
 qrk_status lm_alloc(qrk_lm lm, P** out, size_t bytes) {
@@ -94,8 +99,68 @@ qrk_status lm_iteration(qrk_lm lm, hipStream_t st) {
   return QRK_OK;
 }
 
+// One LM iteration on a banded handle (P stacked problems).
+template <typename T>
+qrk_status lm_iteration_banded(qrk_lm lm, hipStream_t st) {
+  qrk_handle h = lm->h;
+  T* vals = static_cast<T*>(lm->A);
+  T* b = static_cast<T*>(lm->b);
+  const T* vals0 = static_cast<const T*>(lm->A0);
+  const T* y = static_cast<const T*>(lm->y);
+  if (launch_lmbd_eval<T>(h->P, h->M, h->N, h->w, true, lm->row_start, vals0, y, lm->c, lm->x, nullptr, vals, b,
+                          lm->f, lm->d, lm->gJ, lm->fpart, lm->F, st) != hipSuccess)
+    return QRK_EHIP;
+  h->row_start = lm->row_start;
+  h->A = vals;
+  h->b = b;
+  h->d = lm->d;
+  h->lam_ptr = lm->lam;
+  h->factored = true;
+  qrk_status s;
+  if ((s = banded_factor(h, st)) != QRK_OK) return s;
+  if ((s = banded_solve(h, lm->p, lm->sweeps, st)) != QRK_OK) return s;
+  if (launch_lm_control(h->P, lm->noff, lm->p, lm->d, lm->gJ, lm->lam, lm->nu, lm->F, lm->Fnew, lm->pred, lm->acc,
+                        lm->iter, lm->log, lm->max_log, lm->x, st, 0) != hipSuccess)
+    return QRK_EHIP;
+  if (launch_lmbd_eval<T>(h->P, h->M, h->N, h->w, false, lm->row_start, vals0, y, lm->c, lm->x, lm->p, vals, b,
+                          lm->f, lm->d, lm->gJ, lm->fpart, lm->Fnew, st) != hipSuccess)
+    return QRK_EHIP;
+  if (launch_lm_control(h->P, lm->noff, lm->p, lm->d, lm->gJ, lm->lam, lm->nu, lm->F, lm->Fnew, lm->pred, lm->acc,
+                        lm->iter, lm->log, lm->max_log, lm->x, st, 1) != hipSuccess)
+    return QRK_EHIP;
+  return QRK_OK;
+}
+
 qrk_status lm_enqueue(qrk_lm lm, hipStream_t st) {
+  if (lm->h->kind == KIND_BANDED)
+    return lm->h->dtype == QRK_F32 ? lm_iteration_banded<float>(lm, st) : lm_iteration_banded<double>(lm, st);
   return lm->h->dtype == QRK_F32 ? lm_iteration<float>(lm, st) : lm_iteration<double>(lm, st);
+}
+
+// State shared by both structures: x, p, d, J^T f (N_tot), per-problem scalars, the log and
+// the unknown offsets of the problems.
+qrk_status lm_alloc_common(qrk_lm lm, const std::vector<int64_t>& noff) {
+  const size_t P = (size_t)noff.size() - 1, N = (size_t)noff.back();
+  qrk_status s;
+  if ((s = lm_alloc(lm, &lm->x, sizeof(double) * N)) != QRK_OK ||
+      (s = lm_alloc(lm, &lm->p, sizeof(double) * N)) != QRK_OK ||
+      (s = lm_alloc(lm, &lm->d, sizeof(double) * N)) != QRK_OK ||
+      (s = lm_alloc(lm, &lm->gJ, sizeof(double) * N)) != QRK_OK ||
+      (s = lm_alloc(lm, &lm->F, sizeof(double) * P)) != QRK_OK ||
+      (s = lm_alloc(lm, &lm->Fnew, sizeof(double) * P)) != QRK_OK ||
+      (s = lm_alloc(lm, &lm->pred, sizeof(double) * P)) != QRK_OK ||
+      (s = lm_alloc(lm, &lm->lam, sizeof(double) * P)) != QRK_OK ||
+      (s = lm_alloc(lm, &lm->nu, sizeof(double) * P)) != QRK_OK ||
+      (s = lm_alloc(lm, &lm->acc, sizeof(int) * P)) != QRK_OK ||
+      (s = lm_alloc(lm, &lm->iter, sizeof(int))) != QRK_OK ||
+      (s = lm_alloc(lm, &lm->log, sizeof(double) * (size_t)(lm->max_log > 0 ? lm->max_log : 1) * P * 4)) !=
+          QRK_OK ||
+      (s = lm_alloc(lm, &lm->noff, sizeof(int64_t) * (P + 1))) != QRK_OK)
+    return s;
+  if (hipMemcpy(lm->noff, noff.data(), sizeof(int64_t) * (P + 1), hipMemcpyHostToDevice) != hipSuccess ||
+      hipStreamCreateWithFlags(&lm->cap, hipStreamNonBlocking) != hipSuccess)
+    return QRK_EHIP;
+  return QRK_OK;
 }
 
 }  // namespace
@@ -125,35 +190,49 @@ qrk_status qrk_lm_create_blockangular(qrk_handle h, const void* A0, const void* 
     btot += D.M * D.ldb;
     noff[q + 1] = D.noff + D.K * h->n + D.nB;
   }
-  const size_t P = (size_t)h->P, N = (size_t)h->N;
   qrk_status s;
   if ((s = lm_alloc(lm, &lm->A, es * (size_t)h->M * h->n)) != QRK_OK ||
       (s = lm_alloc(lm, &lm->B, es * (size_t)btot)) != QRK_OK ||
       (s = lm_alloc(lm, &lm->b, es * (size_t)h->M)) != QRK_OK ||
-      (s = lm_alloc(lm, &lm->x, sizeof(double) * N)) != QRK_OK ||
-      (s = lm_alloc(lm, &lm->p, sizeof(double) * N)) != QRK_OK ||
-      (s = lm_alloc(lm, &lm->d, sizeof(double) * N)) != QRK_OK ||
-      (s = lm_alloc(lm, &lm->gJ, sizeof(double) * N)) != QRK_OK ||
-      (s = lm_alloc(lm, &lm->F, sizeof(double) * P)) != QRK_OK ||
-      (s = lm_alloc(lm, &lm->Fnew, sizeof(double) * P)) != QRK_OK ||
-      (s = lm_alloc(lm, &lm->pred, sizeof(double) * P)) != QRK_OK ||
-      (s = lm_alloc(lm, &lm->lam, sizeof(double) * P)) != QRK_OK ||
-      (s = lm_alloc(lm, &lm->nu, sizeof(double) * P)) != QRK_OK ||
-      (s = lm_alloc(lm, &lm->acc, sizeof(int) * P)) != QRK_OK ||
-      (s = lm_alloc(lm, &lm->iter, sizeof(int))) != QRK_OK ||
       (s = lm_alloc(lm, &lm->part, sizeof(double) * (size_t)h->nwg * 2 * kMaxDense)) != QRK_OK ||
       (s = lm_alloc(lm, &lm->fpart, sizeof(double) * (size_t)h->nwg)) != QRK_OK ||
-      (s = lm_alloc(lm, &lm->log, sizeof(double) * (size_t)(max_log > 0 ? max_log : 1) * P * 4)) != QRK_OK ||
-      (s = lm_alloc(lm, &lm->noff, sizeof(int64_t) * (P + 1))) != QRK_OK) {
+      (s = lm_alloc_common(lm, noff)) != QRK_OK) {
     lm_free(lm);
     delete lm;
     return s;
   }
-  if (hipMemcpy(lm->noff, noff.data(), sizeof(int64_t) * (P + 1), hipMemcpyHostToDevice) != hipSuccess ||
-      hipStreamCreateWithFlags(&lm->cap, hipStreamNonBlocking) != hipSuccess) {
+  *out = lm;
+  return QRK_OK;
+}
+
+qrk_status qrk_lm_create_banded(qrk_handle h, const int32_t* row_start, const void* vals0, const void* y, double c,
+                                int32_t sweeps, int32_t max_log, qrk_lm* out) {
+  if (!out) return QRK_EINVAL;
+  *out = nullptr;
+  if (!h || h->kind != KIND_BANDED || !row_start || !vals0 || !y || h->M < 1) return QRK_EINVAL;
+  if (!std::isfinite(c) || sweeps < 0 || sweeps > 8 || max_log < 0) return QRK_EINVAL;
+  qrk_lm lm = new (std::nothrow) qrk_lm_s();
+  if (!lm) return QRK_ENOMEM;
+  lm->h = h;
+  lm->A0 = vals0;
+  lm->row_start = row_start;
+  lm->y = y;
+  lm->c = c;
+  lm->sweeps = sweeps;
+  lm->max_log = max_log;
+  const size_t es = h->dtype == QRK_F32 ? 4 : 8;
+  const size_t PM = (size_t)h->P * h->M;
+  std::vector<int64_t> noff(h->P + 1, 0);
+  for (int q = 0; q < h->P; ++q) noff[q + 1] = noff[q] + h->N;
+  const size_t nblk = (size_t)((h->M + 255) / 256);
+  qrk_status s;
+  if ((s = lm_alloc(lm, &lm->A, es * PM * h->w)) != QRK_OK || (s = lm_alloc(lm, &lm->b, es * PM)) != QRK_OK ||
+      (s = lm_alloc(lm, &lm->f, sizeof(double) * PM)) != QRK_OK ||
+      (s = lm_alloc(lm, &lm->fpart, sizeof(double) * nblk * h->P)) != QRK_OK ||
+      (s = lm_alloc_common(lm, noff)) != QRK_OK) {
     lm_free(lm);
     delete lm;
-    return QRK_EHIP;
+    return s;
   }
   *out = lm;
   return QRK_OK;
@@ -163,7 +242,8 @@ qrk_status qrk_lm_reset(qrk_lm lm, const double* x0, const double* lambda0, void
   if (!lm || !x0 || !lambda0) return QRK_EINVAL;
   hipStream_t st = S(stream);
   const int P = lm->h->P;
-  if (hipMemcpyAsync(lm->x, x0, sizeof(double) * (size_t)lm->h->N, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+  if (hipMemcpyAsync(lm->x, x0, sizeof(double) * (size_t)lm_unknowns(lm), hipMemcpyDeviceToDevice, st) !=
+          hipSuccess ||
       hipMemcpyAsync(lm->lam, lambda0, sizeof(double) * (size_t)P, hipMemcpyDeviceToDevice, st) != hipSuccess ||
       launch_lm_init(P, lm->nu, lm->iter, st) != hipSuccess ||
       launch_fill_double(lm->log, (int64_t)(lm->max_log > 0 ? lm->max_log : 1) * P * 4, 0.0, st) != hipSuccess)
@@ -213,7 +293,8 @@ qrk_status qrk_lm_get(qrk_lm lm, double* x, double* lambda, double* log, int32_t
   if (!lm) return QRK_EINVAL;
   hipStream_t st = S(stream);
   const size_t P = (size_t)lm->h->P;
-  if (x && hipMemcpyAsync(x, lm->x, sizeof(double) * (size_t)lm->h->N, hipMemcpyDeviceToDevice, st) != hipSuccess)
+  if (x && hipMemcpyAsync(x, lm->x, sizeof(double) * (size_t)lm_unknowns(lm), hipMemcpyDeviceToDevice, st) !=
+               hipSuccess)
     return QRK_EHIP;
   if (lambda && hipMemcpyAsync(lambda, lm->lam, sizeof(double) * P, hipMemcpyDeviceToDevice, st) != hipSuccess)
     return QRK_EHIP;

@@ -10,7 +10,7 @@ namespace qrk {
 
 template <typename T>
 hipError_t launch_banded_givens(int P, int64_t M, int64_t N, int w, const int32_t* row_start,
-                                const T* vals, const T* b, const double* d, double sqrt_lam, T* Rb,
+                                const T* vals, const T* b, const double* d, const double* lam, T* Rb,
                                 T* cb, int* status, hipStream_t st);
 // p = R^{-1} c (status: singular pivots, non-finite results)
 template <typename T>
@@ -31,7 +31,7 @@ hipError_t launch_banded_apply(int P, int64_t M, int64_t N, int w, const int32_t
 // g = J^T r - lam d^2 v, float64, [P][N]
 template <typename T>
 hipError_t launch_banded_jt(int P, int64_t M, int64_t N, int w, const int32_t* row_start, const T* vals,
-                            const double* r, const double* d, double lam, const double* v, double* g,
+                            const double* r, const double* d, const double* lam, const double* v, double* g,
                             hipStream_t st);
 // dvals[i][l] = r_i u_{s_i+l} - (J u)_i p_{s_i+l}
 template <typename T>

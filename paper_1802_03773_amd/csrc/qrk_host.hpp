@@ -115,7 +115,6 @@ struct qrk_handle_s {
   bool factored = false;
 };
 
-qrk_status banded_solve(qrk_handle h, double* p, int sweeps, hipStream_t st);
 qrk_status banded_adjoint(qrk_handle h, const double* p, const double* g, void* dvals, void* db,
                           double* dlam, double* dd, hipStream_t st);
 qrk_status blockangular_adjoint(qrk_handle h, const double* p, const double* g, void* dA, void* dB,
@@ -126,6 +125,9 @@ qrk_status blockangular_adjoint(qrk_handle h, const double* p, const double* g, 
 qrk_status blockangular_factor(qrk_handle h, hipStream_t st);
 qrk_status blockangular_solve(qrk_handle h, double* p, int sweeps, hipStream_t st);
 qrk::BatchView blockangular_view(qrk_handle h);
+// Banded factor / solve on the handle's current inputs and damping ([P] at h->lam_ptr).
+qrk_status banded_factor(qrk_handle h, hipStream_t st);
+qrk_status banded_solve(qrk_handle h, double* p, int sweeps, hipStream_t st);
 
 // Workspace allocation shared by the create functions (records the allocation in h).
 qrk_status handle_alloc(qrk_handle h, void** out, size_t bytes);

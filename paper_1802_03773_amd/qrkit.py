@@ -42,6 +42,7 @@ _SIGS = {
     "qrk_autotune_blockangular": (_c_i32, [_c_vp, ctypes.POINTER(_c_dbl), _c_vp]),
     "qrk_lm_create_blockangular": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_dbl, _c_i32, _c_i32,
                                             ctypes.POINTER(_c_vp)]),
+    "qrk_lm_create_banded": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_dbl, _c_i32, _c_i32, ctypes.POINTER(_c_vp)]),
     "qrk_lm_reset": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp]),
     "qrk_lm_run": (_c_i32, [_c_vp, _c_i32, _c_i32, _c_vp]),
     "qrk_lm_get": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_i32p, _c_vp]),
@@ -400,22 +401,29 @@ def factor_banded(row_start, vals, b, d, lam, N: int, dtype="float32", stream=No
 
 class LMDriver:
     """Backtrack-LM iterations on f(x) = J0 phi(x) - y (phi(t) = t + c t^3) over every problem of
-    a block-angular solver or batch, run by the library (optionally as a replayed HIP graph)."""
+    a block-angular solver or batch or a banded solver, run by the library (optionally as a
+    replayed HIP graph)."""
 
     def __init__(self, solver, A0, B0, y, c: float, sweeps: int = 1, max_log: int = 64):
+        """Block-angular solver or batch: A0, B0 (None without a dense part), y.  Banded solver:
+        A0 is row_start [P*M] int32 and B0 is vals0 [P*M, w]."""
         torch = _torch()
         td = _torch_dtype(solver.qdtype)
         self.solver, self.P = solver, int(getattr(solver, "P", 1))
         self.max_log = int(max_log)
         h = _c_vp()
-        _check(lib().qrk_lm_create_blockangular(solver.handle, _dev_ptr(A0, td, "A0"),
-                                                _dev_ptr(B0, td, "B0") if B0 is not None else None,
-                                                _dev_ptr(y, td, "y"), float(c), int(sweeps), self.max_log,
-                                                ctypes.byref(h)), "qrk_lm_create_blockangular")
+        if isinstance(solver, BandedSolver):
+            _check(lib().qrk_lm_create_banded(solver.handle, _dev_ptr(A0, torch.int32, "row_start"),
+                                              _dev_ptr(B0, td, "vals0"), _dev_ptr(y, td, "y"), float(c),
+                                              int(sweeps), self.max_log, ctypes.byref(h)), "qrk_lm_create_banded")
+        else:
+            _check(lib().qrk_lm_create_blockangular(solver.handle, _dev_ptr(A0, td, "A0"),
+                                                    _dev_ptr(B0, td, "B0") if B0 is not None else None,
+                                                    _dev_ptr(y, td, "y"), float(c), int(sweeps), self.max_log,
+                                                    ctypes.byref(h)), "qrk_lm_create_blockangular")
         self._lm = h
         self._keep = (A0, B0, y)
         self.N = solver.N
-        del torch
 
     def __del__(self):
         h, self._lm = getattr(self, "_lm", None), None
