@@ -84,7 +84,8 @@ def _cpu_threads() -> int:
 
 
 def algorithmic_work(inst):
-    """Per-phase algorithmic bytes / flops of one step (formulas stated in the design doc)."""
+    """Per-phase algorithmic bytes / flops of one step: what the method must move or compute
+    (inputs read once, factor and solution written once; scratch and re-reads excluded)."""
     K, n, nB, M = inst.K, inst.n, inst.nB, inst.M
     L = nB + 1
     N = K * n + nB

@@ -8,7 +8,7 @@ decomposition (Section 2: Householder matrices H = I - 2 v v^T applied in turn
 to zero the subdiagonal of each column, R = H_{N-1} ... H_0 A, and Q kept only
 implicitly by applying the reflectors to the right-hand side).
 
-Conventions (the paper states none; readings listed in the design doc):
+Conventions (the paper states none; these are the readings taken):
   * reflector for x = A[j:, j]: alpha = x_0, sigma = ||x_{1:}||^2;
     sigma == 0 -> tau = 0 (no reflection, the diagonal keeps its sign);
     otherwise beta = -sign(alpha) sqrt(alpha^2 + sigma) with sign(0) = +1,

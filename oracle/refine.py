@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
 
 Plain float64 QR is accurate only to about cond * 1e-16, which is too loose to
-judge a result at the 1e-10 level.  The reference solution is therefore an
+assess a result at the 1e-10 level.  The reference solution is therefore an
 O1/O2 solution improved by corrected semi-normal-equation sweeps (Bjorck 1987)
 whose residuals are evaluated in numpy.longdouble (80-bit x87 extended on
 x86-64, eps = 2^-63):
