@@ -69,6 +69,11 @@ def _parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (cpu_baseline) leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for PMC byte scaling)")
+    ap.add_argument("--workload", default="scale", choices=["scale", "ragged-batch", "banded-batch"],
+                    help="scale: one block-angular problem (the headline); ragged-batch: 512 block-angular "
+                         "problems in one batch; banded-batch: 2,048 banded problems in one batch")
+    ap.add_argument("--problems", type=int, default=0, help="batch workloads: problems (0 = the recipe's count)")
+    ap.add_argument("--autotune", action="store_true", help="ragged-batch: autotune the leaf shape first")
     return ap.parse_args()
 
 
@@ -104,6 +109,142 @@ def algorithmic_work(inst):
                 refine=("hbm", sweep_bytes, K))
 
 
+def run_batch(args):
+    """Batch workloads: every problem of the batch is one LM step solve (factor + solve + the
+    fewest float64 sweeps reaching 1e-10 on the sampled problems), all problems in the same
+    launches."""
+    import numpy as np
+    import torch
+
+    from paper_1802_03773_amd import BandedSolver, BlockAngularBatch
+    from workloads import generators as gen
+
+    ragged = args.workload == "ragged-batch"
+    P = args.problems or (512 if ragged else 2048)
+    print(f"[bench] generating {args.workload} ({P} problems)", file=sys.stderr, flush=True)
+    if ragged:
+        insts = gen.ragged_batch(200, P=P, lam=args.lam)
+        st = gen.stack_batch(insts)
+        dev = {k: torch.from_numpy(np.ascontiguousarray(st[k])).cuda() for k in ("A", "B", "b", "d", "lam")}
+        N_p = [i.N for i in insts]
+        rows = int(st["row_off"][-1])
+        mode = "plain" if args.mode == "auto" else args.mode
+        solver = BlockAngularBatch(st["K"], st["nB"], st["row_off"], st["n"], dtype="float32", mode=mode)
+
+        def factor():
+            solver.factor(dev["A"], dev["B"], dev["b"], dev["d"], dev["lam"])
+        desc = {"workload": "ragged block-angular batch: %d problems, K_p ~ U{500..8000} blocks of m_i x 3 "
+                            "(m_i ~ U{4,6,..,40}), dense parts n_B ~ U{6,30,90}, float32, lambda = %g" % (P, args.lam),
+                "problems": P, "blocks": int(st["K"].sum()), "rows": rows, "unknowns": int(sum(N_p)), "mode": mode}
+    else:
+        insts = gen.banded_batch(300, P=P, lam=args.lam)
+        i0 = insts[0]
+        dev = {"rs": torch.from_numpy(np.stack([i.row_start for i in insts])).cuda(),
+               "vals": torch.from_numpy(np.stack([i.vals for i in insts])).cuda(),
+               "b": torch.from_numpy(np.stack([i.b for i in insts])).cuda(),
+               "d": torch.from_numpy(np.stack([i.d for i in insts])).cuda()}
+        N_p = [i.N for i in insts]
+        mode = "plain"
+        solver = BandedSolver(i0.M, i0.N, i0.w, dtype="float32", P=P)
+
+        def factor():
+            solver.factor(dev["rs"], dev["vals"], dev["b"], dev["d"], args.lam)
+        desc = {"workload": "banded batch: %d problems of n = %d unknowns, %d rows, %d values per row, float32, "
+                            "lambda = %g" % (P, i0.N, i0.M, i0.w, args.lam),
+                "problems": P, "rows": P * i0.M, "unknowns": P * i0.N, "band_values": i0.w}
+    p = torch.empty(sum(N_p), dtype=torch.float64, device="cuda")
+    offs = np.concatenate([[0], np.cumsum(N_p)])
+
+    def step(sweeps):
+        factor()
+        solver.solve(sweeps=sweeps, out=p)
+
+    sample = sorted({0, P // 2, P - 1})
+    errors, cpu_baseline = {}, None
+    if not args.no_cpu:
+        from oracle import banded as obanded
+        from oracle import refine, structured
+        print(f"[bench] oracle on problems {sample}", file=sys.stderr, flush=True)
+        refs, t_cpu = {}, 0.0
+        for q in sample:
+            t0 = time.perf_counter()
+            if ragged:
+                p0, fac = structured.solve_blockangular(insts[q])
+                t_cpu += time.perf_counter() - t0
+                refs[q] = refine.refine(insts[q], fac, p0, sweeps=2).astype(np.float64)
+            else:
+                R, c, _ = obanded.factor_lapack(insts[q])
+                import scipy.linalg
+                scipy.linalg.solve_triangular(R, c, lower=False)
+                t_cpu += time.perf_counter() - t0
+                refs[q] = obanded.reference_solution(insts[q])[0]
+        cpu_baseline = {"value": len(sample) / t_cpu, "unit": "steps/s", "cores": _cpu_threads(), "kind": "oracle",
+                        "sample": "float64 oracle solves of problems %s of the batch (%s), %.2f s" % (
+                            sample, "structured LAPACK per block and dense part" if ragged else
+                            "LAPACK QR of the assembled band", t_cpu)}
+        if args.autotune and ragged:
+            factor()
+            print(f"[bench] autotune: leaf scale {solver.autotune()}", file=sys.stderr, flush=True)
+        for s_ in range(0, 4):
+            step(s_)
+            torch.cuda.synchronize()
+            x = p.cpu().numpy()
+            errors[s_] = max(float(np.linalg.norm(x[offs[q]:offs[q + 1]] - refs[q]) / np.linalg.norm(refs[q]))
+                             for q in sample)
+    st_ = solver.status()
+    if st_[0] != 0:
+        raise RuntimeError(f"device status {st_}")
+    if args.sweeps >= 0:
+        sweeps = args.sweeps
+    elif errors:
+        ok = [s_ for s_ in sorted(errors) if errors[s_] <= 1e-10]
+        sweeps = ok[0] if ok else 3
+    else:
+        sweeps = 1
+    for _ in range(args.warmup):
+        step(sweeps)
+    torch.cuda.synchronize()
+    solver.profile_enable(args.steps + 1)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        step(sweeps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    phases = solver.profile_read()
+    solver.profile_enable(0)
+    phase_out = {k: {"avg_ms": v[0] / v[1], "launches": v[1]} for k, v in phases.items() if v[1]}
+    dominant = max(phase_out, key=lambda k: phases[k][0])
+    if ragged:
+        # dense-part leaves: 2 (M_p + n_B) L^2 - 2/3 L^3 flops per problem (L = n_B + 1)
+        flops = sum(2.0 * (i.M + i.nB) * (i.nB + 1) ** 2 - (2.0 / 3.0) * (i.nB + 1) ** 3 for i in insts)
+        blk_bytes = sum(i.M * (i.n + i.nB + 1) * 4 + i.N * 8 + i.K * i.n * (i.n + i.nB + 1) * 4
+                        + i.M * (i.nB + 1) * 4 for i in insts)
+        work = {"dense_leaves": ("alu", flops, PEAK_FP32_VECTOR_TFLOPS, "TFLOP/s", 1e12),
+                "block_qr": ("hbm", blk_bytes, PEAK_HBM_GBS, "GB/s", 1e9)}
+    else:
+        # Givens factor: J, b, d in; R (N x w) and c out
+        fbytes = sum(i.M * i.w * 4 + i.M * 4 + i.M * 4 + i.N * 8 + i.N * i.w * 4 + i.N * 4 for i in insts)
+        work = {"banded": ("hbm", fbytes, PEAK_HBM_GBS, "GB/s", 1e9)}
+    for k, (bound, amount, peak, unit, scale) in work.items():
+        if k in phase_out:
+            ach = amount / (phase_out[k]["avg_ms"] * 1e-3) / scale
+            phase_out[k].update(bound=bound, achieved=ach, peak=peak, unit=unit, frac=ach / peak)
+    dom = phase_out[dominant]
+    roofline = {"kernel": dominant, "bound": dom.get("bound"), "achieved": dom.get("achieved"),
+                "peak": dom.get("peak"), "unit": dom.get("unit"), "frac": dom.get("frac"), "traffic": None}
+    desc.update(refine_sweeps=sweeps, refine_dtype="f64")
+    out = {"metric": METRIC, "value": P * 1000.0 / ms, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32" if mode == "plain" else "bf16x3", "data": "synthetic",
+           "config": desc, "accuracy": {"max_rel_err_sampled": errors.get(sweeps), "by_sweeps": errors,
+                                        "sampled_problems": sample},
+           "roofline": roofline, "phases": phase_out, "cpu_baseline": cpu_baseline}
+    print(json.dumps(out))
+    return 0
+
+
 def main():
     args = _parse()
     if args.gpus != 1:
@@ -111,6 +252,8 @@ def main():
               "single GPU (several GPUs would split the blocks and all-gather the dense-part triangles).",
               file=sys.stderr)
         return 2
+    if args.workload != "scale":
+        return run_batch(args)
     import numpy as np
     import torch
 

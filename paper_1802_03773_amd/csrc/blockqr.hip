@@ -9,7 +9,9 @@
 // broadcast once through LDS and each lane updates its own columns.  B_i rows are read with
 // consecutive lanes on consecutive columns (coalesced) and the reduced rows are written the
 // same way, into the problem's slice of the reduced-row buffer.  blk_prob == nullptr: a
-// single problem.
+// single problem.  One launch per block class (register rows 16/32/64 x column slots 1/2):
+// the blocks of a class are listed in blk_list[begin, begin + count) (or are begin.. when the
+// list is null), so small blocks and narrow dense parts do not pay for the widest ones.
 #include "blockqr.hpp"
 #include "qrk_batch.hpp"
 #include "qrk_launch.hpp"
@@ -18,7 +20,8 @@ namespace qrk {
 
 template <typename T, int ROWS, int SLOTS>
 __global__ void __launch_bounds__(256)
-k_blockqr(int64_t Ktot, int n, const ProbDesc* __restrict__ probs, const int32_t* __restrict__ blk_prob,
+k_blockqr(const int32_t* __restrict__ blk_list, int64_t begin, int64_t count, int n,
+          const ProbDesc* __restrict__ probs, const int32_t* __restrict__ blk_prob,
           const int64_t* __restrict__ row_off, const T* __restrict__ A, const T* __restrict__ B,
           const T* __restrict__ bvec, const double* __restrict__ d, const double* __restrict__ lam,
           T* __restrict__ Rblk, T* __restrict__ Sc, T* __restrict__ Red) {
@@ -27,7 +30,8 @@ k_blockqr(int64_t Ktot, int n, const ProbDesc* __restrict__ probs, const int32_t
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int64_t nwaves = (int64_t)gridDim.x * 4;
-  for (int64_t blk = (int64_t)blockIdx.x * 4 + wv; blk < Ktot; blk += nwaves) {
+  for (int64_t it = (int64_t)blockIdx.x * 4 + wv; it < count; it += nwaves) {
+    const int64_t blk = blk_list ? (int64_t)blk_list[begin + it] : begin + it;
     const int pi = blk_prob == nullptr ? 0 : __builtin_amdgcn_readfirstlane(blk_prob[blk]);
     const ProbDesc& P = probs[pi];
     const int64_t r0 = row_off[blk];
@@ -44,21 +48,22 @@ k_blockqr(int64_t Ktot, int n, const ProbDesc* __restrict__ probs, const int32_t
 }
 
 template <typename T>
-hipError_t launch_blockqr(int64_t Ktot, int n, int max_L, int max_rows, int probs_count, const ProbDesc* probs,
-                          const int32_t* blk_prob, const int64_t* row_off, const T* A, const T* B,
-                          const T* b, const double* d, const double* lam, T* Rblk, T* Sc, T* Red, int grid,
-                          hipStream_t st) {
-  const int slots = max_L <= 64 ? 1 : 2;
+hipError_t launch_blockqr(const int32_t* blk_list, int64_t begin, int64_t count, int rows, int slots, int n,
+                          int probs_count, const ProbDesc* probs, const int32_t* blk_prob, const int64_t* row_off,
+                          const T* A, const T* B, const T* b, const double* d, const double* lam, T* Rblk, T* Sc,
+                          T* Red, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
   const bool single = probs_count == 1;
+  const int grid = (int)((count + 3) / 4 < 2048 ? (count + 3) / 4 : 2048);
   dim3 blk(256), grd(grid);
-#define QRK_BQR(R, S)                                                                                 \
-  hipLaunchKernelGGL((k_blockqr<T, R, S>), grd, blk, 0, st, Ktot, n, probs, single ? nullptr : blk_prob, row_off, A, B, b, \
-                     d, lam, Rblk, Sc, Red)
-  if (max_rows <= 16) {
+#define QRK_BQR(R, S)                                                                                  \
+  hipLaunchKernelGGL((k_blockqr<T, R, S>), grd, blk, 0, st, blk_list, begin, count, n, probs,            \
+                     single ? nullptr : blk_prob, row_off, A, B, b, d, lam, Rblk, Sc, Red)
+  if (rows == 16) {
     if (slots == 1) QRK_BQR(16, 1); else QRK_BQR(16, 2);
-  } else if (max_rows <= 32) {
+  } else if (rows == 32) {
     if (slots == 1) QRK_BQR(32, 1); else QRK_BQR(32, 2);
-  } else if (max_rows <= 64) {
+  } else if (rows == 64) {
     if (slots == 1) QRK_BQR(64, 1); else QRK_BQR(64, 2);
   } else {
     return hipErrorInvalidValue;
@@ -68,9 +73,9 @@ hipError_t launch_blockqr(int64_t Ktot, int n, int max_L, int max_rows, int prob
 }
 
 #define QRK_INST(T)                                                                                   \
-  template hipError_t launch_blockqr<T>(int64_t, int, int, int, int, const ProbDesc*, const int32_t*,  \
-                                        const int64_t*, const T*, const T*, const T*, const double*,   \
-                                        const double*, T*, T*, T*, int, hipStream_t);
+  template hipError_t launch_blockqr<T>(const int32_t*, int64_t, int64_t, int, int, int, int,           \
+                                        const ProbDesc*, const int32_t*, const int64_t*, const T*, const T*, \
+                                        const T*, const double*, const double*, T*, T*, T*, hipStream_t);
 QRK_INST(float)
 QRK_INST(double)
 #undef QRK_INST

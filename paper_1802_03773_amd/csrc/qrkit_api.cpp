@@ -16,6 +16,7 @@
 
 #include "qrk_launch.hpp"
 #include "qrk_device.hpp"
+#include "block_classes.hpp"
 #include "qrk_host.hpp"
 
 using namespace qrk;
@@ -65,9 +66,17 @@ qrk_status factor_ba(qrk_handle h, hipStream_t st) {
   T* RB = static_cast<T*>(h->RB);
   if (launch_zero_ints(h->status, h->P, st) != hipSuccess) return QRK_EHIP;
   int pr = prof_begin(h, 0, st);
-  if (launch_blockqr<T>(h->K, h->n, h->max_L, h->max_rows, h->P, h->probs_d, h->blk_prob, h->row_off_d, A, B, b, h->d,
-                        h->lam_ptr, Rblk, Sc, Red, h->grid_blocks, st) != hipSuccess)
-    return QRK_EHIP;
+  // without a list, the one class present covers blocks 0 .. K-1 in order
+  const int32_t* list = h->blk_list_n > 0 ? h->blk_list : nullptr;
+  const int64_t extent = h->blk_list_n > 0 ? h->blk_list_n : h->K;
+  for (int c = 0; c < kBlockClasses; ++c) {
+    if (h->bq_count[c] == 0) continue;
+    if (h->bq_begin[c] < 0 || h->bq_begin[c] + h->bq_count[c] > extent) return QRK_EINVAL;
+    if (launch_blockqr<T>(list, h->bq_begin[c], h->bq_count[c], block_class_rows(c), block_class_slots(c), h->n,
+                          h->P, h->probs_d, h->blk_prob, h->row_off_d, A, B, b, h->d, h->lam_ptr, Rblk, Sc, Red,
+                          st) != hipSuccess)
+      return QRK_EHIP;
+  }
   prof_end(h, pr, st);
   if constexpr (std::is_same<T, float>::value) {
     // dense parts on the matrix cores: leaves and merge trees, one launch per column-block count
@@ -435,6 +444,18 @@ qrk_status create_ba(int32_t P, int32_t n, const int32_t* Kp, const int32_t* nBp
   }
   h->N = noff;
   h->npacks = (int64_t)packs.size() - 1;
+  // per-block QR classes (register rows x column slots)
+  BlockClasses bq;
+  if (!group_block_classes(row_off_host, Ktot, n, [&](int64_t i) { return (int)pd[blk_prob[(size_t)i]].L; }, bq)) {
+    delete h;
+    return QRK_EINVAL;
+  }
+  for (int c = 0; c < kBlockClasses; ++c) {
+    h->bq_begin[c] = bq.begin[c];
+    h->bq_count[c] = bq.count[c];
+  }
+  h->blk_list_n = (int64_t)bq.list.size();
+  const std::vector<int32_t>& blk_list = bq.list;
   // refinement workgroups, in proportion to each problem's packs
   const int64_t target = std::min<int64_t>(ceil_div(h->npacks, 4), 1024);
   std::vector<int32_t> wg_prob;
@@ -460,6 +481,7 @@ qrk_status create_ba(int32_t P, int32_t n, const int32_t* Kp, const int32_t* nBp
   if ((s = dalloc(h, &h->row_off_d, sizeof(int64_t) * (Ktot + 1))) != QRK_OK ||
       (s = dalloc(h, &h->pack_blk, sizeof(int64_t) * packs.size())) != QRK_OK ||
       (s = dalloc(h, &h->blk_prob, sizeof(int32_t) * Ktot)) != QRK_OK ||
+      (!blk_list.empty() && (s = dalloc(h, &h->blk_list, sizeof(int32_t) * blk_list.size())) != QRK_OK) ||
       (s = dalloc(h, &h->wg_prob, sizeof(int32_t) * wg_prob.size())) != QRK_OK ||
       (s = dalloc(h, &h->probs_d, sizeof(ProbDesc) * P)) != QRK_OK ||
       (s = dalloc(h, &h->Rblk, es * (size_t)Ktot * n * n)) != QRK_OK ||
@@ -483,6 +505,8 @@ qrk_status create_ba(int32_t P, int32_t n, const int32_t* Kp, const int32_t* nBp
   if (hipMemcpy(h->row_off_d, row_off_host, sizeof(int64_t) * (Ktot + 1), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(h->pack_blk, packs.data(), sizeof(int64_t) * packs.size(), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(h->blk_prob, blk_prob.data(), sizeof(int32_t) * Ktot, hipMemcpyHostToDevice) != hipSuccess ||
+      (!blk_list.empty() && hipMemcpy(h->blk_list, blk_list.data(), sizeof(int32_t) * blk_list.size(),
+                                      hipMemcpyHostToDevice) != hipSuccess) ||
       hipMemcpy(h->wg_prob, wg_prob.data(), sizeof(int32_t) * wg_prob.size(), hipMemcpyHostToDevice) !=
           hipSuccess ||
       hipMemset(h->status, 0, sizeof(int) * (size_t)std::max(P, 4)) != hipSuccess ||
