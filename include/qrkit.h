@@ -71,6 +71,8 @@ typedef struct qrk_handle_s* qrk_handle;
 /* Limits of this implementation. */
 #define QRK_MAX_BLOCK_COLS 8     /* n, columns per diagonal block                 */
 #define QRK_MAX_BLOCK_ROWS 56    /* m_i, rows per diagonal block                  */
+#define QRK_MAX_LDB (1 << 20)    /* row stride of B (elements): a block's rows of B
+                                    span less than 2^31 bytes                       */
 #define QRK_MAX_DENSE_COLS 127   /* nB, columns of the dense part B               */
 #define QRK_MAX_BAND 31          /* w, nonzeros per banded row                    */
 
@@ -81,9 +83,10 @@ typedef struct qrk_handle_s* qrk_handle;
  *   [row_off_host[i], row_off_host[i+1]) of J, of B and of b; row_off_host[0] = 0,
  *   nondecreasing, 0 <= m_i = row_off[i+1]-row_off[i] <= QRK_MAX_BLOCK_ROWS.  The
  *   row structure is copied; it is fixed for the life of the handle.
- *   ldb >= nB is the row stride (in elements) of B.  Allocates all device
- *   workspace, so later calls allocate nothing.
- *   Returns QRK_EINVAL for K < 1, n outside 1..8, nB outside 0..127, ldb < nB, a bad
+ *   nB <= ldb <= QRK_MAX_LDB is the row stride (in elements) of B.  Allocates all
+ *   device workspace, so later calls allocate nothing.
+ *   Returns QRK_EINVAL for K < 1, n outside 1..8, nB outside 0..127, ldb outside
+ *   nB..QRK_MAX_LDB, a bad
  *   row_off_host, or mode == QRK_BF16X3 with dtype == QRK_F64.
  * ------------------------------------------------------------------------------ */
 qrk_status qrk_create_blockangular(int32_t K, int32_t n, int32_t nB, const int64_t* row_off_host,

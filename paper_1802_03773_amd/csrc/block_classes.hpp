@@ -1,6 +1,8 @@
-// Grouping of the blocks of a batch into the classes the per-block QR kernel is
-// instantiated for: register rows 16 / 32 / 64 (m_i + n rows must fit) times column slots
-// 1 / 2 (the L_p = nB_p + 1 coupled columns of the block's problem must fit 64 per slot).
+// Grouping of the blocks of a batch into the classes the per-block QR kernels are
+// instantiated for.  Classes 0 .. 5: blocks with m_i >= n, register rows 16 / 32 / 64 (m_i + n
+// rows must fit) times column slots 1 / 2 (the L_p = nB_p + 1 coupled columns of the block's
+// problem must fit 64 per slot).  Classes 6 and 7: blocks with m_i < n (at most 15 rows with
+// their damping rows), column slots 1 / 2, factored by the kernel with run-time n.
 // Host-only, no HIP types, so the grouping can be checked on its own.
 #pragma once
 
@@ -10,11 +12,12 @@
 
 namespace qrk {
 
-constexpr int kBlockClasses = 6;
+constexpr int kBlockClasses = 8;
 
-// rows of class c: 16 << (c / 2); column slots: 1 + c % 2
-inline int block_class_rows(int c) { return 16 << (c >> 1); }
+// rows of class c: 16 << (c / 2) (16 for the m_i < n classes); column slots: 1 + c % 2
+inline int block_class_rows(int c) { return c < 6 ? 16 << (c >> 1) : 16; }
 inline int block_class_slots(int c) { return 1 + (c & 1); }
+inline bool block_class_short(int c) { return c >= 6; }
 
 struct BlockClasses {
   int64_t begin[kBlockClasses] = {0};
@@ -26,16 +29,17 @@ struct BlockClasses {
 };
 
 // row_off[0..K] block row offsets; L_of_block(i) the coupled width L of block i's problem.
-// Returns false if a block fits no class (m_i + n > 64 or L > 128).
+// Returns false if a block fits no class (m_i + n > 64, L > 128 or n outside 1 .. 8).
 template <typename LOf>
 inline bool group_block_classes(const int64_t* row_off, int64_t K, int n, LOf L_of_block, BlockClasses& out) {
   out = BlockClasses{};
+  if (n < 1 || n > 8) return false;
   std::vector<uint8_t> cls((size_t)K);
   for (int64_t i = 0; i < K; ++i) {
     const int64_t r = row_off[i + 1] - row_off[i] + n;
     const int L = L_of_block(i);
     if (r > 64 || L > 128 || r < 0) return false;
-    const int rc = r <= 16 ? 0 : (r <= 32 ? 1 : 2);
+    const int rc = row_off[i + 1] - row_off[i] < n ? 3 : (r <= 16 ? 0 : (r <= 32 ? 1 : 2));
     const int c = rc * 2 + (L <= 64 ? 0 : 1);
     cls[(size_t)i] = (uint8_t)c;
     out.count[c] += 1;

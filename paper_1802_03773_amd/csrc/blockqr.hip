@@ -9,12 +9,14 @@
 // broadcast once through LDS and each lane updates its own columns.  B_i rows are read with
 // consecutive lanes on consecutive columns (coalesced) and the reduced rows are written the
 // same way, into the problem's slice of the reduced-row buffer.  blk_prob == nullptr: a
-// single problem.  One launch per block class (register rows 16/32/64 x column slots 1/2):
-// the blocks of a class are listed in blk_list[begin, begin + count) (or are begin.. when the
-// list is null), so small blocks and narrow dense parts do not pay for the widest ones.
+// single problem.  This kernel, with n known only at run time, factors the blocks with fewer
+// rows than columns; blocks with m_i >= n go to the kernels with compile-time n.  One launch
+// per block class: the blocks of a class are listed in blk_list[begin, begin + count) (or
+// are begin .. begin + count - 1 when the list is null).
 #include "blockqr.hpp"
 #include "qrk_batch.hpp"
 #include "qrk_launch.hpp"
+#include "block_classes.hpp"
 
 namespace qrk {
 
@@ -48,34 +50,39 @@ k_blockqr(const int32_t* __restrict__ blk_list, int64_t begin, int64_t count, in
 }
 
 template <typename T>
-hipError_t launch_blockqr(const int32_t* blk_list, int64_t begin, int64_t count, int rows, int slots, int n,
-                          int probs_count, const ProbDesc* probs, const int32_t* blk_prob, const int64_t* row_off,
-                          const T* A, const T* B, const T* b, const double* d, const double* lam, T* Rblk, T* Sc,
-                          T* Red, hipStream_t st) {
+hipError_t launch_blockqr(const int32_t* blk_list, int64_t begin, int64_t count, int cls, int n, int probs_count,
+                          const ProbDesc* probs, const int32_t* blk_prob, const int64_t* row_off, const T* A,
+                          const T* B, const T* b, const double* d, const double* lam, T* Rblk, T* Sc, T* Red,
+                          hipStream_t st) {
   if (count <= 0) return hipSuccess;
-  const bool single = probs_count == 1;
-  const int grid = (int)((count + 3) / 4 < 2048 ? (count + 3) / 4 : 2048);
-  dim3 blk(256), grd(grid);
-#define QRK_BQR(R, S)                                                                                  \
-  hipLaunchKernelGGL((k_blockqr<T, R, S>), grd, blk, 0, st, blk_list, begin, count, n, probs,            \
-                     single ? nullptr : blk_prob, row_off, A, B, b, d, lam, Rblk, Sc, Red)
-  if (rows == 16) {
-    if (slots == 1) QRK_BQR(16, 1); else QRK_BQR(16, 2);
-  } else if (rows == 32) {
-    if (slots == 1) QRK_BQR(32, 1); else QRK_BQR(32, 2);
-  } else if (rows == 64) {
-    if (slots == 1) QRK_BQR(64, 1); else QRK_BQR(64, 2);
-  } else {
-    return hipErrorInvalidValue;
+  const int32_t* bp = probs_count == 1 ? nullptr : blk_prob;
+  const int rows = block_class_rows(cls), slots = block_class_slots(cls);
+  if (!block_class_short(cls)) {
+    switch (n) {
+#define QRK_N(NN) \
+  case NN:        \
+    return launch_blockqr_n<T, NN>(blk_list, begin, count, rows, slots, probs, bp, row_off, A, B, b, d, lam, Rblk, Sc, Red, st);
+      QRK_N(1) QRK_N(2) QRK_N(3) QRK_N(4) QRK_N(5) QRK_N(6) QRK_N(7) QRK_N(8)
+#undef QRK_N
+      default:
+        return hipErrorInvalidValue;
+    }
   }
-#undef QRK_BQR
+  // blocks with fewer rows than columns: run-time n, 16 register rows
+  const int grid = (int)((count + 3) / 4 < 2048 ? (count + 3) / 4 : 2048);
+  if (slots == 1)
+    hipLaunchKernelGGL((k_blockqr<T, 16, 1>), dim3(grid), dim3(256), 0, st, blk_list, begin, count, n, probs, bp,
+                       row_off, A, B, b, d, lam, Rblk, Sc, Red);
+  else
+    hipLaunchKernelGGL((k_blockqr<T, 16, 2>), dim3(grid), dim3(256), 0, st, blk_list, begin, count, n, probs, bp,
+                       row_off, A, B, b, d, lam, Rblk, Sc, Red);
   return hipGetLastError();
 }
 
 #define QRK_INST(T)                                                                                   \
-  template hipError_t launch_blockqr<T>(const int32_t*, int64_t, int64_t, int, int, int, int,           \
-                                        const ProbDesc*, const int32_t*, const int64_t*, const T*, const T*, \
-                                        const T*, const double*, const double*, T*, T*, T*, hipStream_t);
+  template hipError_t launch_blockqr<T>(const int32_t*, int64_t, int64_t, int, int, int, const ProbDesc*, \
+                                        const int32_t*, const int64_t*, const T*, const T*, const T*,       \
+                                        const double*, const double*, T*, T*, T*, hipStream_t);
 QRK_INST(float)
 QRK_INST(double)
 #undef QRK_INST

@@ -45,8 +45,8 @@ struct qrk_handle_s {
   int32_t* blk_prob = nullptr;   // [K]
   int32_t* blk_list = nullptr;   // [blk_list_n] blocks grouped by per-block QR class
   int64_t blk_list_n = 0;        // 0: one class, covering blocks 0 .. K-1 in order
-  int64_t bq_begin[6] = {0};     // class (rows 16/32/64) x (column slots 1/2): range in blk_list
-  int64_t bq_count[6] = {0};
+  int64_t bq_begin[8] = {0};     // per-block QR class (block_classes.hpp): range in blk_list
+  int64_t bq_count[8] = {0};
   int32_t* wg_prob = nullptr;    // [nwg]
   int32_t* leaf_prob = nullptr;  // [leaf_cap]
   int32_t* leaf_idx = nullptr;   // [leaf_cap]

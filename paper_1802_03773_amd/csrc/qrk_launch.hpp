@@ -10,15 +10,22 @@ namespace qrk {
 
 // Per-block Householder QR of [A_i; sqrt(lam_p) D_i] with Q_i^T applied to [B_i | b_i; 0 | 0]
 // for the blocks blk_list[begin .. begin + count) (or begin .. begin + count when blk_list is
-// null), all of one class: m_i + n <= rows (16, 32 or 64) and n_B + 1 <= 64 * slots.  Writes
-// R_i (Rblk, global block order), the coupling rows S_i | c_i (Sc, the problem's slice, row
-// stride L_p) and the m_i reduced rows of every block into the problem's slice of Red (row
-// stride ldr_p).
+// null), all of class cls (the grouping of block_classes.hpp).  Writes R_i (Rblk, global
+// block order), the coupling rows S_i | c_i (Sc, the problem's slice, row stride L_p) and the
+// m_i reduced rows of every block into the problem's slice of Red (row stride ldr_p).
 template <typename T>
-hipError_t launch_blockqr(const int32_t* blk_list, int64_t begin, int64_t count, int rows, int slots, int n,
-                          int probs_count, const ProbDesc* probs, const int32_t* blk_prob, const int64_t* row_off,
-                          const T* A, const T* B, const T* b, const double* d, const double* lam, T* Rblk, T* Sc,
-                          T* Red, hipStream_t st);
+hipError_t launch_blockqr(const int32_t* blk_list, int64_t begin, int64_t count, int cls, int n, int probs_count,
+                          const ProbDesc* probs, const int32_t* blk_prob, const int64_t* row_off, const T* A,
+                          const T* B, const T* b, const double* d, const double* lam, T* Rblk, T* Sc, T* Red,
+                          hipStream_t st);
+
+// Per-block QR with compile-time block width N, for blocks with m_i >= N (rows: 16, 32 or
+// 64 register rows, m_i + N <= rows; slots: 1 or 2, nB + 1 <= 64 slots).
+template <typename T, int N>
+hipError_t launch_blockqr_n(const int32_t* blk_list, int64_t begin, int64_t count, int rows, int slots,
+                            const ProbDesc* probs, const int32_t* blk_prob, const int64_t* row_off, const T* A,
+                            const T* B, const T* b, const double* d, const double* lam, T* Rblk, T* Sc, T* Red,
+                            hipStream_t st);
 
 // Stream rows [g*rows_per_wg, (g+1)*rows_per_wg) of X (nrows x L, row stride ldx) into
 // an L x L upper-triangular R per workgroup g (Householder merges); workgroup 0 starts

@@ -72,9 +72,8 @@ qrk_status factor_ba(qrk_handle h, hipStream_t st) {
   for (int c = 0; c < kBlockClasses; ++c) {
     if (h->bq_count[c] == 0) continue;
     if (h->bq_begin[c] < 0 || h->bq_begin[c] + h->bq_count[c] > extent) return QRK_EINVAL;
-    if (launch_blockqr<T>(list, h->bq_begin[c], h->bq_count[c], block_class_rows(c), block_class_slots(c), h->n,
-                          h->P, h->probs_d, h->blk_prob, h->row_off_d, A, B, b, h->d, h->lam_ptr, Rblk, Sc, Red,
-                          st) != hipSuccess)
+    if (launch_blockqr<T>(list, h->bq_begin[c], h->bq_count[c], c, h->n, h->P, h->probs_d, h->blk_prob,
+                          h->row_off_d, A, B, b, h->d, h->lam_ptr, Rblk, Sc, Red, st) != hipSuccess)
       return QRK_EHIP;
   }
   prof_end(h, pr, st);
@@ -543,7 +542,7 @@ qrk_status qrk_create_blockangular(int32_t K, int32_t n, int32_t nB, const int64
                                    int64_t ldb, qrk_dtype dtype, qrk_mode mode, qrk_handle* out) {
   if (!out) return QRK_EINVAL;
   *out = nullptr;
-  if (ldb < nB) return QRK_EINVAL;
+  if (ldb < nB || ldb > QRK_MAX_LDB) return QRK_EINVAL;
   return create_ba(1, n, &K, &nB, row_off_host, ldb, dtype, mode, out);
 }
 

@@ -44,6 +44,7 @@ def _create(K, n, nB, row_off, ldb, dtype=0, mode=0):
     (2, 3, -1, [0, 1, 2], 4),               # nB < 0
     (2, 3, 128, [0, 1, 2], 128),            # nB > 127
     (2, 3, 4, [0, 1, 2], 3),                # ldb < nB
+    (2, 3, 4, [0, 1, 2], (1 << 20) + 1),    # ldb above the limit
     (2, 3, 4, [1, 2, 3], 4),                # row_off[0] != 0
     (2, 3, 4, [0, 5, 3], 4),                # negative block
     (2, 3, 4, [0, 57, 60], 4),              # block taller than the limit

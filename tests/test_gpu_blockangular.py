@@ -191,3 +191,26 @@ def test_scale_workload_full_size(lam):
     assert e1 <= 1e-10
     p2 = solver.solve(sweeps=2).cpu().numpy()
     assert rel_err(p2, p_ref) <= 1e-10
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_every_block_width(n, dtype):
+    """Block widths 1 .. 8 with ragged blocks covering every per-block QR class: m_i < n
+    (including empty blocks), m_i + n within 16, 32 and 64 rows, and dense parts in one and
+    two column slots."""
+    for nB in (5, 70):
+        rng = np.random.default_rng(500 + 10 * n + nB)
+        K = 48
+        m = rng.integers(0, 56 - 0 + 1, size=K)
+        m = np.minimum(m, 64 - n)
+        m[:6] = [0, max(n - 1, 0), n, 16 - n, 32 - n, 64 - n if 64 - n <= 56 else 56]
+        inst = gen.make_blockangular(600 + 10 * n + nB, K=K, m=m, n=n, nB=nB, lam=1e-2, dtype=dtype)
+        log(f"n={n} nB={nB} {np.dtype(dtype).name} m range {m.min()}..{m.max()}")
+        p_ref, _ = refine.reference_solution(inst)
+        p, st = gpu_solve_blockangular(inst)
+        assert st[0] == 0, st
+        tol = 1e-11 if dtype == np.float64 else 1e-5
+        assert rel_err(p, p_ref) <= tol
+        p1, _ = gpu_solve_blockangular(inst, sweeps=2)
+        assert rel_err(p1, p_ref) <= 1e-10
