@@ -290,36 +290,65 @@ hipError_t launch_adjoint_blocks(const BatchView& bv, const T* Rblk, const T* Sc
 }
 
 // ---------------------------------------------------------------------------------
-// Refinement pass 1: one wave per pack of whole blocks (at most 64 rows), one row per lane.
+// Refinement pass 1: one wave per pack of whole blocks (at most 64 rows).
 //   r = b - A_i p_i - B p_B;  g_i = A_i^T r - lam d_i^2 p_i;  y_i = R_i^{-T} g_i;
 //   per-workgroup partial of  B^T r - sum_i S_i^T y_i.
+// The pack's rows of B are read once, coalesced, 16 rows at a time, and staged in the wave's
+// LDS tile column-major with an odd column stride (17), so both products read it without
+// bank conflicts: B p_B with four lanes per row (each summing every fourth column, then two
+// shuffles), B^T r with one lane per column straight from the registers the chunk was
+// loaded into.  Every sum runs in a fixed order, so the partials are deterministic.
 // Workgroup w serves problem wg_prob[w] only; its packs are that problem's packs
 // lw*4 + wave, lw*4 + wave + 4*nwg, ... (lw = w - wg0), its partial goes to part[w].
 // ---------------------------------------------------------------------------------
 template <typename T>
+__device__ __forceinline__ T buf_ld_row(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(T) == 4)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)voff, (int)soff, 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)voff, (int)soff, 0));
+}
+
+template <typename T, int N>
 __global__ void __launch_bounds__(256)
 k_refine_pass1(const ProbDesc* __restrict__ probs, const int32_t* __restrict__ wg_prob,
-               const int64_t* __restrict__ pack_blk, int n, const int64_t* __restrict__ row_off,
+               const int64_t* __restrict__ pack_blk, const int64_t* __restrict__ row_off,
                const T* __restrict__ A, const T* __restrict__ B, const T* __restrict__ bvec,
                const double* __restrict__ d, const double* __restrict__ lamv, const T* __restrict__ Rblk,
                const T* __restrict__ Sc, const double* __restrict__ p, double* __restrict__ y,
                double* __restrict__ part) {
-  __shared__ double pB[kMaxDense];
-  __shared__ double rr[4][64];
-  __shared__ double prod[4][64][8];
-  __shared__ double yv[4][64][8];
-  __shared__ int rowblk[4][64];
-  __shared__ double red[4][kMaxDense];
+  constexpr int CH = 16;      // rows per staged chunk
+  constexpr int LS = CH + 1;  // column stride of the staged tile
+  static_assert(4 * kMaxDense * LS * sizeof(T) >= 4 * kMaxDense * sizeof(double), "reduction fits the tile");
+  __shared__ T tile_all[4][kMaxDense * LS];
+  __shared__ double rr_all[4][64 + CH];         // r per pack row (0 past the pack)
+  __shared__ double prod_all[4][64 * N];        // A_row * r per pack row
+  __shared__ double yv_all[4][64 * N + CH];     // y per coupling row (0 past the pack's blocks)
+  __shared__ int rowblk_all[4][64];
   const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  T* tile = tile_all[wv];
+  double* rr = rr_all[wv];
+  double* prod = prod_all[wv];
+  double* yv = yv_all[wv];
+  int* rowblk = rowblk_all[wv];
   const int pi = wg_prob[blockIdx.x];
   const ProbDesc& P = probs[pi];
   const int nB = P.nB, L = P.L;
-  const int64_t koff = P.koff, noff = P.noff, moff = P.moff, soff = P.soff, ldb = P.ldb;
-  const T* Bp = B + P.boff;
+  const int64_t koff = P.koff, noff = P.noff, moff = P.moff, soff = P.soff;
+  const int ldb = nB > 0 ? (int)P.ldb : 0;
   const double lam = lamv[pi];
-  for (int j = threadIdx.x; j < nB; j += blockDim.x) pB[j] = p[noff + P.K * n + j];
-  __syncthreads();
+  const double* pBv = p + noff + P.K * N;
+  const int qi = lane & 15, qq = lane >> 4;  // row pass: row qi of the chunk, columns 4t + qq
+  double pq[kMaxDense / 4];
+#pragma unroll
+  for (int t = 0; t < kMaxDense / 4; ++t) {
+    const int j = 4 * t + qq;
+    pq[t] = j < nB ? pBv[j] : 0.0;
+  }
+  const bool c0ok = lane < nB, c1ok = lane + 64 < nB;
+  const uint32_t co0 = (uint32_t)(c0ok ? lane : 0) * (uint32_t)sizeof(T);
+  const uint32_t co1 = (uint32_t)(c1ok ? lane + 64 : 0) * (uint32_t)sizeof(T);
   double t0 = 0.0, t1 = 0.0;  // partial B^T r - S^T y for columns lane, lane + 64
   const int64_t lw = blockIdx.x - P.wg0;
   const int64_t pend = P.pack0 + P.npacks;
@@ -330,98 +359,170 @@ k_refine_pass1(const ProbDesc* __restrict__ probs, const int32_t* __restrict__ w
     const int prows = (int)(row_off[b0 + nb] - pr0);
     if (lane < nb) {
       const int lo = (int)(row_off[b0 + lane] - pr0), hi = (int)(row_off[b0 + lane + 1] - pr0);
-      for (int r = lo; r < hi; ++r) rowblk[wv][r] = lane;
+      for (int r = lo; r < hi; ++r) rowblk[r] = lane;
     }
     wave_lds_sync();
-    if (lane < prows) {
-      const int64_t row = pr0 + lane;
-      const int64_t lb = b0 - koff + rowblk[wv][lane];
-      double a[8], dot = 0.0;
+    // with nB == 0 there may be no B at all: the (discarded) loads then read b[pr0]
+    const T* Bbase = nB > 0 ? B + P.boff + (pr0 - moff) * ldb : bvec + pr0;
+    const __amdgpu_buffer_rsrc_t rsB =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(Bbase), 0, 0x7fffffff, 0x00020000);
+    for (int c0 = 0; c0 < prows; c0 += CH) {
+      const int last = prows - 1 - c0;  // rows past the pack re-read its last row; their r is 0
+      // this lane's row of the chunk for the r update (lanes 0..15): its A row and p_i
+      const int myrow = c0 + (qi < last ? qi : last);
+      const int64_t grow = pr0 + myrow;
+      const int64_t lbr = b0 - koff + rowblk[myrow];
+      T arow[N];
+      double prow[N];
 #pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        a[c] = (c < n) ? (double)A[row * n + c] : 0.0;
-        if (c < n) dot += a[c] * p[noff + lb * n + c];
+      for (int c = 0; c < N; ++c) {
+        arow[c] = A[grow * N + c];
+        prow[c] = p[noff + lbr * N + c];
       }
-      const T* Brow = Bp + (row - moff) * ldb;
-      double d0 = 0.0, d1 = 0.0;
-      int j = 0;
-      for (; j + 1 < nB; j += 2) {
-        d0 += (double)Brow[j] * pB[j];
-        d1 += (double)Brow[j + 1] * pB[j + 1];
-      }
-      if (j < nB) d0 += (double)Brow[j] * pB[j];
-      const double r = (double)bvec[row] - dot - (d0 + d1);
-      rr[wv][lane] = r;
+      const T bval = bvec[grow];
+      // stage rows c0 .. c0 + 15; columns >= nB are zeros
+      T v0[CH], v1[CH];
 #pragma unroll
-      for (int c = 0; c < 8; ++c)
-        if (c < n) prod[wv][lane][c] = a[c] * r;
+      for (int i = 0; i < CH; ++i) {
+        const int ri = i < last ? i : last;
+        const uint32_t so = (uint32_t)((c0 + ri) * ldb) * (uint32_t)sizeof(T);
+        const T x0 = buf_ld_row<T>(rsB, co0, so);
+        const T x1 = buf_ld_row<T>(rsB, co1, so);
+        v0[i] = c0ok ? x0 : T(0);
+        v1[i] = c1ok ? x1 : T(0);
+      }
+#pragma unroll
+      for (int i = 0; i < CH; ++i) {
+        tile[lane * LS + i] = v0[i];
+        tile[(lane + 64) * LS + i] = v1[i];
+      }
+      wave_lds_sync();
+      // B p_B for row c0 + qi: lanes qi, qi + 16, qi + 32, qi + 48 split the columns
+      // (32-column tiers; the columns past nB are zeros)
+      double acc = 0.0;
+      auto tier = [&](auto t_begin) {
+        constexpr int tb = decltype(t_begin)::value;
+#pragma unroll
+        for (int t = tb; t < tb + 8; ++t) acc += (double)tile[(4 * t + qq) * LS + qi] * pq[t];
+      };
+      tier(std::integral_constant<int, 0>{});
+      if (nB > 32) tier(std::integral_constant<int, 8>{});
+      if (nB > 64) tier(std::integral_constant<int, 16>{});
+      if (nB > 96) tier(std::integral_constant<int, 24>{});
+      acc += __shfl_xor(acc, 16, 64);
+      acc += __shfl_xor(acc, 32, 64);
+      if (qq == 0) {
+        double dot = 0.0;
+#pragma unroll
+        for (int c = 0; c < N; ++c) dot += (double)arow[c] * prow[c];
+        const double rv = qi <= last ? (double)bval - dot - acc : 0.0;
+        rr[c0 + qi] = rv;
+        if (qi <= last) {
+#pragma unroll
+          for (int c = 0; c < N; ++c) prod[(c0 + qi) * N + c] = (double)arow[c] * rv;
+        }
+      }
+      wave_lds_sync();
+      // B^T r over the chunk's rows, from the registers the chunk was loaded into
+#pragma unroll
+      for (int i = 0; i < CH; ++i) {
+        const double rv = rr[c0 + i];
+        t0 += (double)v0[i] * rv;
+        t1 += (double)v1[i] * rv;
+      }
+      wave_lds_sync();  // the next chunk overwrites the tile
     }
-    wave_lds_sync();
-    // B^T r over the pack's rows (coalesced across lanes)
-    for (int r = 0; r < prows; ++r) {
-      const T* Brow = Bp + (pr0 + r - moff) * ldb;
-      const double rv = rr[wv][r];
-      if (lane < nB) t0 += (double)Brow[lane] * rv;
-      if (lane + 64 < nB) t1 += (double)Brow[lane + 64] * rv;
-    }
-    // per block: g_i, y_i
+    // per block: g_i = A_i^T r - lam d_i^2 p_i, y_i = R_i^{-T} g_i
     if (lane < nb) {
       const int64_t blk = b0 + lane;
       const int64_t lb = blk - koff;
-      const int lo = (int)(row_off[blk] - pr0), hi = (int)(row_off[blk + 1] - pr0);
-      double g[8], yy[8];
+      double dd[N], pp[N];
+      T Rb[N * N];
 #pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        g[c] = 0.0;
-        yy[c] = 0.0;
+      for (int c = 0; c < N; ++c) {
+        dd[c] = d[noff + lb * N + c];
+        pp[c] = p[noff + lb * N + c];
       }
+#pragma unroll
+      for (int e = 0; e < N * N; ++e) Rb[e] = Rblk[blk * (N * N) + e];
+      const int lo = (int)(row_off[blk] - pr0), hi = (int)(row_off[blk + 1] - pr0);
+      double g[N];
+#pragma unroll
+      for (int c = 0; c < N; ++c) g[c] = 0.0;
       for (int r = lo; r < hi; ++r)
 #pragma unroll
-        for (int c = 0; c < 8; ++c)
-          if (c < n) g[c] += prod[wv][r][c];
+        for (int c = 0; c < N; ++c) g[c] += prod[r * N + c];
 #pragma unroll
-      for (int c = 0; c < 8; ++c)
-        if (c < n) {
-          const double dc = d[noff + lb * n + c];
-          g[c] -= lam * dc * dc * p[noff + lb * n + c];
-        }
-      block_fwdsub_T(Rblk + blk * n * n, n, g, yy);
+      for (int c = 0; c < N; ++c) g[c] -= lam * dd[c] * dd[c] * pp[c];
+      // R_i^T y = g (R_i upper triangular, row-major)
+      double yy[N];
 #pragma unroll
-      for (int c = 0; c < 8; ++c)
-        if (c < n) {
-          y[blk * n + c] = yy[c];
-          yv[wv][lane][c] = yy[c];
-        }
+      for (int i = 0; i < N; ++i) {
+        double sacc = g[i];
+#pragma unroll
+        for (int j = 0; j < i; ++j) sacc -= (double)Rb[j * N + i] * yy[j];
+        yy[i] = sacc / (double)Rb[i * N + i];
+      }
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        y[blk * N + c] = yy[c];
+        yv[lane * N + c] = yy[c];
+      }
     }
+    const int rs = nb * N;  // coupling rows of the pack
+    if (lane < CH) yv[rs + lane] = 0.0;
     wave_lds_sync();
-    // S^T y over the pack's blocks
-    for (int k = 0; k < nb; ++k) {
-      const T* Srow = Sc + soff + (b0 - koff + k) * n * L;
+    // S^T y over the pack's coupling rows (contiguous), 16 rows at a time
+    const __amdgpu_buffer_rsrc_t rsS =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(Sc + soff + (b0 - koff) * N * L), 0, 0x7fffffff,
+                                          0x00020000);
+    const uint32_t so0 = (uint32_t)(c0ok ? lane : 0) * (uint32_t)sizeof(T);
+    const uint32_t so1 = (uint32_t)(c1ok ? lane + 64 : 0) * (uint32_t)sizeof(T);
+    for (int s0 = 0; s0 < rs; s0 += CH) {
+      const int last = rs - 1 - s0;
+      T w0[CH], w1[CH];
 #pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        if (c < n) {
-          const double yc = yv[wv][k][c];
-          if (lane < nB) t0 -= (double)Srow[c * L + lane] * yc;
-          if (lane + 64 < nB) t1 -= (double)Srow[c * L + lane + 64] * yc;
-        }
+      for (int i = 0; i < CH; ++i) {
+        const int ri = i < last ? i : last;
+        const uint32_t so = (uint32_t)((s0 + ri) * L) * (uint32_t)sizeof(T);
+        w0[i] = buf_ld_row<T>(rsS, so0, so);
+        w1[i] = buf_ld_row<T>(rsS, so1, so);
+      }
+#pragma unroll
+      for (int i = 0; i < CH; ++i) {
+        const double yc = yv[s0 + i];
+        if (c0ok) t0 -= (double)w0[i] * yc;
+        if (c1ok) t1 -= (double)w1[i] * yc;
       }
     }
     wave_lds_sync();
   }
-  red[wv][lane] = t0;
-  red[wv][lane + 64] = t1;
+  __syncthreads();  // every wave is done with its tile: the tiles hold the reduction now
+  double* red = reinterpret_cast<double*>(&tile_all[0][0]);
+  red[wv * kMaxDense + lane] = t0;
+  red[wv * kMaxDense + lane + 64] = t1;
   __syncthreads();
   for (int j = threadIdx.x; j < nB; j += blockDim.x)
-    part[(int64_t)blockIdx.x * kMaxDense + j] = ((red[0][j] + red[1][j]) + red[2][j]) + red[3][j];
+    part[(int64_t)blockIdx.x * kMaxDense + j] =
+        ((red[j] + red[kMaxDense + j]) + red[2 * kMaxDense + j]) + red[3 * kMaxDense + j];
 }
 
 template <typename T>
 hipError_t launch_refine_residual(const BatchView& bv, const T* A, const T* B, const T* b, const double* d,
                                   const T* Rblk, const T* Sc, const double* p, double* y, double* part,
                                   hipStream_t st) {
-  if (bv.max_L > kMaxDense || bv.n > 8) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_refine_pass1<T>), dim3(bv.nwg), dim3(256), 0, st, bv.probs, bv.wg_prob, bv.pack_blk,
-                     bv.n, bv.row_off, A, B, b, d, bv.lam, Rblk, Sc, p, y, part);
+  if (bv.max_L > kMaxDense) return hipErrorInvalidValue;
+  switch (bv.n) {
+#define QRK_P1(NN)                                                                                         \
+  case NN:                                                                                                 \
+    hipLaunchKernelGGL((k_refine_pass1<T, NN>), dim3(bv.nwg), dim3(256), 0, st, bv.probs, bv.wg_prob,      \
+                       bv.pack_blk, bv.row_off, A, B, b, d, bv.lam, Rblk, Sc, p, y, part);                \
+    break;
+    QRK_P1(1) QRK_P1(2) QRK_P1(3) QRK_P1(4) QRK_P1(5) QRK_P1(6) QRK_P1(7) QRK_P1(8)
+#undef QRK_P1
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
