@@ -46,7 +46,6 @@ struct BatchView {
   int nwg = 1;
   const double* lam = nullptr;         // [P] damping, read on the device
   int grid_blocks = 1;                 // block-QR launch
-  int solve_grid = 1;                  // block-solve launches
 };
 
 }  // namespace qrk

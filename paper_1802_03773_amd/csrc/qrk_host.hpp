@@ -75,7 +75,6 @@ struct qrk_handle_s {
   int64_t* row_off_d = nullptr;
   int64_t* pack_blk = nullptr;  // packs of whole blocks with at most 64 rows: [npacks+1]
   int64_t npacks = 0;
-  int solve_grid = 1;
   void* Rblk = nullptr;   // [K][n][n]
   void* Sc = nullptr;     // [K][n][nB+1]
   void* Red = nullptr;    // [M][ldr]

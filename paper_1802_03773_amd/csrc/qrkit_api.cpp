@@ -51,7 +51,6 @@ BatchView view(qrk_handle h) {
   bv.nwg = h->nwg;
   bv.lam = h->lam_ptr;
   bv.grid_blocks = h->grid_blocks;
-  bv.solve_grid = h->solve_grid;
   return bv;
 }
 
@@ -469,7 +468,6 @@ qrk_status create_ba(int32_t P, int32_t n, const int32_t* Kp, const int32_t* nBp
   h->nwg = (int)wg_prob.size();
   h->refine_grid = h->nwg;
   h->grid_blocks = (int)std::min<int64_t>(ceil_div(Ktot, 4), 2048);
-  h->solve_grid = (int)std::min<int64_t>(ceil_div(Ktot, 16), 2048);
   h->max_leaves = 1024;
   h->leaves = 0;
   h->fanin = 8;

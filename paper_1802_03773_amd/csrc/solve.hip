@@ -126,167 +126,185 @@ hipError_t launch_backsub_dense(const BatchView& bv, const T* RB, double* p, int
   return hipGetLastError();
 }
 
-// Small triangular solves of one block (n <= 8), evaluated by one lane.
+// Raw buffer load of one element: the descriptor holds the wave-uniform row-block base, the
+// row offset is the scalar offset and the lane's column offset the vector offset.  Word 3
+// is the gfx9 raw-buffer format; the record count only bounds the range check, and every
+// offset used stays inside the rows of the pack.
 template <typename T>
-__device__ __forceinline__ void block_backsub(const T* __restrict__ Rb, int n, const double* rhs,
-                                              double* out) {
-#pragma unroll
-  for (int i = 7; i >= 0; --i) {
-    if (i < n) {
-      double s = rhs[i];
-#pragma unroll
-      for (int j = 0; j < 8; ++j)
-        if (j > i && j < n) s -= (double)Rb[i * n + j] * out[j];
-      out[i] = s / (double)Rb[i * n + i];
-    }
-  }
-}
-
-template <typename T>
-__device__ __forceinline__ void block_fwdsub_T(const T* __restrict__ Rb, int n, const double* g,
-                                               double* out) {
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    if (i < n) {
-      double s = g[i];
-#pragma unroll
-      for (int j = 0; j < 8; ++j)
-        if (j < i) s -= (double)Rb[j * n + i] * out[j];
-      out[i] = s / (double)Rb[i * n + i];
-    }
-  }
-}
-
-__device__ __forceinline__ double sum16(double x) {
-#pragma unroll
-  for (int off = 8; off >= 1; off >>= 1) x += __shfl_xor(x, off, 16);
-  return x;
+__device__ __forceinline__ T buf_ld_row(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(T) == 4)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)voff, (int)soff, 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)voff, (int)soff, 0));
 }
 
 // ---------------------------------------------------------------------------------
-// Blocks: x_i (= | +=) R_i^{-1} (base_i - S_i v), 16 lanes per block, 16 blocks per
-// workgroup in flight; v is the dense-part vector of the block's problem.
-//   MODE 0 back-substitution: base_i = c_i (last column of S|c), v = p_B, p_i set;
+// Blocks, pack-wise: x_i (= | +=) R_i^{-1} (base_i - S_i v) for the blocks of a pack (the
+// packs and workgroup-to-problem map of refinement pass 1); v is the dense-part vector of
+// the pack's problem.  The pack's coupling rows S|c are contiguous: they are streamed 16
+// rows at a time through the wave's LDS tile (column-major, stride 17) and each row's dot
+// with v is summed by four lanes; then lane k back-substitutes block k of the pack.
+//   MODE 0 back-substitution: base_i = c_i (column nB of S|c, staged with weight -1),
+//                             v = p_B, p_i set, pivot and finiteness status;
 //   MODE 1 refinement:        base_i = y_i, v = delta_B, p_i incremented;
 //   MODE 2 adjoint:           base_i = y_i, v = u_B, u_i set.
-// blk_prob == nullptr: a single problem (every block belongs to problem 0).
 // ---------------------------------------------------------------------------------
-template <typename T, int MODE>
+template <typename T, int N, int MODE>
 __global__ void __launch_bounds__(256)
-k_blocks_solve(int64_t Ktot, int n, const ProbDesc* __restrict__ probs, const int32_t* __restrict__ blk_prob,
-               const T* __restrict__ Rblk, const T* __restrict__ Sc, const double* __restrict__ vbuf,
-               const double* __restrict__ ybase, double* __restrict__ x, int* __restrict__ status) {
+k_blocks_solve_n(const ProbDesc* __restrict__ probs, const int32_t* __restrict__ wg_prob,
+                 const int64_t* __restrict__ pack_blk, const T* __restrict__ Rblk, const T* __restrict__ Sc,
+                 const double* __restrict__ vbuf, const double* __restrict__ ybase, double* __restrict__ x,
+                 int* __restrict__ status) {
+  constexpr int CH = 16, LS = CH + 1;
+  constexpr int MAXR = 64 * N;  // coupling rows of a pack (at most 64 blocks)
+  __shared__ T tile_all[4][kMaxDense * LS];
+  __shared__ double rhs_all[4][MAXR + CH];
   const int lane = threadIdx.x & 63;
-  const int l16 = lane & 15;
-  const int grp = threadIdx.x >> 4;  // 0..15
-  int cur = -1;                      // problem whose dense vector vj holds
-  int nB = 0, L = 1;
-  int64_t koff = 0, noff = 0, soff = 0;
-  double vj[8];
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  T* tile = tile_all[wv];
+  double* rhs = rhs_all[wv];
+  const int pi = wg_prob[blockIdx.x];
+  const ProbDesc& P = probs[pi];
+  const int nB = P.nB, L = P.L;
+  const int64_t koff = P.koff, noff = P.noff, soff = P.soff;
+  const double* v = MODE == 1 ? vbuf + (int64_t)pi * kMaxDense : vbuf + P.noff + P.K * N;
+  // staged columns: nB (and the c column with weight -1 in mode 0)
+  const int ncol = MODE == 0 ? L : nB;
+  const int qi = lane & 15, qq = lane >> 4;
+  double pq[kMaxDense / 4];
 #pragma unroll
-  for (int s = 0; s < 8; ++s) vj[s] = 0.0;
-  const int64_t stride = (int64_t)gridDim.x * 16;
-  // every group of a wave runs the same number of iterations (the wave's first group
-  // decides), so the 16-lane reductions always see all their lanes
-  const int64_t first = (int64_t)blockIdx.x * 16 + (grp & ~3);
-  for (int64_t base = first; base < Ktot; base += stride) {
-    const int64_t blk = base + (grp & 3);
-    const bool active = blk < Ktot;
-    const int pi = blk_prob == nullptr ? 0 : (active ? blk_prob[blk] : cur);
-    if (pi != cur) {  // uniform within the 16-lane group
-      const ProbDesc& P = probs[pi];
-      nB = P.nB;
-      L = P.L;
-      koff = P.koff;
-      noff = P.noff;
-      soff = P.soff;
-      const double* v = MODE == 1 ? vbuf + (int64_t)pi * kMaxDense : vbuf + P.noff + P.K * n;
+  for (int t = 0; t < kMaxDense / 4; ++t) {
+    const int j = 4 * t + qq;
+    pq[t] = j < nB ? v[j] : ((MODE == 0 && j == nB) ? -1.0 : 0.0);
+  }
+  const bool c0ok = lane < ncol, c1ok = lane + 64 < ncol;
+  const uint32_t co0 = (uint32_t)(c0ok ? lane : 0) * (uint32_t)sizeof(T);
+  const uint32_t co1 = (uint32_t)(c1ok ? lane + 64 : 0) * (uint32_t)sizeof(T);
+  const int64_t lw = blockIdx.x - P.wg0;
+  const int64_t pend = P.pack0 + P.npacks;
+  for (int64_t pk = P.pack0 + lw * 4 + wv; pk < pend; pk += (int64_t)P.nwg * 4) {
+    const int64_t b0 = pack_blk[pk];
+    const int nb = (int)(pack_blk[pk + 1] - b0);
+    const int rs = nb * N;
+    // this lane's block (lanes < nb): R_i and the base values, loaded before the stream
+    const int kb = lane < nb ? lane : nb - 1;
+    const int64_t blk = b0 + kb;
+    const int64_t lb = blk - koff;
+    T Rb[N * N];
 #pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        const int j = l16 + 16 * s;
-        vj[s] = (j < nB) ? v[j] : 0.0;
+    for (int e = 0; e < N * N; ++e) Rb[e] = Rblk[blk * (N * N) + e];
+    double base[N];
+#pragma unroll
+    for (int c = 0; c < N; ++c) base[c] = MODE == 0 ? 0.0 : ybase[blk * N + c];
+    double xold[N];
+#pragma unroll
+    for (int c = 0; c < N; ++c) xold[c] = MODE == 1 ? x[noff + lb * N + c] : 0.0;
+    const __amdgpu_buffer_rsrc_t rsS =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(Sc + soff + (b0 - koff) * N * L), 0, 0x7fffffff,
+                                          0x00020000);
+    for (int c0 = 0; c0 < rs; c0 += CH) {
+      const int last = rs - 1 - c0;
+      T v0[CH], v1[CH];
+#pragma unroll
+      for (int i = 0; i < CH; ++i) {
+        const int ri = i < last ? i : last;
+        const uint32_t so = (uint32_t)((c0 + ri) * L) * (uint32_t)sizeof(T);
+        const T x0 = buf_ld_row<T>(rsS, co0, so);
+        const T x1 = buf_ld_row<T>(rsS, co1, so);
+        v0[i] = c0ok ? x0 : T(0);
+        v1[i] = c1ok ? x1 : T(0);
       }
-      cur = pi;
-    }
-    const int64_t lb = active ? blk - koff : 0;
-    double rhs[8], out[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      rhs[k] = 0.0;
-      out[k] = 0.0;
-      if (k < n) {
-        double s = 0.0;
-        const T* row = Sc + soff + (lb * n + k) * L;
-        if (active) {
-#pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            const int j = l16 + 16 * q;
-            if (j < nB) s += (double)row[j] * vj[q];
-          }
-        }
-        s = sum16(s);
-        if (active) rhs[k] = (MODE != 0 ? ybase[blk * n + k] : (double)row[nB]) - s;
+      for (int i = 0; i < CH; ++i) {
+        tile[lane * LS + i] = v0[i];
+        tile[(lane + 64) * LS + i] = v1[i];
       }
+      wave_lds_sync();
+      double acc = 0.0;
+      auto tier = [&](auto t_begin) {
+        constexpr int tb = decltype(t_begin)::value;
+#pragma unroll
+        for (int t = tb; t < tb + 8; ++t) acc += (double)tile[(4 * t + qq) * LS + qi] * pq[t];
+      };
+      tier(std::integral_constant<int, 0>{});
+      if (ncol > 32) tier(std::integral_constant<int, 8>{});
+      if (ncol > 64) tier(std::integral_constant<int, 16>{});
+      if (ncol > 96) tier(std::integral_constant<int, 24>{});
+      acc += __shfl_xor(acc, 16, 64);
+      acc += __shfl_xor(acc, 32, 64);
+      if (qq == 0) rhs[c0 + qi] = -acc;  // -(S v) (mode 0: c - S p_B)
+      wave_lds_sync();  // the next chunk overwrites the tile
     }
-    if (active && l16 == 0) {
-      const T* Rb = Rblk + blk * n * n;
-      bool bad = false, nonfinite = false;
-      if (MODE == 0) {
+    if (lane < nb) {
+      double rr[N], out[N];
+#pragma unroll
+      for (int c = 0; c < N; ++c) rr[c] = base[c] + rhs[lane * N + c];
+#pragma unroll
+      for (int i = N - 1; i >= 0; --i) {
+        double sacc = rr[i];
+#pragma unroll
+        for (int j = i + 1; j < N; ++j) sacc -= (double)Rb[i * N + j] * out[j];
+        out[i] = sacc / (double)Rb[i * N + i];
+      }
+      bool nonfinite = false;
+      double* xo = x + noff + lb * N;
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        xo[c] = MODE == 1 ? xold[c] + out[c] : out[c];
+        nonfinite |= !is_finite(out[c]);
+      }
+      if (MODE == 0 && status) {
         double dmax = 0.0;
 #pragma unroll
-        for (int k = 0; k < 8; ++k)
-          if (k < n) dmax = fmax(dmax, fabs((double)Rb[k * n + k]));
+        for (int c = 0; c < N; ++c) dmax = fmax(dmax, fabs((double)Rb[c * N + c]));
+        bool bad = false;
 #pragma unroll
-        for (int k = 0; k < 8; ++k)
-          if (k < n) {
-            const double piv = (double)Rb[k * n + k];
-            if (is_finite(piv) && !(fabs(piv) > (double)n * Eps<T>::value * dmax)) bad = true;
-          }
-      }
-      block_backsub(Rb, n, rhs, out);
-      double* xo = x + noff + lb * n;
-#pragma unroll
-      for (int k = 0; k < 8; ++k)
-        if (k < n) {
-          if (MODE == 1)
-            xo[k] += out[k];
-          else
-            xo[k] = out[k];
-          nonfinite |= !is_finite(out[k]);
+        for (int c = 0; c < N; ++c) {
+          const double piv = (double)Rb[c * N + c];
+          if (is_finite(piv) && !(fabs(piv) > (double)N * Eps<T>::value * dmax)) bad = true;
         }
-      if (MODE == 0 && status) {
         if (bad) set_status(status + pi, ST_SINGULAR);
         if (nonfinite) set_status(status + pi, ST_NONFINITE);
       }
     }
+    wave_lds_sync();  // the next pack overwrites rhs
   }
+}
+
+template <typename T, int MODE>
+static hipError_t launch_blocks_solve(const BatchView& bv, const T* Rblk, const T* Sc, const double* vbuf,
+                                      const double* ybase, double* x, int* status, hipStream_t st) {
+  if (bv.max_L > kMaxDense) return hipErrorInvalidValue;
+  switch (bv.n) {
+#define QRK_BS(NN)                                                                                          \
+  case NN:                                                                                                  \
+    hipLaunchKernelGGL((k_blocks_solve_n<T, NN, MODE>), dim3(bv.nwg), dim3(256), 0, st, bv.probs, bv.wg_prob, \
+                       bv.pack_blk, Rblk, Sc, vbuf, ybase, x, status);                                     \
+    break;
+    QRK_BS(1) QRK_BS(2) QRK_BS(3) QRK_BS(4) QRK_BS(5) QRK_BS(6) QRK_BS(7) QRK_BS(8)
+#undef QRK_BS
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_backsub_blocks(const BatchView& bv, const T* Rblk, const T* Sc, double* p, int* status,
                                  hipStream_t st) {
-  if (bv.max_L > kMaxDense || bv.n > 8) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_blocks_solve<T, 0>), dim3(bv.solve_grid), dim3(256), 0, st, bv.Ktot, bv.n, bv.probs,
-                     bv.P == 1 ? nullptr : bv.blk_prob, Rblk, Sc, (const double*)p, (const double*)nullptr, p, status);
-  return hipGetLastError();
+  return launch_blocks_solve<T, 0>(bv, Rblk, Sc, p, nullptr, p, status, st);
 }
 
 template <typename T>
 hipError_t launch_refine_blocks(const BatchView& bv, const T* Rblk, const T* Sc, const double* y,
                                 const double* delta_B, double* p, hipStream_t st) {
-  if (bv.max_L > kMaxDense || bv.n > 8) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_blocks_solve<T, 1>), dim3(bv.solve_grid), dim3(256), 0, st, bv.Ktot, bv.n, bv.probs,
-                     bv.P == 1 ? nullptr : bv.blk_prob, Rblk, Sc, delta_B, y, p, (int*)nullptr);
-  return hipGetLastError();
+  return launch_blocks_solve<T, 1>(bv, Rblk, Sc, delta_B, y, p, nullptr, st);
 }
 
 template <typename T>
 hipError_t launch_adjoint_blocks(const BatchView& bv, const T* Rblk, const T* Sc, const double* y, double* u,
                                  hipStream_t st) {
-  if (bv.max_L > kMaxDense || bv.n > 8) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_blocks_solve<T, 2>), dim3(bv.solve_grid), dim3(256), 0, st, bv.Ktot, bv.n, bv.probs,
-                     bv.P == 1 ? nullptr : bv.blk_prob, Rblk, Sc, (const double*)u, y, u, (int*)nullptr);
-  return hipGetLastError();
+  return launch_blocks_solve<T, 2>(bv, Rblk, Sc, u, y, u, nullptr, st);
 }
 
 // ---------------------------------------------------------------------------------
@@ -301,13 +319,6 @@ hipError_t launch_adjoint_blocks(const BatchView& bv, const T* Rblk, const T* Sc
 // Workgroup w serves problem wg_prob[w] only; its packs are that problem's packs
 // lw*4 + wave, lw*4 + wave + 4*nwg, ... (lw = w - wg0), its partial goes to part[w].
 // ---------------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ T buf_ld_row(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff) {
-  if constexpr (sizeof(T) == 4)
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)voff, (int)soff, 0));
-  else
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)voff, (int)soff, 0));
-}
 
 template <typename T, int N>
 __global__ void __launch_bounds__(256)
