@@ -20,14 +20,27 @@ namespace qrk {
 // Dense triangle, one wave: forward (R_B^T y = g) and backward (R_B x = y) sweeps with
 // R_B staged in LDS.  Lane i holds rows i and i + 64 of the right-hand side.
 // ---------------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ void stage_dense(const T* __restrict__ RB, int L, float* Rs, double* Rsd,
-                                            int tid, int nthreads) {
-  for (int e = tid; e < L * L; e += nthreads) {
-    if constexpr (sizeof(T) == 4)
-      Rs[e] = (float)RB[e];
-    else
-      Rsd[e] = (double)RB[e];
+// R_B (L x L, row-major) into LDS by NT threads: each thread issues all of its loads before
+// its first store, so the copy costs one memory latency rather than one per element.
+template <typename T, int NT>
+__device__ __forceinline__ void stage_dense(const T* __restrict__ RB, int L, float* Rs, double* Rsd, int tid) {
+  constexpr int PER = (kMaxDense * kMaxDense + NT - 1) / NT;
+  const int LL = L * L;
+  T buf[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = tid + u * NT;
+    buf[u] = e < LL ? RB[e] : T(0);
+  }
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = tid + u * NT;
+    if (e < LL) {
+      if constexpr (sizeof(T) == 4)
+        Rs[e] = (float)buf[u];
+      else
+        Rsd[e] = (double)buf[u];
+    }
   }
 }
 
@@ -46,37 +59,75 @@ __device__ __forceinline__ double read_lane_d(double x, int lane) {
   return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Forward: y = R^{-T} g (upper-triangular R, column sweep).  v0/v1 hold g for rows
-// lane and lane+64 on entry and y on exit.
+// Reciprocals of the diagonal of R for rows lane and lane + 64 (1 past nB), computed by all
+// lanes at once so the sweeps below multiply instead of dividing on their critical path.
+template <typename T>
+__device__ __forceinline__ void dense_diag_inv(const float* Rs, const double* Rsd, int L, int nB, int lane,
+                                               double& dv0, double& dv1) {
+  dv0 = lane < nB ? 1.0 / rs_at<T>(Rs, Rsd, lane * L + lane) : 1.0;
+  dv1 = lane + 64 < nB ? 1.0 / rs_at<T>(Rs, Rsd, (lane + 64) * L + lane + 64) : 1.0;
+}
+
+// Forward: y = R^{-T} g (upper-triangular R, column sweep).  v0/v1 hold g for rows lane and
+// lane + 64 on entry and y on exit; dv0/dv1 the reciprocal diagonal.  Step k broadcasts
+// y_k = v_k / R_kk from lane k and takes R_kj y_k off every later row j; a row's value is
+// final once its own step is past, so every lane scales by its reciprocal at the end.  The
+// entries of R for eight steps are read from LDS in one batch (masked to the rows a step
+// updates), so a step waits on no LDS access.
 template <typename T>
 __device__ __forceinline__ void wave_fwd_T(const float* Rs, const double* Rsd, int L, int nB, int lane,
-                                           double& v0, double& v1) {
-  for (int k = 0; k < nB; ++k) {
-    const double gk = read_lane_d(k < 64 ? v0 : v1, k & 63);
-    const double yk = gk / rs_at<T>(Rs, Rsd, k * L + k);
-    if (lane == (k & 63)) {
-      if (k < 64) v0 = yk; else v1 = yk;
+                                           double dv0, double dv1, double& v0, double& v1) {
+  for (int kb = 0; kb < nB; kb += 8) {
+    double r0[8], r1[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int k = kb + u < nB ? kb + u : nB - 1;
+      const double a0 = rs_at<T>(Rs, Rsd, k * L + lane);
+      const double a1 = rs_at<T>(Rs, Rsd, k * L + lane + 64);
+      r0[u] = (lane > k && lane < nB) ? a0 : 0.0;
+      r1[u] = (lane + 64 > k && lane + 64 < nB) ? a1 : 0.0;
     }
-    if (lane > k && lane < nB) v0 -= rs_at<T>(Rs, Rsd, k * L + lane) * yk;
-    if (lane + 64 > k && lane + 64 < nB) v1 -= rs_at<T>(Rs, Rsd, k * L + lane + 64) * yk;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int k = kb + u;
+      if (k < nB) {
+        const double yk = read_lane_d(k < 64 ? v0 * dv0 : v1 * dv1, k & 63);
+        v0 -= r0[u] * yk;
+        v1 -= r1[u] * yk;
+      }
+    }
   }
+  v0 *= dv0;
+  v1 *= dv1;
 }
 
-// Backward: x = R^{-1} y.
+// Backward: x = R^{-1} y, columns from the last; the same batching and final scaling.
 template <typename T>
 __device__ __forceinline__ void wave_bwd(const float* Rs, const double* Rsd, int L, int nB, int lane,
-                                         double& v0, double& v1) {
-  for (int k = nB - 1; k >= 0; --k) {
-    const double yk = read_lane_d(k < 64 ? v0 : v1, k & 63);
-    const double xk = yk / rs_at<T>(Rs, Rsd, k * L + k);
-    if (lane == (k & 63)) {
-      if (k < 64) v0 = xk; else v1 = xk;
+                                         double dv0, double dv1, double& v0, double& v1) {
+  for (int kb = nB - 1; kb >= 0; kb -= 8) {
+    double r0[8], r1[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int k = kb - u >= 0 ? kb - u : 0;
+      const double a0 = rs_at<T>(Rs, Rsd, lane * L + k);
+      const double a1 = rs_at<T>(Rs, Rsd, (lane + 64) * L + k);
+      r0[u] = lane < k ? a0 : 0.0;
+      r1[u] = lane + 64 < k ? a1 : 0.0;
     }
-    if (lane < k) v0 -= rs_at<T>(Rs, Rsd, lane * L + k) * xk;
-    if (lane + 64 < k) v1 -= rs_at<T>(Rs, Rsd, (lane + 64) * L + k) * xk;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int k = kb - u;
+      if (k >= 0) {
+        const double xk = read_lane_d(k < 64 ? v0 * dv0 : v1 * dv1, k & 63);
+        v0 -= r0[u] * xk;
+        v1 -= r1[u] * xk;
+      }
+    }
   }
+  v0 *= dv0;
+  v1 *= dv1;
 }
-
 
 // ---------------------------------------------------------------------------------
 // Dense part of the back-substitution: R_B p_B = c_B, one workgroup (one working wave)
@@ -92,20 +143,24 @@ k_backsub_dense(const ProbDesc* __restrict__ probs, int n, const T* __restrict__
   const ProbDesc& P = probs[pi];
   const int L = P.L, nB = P.nB;
   const int64_t off = P.noff + P.K * n;
-  stage_dense<T>(RBall + P.rboff, L, Rs, Rsd, threadIdx.x, blockDim.x);
+  stage_dense<T, 256>(RBall + P.rboff, L, Rs, Rsd, threadIdx.x);
   __syncthreads();
   if (threadIdx.x >= 64) return;
   const int lane = threadIdx.x;
   double v0 = lane < nB ? rs_at<T>(Rs, Rsd, lane * L + nB) : 0.0;
   double v1 = lane + 64 < nB ? rs_at<T>(Rs, Rsd, (lane + 64) * L + nB) : 0.0;
-  double dmax = 0.0;
-  for (int k = 0; k < nB; ++k) dmax = fmax(dmax, fabs(rs_at<T>(Rs, Rsd, k * L + k)));
+  // largest pivot magnitude: each lane its own diagonal entries, then a wave maximum
+  const double dg0 = lane < nB ? fabs(rs_at<T>(Rs, Rsd, lane * L + lane)) : 0.0;
+  const double dg1 = lane + 64 < nB ? fabs(rs_at<T>(Rs, Rsd, (lane + 64) * L + lane + 64)) : 0.0;
+  const double dmax = wave_allreduce_max(fmax(dg0, dg1));
   bool bad = false;
   for (int k = lane; k < nB; k += 64) {
     const double piv = rs_at<T>(Rs, Rsd, k * L + k);
     if (is_finite(piv) && !(fabs(piv) > (double)nB * Eps<T>::value * dmax)) bad = true;
   }
-  wave_bwd<T>(Rs, Rsd, L, nB, lane, v0, v1);
+  double dv0, dv1;
+  dense_diag_inv<T>(Rs, Rsd, L, nB, lane, dv0, dv1);
+  wave_bwd<T>(Rs, Rsd, L, nB, lane, dv0, dv1, v0, v1);
   bool nonfinite = false;
   if (lane < nB) {
     p[off + lane] = v0;
@@ -561,23 +616,23 @@ k_refine_dense(const ProbDesc* __restrict__ probs, int n, const double* __restri
   const int nparts = P.nwg;
   const int t = threadIdx.x;
   const int j = t & 127, q = t >> 7;
-  // partials of group q: w = q, q + 8, ...; loaded 16 at a time so the loads overlap, then
+  // partials of group q: w = q, q + 8, ...; loaded 32 at a time so the loads overlap, then
   // added in order
   double s = 0.0;
   if (j < nB) {
-    for (int w0 = q; w0 < nparts; w0 += 8 * 16) {
-      double buf[16];
+    for (int w0 = q; w0 < nparts; w0 += 8 * 32) {
+      double buf[32];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
+      for (int u = 0; u < 32; ++u) {
         const int w = w0 + 8 * u;
         buf[u] = w < nparts ? pp[(int64_t)w * kMaxDense + j] : 0.0;
       }
 #pragma unroll
-      for (int u = 0; u < 16; ++u) s += buf[u];
+      for (int u = 0; u < 32; ++u) s += buf[u];
     }
   }
   acc[q][j] = s;
-  stage_dense<T>(RBall + P.rboff, L, Rs, Rsd, t, blockDim.x);
+  stage_dense<T, 1024>(RBall + P.rboff, L, Rs, Rsd, t);
   __syncthreads();
   if (t >= 64) return;
   const int lane = t;
@@ -605,8 +660,10 @@ k_refine_dense(const ProbDesc* __restrict__ probs, int n, const double* __restri
       v1 = g - lam * dj * dj * p[off + lane + 64];
     }
   }
-  wave_fwd_T<T>(Rs, Rsd, L, nB, lane, v0, v1);
-  wave_bwd<T>(Rs, Rsd, L, nB, lane, v0, v1);
+  double dv0, dv1;
+  dense_diag_inv<T>(Rs, Rsd, L, nB, lane, dv0, dv1);
+  wave_fwd_T<T>(Rs, Rsd, L, nB, lane, dv0, dv1, v0, v1);
+  wave_bwd<T>(Rs, Rsd, L, nB, lane, dv0, dv1, v0, v1);
   double* o = ADJ ? out + off : out + (int64_t)pi * kMaxDense;
   if (lane < nB) {
     o[lane] = v0;
