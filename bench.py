@@ -100,7 +100,7 @@ def algorithmic_work(inst):
     blk_out = K * n * n * es + K * n * L * es + M * L * es
     leaf_flops = 2.0 * rows * L * L - (2.0 / 3.0) * L ** 3
     backsub_bytes = K * n * L * es + K * n * n * es + N * 8 + L * L * es
-    sweep_bytes = (M * n * es + M * nB * es + M * es + N * 8 + (K + 1) * 8   # J, b, d, offsets
+    sweep_bytes = (M * n * es + M * nB * es + M * es + N * 8 + (K + 1) * 8   # J, b, d, offsets (per sweep)
                    + 2 * N * 8 + K * n * n * es * 2 + K * n * L * es * 2      # p in/out, R_i, S twice
                    + 2 * K * n * 8)                                           # y out/in
     return dict(block_qr=("hbm", blk_in + blk_out, K),
@@ -217,18 +217,25 @@ def run_batch(args):
     phase_out = {k: {"avg_ms": v[0] / v[1], "launches": v[1]} for k, v in phases.items() if v[1]}
     dominant = max(phase_out, key=lambda k: phases[k][0])
     if ragged:
-        # dense-part leaves: 2 (M_p + n_B) L^2 - 2/3 L^3 flops per problem (L = n_B + 1)
-        flops = sum(2.0 * (i.M + i.nB) * (i.nB + 1) ** 2 - (2.0 / 3.0) * (i.nB + 1) ** 3 for i in insts)
-        blk_bytes = sum(i.M * (i.n + i.nB + 1) * 4 + i.N * 8 + i.K * i.n * (i.n + i.nB + 1) * 4
-                        + i.M * (i.nB + 1) * 4 for i in insts)
-        work = {"dense_leaves": ("alu", flops, PEAK_FP32_VECTOR_TFLOPS, "TFLOP/s", 1e12),
-                "block_qr": ("hbm", blk_bytes, PEAK_HBM_GBS, "GB/s", 1e9)}
+        # the single-problem per-phase work, summed over the batch's problems
+        work = {}
+        for i in insts:
+            for k, (bound, amount, _units) in algorithmic_work(i).items():
+                prev = work.get(k)
+                work[k] = (bound, amount + (prev[1] if prev else 0.0))
+        work = {k: ((b_, a_, PEAK_FP32_VECTOR_TFLOPS, "TFLOP/s", 1e12) if b_ == "alu" else
+                    (b_, a_, PEAK_HBM_GBS, "GB/s", 1e9)) for k, (b_, a_) in work.items()}
     else:
-        # Givens factor: J, b, d in; R (N x w) and c out
+        # Givens factor: J, b, d in; R (N x w) and c out.  One refinement sweep: J, row starts,
+        # b, d, p in; R read by both triangular solves; p out
         fbytes = sum(i.M * i.w * 4 + i.M * 4 + i.M * 4 + i.N * 8 + i.N * i.w * 4 + i.N * 4 for i in insts)
-        work = {"banded": ("hbm", fbytes, PEAK_HBM_GBS, "GB/s", 1e9)}
+        rbytes = sum(i.M * i.w * 4 + i.M * 4 + i.M * 4 + i.N * 8 + i.N * 8 + 2 * i.N * i.w * 4 + i.N * 8
+                     for i in insts)
+        work = {"banded": ("hbm", fbytes, PEAK_HBM_GBS, "GB/s", 1e9),
+                "refine": ("hbm", rbytes, PEAK_HBM_GBS, "GB/s", 1e9)}
     for k, (bound, amount, peak, unit, scale) in work.items():
         if k in phase_out:
+            amount = amount * (sweeps if k == "refine" else 1)  # one refine record per solve
             ach = amount / (phase_out[k]["avg_ms"] * 1e-3) / scale
             phase_out[k].update(bound=bound, achieved=ach, peak=peak, unit=unit, frac=ach / peak)
     dom = phase_out[dominant]
@@ -352,7 +359,8 @@ def main():
         entry = {"avg_ms": avg_ms, "launches": cnt}
         if name in work:
             bound, amount, units = work[name]
-            per_launch = amount
+            # one refine record covers all of a solve's sweeps
+            per_launch = amount * (sweeps if name == "refine" else 1)
             if bound == "hbm":
                 entry.update(bound="hbm", achieved=per_launch / (avg_ms * 1e-3) / 1e9, unit="GB/s",
                              peak=PEAK_HBM_GBS, algorithmic_bytes=per_launch, units=units)
