@@ -28,7 +28,21 @@ struct ProbDesc {
   int32_t nB, L;          // coupled columns, L = nB + 1
   int32_t leaves;         // dense-part QR leaves
   int32_t wg0, nwg;       // refinement workgroups [wg0, wg0 + nwg)
+  int32_t tree_sep;       // 1: the leaves only store their triangles; a separate launch merges them
   int32_t pad;
+};
+
+// Work the first per-block QR launch of a factor call does before its blocks: workgroup 0
+// clears z0[0..n0) and z1[0..n1) (status words, merge-tree arrival counters), and when
+// lam_out is set every block uses lam_val for lambda and thread 0 of workgroup 0 stores it
+// to *lam_out for the later kernels (which run after the launch completes).
+struct BqrPrologue {
+  int* z0 = nullptr;
+  int64_t n0 = 0;
+  int* z1 = nullptr;
+  int64_t n1 = 0;
+  double* lam_out = nullptr;
+  double lam_val = 0.0;
 };
 
 // Device view of a handle's batch, passed to the launchers.

@@ -6,6 +6,8 @@
 
 #include <type_traits>
 
+#include "qrk_batch.hpp"
+
 namespace qrk {
 
 // Status bits recorded in the handle's device status word.
@@ -13,6 +15,7 @@ enum : int {
   ST_SINGULAR = 1,
   ST_NONFINITE = 2,
   ST_BADINPUT = 4,
+  ST_STALL = 8,  // a dense-part merge did not see its inputs within its wait bound
 };
 
 constexpr int kWave = 64;
@@ -62,6 +65,16 @@ template <>
 struct Eps<double> {
   static constexpr double value = 1.1102230246251565e-16;  // 2^-53
 };
+
+// The first per-block QR launch's clearing and lambda store (BqrPrologue), by the NT threads
+// of workgroup 0.
+template <int NT>
+__device__ __forceinline__ void bqr_prologue(const BqrPrologue& pro) {
+  if (blockIdx.x != 0) return;
+  for (int64_t i = threadIdx.x; i < pro.n0; i += NT) pro.z0[i] = 0;
+  for (int64_t i = threadIdx.x; i < pro.n1; i += NT) pro.z1[i] = 0;
+  if (threadIdx.x == 0 && pro.lam_out) *pro.lam_out = pro.lam_val;
+}
 
 __device__ __forceinline__ void set_status(int* status, int bits) {
   if (status) atomicOr(status, bits);

@@ -54,6 +54,10 @@ struct qrk_handle_s {
   int64_t slot_cap = 0;          // floats
   int64_t ctr_cap = 0;           // ints
   int64_t nctr = 1;              // counters in use
+  int32_t* node_l = nullptr;     // pipelined merge tree of a single problem (tree_sep):
+  int32_t* node_r = nullptr;     //   child references of the inner nodes, level order
+  int64_t node_cap = 0;
+  int nnodes = 0;                //   0: the merges run inside the leaf launch
   int cls_begin[9] = {0};        // float32 leaves grouped by 16-column-block count
   int cls_count[9] = {0};
   int nwg = 1;                   // refinement workgroups over the batch

@@ -13,11 +13,13 @@ namespace qrk {
 // null), all of class cls (the grouping of block_classes.hpp).  Writes R_i (Rblk, global
 // block order), the coupling rows S_i | c_i (Sc, the problem's slice, row stride L_p) and the
 // m_i reduced rows of every block into the problem's slice of Red (row stride ldr_p).
+// pro: the clearing and lambda store of the factor call's first launch (an empty prologue for
+// the others).
 template <typename T>
 hipError_t launch_blockqr(const int32_t* blk_list, int64_t begin, int64_t count, int cls, int n, int probs_count,
                           const ProbDesc* probs, const int32_t* blk_prob, const int64_t* row_off, const T* A,
                           const T* B, const T* b, const double* d, const double* lam, T* Rblk, T* Sc, T* Red,
-                          hipStream_t st);
+                          const BqrPrologue& pro, hipStream_t st);
 
 // Per-block QR with compile-time block width N, for blocks with m_i >= N (rows: 16, 32 or
 // 64 register rows, m_i + N <= rows; slots: 1 or 2, nB + 1 <= 64 slots).
@@ -25,7 +27,7 @@ template <typename T, int N>
 hipError_t launch_blockqr_n(const int32_t* blk_list, int64_t begin, int64_t count, int rows, int slots,
                             const ProbDesc* probs, const int32_t* blk_prob, const int64_t* row_off, const T* A,
                             const T* B, const T* b, const double* d, const double* lam, T* Rblk, T* Sc, T* Red,
-                            hipStream_t st);
+                            const BqrPrologue& pro, hipStream_t st);
 
 // Stream rows [g*rows_per_wg, (g+1)*rows_per_wg) of X (nrows x L, row stride ldx) into
 // an L x L upper-triangular R per workgroup g (Householder merges); workgroup 0 starts
@@ -44,6 +46,12 @@ hipError_t launch_tsqr_stream(const T* X, int64_t ldx, int64_t nrows, int L, int
 int tsqr_mfma_slot_floats(int L);
 // p[0 .. n) = 0 (a kernel, so it may be captured into a graph).
 hipError_t launch_zero_ints(int* p, int64_t n, hipStream_t st);
+
+// Pipelined merge tree of a single problem whose leaves stored their triangles (tree_sep):
+// nnodes inner nodes in level order (node_l / node_r child references, r < 0 leaf -1 - r),
+// flags[nnodes * ncb] cleared beforehand; ncb <= 6.  The root writes R_B | c_B.
+hipError_t launch_tsqr_tree(int ncb, const ProbDesc* probs, const int32_t* node_l, const int32_t* node_r,
+                            int nnodes, float* slots, int* flags, float* RB, int* status, hipStream_t st);
 hipError_t launch_tsqr_mfma(bool bf16x3, const int* cls_begin, const int* cls_count, const int32_t* leaf_prob,
                             const int32_t* leaf_idx, const ProbDesc* probs, int n, const float* Red,
                             const double* d, const double* lam, float* slots, int* counters, int64_t nctr,

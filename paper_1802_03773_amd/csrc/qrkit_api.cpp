@@ -54,8 +54,10 @@ BatchView view(qrk_handle h) {
   return bv;
 }
 
+// lam_host: lambda of a single problem given by value (stored to the handle's device copy by
+// the first launch); null when lambda is already on the device.
 template <typename T>
-qrk_status factor_ba(qrk_handle h, hipStream_t st) {
+qrk_status factor_ba(qrk_handle h, hipStream_t st, const double* lam_host = nullptr) {
   const T* A = static_cast<const T*>(h->A);
   const T* B = static_cast<const T*>(h->B);
   const T* b = static_cast<const T*>(h->b);
@@ -63,7 +65,18 @@ qrk_status factor_ba(qrk_handle h, hipStream_t st) {
   T* Sc = static_cast<T*>(h->Sc);
   T* Red = static_cast<T*>(h->Red);
   T* RB = static_cast<T*>(h->RB);
-  if (launch_zero_ints(h->status, h->P, st) != hipSuccess) return QRK_EHIP;
+  // the first launch clears the status words and the merge-tree arrival counters
+  BqrPrologue pro;
+  pro.z0 = h->status;
+  pro.n0 = h->P;
+  if (std::is_same<T, float>::value) {
+    pro.z1 = h->counters;
+    pro.n1 = h->nctr;
+  }
+  if (lam_host) {
+    pro.lam_out = h->lam_d;
+    pro.lam_val = *lam_host;
+  }
   int pr = prof_begin(h, 0, st);
   // without a list, the one class present covers blocks 0 .. K-1 in order
   const int32_t* list = h->blk_list_n > 0 ? h->blk_list : nullptr;
@@ -72,8 +85,9 @@ qrk_status factor_ba(qrk_handle h, hipStream_t st) {
     if (h->bq_count[c] == 0) continue;
     if (h->bq_begin[c] < 0 || h->bq_begin[c] + h->bq_count[c] > extent) return QRK_EINVAL;
     if (launch_blockqr<T>(list, h->bq_begin[c], h->bq_count[c], c, h->n, h->P, h->probs_d, h->blk_prob,
-                          h->row_off_d, A, B, b, h->d, h->lam_ptr, Rblk, Sc, Red, st) != hipSuccess)
+                          h->row_off_d, A, B, b, h->d, h->lam_ptr, Rblk, Sc, Red, pro, st) != hipSuccess)
       return QRK_EHIP;
+    pro = BqrPrologue();  // later launches: nothing to clear, lambda on the device
   }
   prof_end(h, pr, st);
   if constexpr (std::is_same<T, float>::value) {
@@ -81,6 +95,10 @@ qrk_status factor_ba(qrk_handle h, hipStream_t st) {
     pr = prof_begin(h, 1, st);
     if (launch_tsqr_mfma(h->mode == QRK_BF16X3, h->cls_begin, h->cls_count, h->leaf_prob, h->leaf_idx, h->probs_d, h->n, Red, h->d,
                          h->lam_ptr, h->slots, h->counters, h->nctr, RB, st) != hipSuccess)
+      return QRK_EHIP;
+    if (h->nnodes > 0 &&
+        launch_tsqr_tree((h->probs_h[0].L + 15) / 16, h->probs_d, h->node_l, h->node_r, h->nnodes, h->slots,
+                         h->counters, RB, h->status, st) != hipSuccess)
       return QRK_EHIP;
     prof_end(h, pr, st);
     return QRK_OK;
@@ -233,15 +251,55 @@ qrk_status assign_leaves(qrk_handle h) {
           }
       h->cls_count[c] = (int)lp.size() - h->cls_begin[c];
     }
+    // a single problem of at most 6 column blocks merges its leaves in a separate launch,
+    // pipelined over column blocks; otherwise the merges run inside the leaf launch
+    std::vector<int32_t> nl, nr;
+    const bool sep = P == 1 && pd[0].leaves > 1 && (pd[0].L + 15) / 16 <= 6;
+    if (sep) {
+      std::vector<int32_t> items((size_t)pd[0].leaves);
+      for (int i = 0; i < pd[0].leaves; ++i) items[(size_t)i] = -1 - i;
+      while (items.size() > 1) {
+        std::vector<int32_t> next;
+        for (size_t i = 0; i + 1 < items.size(); i += 2) {
+          nl.push_back(items[i]);
+          nr.push_back(items[i + 1]);
+          next.push_back((int32_t)nl.size() - 1);
+        }
+        if (items.size() & 1) next.push_back(items.back());
+        items.swap(next);
+      }
+    }
+    h->nnodes = (int)nl.size();
     int64_t slot = 0, ctr = 0;
     for (auto& D : pd) {
       D.slot0 = slot;
       D.ctr0 = ctr;
-      const TreeSize ts = tree_size(D.leaves);
-      slot += ts.slots * tsqr_mfma_slot_floats(D.L);
-      ctr += ts.counters;
+      D.tree_sep = sep ? 1 : 0;
+      if (sep) {
+        slot += (int64_t)(D.leaves + h->nnodes) * tsqr_mfma_slot_floats(D.L);
+        ctr += std::max<int64_t>(1, (int64_t)h->nnodes * ((D.L + 15) / 16));
+      } else {
+        const TreeSize ts = tree_size(D.leaves);
+        slot += ts.slots * tsqr_mfma_slot_floats(D.L);
+        ctr += ts.counters;
+      }
     }
     h->nctr = ctr;
+    if (h->nnodes > h->node_cap) {
+      dfree(h, h->node_l);
+      dfree(h, h->node_r);
+      h->node_l = h->node_r = nullptr;
+      h->node_cap = 0;
+      qrk_status s2;
+      if ((s2 = dalloc(h, &h->node_l, sizeof(int32_t) * h->nnodes)) != QRK_OK ||
+          (s2 = dalloc(h, &h->node_r, sizeof(int32_t) * h->nnodes)) != QRK_OK)
+        return s2;
+      h->node_cap = h->nnodes;
+    }
+    if (h->nnodes > 0 &&
+        (hipMemcpy(h->node_l, nl.data(), sizeof(int32_t) * nl.size(), hipMemcpyHostToDevice) != hipSuccess ||
+         hipMemcpy(h->node_r, nr.data(), sizeof(int32_t) * nr.size(), hipMemcpyHostToDevice) != hipSuccess))
+      return QRK_EHIP;
     const int64_t nleaf = (int64_t)lp.size();
     qrk_status s;
     if (nleaf > h->leaf_cap) {
@@ -557,7 +615,6 @@ qrk_status qrk_factor_blockangular(qrk_handle h, const void* A, const void* B, c
   if (!h || h->kind != KIND_BLOCKANGULAR || h->P != 1) return QRK_EINVAL;
   if (!A || !b || !d || (h->nB > 0 && !B)) return QRK_EINVAL;
   if (!(lambda >= 0.0) || !std::isfinite(lambda)) return QRK_EINVAL;
-  if (launch_fill_double(h->lam_d, 1, lambda, S(stream)) != hipSuccess) return QRK_EHIP;
   h->A = A;
   h->B = B;
   h->b = b;
@@ -565,7 +622,7 @@ qrk_status qrk_factor_blockangular(qrk_handle h, const void* A, const void* B, c
   h->lam = lambda;
   h->lam_ptr = h->lam_d;
   h->factored = true;
-  return h->dtype == QRK_F32 ? factor_ba<float>(h, S(stream)) : factor_ba<double>(h, S(stream));
+  return h->dtype == QRK_F32 ? factor_ba<float>(h, S(stream), &lambda) : factor_ba<double>(h, S(stream), &lambda);
 }
 
 qrk_status qrk_factor_blockangular_batched(qrk_handle h, const void* A, const void* B, const void* b,
@@ -653,6 +710,7 @@ qrk_status qrk_status_get(qrk_handle h, int32_t* detail_host, void* stream) {
   if (detail_host) *detail_host = bits;
   // a zero pivot also makes p non-finite, so singularity is reported first
   if (bits & ST_BADINPUT) return QRK_EINVAL;
+  if (bits & ST_STALL) return QRK_EHIP;
   if (bits & ST_SINGULAR) return QRK_ESINGULAR;
   if (bits & ST_NONFINITE) return QRK_ENONFINITE;
   return QRK_OK;

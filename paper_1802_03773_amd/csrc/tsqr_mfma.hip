@@ -31,8 +31,9 @@ hipError_t launch_tsqr_mfma(bool bf16x3, const int* cls_begin, const int* cls_co
                             const int32_t* leaf_idx, const ProbDesc* probs, int n, const float* Red,
                             const double* d, const double* lam, float* slots, int* counters, int64_t nctr,
                             float* RB, hipStream_t st) {
+  // the arrival counters are cleared by the factor call's first per-block QR launch
   if (nctr < 1) return hipErrorInvalidValue;
-  hipError_t e = launch_zero_ints(counters, nctr, st);
+  hipError_t e = hipSuccess;
   for (int c = 8; c >= 1 && e == hipSuccess; --c) {  // widest (slowest) problems first
     const int b = cls_begin[c], k = cls_count[c];
     if (k == 0) continue;

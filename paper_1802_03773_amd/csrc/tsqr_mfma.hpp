@@ -416,6 +416,10 @@ k_tsqr_mfma(int leaf_begin, int nleaves_cls, const int32_t* __restrict__ leaf_pr
 
   // ---- pairwise merges up the problem's tree, in the same launch ----------------------------
   float* pslots = slots + P.slot0;
+  if (P.tree_sep && nleaves > 1) {  // the merges are a separate, pipelined launch
+    store_tri<NCB>(pslots + (int64_t)leaf * SLOT, R, lane);
+    return;
+  }
   int* pctr = counters + P.ctr0;
   int nl = nleaves;
   int slot = leaf;

@@ -1,0 +1,250 @@
+// Dense-part merge tree as a launch of its own, pipelined over column blocks (float32).
+//
+// What is computed (QRkit Section 4.2): the triangle of QR([R_left; R_right]) at every inner
+// node of the tall-skinny QR's reduction tree, the root being R_B | c_B.
+//
+// Organisation.  The leaves (k_tsqr_mfma with the problem's tree_sep set) store their
+// triangles and exit.  Here one wave per merge node works left-looking over column blocks of
+// 16: for column block q it waits until both children have published their column block q,
+// loads it, applies the reflectors of its own panels 0..q-1 (compact WY, kept in LDS),
+// factors panel q, keeps that panel's reflectors (T, column scales, raw tile columns W) for
+// the later column blocks, and publishes its column block q (stores, release fence, then a
+// per-node, per-block flag).  A parent starts on column block 0 while its children are still
+// on later ones, so the root trails the leaves by about (tree depth + column blocks) panel
+// times rather than (tree depth) whole merges.
+//
+// Forward progress.  Nodes are numbered level by level from the leaves up, and the children
+// of a node are leaves or nodes with smaller numbers.  Wave w of the launch runs node w and
+// workgroups are dispatched in order, so a wave only waits for waves that were dispatched
+// before it or belong to its own workgroup.  Every wait is bounded: a flag not seen within the
+// bound sets the problem's ST_STALL status bit, and the wave still publishes every column
+// block so that no other wave waits on it.
+//
+// The panel factorisation and the compact-WY application are those of merge_tile (same
+// reflector sign, scales, T recurrence and layouts), split so that a panel's reflectors can be
+// applied to column blocks that arrive later.
+#pragma once
+
+#include "tsqr_mfma.hpp"
+
+namespace qrk {
+
+// Per-wave LDS for the kept panels: panel p holds T (256 floats, row-major), the column
+// scales (16 floats, padded to 64) and W (p + 1 blocks of 256 floats, accumulator layout).
+template <int NCB>
+struct TreeKeep {
+  static constexpr int off(int p) { return p * (256 + 64) + 256 * (p * (p + 1) / 2); }
+  static constexpr int total = off(NCB);
+};
+
+// Factor the panel [Rd; X[0..RBN-1]]: Rd is the 16x16 diagonal block of the R part, X the
+// tile blocks of this column block (accumulator layout).  On return Rd holds the new diagonal
+// block and R's row j entries, X the raw reflector columns, and T, the scales and W are kept
+// in LDS at `keep`.
+template <int RBN>
+__device__ __forceinline__ void tree_panel_factor(f4& Rd, f4* X, float* __restrict__ keep, int lane) {
+  const int g = lane >> 4;
+  const int c = lane & 15;
+  float trow[16];  // lane (g, c) builds row c of T
+  float sc = 0.f;  // scale of this lane's column once it has been reduced
+  static_for<0, 16>([&](auto JJ) {
+    constexpr int j = decltype(JJ)::value;
+    float ps0 = 0.f, ps1 = 0.f;
+#pragma unroll
+    for (int rb = 0; rb < RBN; ++rb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        if (v & 1)
+          ps1 += X[rb][v] * X[rb][v];
+        else
+          ps0 += X[rb][v] * X[rb][v];
+      }
+    const float ps = sum_rows4(ps0 + ps1);
+    const float sigma = row_bcast<j>(ps);
+    const float alpha = read_lane(Rd[j & 3], (j >> 2) * 16 + j);
+    // sigma below the smallest normal float counts as zero (identity reflector): the
+    // hardware square root would return 0 for it
+    const bool refl = sigma >= 0x1p-126f;
+    const float nrm = __builtin_amdgcn_sqrtf(alpha * alpha + sigma);
+    const float bneg = alpha >= 0.f ? -nrm : nrm;
+    const float beta = refl ? bneg : alpha;
+    const float tau = refl ? (bneg - alpha) * __builtin_amdgcn_rcpf(bneg) : 0.f;
+    const float scale = refl ? __builtin_amdgcn_rcpf(alpha - bneg) : 0.f;
+    float pr0 = 0.f, pr1 = 0.f;
+#pragma unroll
+    for (int rb = 0; rb < RBN; ++rb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        if (v & 1)
+          pr1 += row_bcast<j>(X[rb][v]) * X[rb][v];
+        else
+          pr0 += row_bcast<j>(X[rb][v]) * X[rb][v];
+      }
+    const float rj = (g == (j >> 2)) ? Rd[j & 3] : 0.f;
+    const float pd = sum_rows4((pr0 + pr1) * scale + rj);  // R[j][c] + w_j^T x_c
+    const float s = tau * pd;
+    const float nf = (c > j) ? -scale * s : 0.f;
+#pragma unroll
+    for (int rb = 0; rb < RBN; ++rb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) X[rb][v] += row_bcast<j>(X[rb][v]) * nf;
+    if (g == (j >> 2)) Rd[j & 3] = (c > j) ? Rd[j & 3] - s : (c == j ? beta : Rd[j & 3]);
+    const float gk = sc * pd;
+    float t = 0.f;
+    static_for<0, j>([&](auto KK) {
+      constexpr int k = decltype(KK)::value;
+      t += trow[k] * row_bcast<k>(gk);
+    });
+    trow[j] = (c < j) ? -tau * t : (c == j ? tau : 0.f);
+    if (c == j) sc = scale;
+  });
+  float* Tl = keep;
+  float* Sl = keep + 256;
+  float* Wl = keep + 320;
+  if (g == 0) {
+#pragma unroll
+    for (int k = 0; k < 16; k += 4)
+      *reinterpret_cast<f4*>(Tl + c * 16 + k) = f4{trow[k], trow[k + 1], trow[k + 2], trow[k + 3]};
+    Sl[c] = sc;
+  }
+#pragma unroll
+  for (int rb = 0; rb < RBN; ++rb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Wl[rb * 256 + (4 * g + v) * 16 + c] = X[rb][v];
+  wave_lds_sync();
+}
+
+// Apply a kept panel (RBN tile blocks) to one column block: Rp is the column block's R-part
+// block in the panel's block row, X its tile blocks 0..RBN-1.
+//   Z = Rp + diag(s) X_P^T X;  Z' = T^T Z;  Rp -= Z';  X -= X_P diag(s) Z'
+template <int RBN>
+__device__ __forceinline__ void tree_panel_apply(const float* __restrict__ keep, f4& Rp, f4* X, int lane) {
+  const int g = lane >> 4;
+  const int c = lane & 15;
+  const float* Tl = keep;
+  const float* Sl = keep + 256;
+  const float* Wl = keep + 320;
+  f4 Td;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) Td[v] = Tl[(4 * g + v) * 16 + c];
+  const f4 srow = *reinterpret_cast<const f4*>(Sl + 4 * g);
+  float Pa[RBN][4];  // x[rb*16 + 4g + v][c]       (panel columns, accumulator layout)
+  float Wt[RBN][4];  // -x[rb*16 + c][4g + v]      (transposed)
+#pragma unroll
+  for (int rb = 0; rb < RBN; ++rb) {
+    const f4 w4 = *reinterpret_cast<const f4*>(Wl + rb * 256 + c * 16 + 4 * g);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      Pa[rb][v] = Wl[rb * 256 + (4 * g + v) * 16 + c];
+      Wt[rb][v] = -w4[v];
+    }
+  }
+  f4 Y0 = {0.f, 0.f, 0.f, 0.f}, Y1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int rb = 0; rb < RBN; ++rb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      if ((rb * 4 + v) & 1)
+        Y1 = mfma4(Pa[rb][v], X[rb][v], Y1);
+      else
+        Y0 = mfma4(Pa[rb][v], X[rb][v], Y0);
+    }
+  const f4 Z = Rp + srow * (Y0 + Y1);
+  f4 Zp = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int v = 0; v < 4; ++v) Zp = mfma4(Td[v], Z[v], Zp);
+  Rp -= Zp;
+  const f4 Zs = srow * Zp;
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int rb = 0; rb < RBN; ++rb) X[rb] = mfma4(Wt[rb][v], Zs[v], X[rb]);
+}
+
+// Wait (bounded) until *flag is set; false on timeout.  Lane 0 polls with relaxed
+// device-scope loads (coherent, but no cache invalidation per poll: an acquiring poll would
+// invalidate the L2 on every iteration, under every other wave); the caller then issues one
+// acquire fence.
+__device__ __forceinline__ bool tree_wait(const int* flag, int lane) {
+  for (int it = 0; it < (1 << 20); ++it) {
+    int v = 0;
+    if (lane == 0) v = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (__builtin_amdgcn_readfirstlane(v) != 0) return true;
+    __builtin_amdgcn_s_sleep(2);
+  }
+  return false;
+}
+
+// One wave per inner node of the (single) problem's tree.  node_l / node_r: child references,
+// r >= 0 an inner node, r < 0 leaf -1 - r.  Leaf triangles are at slots 0 .. leaves-1 of the
+// problem, node outputs at slots leaves + node; flags[node * NCB + q] marks column block q of
+// a node's output as published.  The root (the last node) writes R_B | c_B row-major.
+template <int NCB>
+__global__ void __launch_bounds__(256)
+k_tsqr_tree(const ProbDesc* __restrict__ probs, const int32_t* __restrict__ node_l,
+            const int32_t* __restrict__ node_r, int nnodes, float* __restrict__ slots, int* __restrict__ flags,
+            float* __restrict__ RBall, int* __restrict__ status) {
+  __shared__ float keep_all[4][TreeKeep<NCB>::total];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int node = blockIdx.x * 4 + wv;
+  if (node >= nnodes) return;
+  const ProbDesc& P = probs[0];
+  const int L = P.L;
+  const int nleaves = P.leaves;
+  constexpr int SLOT = Tri<NCB>::count * 256;
+  float* pslots = slots + P.slot0;
+  int* pflags = flags + P.ctr0;
+  const int lref = node_l[node], rref = node_r[node];
+  const float* lsrc = pslots + (int64_t)(lref >= 0 ? nleaves + lref : -1 - lref) * SLOT;
+  const float* rsrc = pslots + (int64_t)(rref >= 0 ? nleaves + rref : -1 - rref) * SLOT;
+  float* out = pslots + (int64_t)(nleaves + node) * SLOT;
+  const bool root = node == nnodes - 1;
+  float* keep = keep_all[wv];
+  const int g = lane >> 4;
+  const int c = lane & 15;
+  bool stalled = false;
+  f4 a[NCB];  // column block q: R part (left child), block rows 0..q
+  f4 x[NCB];  // column block q: tile (right child), block rows 0..q
+  static_for<0, NCB>([&](auto QQ) {
+    constexpr int q = decltype(QQ)::value;
+    if (!stalled && lref >= 0) stalled = !tree_wait(pflags + (int64_t)lref * NCB + q, lane);
+    if (!stalled && rref >= 0) stalled = !tree_wait(pflags + (int64_t)rref * NCB + q, lane);
+    if (lref >= 0 || rref >= 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+#pragma unroll
+    for (int p = 0; p <= q; ++p) {
+      a[p] = __builtin_nontemporal_load(reinterpret_cast<const f4*>(lsrc + Tri<NCB>::idx(p, q) * 256 + lane * 4));
+      x[p] = __builtin_nontemporal_load(reinterpret_cast<const f4*>(rsrc + Tri<NCB>::idx(p, q) * 256 + lane * 4));
+    }
+    static_for<0, q>([&](auto PP) {
+      constexpr int p = decltype(PP)::value;
+      tree_panel_apply<p + 1>(keep + TreeKeep<NCB>::off(p), a[p], x, lane);
+    });
+    tree_panel_factor<q + 1>(a[q], x, keep + TreeKeep<NCB>::off(q), lane);
+    if (root) {
+      // column block q of R_B | c_B, row-major L x L (zeros below the diagonal)
+      float* Rout = RBall + P.rboff;
+      static_for<0, NCB>([&](auto PR) {
+        constexpr int p = decltype(PR)::value;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 16 * p + 4 * g + v;
+          const int col = 16 * q + c;
+          float val = 0.f;
+          if constexpr (p < q) val = a[p][v];
+          if constexpr (p == q) val = (col >= row) ? a[p][v] : 0.f;
+          if (row < L && col < L) Rout[(int64_t)row * L + col] = val;
+        }
+      });
+    } else {
+#pragma unroll
+      for (int p = 0; p <= q; ++p)
+        *reinterpret_cast<f4*>(out + Tri<NCB>::idx(p, q) * 256 + lane * 4) = a[p];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      if (lane == 0) __hip_atomic_store(pflags + (int64_t)node * NCB + q, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  });
+  if (stalled) set_status(status, ST_STALL);
+}
+
+}  // namespace qrk
