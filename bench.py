@@ -10,7 +10,7 @@ relative error <= 1e-10 against the float64 oracle.  Inputs are resident in HBM
 before the timed region; the whole step runs in libqrkit.so's HIP kernels.
 
 Prints one JSON line.  `python bench.py` runs on one GPU; --gpus above 1 is refused
-(this build targets a single GPU).
+(the library and this benchmark run on a single GPU).
 """
 from __future__ import annotations
 
@@ -69,7 +69,8 @@ def _parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (cpu_baseline) leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for PMC byte scaling)")
-    ap.add_argument("--workload", default="scale", choices=["scale", "ragged-batch", "banded-batch"],
+    ap.add_argument("--workload", default="scale",
+                    choices=["scale", "ragged-batch", "banded-batch", "lm-scale", "lm-banded-batch"],
                     help="scale: one block-angular problem (the headline); ragged-batch: 512 block-angular "
                          "problems in one batch; banded-batch: 2,048 banded problems in one batch")
     ap.add_argument("--problems", type=int, default=0, help="batch workloads: problems (0 = the recipe's count)")
@@ -252,6 +253,118 @@ def run_batch(args):
     return 0
 
 
+def run_lm(args):
+    """Device-side Backtrack-LM iterations replayed from one captured HIP graph: every LM
+    iteration of every problem is one LM step solve (model evaluation, structured factor,
+    solve with float64 refinement, gain ratio and damping update, all on the device)."""
+    import numpy as np
+    import torch
+
+    from oracle import lm as olm
+    from paper_1802_03773_amd import BandedSolver, BlockAngularSolver, LMDriver
+    from workloads import generators as gen
+
+    banded = args.workload == "lm-banded-batch"
+    c, sweeps = 0.1, 1
+    check_iters = 5 if banded else 2
+    P = (args.problems or 2048) if banded else 1
+    print(f"[bench] generating {args.workload} ({P} problems)", file=sys.stderr, flush=True)
+    if banded:
+        probs = [gen.lm_banded(320 + k, N=2048, w=12, c=c)[:3] for k in range(P)]
+        i0 = probs[0][0]
+        solver = BandedSolver(i0.M, i0.N, i0.w, dtype="float32", P=P)
+        A0 = torch.from_numpy(np.concatenate([q[0].row_start for q in probs]).astype(np.int32)).cuda()
+        B0 = torch.from_numpy(np.concatenate([q[0].vals for q in probs])).cuda()
+        desc = {"workload": "LM on a banded batch: %d problems of n = %d unknowns, %d rows, %d values per row, "
+                            "f(x) = J0 (x + %g x^3) - y, float32 factor, %d float64 sweep" % (P, i0.N, i0.M, i0.w, c, sweeps),
+                "problems": P, "rows": P * i0.M, "unknowns": P * i0.N}
+    else:
+        probs = [gen.lm_blockangular(310, K=50_000, m=12, n=3, nB=90, c=c)[:3]]
+        i0 = probs[0][0]
+        solver = BlockAngularSolver(i0.row_off, i0.n, i0.nB, dtype="float32")
+        A0 = torch.from_numpy(i0.A).cuda()
+        B0 = torch.from_numpy(i0.B).cuda()
+        desc = {"workload": "LM on one block-angular problem: 50,000 blocks of 12x3 + dense 600,000x90, "
+                            "f(x) = J0 (x + %g x^3) - y, float32 factor, %d float64 sweep" % (c, sweeps),
+                "problems": 1, "rows": i0.M, "unknowns": i0.N}
+    y = torch.from_numpy(np.concatenate([q[1] for q in probs]).astype(np.float32)).cuda()
+    x0 = torch.from_numpy(np.concatenate([q[2] for q in probs])).cuda()
+    lam0 = torch.full((P,), 1e-2, dtype=torch.float64, device="cuda")
+    drv = LMDriver(solver, A0, B0, y, c, sweeps=sweeps, max_log=check_iters)
+
+    # agreement with the LM oracle over the first iterations (sampled problems)
+    drv.reset(x0, lam0)
+    drv.run(check_iters)
+    _, _, lg, _ = drv.get()
+    lg = lg.cpu().numpy()
+    sample = sorted({0, P // 2, P - 1})
+    errors, cpu_baseline = None, None
+    if not args.no_cpu:
+        worst, flips, t_cpu = 0.0, 0, 0.0
+        for q in sample:
+            inst0, yq, x0q = probs[q]
+            model = (olm.BandedModel(inst0, yq.astype(np.float64), c) if banded else
+                     olm.BlockAngularModel(inst0, yq.astype(np.float64), c))
+            t0 = time.perf_counter()
+            _, _, lgo = (olm.bd_lm if banded else olm.ba_lm)(model, x0q, 1e-2, check_iters, store=np.float32)
+            t_cpu += time.perf_counter() - t0
+            F = lg[:, q, 0]
+            worst = max(worst, float(np.max(np.abs(F - lgo[:, 0]) / np.abs(lgo[:, 0]))))
+            flips += int(np.sum(lg[:, q, 3] != lgo[:, 3]))
+        errors = {"max_rel_err_F_first_%d_iterations" % check_iters: worst,
+                  "accept_decisions_differing": flips, "sampled_problems": sample}
+        cpu_baseline = {"value": len(sample) * check_iters / t_cpu, "unit": "steps/s", "cores": _cpu_threads(),
+                        "kind": "oracle", "sample": "%d Backtrack-LM iterations of problems %s with the float64 "
+                        "oracle step (float32-rounded J), %.2f s" % (check_iters, sample, t_cpu)}
+
+    # per-phase timing from eager iterations (profiling is off inside a graph)
+    drv.reset(x0, lam0)
+    drv.run(1)
+    solver.profile_enable(64)
+    drv.run(3)
+    torch.cuda.synchronize()
+    phases = solver.profile_read()
+    solver.profile_enable(0)
+
+    drv.reset(x0, lam0)
+    drv.run(args.warmup, graph=True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    drv.run(args.steps, graph=True)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+
+    phase_out = {k: {"avg_ms": v[0] / v[1], "launches": v[1]} for k, v in phases.items() if v[1]}
+    if banded:
+        ins = [q[0] for q in probs]
+        fb = sum(i.M * i.w * 4 + i.M * 4 + i.M * 4 + i.N * 8 + i.N * i.w * 4 + i.N * 4 for i in ins)
+        rb = sum(i.M * i.w * 4 + i.M * 4 + i.M * 4 + i.N * 8 + i.N * 8 + 2 * i.N * i.w * 4 + i.N * 8 for i in ins)
+        work = {"banded": ("hbm", fb, PEAK_HBM_GBS, "GB/s", 1e9), "refine": ("hbm", rb, PEAK_HBM_GBS, "GB/s", 1e9)}
+    else:
+        wk = algorithmic_work(i0)
+        work = {k: (b_, a_, PEAK_FP32_VECTOR_TFLOPS if b_ == "alu" else PEAK_HBM_GBS,
+                    "TFLOP/s" if b_ == "alu" else "GB/s", 1e12 if b_ == "alu" else 1e9)
+                for k, (b_, a_, _u) in wk.items()}
+    for k, (bound, amount, peak, unit, scale) in work.items():
+        if k in phase_out:
+            amount = amount * (sweeps if k == "refine" else 1)
+            ach = amount / (phase_out[k]["avg_ms"] * 1e-3) / scale
+            phase_out[k].update(bound=bound, achieved=ach, peak=peak, unit=unit, frac=ach / peak)
+    dominant = max(phase_out, key=lambda k: phase_out[k]["avg_ms"]) if phase_out else None
+    dom = phase_out.get(dominant, {})
+    roofline = {"kernel": dominant, "bound": dom.get("bound"), "achieved": dom.get("achieved"),
+                "peak": dom.get("peak"), "unit": dom.get("unit"), "frac": dom.get("frac"), "traffic": None}
+    desc.update(refine_sweeps=sweeps, refine_dtype="f64", graph=True)
+    out = {"metric": METRIC, "value": P * 1000.0 / ms, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic", "config": desc, "accuracy": errors,
+           "roofline": roofline, "phases": phase_out, "cpu_baseline": cpu_baseline}
+    print(json.dumps(out))
+    return 0
+
+
 def main():
     args = _parse()
     if args.gpus != 1:
@@ -259,6 +372,8 @@ def main():
               "single GPU (several GPUs would split the blocks and all-gather the dense-part triangles).",
               file=sys.stderr)
         return 2
+    if args.workload in ("lm-scale", "lm-banded-batch"):
+        return run_lm(args)
     if args.workload != "scale":
         return run_batch(args)
     import numpy as np

@@ -212,7 +212,8 @@ qrk_status qrk_get_factor(qrk_handle h, void* Rblk, void* S, void* RB, void* str
 qrk_status qrk_status_get(qrk_handle h, int32_t* detail_host, void* stream);
 
 /* Set the launch shape of the dense-part leaves of a single-problem handle (0 = library
- * default): number of leaves (at most 1024) and, for float64 handles, the tree fan-in.
+ * default): number of leaves (at most 4096 for float32 handles, 1024 for float64 ones) and,
+ * for float64 handles, the tree fan-in.
  * Not capturable (it may reallocate the merge-tree workspace).  QRK_EINVAL for
  * out-of-range values or a batched handle. */
 qrk_status qrk_set_tsqr_shape(qrk_handle h, int32_t leaves, int32_t fanin);

@@ -16,7 +16,7 @@ D = diag of the column norms of J(x), recomputed every iteration; a zero column 
     rho > 0:  x <- x + p,  lam <- lam * max(1/3, 1 - (2 rho - 1)^3),  nu <- 2
     else   :  lam <- lam * nu,  nu <- 2 nu
 The paper says only that its lambda update adapts a published rule; the rule above is
-Nielsen's gain-ratio rule (Madsen, Nielsen and Tingleff), the reading this build takes.
+Nielsen's gain-ratio rule (Madsen, Nielsen and Tingleff), the reading taken here.
 
 Storage.  The GPU path keeps J(x) and -f in the factor's storage type; `store` rounds them
 the same way here (float32 -> np.float32), so both sides solve the same instance.  The step

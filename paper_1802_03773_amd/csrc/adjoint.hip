@@ -1,5 +1,5 @@
-// Adjoint of the LM step through the stored factor (an addition of this build; the
-// derivation differentiates the paper's Eq. 1, (J^T J + lam D^2) p = J^T b):
+// Adjoint of the LM step through the stored factor (not in the paper; the derivation
+// differentiates the paper's Eq. 1, (J^T J + lam D^2) p = J^T b):
 //   M dp = dJ^T r + J^T db - J^T dJ p - dlam D^2 p - 2 lam D dD p,   r = b - J p,
 // so for a loss with g = dL/dp and u = M^{-1} g = (R^T R)^{-1} g (two triangular solves):
 //   dL/db = J u,  dL/dJ_ab = r_a u_b - (J u)_a p_b,  dL/dlam = -u^T D^2 p,

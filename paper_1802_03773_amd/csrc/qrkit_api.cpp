@@ -526,7 +526,7 @@ qrk_status create_ba(int32_t P, int32_t n, const int32_t* Kp, const int32_t* nBp
   h->nwg = (int)wg_prob.size();
   h->refine_grid = h->nwg;
   h->grid_blocks = (int)std::min<int64_t>(ceil_div(Ktot, 4), 2048);
-  h->max_leaves = 1024;
+  h->max_leaves = dtype == QRK_F32 ? 4096 : 1024;
   h->leaves = 0;
   h->fanin = 8;
   h->leaf_scale = remembered_leaf_scale(h);

@@ -8,10 +8,15 @@
 // 16: for column block q it waits until both children have published their column block q,
 // loads it, applies the reflectors of its own panels 0..q-1 (compact WY, kept in LDS),
 // factors panel q, keeps that panel's reflectors (T, column scales, raw tile columns W) for
-// the later column blocks, and publishes its column block q (stores, release fence, then a
-// per-node, per-block flag).  A parent starts on column block 0 while its children are still
+// the later column blocks, and publishes its column block q (stores, then a per-node,
+// per-block flag).  A parent starts on column block 0 while its children are still
 // on later ones, so the root trails the leaves by about (tree depth + column blocks) panel
 // times rather than (tree depth) whole merges.
+//
+// Memory ordering.  A node's published blocks are written and read with device-scope relaxed
+// atomic accesses (through the L2 to memory and back); the producer waits for its block
+// stores to complete before storing the flag, the consumer polls the flag with device-scope
+// loads and only then issues the block's loads.
 //
 // Forward progress.  Nodes are numbered level by level from the leaves up, and the children
 // of a node are leaves or nodes with smaller numbers.  Wave w of the launch runs node w and
@@ -161,10 +166,24 @@ __device__ __forceinline__ void tree_panel_apply(const float* __restrict__ keep,
     for (int rb = 0; rb < RBN; ++rb) X[rb] = mfma4(Wt[rb][v], Zs[v], X[rb]);
 }
 
+// Published node outputs move through device-scope (relaxed atomic) accesses, which write
+// through and read past the per-XCD L2: a consumer never sees a stale L2 copy, and a
+// producer's release is just the wait for its own stores to complete before the flag store —
+// no L2-wide write-back or invalidation, which at one per column block and node (on every
+// XCD) had cost more than the arithmetic.
+__device__ __forceinline__ void tree_store_block(float* dst, const f4& v, int lane) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) __hip_atomic_store(dst + lane * 4 + k, v[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ f4 tree_load_block(const float* src, int lane) {
+  f4 v;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) v[k] = __hip_atomic_load(src + lane * 4 + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return v;
+}
+
 // Wait (bounded) until *flag is set; false on timeout.  Lane 0 polls with relaxed
-// device-scope loads (coherent, but no cache invalidation per poll: an acquiring poll would
-// invalidate the L2 on every iteration, under every other wave); the caller then issues one
-// acquire fence.
+// device-scope loads (no cache invalidation per poll).
 __device__ __forceinline__ bool tree_wait(const int* flag, int lane) {
   for (int it = 0; it < (1 << 20); ++it) {
     int v = 0;
@@ -210,11 +229,15 @@ k_tsqr_tree(const ProbDesc* __restrict__ probs, const int32_t* __restrict__ node
     constexpr int q = decltype(QQ)::value;
     if (!stalled && lref >= 0) stalled = !tree_wait(pflags + (int64_t)lref * NCB + q, lane);
     if (!stalled && rref >= 0) stalled = !tree_wait(pflags + (int64_t)rref * NCB + q, lane);
-    if (lref >= 0 || rref >= 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    asm volatile("" ::: "memory");  // the block's loads stay after the flags were seen
+    // leaf triangles come from the previous launch (plain loads); node outputs are read past
+    // the L2
 #pragma unroll
     for (int p = 0; p <= q; ++p) {
-      a[p] = __builtin_nontemporal_load(reinterpret_cast<const f4*>(lsrc + Tri<NCB>::idx(p, q) * 256 + lane * 4));
-      x[p] = __builtin_nontemporal_load(reinterpret_cast<const f4*>(rsrc + Tri<NCB>::idx(p, q) * 256 + lane * 4));
+      const float* ls = lsrc + Tri<NCB>::idx(p, q) * 256;
+      const float* rs = rsrc + Tri<NCB>::idx(p, q) * 256;
+      a[p] = lref >= 0 ? tree_load_block(ls, lane) : __builtin_nontemporal_load(reinterpret_cast<const f4*>(ls + lane * 4));
+      x[p] = rref >= 0 ? tree_load_block(rs, lane) : __builtin_nontemporal_load(reinterpret_cast<const f4*>(rs + lane * 4));
     }
     static_for<0, q>([&](auto PP) {
       constexpr int p = decltype(PP)::value;
@@ -238,9 +261,9 @@ k_tsqr_tree(const ProbDesc* __restrict__ probs, const int32_t* __restrict__ node
       });
     } else {
 #pragma unroll
-      for (int p = 0; p <= q; ++p)
-        *reinterpret_cast<f4*>(out + Tri<NCB>::idx(p, q) * 256 + lane * 4) = a[p];
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      for (int p = 0; p <= q; ++p) tree_store_block(out + Tri<NCB>::idx(p, q) * 256, a[p], lane);
+      // the flag store follows the completion of the block's stores
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       if (lane == 0) __hip_atomic_store(pflags + (int64_t)node * NCB + q, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   });
