@@ -7,10 +7,13 @@
 // upper bandwidth w - 1 and a w x w window of R (rows and columns s .. s + w - 1) is all
 // that is live while row i is processed.
 //
-// Layout: one problem per group of G lanes (G = 16: one DPP row; G = 32 for w > 15).
-// Lane l < w holds column s + l of the window (its entries in window rows 0..w-1), lane w
-// holds the right-hand side c of those rows.  The pivot of rotation k is lane k; its two
-// inputs are broadcast to the group, every lane applies the rotation to its own column.
+// This file holds the run-time-width kernels, used for 16 <= w <= 31 (bands up to 15 use
+// the compile-time-width kernels of banded_w.hpp), and the kernels shared by every width
+// (J v, J^T r, adjoint entries).
+// Layout of the run-time-width kernels: one problem per group of G = 32 lanes.  Lane l < w
+// holds column s + l of the window (its entries in window rows 0..w-1), lane w holds the
+// right-hand side c of those rows.  The pivot of rotation k is lane k; its two inputs are
+// broadcast to the group, every lane applies the rotation to its own column.
 // R is stored banded: row j holds R[j][j .. j + w - 1] (float or double), c is [N].
 #include "qrk_device.hpp"
 #include "qrk_banded.hpp"
@@ -224,35 +227,120 @@ k_banded_apply(int P, int64_t M, int64_t N, int w, const int32_t* __restrict__ r
   r[t] = bvec ? (double)bvec[t] - acc : acc;
 }
 
-// g = J^T r - lam d^2 v (float64) by a sweep over the rows of each problem (deterministic).
-template <typename T, int G>
+// Row starts clamped to [0, N - w] (the same clamp as the factorisation's for valid input).
+__device__ __forceinline__ int64_t band_start(const int32_t* rs, int64_t i, int64_t N, int w) {
+  const int64_t s = rs[i];
+  return s < 0 ? 0 : (s > N - w ? N - w : s);
+}
+
+// First-row table of every problem: fr[c] (c = 0 .. N) = the first row whose start is >= c,
+// for nondecreasing starts.  Thread i (0 .. M) fills the columns after row i-1's start up to
+// row i's start (thread M: up to N).  Starts out of order leave entries unset; the readers
+// clamp what they read.
 __global__ void __launch_bounds__(256)
-k_banded_jt(int P, int64_t M, int64_t N, int w, const int32_t* __restrict__ row_start,
+k_band_first_row(int P, int64_t M, int64_t N, int w, const int32_t* __restrict__ row_start,
+                 int32_t* __restrict__ fr) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)P * (M + 1)) return;
+  const int64_t prob = t / (M + 1), i = t % (M + 1);
+  const int32_t* rs = row_start + prob * M;
+  int32_t* f = fr + prob * (N + 1);
+  const int64_t c0 = i == 0 ? 0 : band_start(rs, i - 1, N, w) + 1;
+  const int64_t c1 = i == M ? N : band_start(rs, i, N, w);
+  for (int64_t c = c0; c <= c1; ++c) f[c] = (int32_t)i;
+}
+
+// g = J^T r - lam d^2 v (float64), one thread per column: column j of a problem collects the
+// rows whose start lies in [j - w + 1, j] in row order, so the sum is deterministic.  The row
+// ranges come from the first-row table.  A workgroup covers 256 consecutive columns of one
+// problem: the starts, residuals and values of its rows (one contiguous range) are copied to
+// LDS with coalesced loads, eight per thread in flight, and each column then reads only LDS.
+// Ranges beyond the LDS capacity read their rows from memory.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_banded_jt(int P, int64_t M, int64_t N, int w, const int32_t* __restrict__ row_start, const int32_t* __restrict__ fr,
             const T* __restrict__ vals, const double* __restrict__ r, const double* __restrict__ d,
             const double* __restrict__ lamv, const double* __restrict__ v, double* __restrict__ g) {
-  const int lane = threadIdx.x % G;
-  const int64_t prob = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
-  if (prob >= P) return;
-  const double lam = lamv[prob];
+  constexpr int CAP = 1024;                          // rows
+  constexpr int VCAP = 40960 / (int)sizeof(T);       // values
+  __shared__ int32_t s_st[CAP];
+  __shared__ double s_r[CAP];
+  __shared__ T s_v[VCAP];
+  const int64_t nb = (N + 255) / 256;
+  const int64_t prob = blockIdx.x / nb;
+  const int64_t c0 = (int64_t)(blockIdx.x % nb) * 256;
+  const int64_t j = c0 + threadIdx.x;
   const int32_t* rs = row_start + prob * M;
-  double acc = 0.0;  // lane l accumulates column s + l
-  int64_t s = 0;
-  auto flush = [&]() {
-    if (lane == 0) {
-      const double dj = d[prob * N + s];
-      g[prob * N + s] = acc - lam * dj * dj * v[prob * N + s];
-    }
-    acc = from_next<G>(acc);
-    if (lane == G - 1) acc = 0.0;
-    ++s;
+  const int32_t* f = fr + prob * (N + 1);
+  const double* rp = r + prob * M;
+  const T* V = vals + prob * M * w;
+  auto row_at = [&](int64_t c) -> int64_t {  // table entry, clamped to [0, M]
+    c = c < 0 ? 0 : (c > N ? N : c);
+    const int64_t i = f[c];
+    return i < 0 ? 0 : (i > M ? M : i);
   };
-  for (int64_t i = 0; i < M; ++i) {
-    int64_t si = rs[i];
-    si = si < s ? s : (si > N - w ? N - w : si);
-    while (s < si) flush();
-    if (lane < w) acc += (double)vals[(prob * M + i) * w + lane] * r[prob * M + i];
+  const int64_t lo = row_at(c0 - w + 1);
+  int64_t hi = row_at(c0 + 256);
+  hi = hi < lo ? lo : hi;
+  const int64_t n = hi - lo;
+  const bool staged = n <= CAP && n * w <= VCAP;
+  if (staged) {
+    const int64_t nv = n * w;
+    const T* Vlo = V + lo * w;
+    for (int64_t i0 = 0; i0 < nv; i0 += 256 * 8) {
+      T buf[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t i = i0 + u * 256 + threadIdx.x;
+        buf[u] = i < nv ? Vlo[i] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t i = i0 + u * 256 + threadIdx.x;
+        if (i < nv) s_v[i] = buf[u];
+      }
+    }
+    for (int64_t i0 = 0; i0 < n; i0 += 256 * 4) {
+      int32_t sb[4];
+      double rb[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t i = i0 + u * 256 + threadIdx.x;
+        sb[u] = i < n ? (int32_t)band_start(rs, lo + i, N, w) : 0;
+        rb[u] = i < n ? rp[lo + i] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t i = i0 + u * 256 + threadIdx.x;
+        if (i < n) {
+          s_st[i] = sb[u];
+          s_r[i] = rb[u];
+        }
+      }
+    }
+    __syncthreads();
   }
-  while (s < N) flush();
+  if (j >= N) return;
+  int64_t a = row_at(j - w + 1), e = row_at(j + 1);
+  double acc = 0.0;
+  if (staged) {
+    a = a < lo ? lo : a;
+    e = e > hi ? hi : e;
+    for (int64_t i = a - lo; i < e - lo; ++i) {
+      const int64_t k = j - s_st[i];
+      if (k < 0 || k >= w) continue;
+      acc += (double)s_v[i * w + k] * s_r[i];
+    }
+  } else {
+    for (int64_t i = a; i < e; ++i) {
+      const int64_t k = j - band_start(rs, i, N, w);
+      if (k < 0 || k >= w) continue;
+      acc += (double)V[i * w + k] * rp[i];
+    }
+  }
+  const int64_t t = prob * N + j;
+  const double dj = d[t];
+  g[t] = acc - lamv[prob] * dj * dj * v[t];
 }
 
 // Adjoint entries on the structural nonzeros: dvals[i][l] = r_i u_{s_i+l} - (J u)_i p_{s_i+l}.
@@ -273,33 +361,24 @@ k_banded_dvals(int P, int64_t M, int64_t N, int w, const int32_t* __restrict__ r
 }
 
 // ---------------------------------------------------------------------------------
-#define QRK_G_DISPATCH(KERNEL, T, ...)                                                           \
-  do {                                                                                           \
-    if (w < 16) {                                                                                \
-      const int64_t threads = (int64_t)P * 16;                                                   \
-      hipLaunchKernelGGL((KERNEL<T, 16>), dim3((threads + 255) / 256), dim3(256), 0, st, __VA_ARGS__); \
-    } else {                                                                                     \
-      const int64_t threads = (int64_t)P * 32;                                                   \
-      hipLaunchKernelGGL((KERNEL<T, 32>), dim3((threads + 255) / 256), dim3(256), 0, st, __VA_ARGS__); \
-    }                                                                                            \
-  } while (0)
 
 template <typename T>
 hipError_t launch_banded_givens(int P, int64_t M, int64_t N, int w, const int32_t* row_start,
                                 const T* vals, const T* b, const double* d, const double* lam, T* Rb,
-                                T* cb, int* status, hipStream_t st) {
+                                T* cb, double* binv, T* R16, int* status, hipStream_t st) {
   if (w < 1 || w > 31) return hipErrorInvalidValue;
-  QRK_G_DISPATCH(k_banded_givens, T, P, M, N, w, row_start, vals, b, d, lam, Rb, cb, status);
+  if (w <= 15) return launch_bgivens_w<T>(P, M, N, w, row_start, vals, b, d, lam, Rb, cb, binv, R16, status, st);
+  const int64_t threads = (int64_t)P * 32;
+  hipLaunchKernelGGL((k_banded_givens<T, 32>), dim3((threads + 255) / 256), dim3(256), 0, st, P, M, N, w, row_start,
+                     vals, b, d, lam, Rb, cb, status);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_banded_backsub(int P, int64_t N, int w, const T* Rb, const T* cb, double* p, int* status,
-                                 hipStream_t st) {
-  if (w < 16) {
-    const int64_t threads = (int64_t)P * 16;
-    hipLaunchKernelGGL((k_banded_bwd<T, 16, false>), dim3((threads + 255) / 256), dim3(256), 0, st, P, N, w,
-                       Rb, cb, (const double*)nullptr, p, status);
+hipError_t launch_banded_backsub(int P, int64_t N, int w, const T* Rb, const T* R16, const double* binv, const T* cb,
+                                 double* p, int* status, hipStream_t st) {
+  if (R16) {
+    return launch_bsweep_w<T>(0, P, N, w, R16, binv, cb, nullptr, p, status, st);
   } else {
     const int64_t threads = (int64_t)P * 32;
     hipLaunchKernelGGL((k_banded_bwd<T, 32, false>), dim3((threads + 255) / 256), dim3(256), 0, st, P, N, w,
@@ -309,12 +388,10 @@ hipError_t launch_banded_backsub(int P, int64_t N, int w, const T* Rb, const T* 
 }
 
 template <typename T>
-hipError_t launch_banded_solve_add(int P, int64_t N, int w, const T* Rb, const double* rhs, double* out,
-                                   hipStream_t st) {
-  if (w < 16) {
-    const int64_t threads = (int64_t)P * 16;
-    hipLaunchKernelGGL((k_banded_bwd<T, 16, true>), dim3((threads + 255) / 256), dim3(256), 0, st, P, N, w,
-                       Rb, (const T*)nullptr, rhs, out, (int*)nullptr);
+hipError_t launch_banded_solve_add(int P, int64_t N, int w, const T* Rb, const T* R16, const double* binv,
+                                   const double* rhs, double* out, hipStream_t st) {
+  if (R16) {
+    return launch_bsweep_w<T>(1, P, N, w, R16, binv, nullptr, rhs, out, nullptr, st);
   } else {
     const int64_t threads = (int64_t)P * 32;
     hipLaunchKernelGGL((k_banded_bwd<T, 32, true>), dim3((threads + 255) / 256), dim3(256), 0, st, P, N, w,
@@ -324,9 +401,11 @@ hipError_t launch_banded_solve_add(int P, int64_t N, int w, const T* Rb, const d
 }
 
 template <typename T>
-hipError_t launch_banded_fwd(int P, int64_t N, int w, const T* Rb, const double* g, double* y,
-                             hipStream_t st) {
-  QRK_G_DISPATCH(k_banded_fwd, T, P, N, w, Rb, g, y);
+hipError_t launch_banded_fwd(int P, int64_t N, int w, const T* Rb, const T* R16, const double* binv, const double* g,
+                             double* y, hipStream_t st) {
+  if (R16) return launch_bsweep_w<T>(2, P, N, w, R16, binv, nullptr, g, y, nullptr, st);
+  const int64_t threads = (int64_t)P * 32;
+  hipLaunchKernelGGL((k_banded_fwd<T, 32>), dim3((threads + 255) / 256), dim3(256), 0, st, P, N, w, Rb, g, y);
   return hipGetLastError();
 }
 
@@ -335,16 +414,27 @@ hipError_t launch_banded_apply(int P, int64_t M, int64_t N, int w, const int32_t
                                const T* b, const double* v, double* r, hipStream_t st) {
   const int64_t threads = (int64_t)P * M;
   if (threads == 0) return hipSuccess;
+  if (w <= 15) return launch_bapply_w<T>(P, M, N, w, row_start, vals, b, v, r, st);
   hipLaunchKernelGGL((k_banded_apply<T>), dim3((threads + 255) / 256), dim3(256), 0, st, P, M, N, w, row_start,
                      vals, b, v, r);
   return hipGetLastError();
 }
 
+hipError_t launch_band_first_row(int P, int64_t M, int64_t N, int w, const int32_t* row_start, int32_t* fr,
+                                 hipStream_t st) {
+  const int64_t threads = (int64_t)P * (M + 1);
+  hipLaunchKernelGGL(k_band_first_row, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, P, M, N, w,
+                     row_start, fr);
+  return hipGetLastError();
+}
+
 template <typename T>
-hipError_t launch_banded_jt(int P, int64_t M, int64_t N, int w, const int32_t* row_start, const T* vals,
-                            const double* r, const double* d, const double* lam, const double* v, double* g,
-                            hipStream_t st) {
-  QRK_G_DISPATCH(k_banded_jt, T, P, M, N, w, row_start, vals, r, d, lam, v, g);
+hipError_t launch_banded_jt(int P, int64_t M, int64_t N, int w, const int32_t* row_start, const int32_t* fr,
+                            const T* vals, const double* r, const double* d, const double* lam, const double* v,
+                            double* g, hipStream_t st) {
+  const int64_t blocks = (int64_t)P * ((N + 255) / 256);
+  hipLaunchKernelGGL((k_banded_jt<T>), dim3((unsigned)blocks), dim3(256), 0, st, P, M, N, w, row_start, fr, vals, r,
+                     d, lam, v, g);
   return hipGetLastError();
 }
 
@@ -360,16 +450,16 @@ hipError_t launch_banded_dvals(int P, int64_t M, int64_t N, int w, const int32_t
 
 #define QRK_BINST(T)                                                                                     \
   template hipError_t launch_banded_givens<T>(int, int64_t, int64_t, int, const int32_t*, const T*,        \
-                                              const T*, const double*, const double*, T*, T*, int*, hipStream_t); \
-  template hipError_t launch_banded_backsub<T>(int, int64_t, int, const T*, const T*, double*, int*,       \
-                                               hipStream_t);                                              \
-  template hipError_t launch_banded_solve_add<T>(int, int64_t, int, const T*, const double*, double*,      \
-                                                 hipStream_t);                                            \
-  template hipError_t launch_banded_fwd<T>(int, int64_t, int, const T*, const double*, double*,            \
-                                           hipStream_t);                                                  \
+                                              const T*, const double*, const double*, T*, T*, double*, T*, int*, hipStream_t); \
+  template hipError_t launch_banded_backsub<T>(int, int64_t, int, const T*, const T*, const double*, const T*, \
+                                               double*, int*, hipStream_t);                               \
+  template hipError_t launch_banded_solve_add<T>(int, int64_t, int, const T*, const T*, const double*,     \
+                                                 const double*, double*, hipStream_t);                    \
+  template hipError_t launch_banded_fwd<T>(int, int64_t, int, const T*, const T*, const double*,           \
+                                           const double*, double*, hipStream_t);                          \
   template hipError_t launch_banded_apply<T>(int, int64_t, int64_t, int, const int32_t*, const T*,         \
                                              const T*, const double*, double*, hipStream_t);              \
-  template hipError_t launch_banded_jt<T>(int, int64_t, int64_t, int, const int32_t*, const T*,            \
+  template hipError_t launch_banded_jt<T>(int, int64_t, int64_t, int, const int32_t*, const int32_t*, const T*, \
                                           const double*, const double*, const double*, const double*, double*, \
                                           hipStream_t);                                                   \
   template hipError_t launch_banded_dvals<T>(int, int64_t, int64_t, int, const int32_t*, const double*,    \

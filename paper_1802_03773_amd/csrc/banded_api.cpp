@@ -24,17 +24,19 @@ qrk_status banded_solve_t(qrk_handle h, double* p, int sweeps, hipStream_t st) {
   const T* R = static_cast<const T*>(h->bandR);
   const T* c = static_cast<const T*>(h->bandc);
   int pr = prof_begin(h, 3, st);
-  if (launch_banded_backsub<T>(h->P, h->N, h->w, R, c, p, h->status, st) != hipSuccess) return QRK_EHIP;
+  const T* R16 = static_cast<const T*>(h->bandR16);
+  if (launch_banded_backsub<T>(h->P, h->N, h->w, R, R16, h->bandinv, c, p, h->status, st) != hipSuccess)
+    return QRK_EHIP;
   prof_end(h, pr, st);
   pr = sweeps > 0 ? prof_begin(h, 4, st) : -1;
   for (int s = 0; s < sweeps; ++s) {
     // r = b - J p; g = J^T r - lam D^2 p; y = R^{-T} g; p += R^{-1} y
     if (launch_banded_apply<T>(h->P, h->M, h->N, h->w, h->row_start, static_cast<const T*>(h->A),
                                static_cast<const T*>(h->b), p, h->rbuf, st) != hipSuccess ||
-        launch_banded_jt<T>(h->P, h->M, h->N, h->w, h->row_start, static_cast<const T*>(h->A), h->rbuf,
+        launch_banded_jt<T>(h->P, h->M, h->N, h->w, h->row_start, h->bandfr, static_cast<const T*>(h->A), h->rbuf,
                             h->d, h->lam_ptr, p, h->gbuf, st) != hipSuccess ||
-        launch_banded_fwd<T>(h->P, h->N, h->w, R, h->gbuf, h->gbuf, st) != hipSuccess ||
-        launch_banded_solve_add<T>(h->P, h->N, h->w, R, h->gbuf, p, st) != hipSuccess)
+        launch_banded_fwd<T>(h->P, h->N, h->w, R, R16, h->bandinv, h->gbuf, h->gbuf, st) != hipSuccess ||
+        launch_banded_solve_add<T>(h->P, h->N, h->w, R, R16, h->bandinv, h->gbuf, p, st) != hipSuccess)
       return QRK_EHIP;
   }
   prof_end(h, pr, st);
@@ -45,11 +47,12 @@ template <typename T>
 qrk_status banded_adjoint_t(qrk_handle h, const double* p, const double* g, void* dvals, void* db,
                             double* dlam, double* dd, hipStream_t st) {
   const T* R = static_cast<const T*>(h->bandR);
+  const T* R16 = static_cast<const T*>(h->bandR16);
   const int64_t PN = (int64_t)h->P * h->N, PM = (int64_t)h->P * h->M;
   // u = R^{-1} R^{-T} g
-  if (launch_banded_fwd<T>(h->P, h->N, h->w, R, g, h->gbuf, st) != hipSuccess ||
+  if (launch_banded_fwd<T>(h->P, h->N, h->w, R, R16, h->bandinv, g, h->gbuf, st) != hipSuccess ||
       launch_fill_double(h->ubuf, PN, 0.0, st) != hipSuccess ||
-      launch_banded_solve_add<T>(h->P, h->N, h->w, R, h->gbuf, h->ubuf, st) != hipSuccess)
+      launch_banded_solve_add<T>(h->P, h->N, h->w, R, R16, h->bandinv, h->gbuf, h->ubuf, st) != hipSuccess)
     return QRK_EHIP;
   const T* vals = static_cast<const T*>(h->A);
   if (dvals || db) {
@@ -94,6 +97,8 @@ qrk_status create_banded(int32_t P, int64_t M, int64_t N, int32_t w, qrk_dtype d
   qrk_status s;
   if ((s = handle_alloc(h, &h->bandR, es * PN * w)) != QRK_OK ||
       (s = handle_alloc(h, &h->bandc, es * PN)) != QRK_OK ||
+      (s = handle_alloc(h, reinterpret_cast<void**>(&h->bandinv), sizeof(double) * PN)) != QRK_OK ||
+      (s = handle_alloc(h, reinterpret_cast<void**>(&h->bandfr), sizeof(int32_t) * (size_t)P * (N + 1))) != QRK_OK ||
       (s = handle_alloc(h, reinterpret_cast<void**>(&h->rbuf), sizeof(double) * PM)) != QRK_OK ||
       (s = handle_alloc(h, reinterpret_cast<void**>(&h->jubuf), sizeof(double) * PM)) != QRK_OK ||
       (s = handle_alloc(h, reinterpret_cast<void**>(&h->gbuf), sizeof(double) * PN)) != QRK_OK ||
@@ -110,6 +115,17 @@ qrk_status create_banded(int32_t P, int64_t M, int64_t N, int32_t w, qrk_dtype d
     handle_free(h);
     delete h;
     return QRK_EHIP;
+  }
+  // bands up to 15 keep a padded sweep copy of R (zeroed once; the padding stays zero)
+  if (bsweep_w_fits(P, N, w, es)) {
+    void* r16 = nullptr;
+    const size_t bytes = es * 16 * ((size_t)P * N + 2 * kBandPad);
+    if ((s = handle_alloc(h, &r16, bytes)) != QRK_OK || hipMemset(r16, 0, bytes) != hipSuccess) {
+      handle_free(h);
+      delete h;
+      return s != QRK_OK ? s : QRK_EHIP;
+    }
+    h->bandR16 = static_cast<char*>(r16) + es * 16 * kBandPad;
   }
   *out = h;
   return QRK_OK;
@@ -166,17 +182,20 @@ qrk_status banded_factor(qrk_handle h, hipStream_t st) {
   const void* b = h->b;
   const double* d = h->d;
   int pr = prof_begin(h, 5, st);
+  if (launch_band_first_row(h->P, h->M, h->N, h->w, row_start, h->bandfr, st) != hipSuccess) return QRK_EHIP;
   hipError_t e = h->dtype == QRK_F32
                      ? launch_banded_givens<float>(h->P, h->M, h->N, h->w, row_start,
                                                    static_cast<const float*>(vals),
                                                    static_cast<const float*>(b), d, h->lam_ptr,
                                                    static_cast<float*>(h->bandR),
-                                                   static_cast<float*>(h->bandc), h->status, st)
+                                                   static_cast<float*>(h->bandc), h->bandinv,
+                                                   static_cast<float*>(h->bandR16), h->status, st)
                      : launch_banded_givens<double>(h->P, h->M, h->N, h->w, row_start,
                                                     static_cast<const double*>(vals),
                                                     static_cast<const double*>(b), d, h->lam_ptr,
                                                     static_cast<double*>(h->bandR),
-                                                    static_cast<double*>(h->bandc), h->status, st);
+                                                    static_cast<double*>(h->bandc), h->bandinv,
+                                                    static_cast<double*>(h->bandR16), h->status, st);
   prof_end(h, pr, st);
   return e == hipSuccess ? QRK_OK : QRK_EHIP;
 }

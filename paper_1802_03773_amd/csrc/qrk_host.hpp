@@ -96,6 +96,9 @@ struct qrk_handle_s {
   int* status = nullptr;
   void* bandR = nullptr;      // banded: [P][N][w]
   void* bandc = nullptr;      // banded: [P][N]
+  double* bandinv = nullptr;  // banded: reciprocal pivots 1 / R[j][j], [P][N]
+  int32_t* bandfr = nullptr;  // banded: first row with start >= c, [P][N+1]
+  void* bandR16 = nullptr;    // banded: sweep copy of the band, [P][N][16] (null if not kept)
   double* rbuf = nullptr;     // banded: residual / J u, [P][M] each
   double* jubuf = nullptr;
   double* gbuf = nullptr;     // banded: [P][N]
