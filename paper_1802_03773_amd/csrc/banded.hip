@@ -326,10 +326,27 @@ k_banded_jt(int P, int64_t M, int64_t N, int w, const int32_t* __restrict__ row_
   if (staged) {
     a = a < lo ? lo : a;
     e = e > hi ? hi : e;
-    for (int64_t i = a - lo; i < e - lo; ++i) {
-      const int64_t k = j - s_st[i];
-      if (k < 0 || k >= w) continue;
-      acc += (double)s_v[i * w + k] * s_r[i];
+    // eight rows per batch: their LDS reads are independent, the sum keeps row order
+    const int i1 = (int)(e - lo);
+    for (int i0 = (int)(a - lo); i0 < i1; i0 += 8) {
+      int kk[8];
+      double rr[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = i0 + u < i1 ? i0 + u : i1 - 1;
+        kk[u] = (int)(j - s_st[i]);
+        rr[u] = s_r[i];
+      }
+      T vv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = i0 + u < i1 ? i0 + u : i1 - 1;
+        const int k = kk[u] < 0 ? 0 : (kk[u] >= w ? w - 1 : kk[u]);
+        vv[u] = s_v[i * w + k];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (i0 + u < i1 && kk[u] >= 0 && kk[u] < w) acc += (double)vv[u] * rr[u];
     }
   } else {
     for (int64_t i = a; i < e; ++i) {

@@ -249,6 +249,222 @@ k_bgivens_w(int P, int64_t M, int64_t N, const int32_t* __restrict__ row_start, 
   if (bad) set_status(status, ST_BADINPUT);
 }
 
+// Exchange the odd 16-lane rows of v0 with the even rows of v1 (v_permlane16_swap).
+__device__ __forceinline__ void bw_swap16(float& v0, float& v1) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, v0), __builtin_bit_cast(unsigned, v1),
+                                                  false, false);
+  v0 = __builtin_bit_cast(float, (unsigned)r[0]);
+  v1 = __builtin_bit_cast(float, (unsigned)r[1]);
+}
+__device__ __forceinline__ void bw_swap16(double& v0, double& v1) {
+  const uint64_t a = __builtin_bit_cast(uint64_t, v0), b = __builtin_bit_cast(uint64_t, v1);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)a, (unsigned)b, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(a >> 32), (unsigned)(b >> 32), false, false);
+  v0 = __builtin_bit_cast(double, ((uint64_t)(unsigned)hi[0] << 32) | (unsigned)lo[0]);
+  v1 = __builtin_bit_cast(double, ((uint64_t)(unsigned)hi[1] << 32) | (unsigned)lo[1]);
+}
+// The odd row's value in both rows of each pair of 16-lane rows.
+template <typename T>
+__device__ __forceinline__ T bw_from_odd(T x) {
+  T y = x;
+  if constexpr (sizeof(T) == 4) {
+    asm volatile("" : "+v"(y));
+  } else {
+    uint64_t u = __builtin_bit_cast(uint64_t, y);
+    asm volatile("" : "+v"(u));
+    y = __builtin_bit_cast(T, u);
+  }
+  bw_swap16(x, y);  // y: even rows take the odd rows' values
+  return y;
+}
+
+// The same Givens QR with two problems per wave and two rows in flight per problem: a problem
+// owns 32 lanes, rows taken in pairs of equal start go through the window together, the first
+// (lanes 0-15, "A") one rotation ahead of the second (lanes 16-31, "B").  At step t, A rotates
+// against window row t and B against window row t - 1 in the same instructions: register k
+// holds window row k in A's lanes and window row k - 1 in B's lanes.  After each step
+// v_permlane16_swap hands the row A just rotated to B (register t of A -> register t + 1 of
+// B) and the row B just rotated back to A (register t of B -> register t - 1 of A), so every
+// row is current in A's lanes once a pair is done.  Rows whose starts differ go one at a time
+// in A's lanes.  With every SIMD holding a wave, this takes about half the time of four
+// problems per wave when the problems number fewer than four per SIMD.
+template <typename T, int W>
+__global__ void __launch_bounds__(256)
+k_bgivens2_w(int P, int64_t M, int64_t N, const int32_t* __restrict__ row_start, const T* __restrict__ vals,
+             const T* __restrict__ bvec, const double* __restrict__ d, const double* __restrict__ lam,
+             T* __restrict__ Rb, T* __restrict__ cb, double* __restrict__ binv, T* __restrict__ R16,
+             int* __restrict__ status) {
+  static_assert(W >= 1 && W <= 15, "band width");
+  constexpr int C = 8;    // rows per prefetch chunk (4 pairs)
+  constexpr int NP = C / 2;
+  constexpr int RHS = 15; // lane of the right-hand side (in each half)
+  const int lane32 = threadIdx.x & 31;
+  const int half = lane32 >> 4;
+  const int lane = lane32 & 15;
+  const int64_t prob = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 5;
+  if (prob >= P) return;
+  const T sl = (T)sqrt(lam[prob]);
+  const int32_t* rs = row_start + prob * M;
+  const T* V = vals + prob * M * W;
+  const T* bb = bvec + prob * M;
+  const double* dd = d + prob * N;
+  T* R = Rb + prob * N * W;
+  T* cc = cb + prob * N;
+  double* iv = binv + prob * N;
+  T* S16 = R16 ? R16 + prob * N * 16 : nullptr;
+  const int64_t smax = N - W;
+  const bool isA = half == 0;
+
+  T Rw[W + 1];  // A: register k = window row k (k < W);  B: register k = window row k - 1
+#pragma unroll
+  for (int k = 0; k <= W; ++k) Rw[k] = (isA && k < W && lane == 0) ? sl * (T)dd[k] : T(0);
+
+  auto load_x = [&](int64_t i) -> T {  // row i in this lane's half
+    if (i >= M) return T(0);
+    if (lane < W) return V[i * W + lane];
+    return lane == RHS ? bb[i] : T(0);
+  };
+  auto load_st = [&](int64_t i) -> int32_t { return i < M ? rs[i] : 0; };
+  auto load_dq = [&](int64_t s0) -> T {
+    const int64_t col = s0 + W + lane;
+    return (lane < 15 && col < N) ? sl * (T)dd[col] : T(0);
+  };
+
+  T cx[NP], nx[NP];
+  int32_t cst[C], nst[C];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) cx[p] = load_x(2 * p + half);
+#pragma unroll
+  for (int c = 0; c < C; ++c) cst[c] = load_st(c);
+  T dq = load_dq(0);
+  int64_t s = 0;
+  bool bad = false;
+
+  auto retire = [&]() {  // window row 0 (R row s) is final; A's lanes hold it
+    if (isA) {
+      if (lane < W) R[s * W + lane] = Rw[0];
+      if (lane == RHS) cc[s] = Rw[0];
+      if (lane == 0) iv[s] = 1.0 / (double)Rw[0];
+      if (S16) S16[s * 16 + lane] = (lane >= 1 && lane < W) ? Rw[0] : T(0);
+    }
+  };
+  auto clamp_start = [&](int64_t si) -> int64_t {
+    if (si < s || si > smax) {
+      bad = true;
+      si = si < s ? s : smax;
+    }
+    return si;
+  };
+  // rotation of the row held in x against register K (see the layout above)
+  auto rotate = [&](auto KK, T& x, T& xk) {
+    constexpr int k = decltype(KK)::value;
+    const T Rk = Rw[k];
+    const T a = bw_bcast<0>(Rk);
+    const T q = fma(xk, xk, a * a);
+    const bool refl = q >= BwTiny<T>::value;
+    const T inv = bw_rsqrt(q);
+    const T rn = fma(xk, x, a * Rk);
+    const T xn = fma(-xk, Rk, a * x);
+    Rw[k] = refl ? inv * rn : Rk;
+    const T xr = refl ? inv * xn : x;
+    xk = bw_bcast<1>(xr);
+    if constexpr (W <= 12) {
+      x = bw_dpp<0x101, 0x7, false>(xr, xr);
+    } else {
+      const T dn = bw_down(xr);
+      x = lane == RHS ? xr : (lane == RHS - 1 ? T(0) : dn);
+    }
+  };
+
+  for (int64_t base = 0; base < M; base += C) {
+    int64_t s_end = s;
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+      if (base + c < M) {
+        int64_t si = cst[c];
+        si = si < s_end ? s_end : (si > smax ? smax : si);
+        s_end = si;
+      }
+#pragma unroll
+    for (int p = 0; p < NP; ++p) nx[p] = load_x(base + C + 2 * p + half);
+#pragma unroll
+    for (int c = 0; c < C; ++c) nst[c] = load_st(base + C + c);
+    const T ndq = load_dq(s_end);
+    int jsh = 0;
+    auto shift_to = [&](int64_t si) {
+      while (s < si) {
+        retire();
+#pragma unroll
+        for (int k = 0; k + 1 < W; ++k) Rw[k] = Rw[k + 1];
+        T e;
+        if (jsh < 15) {
+          e = dq;
+        } else {
+          e = (isA && lane == 0) ? sl * (T)dd[s + W] : T(0);
+        }
+        Rw[W - 1] = (isA && lane == 0) ? e : T(0);
+        dq = bw_down(dq);
+        ++jsh;
+        ++s;
+      }
+    };
+    static_for<0, NP>([&](auto PP) {
+      constexpr int p = decltype(PP)::value;
+      constexpr int c = 2 * p;
+      if (base + c >= M) return;
+      shift_to(clamp_start(cst[c]));
+      const bool hasB = base + c + 1 < M;
+      const int64_t sb = hasB ? clamp_start(cst[c + 1]) : s;
+      T x = cx[p];
+      T xk = bw_bcast<0>(x);
+      if (hasB && sb == s) {
+        static_for<0, W + 1>([&](auto TT) {
+          constexpr int t = decltype(TT)::value;
+          if constexpr (t == 0) {
+            if (isA) rotate(std::integral_constant<int, 0>{}, x, xk);
+          } else if constexpr (t == W) {
+            if (!isA) rotate(std::integral_constant<int, W>{}, x, xk);
+          } else {
+            rotate(std::integral_constant<int, t>{}, x, xk);
+          }
+          if constexpr (t >= 1) bw_swap16(Rw[t], Rw[t - 1]);      // B's row t-1 back to A
+          if constexpr (t + 1 <= W && t < W) bw_swap16(Rw[t + 1], Rw[t]);  // A's row t on to B
+        });
+      } else {
+        if (isA) static_for<0, W>([&](auto KK) { rotate(KK, x, xk); });
+        if (hasB) {
+          shift_to(sb);
+          T y = bw_from_odd(cx[p]);  // B's row, into A's lanes
+          T yk = bw_bcast<0>(y);
+          if (isA) static_for<0, W>([&](auto KK) { rotate(KK, y, yk); });
+        }
+      }
+    });
+#pragma unroll
+    for (int p = 0; p < NP; ++p) cx[p] = nx[p];
+#pragma unroll
+    for (int c = 0; c < C; ++c) cst[c] = nst[c];
+    dq = ndq;
+  }
+  while (s < smax) {
+    retire();
+#pragma unroll
+    for (int k = 0; k + 1 < W; ++k) Rw[k] = Rw[k + 1];
+    Rw[W - 1] = (isA && lane == 0) ? sl * (T)dd[s + W] : T(0);
+    ++s;
+  }
+  if (isA) {
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      if (lane < W) R[(s + k) * W + lane] = Rw[k];
+      if (lane == RHS) cc[s + k] = Rw[k];
+      if (lane == 0) iv[s + k] = 1.0 / (double)Rw[k];
+      if (S16) S16[(s + k) * 16 + lane] = (lane >= 1 && lane < W) ? Rw[k] : T(0);
+    }
+  }
+  if (bad && isA && lane == 0) set_status(status, ST_BADINPUT);
+}
+
 // Banded triangular sweep over every problem, one unknown per step.
 //   BWD:  x = R^{-1} rhs, steps t = 0 .. N-1 on rows j = N-1-t;
 //         x_j = (rhs_j - sum_{l=1}^{W-1} R[j][j+l] x_{j+l}) / R[j][j]
@@ -420,11 +636,17 @@ hipError_t launch_bgivens_w(int P, int64_t M, int64_t N, int w, const int32_t* r
   hipError_t e = hipErrorInvalidValue;
   bw_host_for<1, 16>([&](auto WW) {
     constexpr int W = decltype(WW)::value;
-    if (w == W) {
+    if (w != W) return;
+    if (P < 4096) {
+      // fewer than four problems per SIMD: two per wave, two rows in flight
+      const dim3 grid2((unsigned)(((int64_t)P * 32 + 255) / 256));
+      hipLaunchKernelGGL((k_bgivens2_w<T, W>), grid2, blk, 0, st, P, M, N, row_start, vals, b, d, lam, Rb, cb, binv,
+                         R16, status);
+    } else {
       hipLaunchKernelGGL((k_bgivens_w<T, W>), grid, blk, 0, st, P, M, N, row_start, vals, b, d, lam, Rb, cb, binv,
                          R16, status);
-      e = hipGetLastError();
     }
+    e = hipGetLastError();
   });
   return e;
 }

@@ -82,6 +82,37 @@ def test_banded_full_size_sampled():
         assert rel_err(p1[k], p_ref) <= 1e-10
 
 
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("rows_per_col,w", [(1, 5), (3, 12), (1, 15), (3, 13)])
+def test_banded_row_patterns(rows_per_col, w, dtype):
+    """Rows with distinct starts (one at a time through the window) and runs of three equal
+    starts (pairs and single rows mixed), four problems in one handle."""
+    log(f"banded patterns rows_per_col={rows_per_col} w={w} {np.dtype(dtype).name}")
+    insts = [gen.make_banded(1300 + 10 * k + w, N=90, w=w, rows_per_col=rows_per_col, lam=1e-2, dtype=dtype)
+             for k in range(4)]
+    p0, st, _, _ = _banded_solve(insts)
+    assert st[0] == 0
+    p2, st, _, _ = _banded_solve(insts, sweeps=2)
+    tol = 1e-12 if dtype == np.float64 else 1e-5
+    for k, inst in enumerate(insts):
+        p_ref, _, _ = banded.reference_solution(inst)
+        assert rel_err(p0[k], p_ref) <= tol
+        assert rel_err(p2[k], p_ref) <= 1e-10
+
+
+def test_banded_many_small_problems():
+    """4,100 problems (four per wave in the factorisation): sampled problems vs oracle."""
+    log("banded P=4100 N=40 w=7")
+    insts = [gen.make_banded(2000 + k, N=40, w=7, lam=1e-2, dtype=np.float32) for k in range(4100)]
+    p0, st, solver, _ = _banded_solve(insts)
+    assert st[0] == 0
+    p1 = solver.solve(sweeps=1).cpu().numpy().reshape(4100, -1)
+    for k in (0, 1, 2049, 4099):
+        p_ref, _, _ = banded.reference_solution(insts[k])
+        assert rel_err(p0[k], p_ref) <= 1e-5
+        assert rel_err(p1[k], p_ref) <= 1e-10
+
+
 def test_banded_bad_row_start_is_reported():
     log("banded bad row_start")
     inst = gen.make_banded(5, N=40, w=4, dtype=np.float32)
