@@ -280,12 +280,13 @@ __device__ __forceinline__ T bw_from_odd(T x) {
 
 // The same Givens QR with two problems per wave and two rows in flight per problem: a problem
 // owns 32 lanes, rows taken in pairs of equal start go through the window together, the first
-// (lanes 0-15, "A") one rotation ahead of the second (lanes 16-31, "B").  At step t, A rotates
-// against window row t and B against window row t - 1 in the same instructions: register k
-// holds window row k in A's lanes and window row k - 1 in B's lanes.  After each step
-// v_permlane16_swap hands the row A just rotated to B (register t of A -> register t + 1 of
-// B) and the row B just rotated back to A (register t of B -> register t - 1 of A), so every
-// row is current in A's lanes once a pair is done.  Rows whose starts differ go one at a time
+// (lanes 0-15, "A") two rotations ahead of the second (lanes 16-31, "B").  At step t, A
+// rotates against window row t and B against window row t - 2 in the same instructions:
+// register k holds window row k in A's lanes and window row k - 2 in B's lanes.  After each
+// step v_permlane16_swap hands the row A just rotated to B (register t of A -> register t + 2
+// of B) and the row B just rotated back to A (register t of B -> register t - 2 of A), so
+// every row is current in A's lanes once a pair is done.  The two-step lag keeps the hand-over
+// off the dependency chain of the rotations.  Rows whose starts differ go one at a time
 // in A's lanes.  With every SIMD holding a wave, this takes about half the time of four
 // problems per wave when the problems number fewer than four per SIMD.
 template <typename T, int W>
@@ -315,9 +316,9 @@ k_bgivens2_w(int P, int64_t M, int64_t N, const int32_t* __restrict__ row_start,
   const int64_t smax = N - W;
   const bool isA = half == 0;
 
-  T Rw[W + 1];  // A: register k = window row k (k < W);  B: register k = window row k - 1
+  T Rw[W + 2];  // A: register k = window row k (k < W);  B: register k = window row k - 2
 #pragma unroll
-  for (int k = 0; k <= W; ++k) Rw[k] = (isA && k < W && lane == 0) ? sl * (T)dd[k] : T(0);
+  for (int k = 0; k < W + 2; ++k) Rw[k] = (isA && k < W && lane == 0) ? sl * (T)dd[k] : T(0);
 
   auto load_x = [&](int64_t i) -> T {  // row i in this lane's half
     if (i >= M) return T(0);
@@ -418,17 +419,18 @@ k_bgivens2_w(int P, int64_t M, int64_t N, const int32_t* __restrict__ row_start,
       T x = cx[p];
       T xk = bw_bcast<0>(x);
       if (hasB && sb == s) {
-        static_for<0, W + 1>([&](auto TT) {
+        static_for<0, W + 2>([&](auto TT) {
           constexpr int t = decltype(TT)::value;
-          if constexpr (t == 0) {
-            if (isA) rotate(std::integral_constant<int, 0>{}, x, xk);
-          } else if constexpr (t == W) {
-            if (!isA) rotate(std::integral_constant<int, W>{}, x, xk);
-          } else {
+          constexpr bool runA = t < W, runB = t >= 2;
+          if constexpr (runA && runB) {
             rotate(std::integral_constant<int, t>{}, x, xk);
+          } else if constexpr (runA) {
+            if (isA) rotate(std::integral_constant<int, t>{}, x, xk);
+          } else if constexpr (runB) {
+            if (!isA) rotate(std::integral_constant<int, t>{}, x, xk);
           }
-          if constexpr (t >= 1) bw_swap16(Rw[t], Rw[t - 1]);      // B's row t-1 back to A
-          if constexpr (t + 1 <= W && t < W) bw_swap16(Rw[t + 1], Rw[t]);  // A's row t on to B
+          if constexpr (t >= 2) bw_swap16(Rw[t], Rw[t - 2]);  // B's row t-2 back to A
+          if constexpr (t < W) bw_swap16(Rw[t + 2], Rw[t]);   // A's row t on to B
         });
       } else {
         if (isA) static_for<0, W>([&](auto KK) { rotate(KK, x, xk); });
