@@ -27,17 +27,20 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP32_VECTOR_TFLOPS = 157.3
 PEAK_FP64_VECTOR_TFLOPS = 78.6
 
-# HBM bytes per launch of a phase's kernel, from two rocprofv3 PMC runs of this script
+# HBM bytes per launch of a phase's kernels, from two rocprofv3 PMC runs of this script
 # (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, factors read off a 256 MiB device copy; the runs
-# and figures are in profiles/blockangular_scale_pmc_traffic.md).  A figure holds only for the
-# workload it was taken on and while the kernel's sources hash to the recorded digest.
+# and figures are in profiles/blockangular_scale_pmc_traffic.md).  The dense-part phase is the
+# leaf launch plus the merge-tree launch.  A figure holds only for the workload it was taken on
+# and while the kernels' sources hash to the recorded digest.
 _TSQR_SOURCES = ["paper_1802_03773_amd/csrc/tsqr_mfma.hpp", "paper_1802_03773_amd/csrc/tsqr_mfma.hip",
-                 "paper_1802_03773_amd/csrc/tsqr_mfma_ncb6.hip", "paper_1802_03773_amd/csrc/qrk_device.hpp"]
-_TSQR_DIGEST = "15269bfcacf69cdc72b50c88cb2d11cabc9d96efb3f64e53ab9e76c4906001fc"
+                 "paper_1802_03773_amd/csrc/tsqr_mfma_ncb6.hip", "paper_1802_03773_amd/csrc/qrk_device.hpp",
+                 "paper_1802_03773_amd/csrc/tsqr_tree.hpp", "paper_1802_03773_amd/csrc/tsqr_tree.hip"]
+_TSQR_DIGEST = "3798e3bc9889389743fff56c25236503761982cbe027677f69bb03693ec358e2"
+_TREE_KIB = 22487.6 * 2.000 + 21686.1
 MEASURED_TRAFFIC = {
-    ("dense_leaves", "plain"): {"bytes": (131342.3 * 2.000 + 43062.3) * 1024.0, "lam": 1e-2,
+    ("dense_leaves", "plain"): {"bytes": (108968.8 * 2.000 + 21504.0 + _TREE_KIB) * 1024.0, "lam": 1e-2,
                                 "sources": _TSQR_SOURCES, "sha256": _TSQR_DIGEST},
-    ("dense_leaves", "bf16x3"): {"bytes": (131284.2 * 2.000 + 43062.3) * 1024.0, "lam": 1e-2,
+    ("dense_leaves", "bf16x3"): {"bytes": (109115.0 * 2.000 + 21504.0 + _TREE_KIB) * 1024.0, "lam": 1e-2,
                                  "sources": _TSQR_SOURCES, "sha256": _TSQR_DIGEST},
 }
 

@@ -13,10 +13,10 @@
 // on later ones, so the root trails the leaves by about (tree depth + column blocks) panel
 // times rather than (tree depth) whole merges.
 //
-// Memory ordering.  A node's published blocks are written and read with device-scope relaxed
-// atomic accesses (through the L2 to memory and back); the producer waits for its block
-// stores to complete before storing the flag, the consumer polls the flag with device-scope
-// loads and only then issues the block's loads.
+// Memory ordering.  A node's published blocks are written and read with device-coherent
+// accesses (through the L2 to memory and back); the producer waits for its block stores to
+// complete before storing the flag, the consumer polls the flag with device-scope loads and
+// only then issues the block's loads.
 //
 // Forward progress.  Nodes are numbered level by level from the leaves up, and the children
 // of a node are leaves or nodes with smaller numbers.  Wave w of the launch runs node w and
@@ -166,20 +166,20 @@ __device__ __forceinline__ void tree_panel_apply(const float* __restrict__ keep,
     for (int rb = 0; rb < RBN; ++rb) X[rb] = mfma4(Wt[rb][v], Zs[v], X[rb]);
 }
 
-// Published node outputs move through device-scope (relaxed atomic) accesses, which write
-// through and read past the per-XCD L2: a consumer never sees a stale L2 copy, and a
-// producer's release is just the wait for its own stores to complete before the flag store —
-// no L2-wide write-back or invalidation, which at one per column block and node (on every
-// XCD) had cost more than the arithmetic.
+// Published node outputs move through device-coherent accesses (the sc1 cache policy, which is
+// what a relaxed device-scope atomic access compiles to): stores write through and loads read
+// past the per-XCD L2, so a consumer never sees a stale L2 copy, and a producer's release is
+// just the wait for its own stores to complete before the flag store -- no L2-wide write-back
+// or invalidation, which at one per column block and node (on every XCD) had cost more than
+// the arithmetic.  Each lane moves its four values of a 16x16 block as one 16-byte access.
+constexpr int kCoherent = 16;  // buffer cache-policy bits: sc1
 __device__ __forceinline__ void tree_store_block(float* dst, const f4& v, int lane) {
-#pragma unroll
-  for (int k = 0; k < 4; ++k) __hip_atomic_store(dst + lane * 4 + k, v[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const auto rs = __builtin_amdgcn_make_buffer_rsrc(dst, 0, 1024, 0x00020000);
+  __builtin_amdgcn_raw_buffer_store_b128(v, rs, lane * 16, 0, kCoherent);
 }
 __device__ __forceinline__ f4 tree_load_block(const float* src, int lane) {
-  f4 v;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) v[k] = __hip_atomic_load(src + lane * 4 + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return v;
+  const auto rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(src), 0, 1024, 0x00020000);
+  return __builtin_amdgcn_raw_buffer_load_b128(rs, lane * 16, 0, kCoherent);
 }
 
 // Wait (bounded) until *flag is set; false on timeout.  Lane 0 polls with relaxed
