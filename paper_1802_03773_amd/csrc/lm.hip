@@ -13,6 +13,8 @@
 //   accept         : rho = (F - F_new) / pred; rho > 0: x += p, lam *= max(1/3, 1 - (2 rho - 1)^3),
 //                    nu = 2; else lam *= nu, nu *= 2
 // Sums are deterministic (fixed-order per wave, per workgroup and per problem).
+#include <type_traits>
+
 #include "qrk_batch.hpp"
 #include "qrk_device.hpp"
 #include "qrk_lm.hpp"
@@ -244,32 +246,155 @@ __global__ void k_lmbd_fsum(int nblk, const double* __restrict__ fpart, double* 
   Fout[prob] = 0.5 * s;
 }
 
+// The row kernel with the band width W (<= 15) at compile time: every load of a row is in
+// flight at once.  Same arithmetic, in the same order, as k_lmbd_rows.
+template <typename T, bool JAC, int W>
+__global__ void __launch_bounds__(256)
+k_lmbd_rows_w(int64_t M, int64_t N, const int32_t* __restrict__ row_start, const T* __restrict__ vals0,
+              const T* __restrict__ y, double c, const double* __restrict__ x, const double* __restrict__ pstep,
+              T* __restrict__ vals, T* __restrict__ b, double* __restrict__ f, double* __restrict__ fpart) {
+  __shared__ double red[256];
+  const int64_t prob = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double fi = 0.0;
+  if (i < M) {
+    const int64_t row = prob * M + i;
+    const int64_t s = lm_row_start(row_start + prob * M, i, N, W);
+    const double* xp = x + prob * N + s;
+    const double* pp = JAC ? nullptr : pstep + prob * N + s;
+    double u[W];
+    T v0[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      u[k] = xp[k] + (JAC ? 0.0 : pp[k]);
+      v0[k] = vals0[row * W + k];
+    }
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      fi += (double)v0[k] * lm_phi(u[k], c);
+      if (JAC) vals[row * W + k] = (T)((double)v0[k] * lm_dphi(u[k], c));
+    }
+    fi -= (double)y[row];
+    if (JAC) {
+      b[row] = (T)(-fi);
+      f[row] = fi;
+    }
+  }
+  red[threadIdx.x] = fi * fi;
+  __syncthreads();
+  for (int h = 128; h >= 1; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) fpart[prob * gridDim.x + blockIdx.x] = red[0];
+}
+
+// Column norms and J^T f with the first-row table fr [P][N+1] (first row whose start is >= c):
+// a workgroup covers 256 consecutive columns of one problem and copies its rows' values, starts
+// and residuals into LDS with coalesced loads; each column then sums its rows in row order
+// (the order of k_lmbd_cols).  Ranges beyond the LDS capacity read their rows from memory.
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_lmbd_cols(int64_t M, int64_t N, int w, const int32_t* __restrict__ row_start, const T* __restrict__ vals,
-            const double* __restrict__ f, double* __restrict__ d, double* __restrict__ gJ) {
+k_lmbd_cols_t(int64_t M, int64_t N, int w, const int32_t* __restrict__ row_start, const int32_t* __restrict__ fr,
+              const T* __restrict__ vals, const double* __restrict__ f, double* __restrict__ d,
+              double* __restrict__ gJ) {
+  constexpr int CAP = 1024;
+  constexpr int VCAP = 40960 / (int)sizeof(T);
+  __shared__ int32_t s_st[CAP];
+  __shared__ double s_f[CAP];
+  __shared__ T s_v[VCAP];
   const int64_t prob = blockIdx.y;
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (j >= N) return;
+  const int64_t c0 = (int64_t)blockIdx.x * 256;
+  const int64_t j = c0 + threadIdx.x;
   const int32_t* rs = row_start + prob * M;
-  // rows with j - w + 1 <= s_i <= j
-  int64_t lo = 0, hi = M;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) / 2;
-    if (lm_row_start(rs, mid, N, w) < j - w + 1) lo = mid + 1; else hi = mid;
+  const int32_t* fp = fr + prob * (N + 1);
+  const double* fv = f + prob * M;
+  const T* V = vals + prob * M * w;
+  auto row_at = [&](int64_t cc) -> int64_t {
+    cc = cc < 0 ? 0 : (cc > N ? N : cc);
+    const int64_t r = fp[cc];
+    return r < 0 ? 0 : (r > M ? M : r);
+  };
+  const int64_t lo = row_at(c0 - w + 1);
+  int64_t hi = row_at(c0 + 256);
+  hi = hi < lo ? lo : hi;
+  const int64_t n = hi - lo;
+  const bool staged = n <= CAP && n * w <= VCAP;
+  if (staged) {
+    const int64_t nv = n * w;
+    const T* Vlo = V + lo * w;
+    for (int64_t i0 = 0; i0 < nv; i0 += 256 * 8) {
+      T buf[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t i = i0 + u * 256 + threadIdx.x;
+        buf[u] = i < nv ? Vlo[i] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t i = i0 + u * 256 + threadIdx.x;
+        if (i < nv) s_v[i] = buf[u];
+      }
+    }
+    for (int64_t i0 = 0; i0 < n; i0 += 256 * 4) {
+      int32_t sb[4];
+      double fb[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t i = i0 + u * 256 + threadIdx.x;
+        sb[u] = i < n ? (int32_t)lm_row_start(rs, lo + i, N, w) : 0;
+        fb[u] = i < n ? fv[lo + i] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t i = i0 + u * 256 + threadIdx.x;
+        if (i < n) {
+          s_st[i] = sb[u];
+          s_f[i] = fb[u];
+        }
+      }
+    }
+    __syncthreads();
   }
-  int64_t e = lo, eh = M;
-  while (e < eh) {
-    const int64_t mid = (e + eh) / 2;
-    if (lm_row_start(rs, mid, N, w) <= j) e = mid + 1; else eh = mid;
-  }
+  if (j >= N) return;
+  int64_t a = row_at(j - w + 1), e = row_at(j + 1);
   double sq = 0.0, gf = 0.0;
-  for (int64_t i = lo; i < e; ++i) {
-    const int64_t k = j - lm_row_start(rs, i, N, w);
-    if (k < 0 || k >= w) continue;
-    const double v = (double)vals[(prob * M + i) * w + k];
-    sq += v * v;
-    gf += v * f[prob * M + i];
+  if (staged) {
+    a = a < lo ? lo : a;
+    e = e > hi ? hi : e;
+    const int i1 = (int)(e - lo);
+    for (int i0 = (int)(a - lo); i0 < i1; i0 += 8) {
+      int kk[8];
+      double ff[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = i0 + u < i1 ? i0 + u : i1 - 1;
+        kk[u] = (int)(j - s_st[i]);
+        ff[u] = s_f[i];
+      }
+      T vv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = i0 + u < i1 ? i0 + u : i1 - 1;
+        const int k = kk[u] < 0 ? 0 : (kk[u] >= w ? w - 1 : kk[u]);
+        vv[u] = s_v[i * w + k];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (i0 + u < i1 && kk[u] >= 0 && kk[u] < w) {
+          const double v = (double)vv[u];
+          sq += v * v;
+          gf += v * ff[u];
+        }
+    }
+  } else {
+    for (int64_t i = a; i < e; ++i) {
+      const int64_t k = j - lm_row_start(rs, i, N, w);
+      if (k < 0 || k >= w) continue;
+      const double v = (double)V[i * w + k];
+      sq += v * v;
+      gf += v * fv[i];
+    }
   }
   d[prob * N + j] = sq > 0.0 ? sqrt(sq) : 1.0;
   gJ[prob * N + j] = gf;
@@ -391,26 +516,46 @@ hipError_t launch_lm_init(int P, double* nu, int* iter, hipStream_t st) {
 }
 
 
+template <int A, int B, typename F>
+inline void lm_host_for(F&& fn) {
+  if constexpr (A < B) {
+    fn(std::integral_constant<int, A>{});
+    lm_host_for<A + 1, B>(fn);
+  }
+}
+
 template <typename T>
-hipError_t launch_lmbd_eval(int P, int64_t M, int64_t N, int w, bool jac, const int32_t* row_start, const T* vals0,
-                            const T* y, double c, const double* x, const double* p, T* vals, T* b, double* f,
-                            double* d, double* gJ, double* fpart, double* Fout, hipStream_t st) {
+hipError_t launch_lmbd_eval(int P, int64_t M, int64_t N, int w, bool jac, const int32_t* row_start, const int32_t* fr,
+                            const T* vals0, const T* y, double c, const double* x, const double* p, T* vals, T* b,
+                            double* f, double* d, double* gJ, double* fpart, double* Fout, hipStream_t st) {
   const int nblk = (int)((M + 255) / 256);
   if (P < 1 || nblk < 1) return hipErrorInvalidValue;
   dim3 grd(nblk, P);
-  if (jac)
+  if (w <= 15) {
+    lm_host_for<1, 16>([&](auto WW) {
+      constexpr int W = decltype(WW)::value;
+      if (w != W) return;
+      if (jac)
+        hipLaunchKernelGGL((k_lmbd_rows_w<T, true, W>), grd, dim3(256), 0, st, M, N, row_start, vals0, y, c, x, p,
+                           vals, b, f, fpart);
+      else
+        hipLaunchKernelGGL((k_lmbd_rows_w<T, false, W>), grd, dim3(256), 0, st, M, N, row_start, vals0, y, c, x, p,
+                           vals, b, f, fpart);
+    });
+  } else if (jac) {
     hipLaunchKernelGGL((k_lmbd_rows<T, true>), grd, dim3(256), 0, st, M, N, w, row_start, vals0, y, c, x, p, vals, b,
                        f, fpart);
-  else
+  } else {
     hipLaunchKernelGGL((k_lmbd_rows<T, false>), grd, dim3(256), 0, st, M, N, w, row_start, vals0, y, c, x, p, vals,
                        b, f, fpart);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_lmbd_fsum, dim3(P), dim3(64), 0, st, nblk, fpart, Fout);
   e = hipGetLastError();
   if (e != hipSuccess || !jac) return e;
-  hipLaunchKernelGGL((k_lmbd_cols<T>), dim3((unsigned)((N + 255) / 256), P), dim3(256), 0, st, M, N, w, row_start,
-                     vals, f, d, gJ);
+  hipLaunchKernelGGL((k_lmbd_cols_t<T>), dim3((unsigned)((N + 255) / 256), P), dim3(256), 0, st, M, N, w, row_start,
+                     fr, vals, f, d, gJ);
   return hipGetLastError();
 }
 
@@ -418,7 +563,7 @@ hipError_t launch_lmbd_eval(int P, int64_t M, int64_t N, int w, bool jac, const 
   template hipError_t launch_lmba_eval<T>(const BatchView&, bool, const T*, const T*, const T*, double,    \
                                           const double*, const double*, T*, T*, T*, double*, double*,      \
                                           double*, double*, double*, hipStream_t);                         \
-  template hipError_t launch_lmbd_eval<T>(int, int64_t, int64_t, int, bool, const int32_t*, const T*, const T*,  \
+  template hipError_t launch_lmbd_eval<T>(int, int64_t, int64_t, int, bool, const int32_t*, const int32_t*, const T*, const T*,  \
                                           double, const double*, const double*, T*, T*, double*, double*, double*, \
                                           double*, double*, hipStream_t);
 QRK_INST(float)

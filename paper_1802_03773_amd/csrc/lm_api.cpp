@@ -7,6 +7,7 @@
 #include <new>
 #include <vector>
 
+#include "qrk_banded.hpp"
 #include "qrk_device.hpp"
 #include "qrk_host.hpp"
 #include "qrk_launch.hpp"
@@ -107,8 +108,9 @@ qrk_status lm_iteration_banded(qrk_lm lm, hipStream_t st) {
   T* b = static_cast<T*>(lm->b);
   const T* vals0 = static_cast<const T*>(lm->A0);
   const T* y = static_cast<const T*>(lm->y);
-  if (launch_lmbd_eval<T>(h->P, h->M, h->N, h->w, true, lm->row_start, vals0, y, lm->c, lm->x, nullptr, vals, b,
-                          lm->f, lm->d, lm->gJ, lm->fpart, lm->F, st) != hipSuccess)
+  if (launch_band_first_row(h->P, h->M, h->N, h->w, lm->row_start, h->bandfr, st) != hipSuccess ||
+      launch_lmbd_eval<T>(h->P, h->M, h->N, h->w, true, lm->row_start, h->bandfr, vals0, y, lm->c, lm->x, nullptr,
+                          vals, b, lm->f, lm->d, lm->gJ, lm->fpart, lm->F, st) != hipSuccess)
     return QRK_EHIP;
   h->row_start = lm->row_start;
   h->A = vals;
@@ -122,8 +124,8 @@ qrk_status lm_iteration_banded(qrk_lm lm, hipStream_t st) {
   if (launch_lm_control(h->P, lm->noff, lm->p, lm->d, lm->gJ, lm->lam, lm->nu, lm->F, lm->Fnew, lm->pred, lm->acc,
                         lm->iter, lm->log, lm->max_log, lm->x, st, 0) != hipSuccess)
     return QRK_EHIP;
-  if (launch_lmbd_eval<T>(h->P, h->M, h->N, h->w, false, lm->row_start, vals0, y, lm->c, lm->x, lm->p, vals, b,
-                          lm->f, lm->d, lm->gJ, lm->fpart, lm->Fnew, st) != hipSuccess)
+  if (launch_lmbd_eval<T>(h->P, h->M, h->N, h->w, false, lm->row_start, h->bandfr, vals0, y, lm->c, lm->x, lm->p,
+                          vals, b, lm->f, lm->d, lm->gJ, lm->fpart, lm->Fnew, st) != hipSuccess)
     return QRK_EHIP;
   if (launch_lm_control(h->P, lm->noff, lm->p, lm->d, lm->gJ, lm->lam, lm->nu, lm->F, lm->Fnew, lm->pred, lm->acc,
                         lm->iter, lm->log, lm->max_log, lm->x, st, 1) != hipSuccess)

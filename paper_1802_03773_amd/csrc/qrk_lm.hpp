@@ -21,9 +21,9 @@ hipError_t launch_lmba_eval(const BatchView& bv, bool jac, const T* A0, const T*
 // true at x: J(x) into vals, b = -f, f (float64), d and J^T f, F into Fout; jac = false at
 // x + p: F_new into Fout.  fpart holds P * ceil(M / 256) doubles.
 template <typename T>
-hipError_t launch_lmbd_eval(int P, int64_t M, int64_t N, int w, bool jac, const int32_t* row_start, const T* vals0,
-                            const T* y, double c, const double* x, const double* p, T* vals, T* b, double* f,
-                            double* d, double* gJ, double* fpart, double* Fout, hipStream_t st);
+hipError_t launch_lmbd_eval(int P, int64_t M, int64_t N, int w, bool jac, const int32_t* row_start, const int32_t* fr,
+                            const T* vals0, const T* y, double c, const double* x, const double* p, T* vals, T* b,
+                            double* f, double* d, double* gJ, double* fpart, double* Fout, hipStream_t st);
 
 // stage 0: pred = p^T (lam D^2 p - J^T f) / 2 per problem.  stage 1: gain ratio, damping
 // update, accept flags, log row of this iteration, iteration counter, x += p where accepted.
