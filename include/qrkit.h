@@ -107,6 +107,24 @@ qrk_status qrk_factor_blockangular(qrk_handle h, const void* A, const void* B, c
                                    const double* d, double lambda, void* stream);
 
 /* ------------------------------------------------------------------------------
+ * qrk_factor_lambda  (single-problem block-angular handles)
+ *   Moré's two-stage damping (Section 5.2, Eq. LMTwoStep): with J = Q R factored once by
+ *   qrk_factor_blockangular(h, ..., lambda = 0, ...), each call factors [R; sqrt(lambda) D]
+ *   instead of [J; sqrt(lambda) D].  The damping rows of each block are permuted next to its
+ *   R_i, so the second QR is again structured: blocks [R_i; sqrt(lambda) D_i] with coupled
+ *   rows [S_i | c_i; 0], and a dense part over the blocks' reduced rows, the rows of
+ *   R_B | c_B and sqrt(lambda) D_B.  The result replaces the handle's factor (the factor of J
+ *   is kept aside, so any number of calls may follow one factorisation of J); qrk_solve then
+ *   solves the damped problem for this lambda, its refinement using the original J, b, d
+ *   given to qrk_factor_blockangular (still borrowed: they must stay valid and unchanged).
+ *   lambda > 0, finite.  QRK_EINVAL for a batched or banded handle, before any factor, or when
+ *   the factor of J saved by an earlier call is gone (a new qrk_factor_blockangular call) and
+ *   the current factor's lambda is not 0.  Allocates the kept factor and the second-stage
+ *   workspace on its first call.  Not capturable on its first call after a factor of J.
+ * ------------------------------------------------------------------------------ */
+qrk_status qrk_factor_lambda(qrk_handle h, double lambda, void* stream);
+
+/* ------------------------------------------------------------------------------
  * qrk_create_blockangular_batched / qrk_factor_blockangular_batched
  *   P independent block-angular problems with the same block width n, factored and solved
  *   together: every phase of qrk_factor_blockangular / qrk_solve runs over all problems in

@@ -81,6 +81,38 @@ def factor_blockangular(inst) -> BlockAngularFactor:
                               float(abs(Rr[nB, nB])))
 
 
+def factor_two_stage(inst, lam: float) -> BlockAngularFactor:
+    """Moré's two-stage factor (Section 5.2, Eq. LMTwoStep): J = Q R first (the structured
+    factor above with lambda = 0), then [R; sqrt(lam) D] = Q' R'.  The damping rows of each
+    block go next to its R_i, so the second QR is the same horizontal-concatenation step on R's
+    rows: block i is [R_i; sqrt(lam) D_i] with coupled rows [S_i | c_i; 0 | 0], and the dense
+    part is the QR of the blocks' reduced rows stacked with the rows of [R_B | c_B], the
+    residual row [0 | resid] and [sqrt(lam) D_B | 0]."""
+    K, n, nB = inst.K, inst.n, inst.nB
+    base = factor_blockangular(dataclasses.replace(inst, lam=0.0))
+    sq = np.sqrt(float(lam))
+    d = np.asarray(inst.d, np.float64)
+    Di = np.zeros((K, n, n))
+    Di[:, np.arange(n), np.arange(n)] = sq * d[:K * n].reshape(K, n)
+    Aaug = np.concatenate([base.R_blk, Di], axis=1)                                   # [K, 2n, n]
+    C = np.concatenate([base.S, base.c_blk[:, :, None]], axis=2)                      # [K, n, nB+1]
+    Caug = np.concatenate([C, np.zeros((K, n, nB + 1))], axis=1)                      # [K, 2n, nB+1]
+    Q, Rr = np.linalg.qr(Aaug, mode="complete")
+    QtC = np.matmul(np.swapaxes(Q, 1, 2), Caug)
+    R_blk, S, c_blk = Rr[:, :n, :], QtC[:, :n, :nB], QtC[:, :n, nB]
+    reduced = QtC[:, n:, :].reshape(-1, nB + 1)
+    RBc = np.zeros((nB + 1, nB + 1))
+    RBc[:nB, :nB] = base.R_B
+    RBc[:nB, nB] = base.c_B
+    RBc[nB, nB] = base.resid
+    dB = np.zeros((nB, nB + 1))
+    dB[np.arange(nB), np.arange(nB)] = sq * d[K * n:]
+    stack = np.concatenate([reduced, RBc, dB], axis=0)
+    R2 = np.linalg.qr(stack, mode="r")
+    return BlockAngularFactor(R_blk.copy(), S.copy(), c_blk.copy(), R2[:nB, :nB].copy(), R2[:nB, nB].copy(),
+                              float(abs(R2[nB, nB])))
+
+
 def _backsub_batched(R: np.ndarray, c: np.ndarray) -> np.ndarray:
     """Solve R_k x_k = c_k for a stack of small upper-triangular R_k."""
     K, n, _ = R.shape

@@ -99,6 +99,14 @@ struct qrk_handle_s {
   double* bandinv = nullptr;  // banded: reciprocal pivots 1 / R[j][j], [P][N]
   int32_t* bandfr = nullptr;  // banded: first row with start >= c, [P][N+1]
   void* bandR16 = nullptr;    // banded: sweep copy of the band, [P][N][16] (null if not kept)
+  // two-stage damping (qrk_factor_lambda): the factor of J alone kept aside, c of that factor
+  // as a contiguous vector, and the handle of the second-stage problem
+  bool lam_base_saved = false;
+  void* Rblk0 = nullptr;
+  void* Sc0 = nullptr;
+  void* RB0 = nullptr;
+  void* c0 = nullptr;
+  qrk_handle_s* lam_stage = nullptr;
   double* rbuf = nullptr;     // banded: residual / J u, [P][M] each
   double* jubuf = nullptr;
   double* gbuf = nullptr;     // banded: [P][N]

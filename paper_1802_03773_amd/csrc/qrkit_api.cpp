@@ -171,6 +171,11 @@ void prof_free(qrk_handle h) {
 }
 
 void free_all(qrk_handle h) {
+  if (h->lam_stage) {
+    free_all(h->lam_stage);
+    delete h->lam_stage;
+    h->lam_stage = nullptr;
+  }
   prof_free(h);
   for (void* ptr : h->allocs) (void)hipFree(ptr);
   h->allocs.clear();
@@ -622,7 +627,84 @@ qrk_status qrk_factor_blockangular(qrk_handle h, const void* A, const void* B, c
   h->lam = lambda;
   h->lam_ptr = h->lam_d;
   h->factored = true;
+  h->lam_base_saved = false;
   return h->dtype == QRK_F32 ? factor_ba<float>(h, S(stream), &lambda) : factor_ba<double>(h, S(stream), &lambda);
+}
+
+// Moré's two-stage damping (Section 5.2, Eq. LMTwoStep): J = Q R once, then per damping value
+// the QR of [R; sqrt(lambda) D].  With the damping rows of each block permuted next to its R_i,
+// that second QR is again the structured factorisation of Sections 4.1 and 4.2, now of a
+// problem whose blocks are the n rows of R_i (coupled rows S_i | c_i) and whose dense part also
+// takes the rows of R_B | c_B; it runs on an internal handle of that shape.
+qrk_status qrk_factor_lambda(qrk_handle h, double lambda, void* stream) {
+  if (!h || h->kind != KIND_BLOCKANGULAR || h->P != 1 || !h->factored) return QRK_EINVAL;
+  if (!(lambda > 0.0) || !std::isfinite(lambda)) return QRK_EINVAL;
+  hipStream_t st = S(stream);
+  const size_t es = h->dtype == QRK_F32 ? 4 : 8;
+  const int n = h->n;
+  const int L = h->nB + 1;
+  const int64_t Kn = h->K * n;
+  qrk_status s;
+  if (!h->lam_base_saved) {
+    if (h->lam != 0.0) return QRK_EINVAL;  // the current factor must be that of J alone
+    if (!h->lam_stage) {
+      if ((s = dalloc(h, &h->Rblk0, es * (size_t)Kn * n)) != QRK_OK ||
+          (s = dalloc(h, &h->Sc0, es * (size_t)Kn * L)) != QRK_OK ||
+          (s = dalloc(h, &h->RB0, es * (size_t)L * L)) != QRK_OK ||
+          (s = dalloc(h, &h->c0, es * (size_t)Kn)) != QRK_OK)
+        return s;
+      // second-stage problem: K blocks of n rows (R_i), coupled rows of stride L (S_i | c_i)
+      std::vector<int64_t> ro((size_t)h->K + 1);
+      for (int64_t i = 0; i <= h->K; ++i) ro[(size_t)i] = i * n;
+      const int32_t K32 = (int32_t)h->K, nB32 = h->nB;
+      qrk_handle h2 = nullptr;
+      if ((s = create_ba(1, n, &K32, &nB32, ro.data(), L, h->dtype, h->mode, &h2)) != QRK_OK) return s;
+      // its dense part also takes the L rows of R_B | c_B, after the blocks' reduced rows
+      h2->probs_h[0].M += L;
+      h2->M += L;
+      dfree(h2, h2->Red);
+      h2->Red = nullptr;
+      if ((s = dalloc(h2, &h2->Red, es * (size_t)(Kn + L) * h2->ldr)) != QRK_OK ||
+          (s = assign_leaves(h2)) != QRK_OK) {
+        free_all(h2);
+        delete h2;
+        return s;
+      }
+      h->lam_stage = h2;
+    }
+    // keep the factor of J aside; c as a contiguous vector (column nB of S | c)
+    if (hipMemcpyAsync(h->Rblk0, h->Rblk, es * (size_t)Kn * n, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(h->Sc0, h->Sc, es * (size_t)Kn * L, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(h->RB0, h->RB, es * (size_t)L * L, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipMemcpy2DAsync(h->c0, es, static_cast<char*>(h->Sc0) + es * (size_t)h->nB, es * (size_t)L, es,
+                         (size_t)Kn, hipMemcpyDeviceToDevice, st) != hipSuccess)
+      return QRK_EHIP;
+    h->lam_base_saved = true;
+  }
+  qrk_handle h2 = h->lam_stage;
+  if (hipMemcpy2DAsync(static_cast<char*>(h2->Red) + es * (size_t)Kn * h2->ldr, es * (size_t)h2->ldr, h->RB0,
+                       es * (size_t)L, es * (size_t)L, (size_t)L, hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return QRK_EHIP;
+  h2->A = h->Rblk0;
+  h2->B = h->Sc0;
+  h2->b = h->c0;
+  h2->d = h->d;
+  h2->lam = lambda;
+  h2->lam_ptr = h2->lam_d;
+  h2->factored = true;
+  if ((s = h->dtype == QRK_F32 ? factor_ba<float>(h2, st, &lambda) : factor_ba<double>(h2, st, &lambda)) != QRK_OK)
+    return s;
+  // the second-stage factor is the factor of [J; sqrt(lambda) D]: solves and refinement use it
+  // with the original J
+  if (hipMemcpyAsync(h->Rblk, h2->Rblk, es * (size_t)Kn * n, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(h->Sc, h2->Sc, es * (size_t)Kn * L, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(h->RB, h2->RB, es * (size_t)L * L, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(h->status, h2->status, sizeof(int) * 4, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+      launch_fill_double(h->lam_d, 1, lambda, st) != hipSuccess)
+    return QRK_EHIP;
+  h->lam = lambda;
+  h->lam_ptr = h->lam_d;
+  return QRK_OK;
 }
 
 qrk_status qrk_factor_blockangular_batched(qrk_handle h, const void* A, const void* B, const void* b,

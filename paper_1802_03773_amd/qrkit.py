@@ -35,6 +35,7 @@ _SIGS = {
     "qrk_create_blockangular": (_c_i32, [_c_i32, _c_i32, _c_i32, _c_i64p, _c_i64, _c_i32, _c_i32,
                                          ctypes.POINTER(_c_vp)]),
     "qrk_factor_blockangular": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_dbl, _c_vp]),
+    "qrk_factor_lambda": (_c_i32, [_c_vp, _c_dbl, _c_vp]),
     "qrk_create_blockangular_batched": (_c_i32, [_c_i32, _c_i32, _c_i32p, _c_i32p, _c_i64p, _c_i32, _c_i32,
                                                  ctypes.POINTER(_c_vp)]),
     "qrk_factor_blockangular_batched": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp]),
@@ -226,6 +227,13 @@ class BlockAngularSolver(Factor):
         _check(lib().qrk_factor_blockangular(self._h, pa, pB, pb, pd, float(lam), _stream_ptr(stream)),
                "qrk_factor_blockangular")
         self._keep = (A, B, b, d)
+        self.lam = float(lam)
+        return self
+
+    def factor_lambda(self, lam: float, stream=None):
+        """Moré's two-stage damping: after factor(..., lam=0), factor [R; sqrt(lam) D] from the
+        kept factor of J (qrk_factor_lambda); solve() then solves the damped problem."""
+        _check(lib().qrk_factor_lambda(self._h, float(lam), _stream_ptr(stream)), "qrk_factor_lambda")
         self.lam = float(lam)
         return self
 

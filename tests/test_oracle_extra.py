@@ -172,3 +172,49 @@ def test_bf16_split_accuracy_and_exact_products():
     C = bf16.bf16x3_matmul(A, B)
     C64 = A.astype(np.float64) @ B.astype(np.float64)
     assert np.max(np.abs(C - C64)) <= 64 * 2.0 ** -15 * np.max(np.abs(A)) * np.max(np.abs(B))
+
+
+# -------------------------------------------------------------- two-stage damping (Section 5.2)
+
+def _structured_R(f, K, n, nB):
+    """Assemble [[blkdiag(R_i), S], [0, R_B]] densely."""
+    N = K * n + nB
+    R = np.zeros((N, N))
+    for i in range(K):
+        R[i * n:(i + 1) * n, i * n:(i + 1) * n] = f.R_blk[i]
+        R[i * n:(i + 1) * n, K * n:] = f.S[i]
+    R[K * n:, K * n:] = f.R_B
+    return R
+
+
+@pytest.mark.parametrize("lam", [1e-4, 1e-2, 1.0])
+def test_two_stage_matches_direct(lam):
+    """Eq. LMTwoStep: the QR of [R; sqrt(lam) D] (R from J alone) gives the solution of the
+    directly damped problem, R'^T R' = J^T J + lam D^2 (closed form), and the same residual norm."""
+    inst = gen.make_blockangular(41, K=12, m=7, n=3, nB=5, lam=lam)
+    f2 = structured.factor_two_stage(inst, lam)
+    f1 = structured.factor_blockangular(inst)
+    p2 = structured.solve_factor(f2)
+    p1 = structured.solve_factor(f1)
+    assert np.linalg.norm(p2 - p1) <= 1e-11 * np.linalg.norm(p1)
+    J = dense.assemble_blockangular(inst)
+    R2 = _structured_R(f2, inst.K, inst.n, inst.nB)
+    M = J.T @ J + lam * np.diag(inst.d ** 2)
+    assert np.abs(R2.T @ R2 - M).max() <= 1e-12 * np.abs(M).max()
+    assert abs(f2.resid - f1.resid) <= 1e-10 * max(f1.resid, 1.0)
+    # and against LAPACK least squares on the augmented system
+    Aaug = np.vstack([J, np.sqrt(lam) * np.diag(inst.d)])
+    p_ls = np.linalg.lstsq(Aaug, np.concatenate([inst.b, np.zeros(inst.N)]), rcond=None)[0]
+    assert np.linalg.norm(p2 - p_ls) <= 1e-10 * np.linalg.norm(p_ls)
+
+
+def test_two_stage_small_lambda_reproduces_R():
+    """As lam -> 0 the second stage returns R itself (up to row signs): [R; 0] = I [R; 0]."""
+    inst = gen.make_blockangular(42, K=5, m=6, n=2, nB=3, lam=0.0)
+    f0 = structured.factor_blockangular(inst)
+    f2 = structured.factor_two_stage(inst, 1e-30)
+    R0 = _structured_R(f0, inst.K, inst.n, inst.nB)
+    R2 = _structured_R(f2, inst.K, inst.n, inst.nB)
+    s0 = np.sign(np.diag(R0))
+    s2 = np.sign(np.diag(R2))
+    assert np.abs(s2[:, None] * R2 - s0[:, None] * R0).max() <= 1e-12 * np.abs(R0).max()
