@@ -100,6 +100,45 @@ def test_banded_row_patterns(rows_per_col, w, dtype):
         assert rel_err(p2[k], p_ref) <= 1e-10
 
 
+def _custom_banded(seed, N, w, row_start, lam, dtype):
+    rng = np.random.default_rng(seed)
+    rs = np.asarray(row_start, np.int32)
+    vals = rng.standard_normal((rs.shape[0], w)).astype(dtype)
+    b = rng.standard_normal(rs.shape[0]).astype(dtype)
+    d = gen.column_norms_banded(N, w, rs, vals) if rs.shape[0] else np.ones(N)
+    d = np.where(d > 0, d, 1.0)
+    return gen.Banded(N, w, rs, vals, b, d, float(lam), np.dtype(dtype))
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("case", ["N_eq_w", "tiny_N", "few_rows", "jumps", "one_start"])
+def test_banded_edge_shapes(case, dtype):
+    """Window edge cases: a single window (N = w), N below one sweep chunk, fewer rows than
+    columns (the damping rows carry the rest), starts that jump by more than the window, and
+    every row at one start."""
+    w = 12 if case != "tiny_N" else 5
+    if case == "N_eq_w":
+        N, rs = 12, [0] * 30
+    elif case == "tiny_N":
+        N, rs = 9, [min(i // 2, 4) for i in range(14)]
+    elif case == "few_rows":
+        N, rs = 80, [0, 3, 3, 20, 41, 68]
+    elif case == "jumps":
+        N, rs = 200, sorted([0, 0, 1, 30, 30, 31, 100, 100, 150, 170, 188, 188])
+    else:
+        N, rs = 40, [10] * 25
+    log(f"banded edge {case} {np.dtype(dtype).name}")
+    insts = [_custom_banded(1500 + k, N, w, rs, 1e-2, dtype) for k in range(3)]
+    p0, st, _, _ = _banded_solve(insts)
+    assert st[0] == 0
+    p2, st, _, _ = _banded_solve(insts, sweeps=2)
+    tol = 1e-12 if dtype == np.float64 else 1e-5
+    for k, inst in enumerate(insts):
+        p_ref, _, _ = banded.reference_solution(inst)
+        assert rel_err(p0[k], p_ref) <= tol
+        assert rel_err(p2[k], p_ref) <= 1e-10
+
+
 def test_banded_many_small_problems():
     """4,100 problems (four per wave in the factorisation): sampled problems vs oracle."""
     log("banded P=4100 N=40 w=7")

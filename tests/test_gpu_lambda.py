@@ -100,3 +100,18 @@ def test_two_stage_new_base_and_errors():
     s.factor_lambda(1e-1)
     p_ref2, _ = refine.reference_solution(dataclasses.replace(inst2, lam=1e-1))
     assert rel_err(s.solve(sweeps=2).cpu().numpy(), p_ref2) <= 1e-10
+
+
+@pytest.mark.parametrize("nB", [0, 5])
+def test_two_stage_small_dense_parts(nB):
+    """No dense part (the second stage's dense part is only the residual row) and a narrow one."""
+    inst = gen.make_blockangular(61 + nB, K=40, m=6, n=3, nB=nB, lam=0.0, dtype=np.float64)
+    s = _solver(inst)
+    A, B, b, d = to_device(inst)
+    s.factor(A, B, b, d, 0.0)
+    for lam in (1e-3, 0.5):
+        s.factor_lambda(lam)
+        p = s.solve(sweeps=1).cpu().numpy()
+        s.raise_on_status()
+        p_ref, _ = refine.reference_solution(dataclasses.replace(inst, lam=lam))
+        assert rel_err(p, p_ref) <= 1e-12
