@@ -13,6 +13,7 @@
 //   accept         : rho = (F - F_new) / pred; rho > 0: x += p, lam *= max(1/3, 1 - (2 rho - 1)^3),
 //                    nu = 2; else lam *= nu, nu *= 2
 // Sums are deterministic (fixed-order per wave, per workgroup and per problem).
+#include <algorithm>
 #include <type_traits>
 
 #include "qrk_batch.hpp"
@@ -168,28 +169,65 @@ k_lmba_eval(const ProbDesc* __restrict__ probs, const int32_t* __restrict__ wg_p
 // Per problem (one workgroup each): the dense columns' d and J^T f from the workgroup
 // partials (JAC), and F = sum f^2 / 2 into Fout[p].
 template <bool JAC>
-__global__ void __launch_bounds__(128)
+__global__ void __launch_bounds__(1024)
 k_lmba_reduce(const ProbDesc* __restrict__ probs, int n, const double* __restrict__ part,
               const double* __restrict__ fpart, double* __restrict__ d, double* __restrict__ gJ,
               double* __restrict__ Fout) {
+  // Fixed-order two-level sums over the problem's workgroup partials: thread (seg, j) sums
+  // segment seg of the partials of column j (eight loads in flight), then the eight segments are
+  // added in order; the F partials go through a 1,024-wide tree.
+  constexpr int SEG = 8;
+  __shared__ double s2_all[SEG][kMaxDense];
+  __shared__ double sf_all[SEG][kMaxDense];
+  __shared__ double red[1024];
   const int pi = blockIdx.x;
   const ProbDesc& P = probs[pi];
-  const int j = threadIdx.x;
+  const int t = threadIdx.x;
+  const int seg = t / kMaxDense, j = t % kMaxDense;
   const int64_t offB = P.noff + P.K * n;
-  if (JAC && j < P.nB) {
+  const int64_t w0 = P.wg0, nw = P.nwg;
+  if (JAC) {
+    const int64_t per = (nw + SEG - 1) / SEG;
+    const int64_t lo = w0 + seg * per, hi = w0 + (seg + 1) * per < w0 + nw ? w0 + (seg + 1) * per : w0 + nw;
     double s2 = 0.0, sf = 0.0;
-    for (int w = P.wg0; w < P.wg0 + P.nwg; ++w) {
-      s2 += part[(int64_t)w * 2 * kMaxDense + j];
-      sf += part[(int64_t)w * 2 * kMaxDense + kMaxDense + j];
+    if (j < P.nB) {
+      for (int64_t w = lo; w < hi; w += 8) {
+        double a2[8], af[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const bool ok = w + u < hi;
+          a2[u] = ok ? part[(w + u) * 2 * kMaxDense + j] : 0.0;
+          af[u] = ok ? part[(w + u) * 2 * kMaxDense + kMaxDense + j] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          s2 += a2[u];
+          sf += af[u];
+        }
+      }
+    }
+    s2_all[seg][j] = s2;
+    sf_all[seg][j] = sf;
+  }
+  double fs = 0.0;
+  for (int64_t w = w0 + t; w < w0 + nw; w += 1024) fs += fpart[w];
+  red[t] = fs;
+  __syncthreads();
+  if (JAC && seg == 0 && j < P.nB) {
+    double s2 = 0.0, sf = 0.0;
+#pragma unroll
+    for (int g = 0; g < SEG; ++g) {
+      s2 += s2_all[g][j];
+      sf += sf_all[g][j];
     }
     d[offB + j] = s2 > 0.0 ? sqrt(s2) : 1.0;
     gJ[offB + j] = sf;
   }
-  if (j == 0) {
-    double s = 0.0;
-    for (int w = P.wg0; w < P.wg0 + P.nwg; ++w) s += fpart[w];
-    Fout[pi] = 0.5 * s;
+  for (int h = 512; h >= 1; h >>= 1) {
+    if (t < h) red[t] += red[t + h];
+    __syncthreads();
   }
+  if (t == 0) Fout[pi] = 0.5 * red[0];
 }
 
 // ---------------------------------------------------------------------------------------
@@ -403,15 +441,45 @@ k_lmbd_cols_t(int64_t M, int64_t N, int w, const int32_t* __restrict__ row_start
 // ---------------------------------------------------------------------------------------
 // Problem-generic pieces (unknowns of problem p: [noff[p], noff[p+1])).
 // ---------------------------------------------------------------------------------------
+// pred = p^T (lam D^2 p - J^T f) / 2, deterministic two-level sum: workgroup (bx, p) sums its
+// 2,048 unknowns of problem p (eight per thread, loads in flight together) through an LDS
+// tree into part[p][bx]; one workgroup per problem then adds the parts in a fixed tree.
+constexpr int kPredChunk = 2048;
 __global__ void __launch_bounds__(256)
-k_lm_pred(const int64_t* __restrict__ noff, const double* __restrict__ p, const double* __restrict__ d,
-          const double* __restrict__ gJ, const double* __restrict__ lam, double* __restrict__ pred) {
+k_lm_pred_part(const int64_t* __restrict__ noff, const double* __restrict__ p, const double* __restrict__ d,
+               const double* __restrict__ gJ, const double* __restrict__ lam, double* __restrict__ part) {
+  __shared__ double red[256];
+  const int pi = blockIdx.y;
+  const int64_t a = noff[pi], e = noff[pi + 1];
+  const int64_t j0 = a + (int64_t)blockIdx.x * kPredChunk + threadIdx.x;
+  const double l = lam[pi];
+  double pv[8], dv[8], gv[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int64_t j = j0 + u * 256;
+    const bool ok = j < e;
+    pv[u] = ok ? p[j] : 0.0;
+    dv[u] = ok ? d[j] : 0.0;
+    gv[u] = ok ? gJ[j] : 0.0;
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) s += pv[u] * (l * dv[u] * dv[u] * pv[u] - gv[u]);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h >= 1; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(int64_t)pi * gridDim.x + blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256)
+k_lm_pred_final(int nbx, const double* __restrict__ part, double* __restrict__ pred) {
   __shared__ double red[256];
   const int pi = blockIdx.x;
-  const int64_t a = noff[pi], e = noff[pi + 1];
-  const double l = lam[pi];
   double s = 0.0;
-  for (int64_t j = a + threadIdx.x; j < e; j += blockDim.x) s += p[j] * (l * d[j] * d[j] * p[j] - gJ[j]);
+  for (int k = threadIdx.x; k < nbx; k += 256) s += part[(int64_t)pi * nbx + k];
   red[threadIdx.x] = s;
   __syncthreads();
   for (int h = 128; h >= 1; h >>= 1) {
@@ -457,12 +525,14 @@ k_lm_accept(int P, const double* __restrict__ F, const double* __restrict__ Fnew
   if (threadIdx.x == 0) *iter = it + 1;
 }
 
+// x += p for the problems whose step was accepted: one thread per unknown, grid (., P).
 __global__ void __launch_bounds__(256)
 k_lm_step(const int64_t* __restrict__ noff, const int* __restrict__ acc, const double* __restrict__ p,
           double* __restrict__ x) {
-  const int pi = blockIdx.x;
+  const int pi = blockIdx.y;
   if (!acc[pi]) return;
-  for (int64_t j = noff[pi] + threadIdx.x; j < noff[pi + 1]; j += blockDim.x) x[j] += p[j];
+  const int64_t j = noff[pi] + (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j < noff[pi + 1]) x[j] += p[j];
 }
 
 __global__ void k_lm_init(int P, double* __restrict__ nu, int* __restrict__ iter) {
@@ -488,24 +558,32 @@ hipError_t launch_lmba_eval(const BatchView& bv, bool jac, const T* A0, const T*
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (jac)
-    hipLaunchKernelGGL((k_lmba_reduce<true>), dim3(bv.P), dim3(128), 0, st, bv.probs, bv.n, part, fpart, d, gJ,
+    hipLaunchKernelGGL((k_lmba_reduce<true>), dim3(bv.P), dim3(1024), 0, st, bv.probs, bv.n, part, fpart, d, gJ,
                        Fout);
   else
-    hipLaunchKernelGGL((k_lmba_reduce<false>), dim3(bv.P), dim3(128), 0, st, bv.probs, bv.n, part, fpart, d, gJ,
+    hipLaunchKernelGGL((k_lmba_reduce<false>), dim3(bv.P), dim3(1024), 0, st, bv.probs, bv.n, part, fpart, d, gJ,
                        Fout);
   return hipGetLastError();
 }
 
-hipError_t launch_lm_control(int P, const int64_t* noff, const double* p, const double* d, const double* gJ,
-                             double* lam, double* nu, const double* F, const double* Fnew, double* pred, int* acc,
-                             int* iter, double* log, int max_log, double* x, hipStream_t st, int stage) {
+int lm_pred_blocks(int64_t maxN) { return (int)std::max<int64_t>(1, (maxN + kPredChunk - 1) / kPredChunk); }
+
+hipError_t launch_lm_control(int P, int64_t maxN, const int64_t* noff, const double* p, const double* d,
+                             const double* gJ, double* lam, double* nu, const double* F, const double* Fnew,
+                             double* pred, double* predpart, int* acc, int* iter, double* log, int max_log, double* x,
+                             hipStream_t st, int stage) {
   if (stage == 0) {
-    hipLaunchKernelGGL(k_lm_pred, dim3(P), dim3(256), 0, st, noff, p, d, gJ, lam, pred);
+    const int nbx = lm_pred_blocks(maxN);
+    hipLaunchKernelGGL(k_lm_pred_part, dim3(nbx, P), dim3(256), 0, st, noff, p, d, gJ, lam, predpart);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_lm_pred_final, dim3(P), dim3(256), 0, st, nbx, predpart, pred);
   } else {
     hipLaunchKernelGGL(k_lm_accept, dim3(1), dim3(256), 0, st, P, F, Fnew, pred, lam, nu, acc, iter, log, max_log);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_lm_step, dim3(P), dim3(256), 0, st, noff, acc, p, x);
+    const unsigned nbx = (unsigned)std::max<int64_t>(1, (maxN + 255) / 256);
+    hipLaunchKernelGGL(k_lm_step, dim3(nbx, P), dim3(256), 0, st, noff, acc, p, x);
   }
   return hipGetLastError();
 }

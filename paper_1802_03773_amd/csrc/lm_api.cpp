@@ -3,6 +3,7 @@
 // and damping update), and its capture into a HIP graph that is replayed per iteration.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <new>
 #include <vector>
@@ -31,6 +32,8 @@ struct qrk_lm_s {
   double *x = nullptr, *p = nullptr, *d = nullptr, *gJ = nullptr;
   double *F = nullptr, *Fnew = nullptr, *pred = nullptr, *lam = nullptr, *nu = nullptr;
   double *part = nullptr, *fpart = nullptr, *log = nullptr;
+  double* predpart = nullptr;  // per-workgroup parts of the predicted decrease
+  int64_t maxN = 0;            // unknowns of the largest problem
   double* f = nullptr;  // banded: f(x) per row
   int *acc = nullptr, *iter = nullptr;
   int64_t* noff = nullptr;
@@ -88,13 +91,15 @@ qrk_status lm_iteration(qrk_lm lm, hipStream_t st) {
   qrk_status s;
   if ((s = blockangular_factor(h, st)) != QRK_OK) return s;
   if ((s = blockangular_solve(h, lm->p, lm->sweeps, st)) != QRK_OK) return s;
-  if (launch_lm_control(h->P, lm->noff, lm->p, lm->d, lm->gJ, lm->lam, lm->nu, lm->F, lm->Fnew, lm->pred, lm->acc,
+  if (launch_lm_control(h->P, lm->maxN, lm->noff, lm->p, lm->d, lm->gJ, lm->lam, lm->nu, lm->F, lm->Fnew, lm->pred,
+                        lm->predpart, lm->acc,
                         lm->iter, lm->log, lm->max_log, lm->x, st, 0) != hipSuccess)
     return QRK_EHIP;
   if (launch_lmba_eval<T>(bv, false, A0, B0, y, lm->c, lm->x, lm->p, A, B, b, lm->d, lm->gJ, lm->part, lm->fpart,
                           lm->Fnew, st) != hipSuccess)
     return QRK_EHIP;
-  if (launch_lm_control(h->P, lm->noff, lm->p, lm->d, lm->gJ, lm->lam, lm->nu, lm->F, lm->Fnew, lm->pred, lm->acc,
+  if (launch_lm_control(h->P, lm->maxN, lm->noff, lm->p, lm->d, lm->gJ, lm->lam, lm->nu, lm->F, lm->Fnew, lm->pred,
+                        lm->predpart, lm->acc,
                         lm->iter, lm->log, lm->max_log, lm->x, st, 1) != hipSuccess)
     return QRK_EHIP;
   return QRK_OK;
@@ -121,13 +126,15 @@ qrk_status lm_iteration_banded(qrk_lm lm, hipStream_t st) {
   qrk_status s;
   if ((s = banded_factor(h, st)) != QRK_OK) return s;
   if ((s = banded_solve(h, lm->p, lm->sweeps, st)) != QRK_OK) return s;
-  if (launch_lm_control(h->P, lm->noff, lm->p, lm->d, lm->gJ, lm->lam, lm->nu, lm->F, lm->Fnew, lm->pred, lm->acc,
+  if (launch_lm_control(h->P, lm->maxN, lm->noff, lm->p, lm->d, lm->gJ, lm->lam, lm->nu, lm->F, lm->Fnew, lm->pred,
+                        lm->predpart, lm->acc,
                         lm->iter, lm->log, lm->max_log, lm->x, st, 0) != hipSuccess)
     return QRK_EHIP;
   if (launch_lmbd_eval<T>(h->P, h->M, h->N, h->w, false, lm->row_start, h->bandfr, vals0, y, lm->c, lm->x, lm->p,
                           vals, b, lm->f, lm->d, lm->gJ, lm->fpart, lm->Fnew, st) != hipSuccess)
     return QRK_EHIP;
-  if (launch_lm_control(h->P, lm->noff, lm->p, lm->d, lm->gJ, lm->lam, lm->nu, lm->F, lm->Fnew, lm->pred, lm->acc,
+  if (launch_lm_control(h->P, lm->maxN, lm->noff, lm->p, lm->d, lm->gJ, lm->lam, lm->nu, lm->F, lm->Fnew, lm->pred,
+                        lm->predpart, lm->acc,
                         lm->iter, lm->log, lm->max_log, lm->x, st, 1) != hipSuccess)
     return QRK_EHIP;
   return QRK_OK;
@@ -159,6 +166,8 @@ qrk_status lm_alloc_common(qrk_lm lm, const std::vector<int64_t>& noff) {
           QRK_OK ||
       (s = lm_alloc(lm, &lm->noff, sizeof(int64_t) * (P + 1))) != QRK_OK)
     return s;
+  for (size_t q = 0; q < P; ++q) lm->maxN = std::max<int64_t>(lm->maxN, noff[q + 1] - noff[q]);
+  if ((s = lm_alloc(lm, &lm->predpart, sizeof(double) * (size_t)P * lm_pred_blocks(lm->maxN))) != QRK_OK) return s;
   if (hipMemcpy(lm->noff, noff.data(), sizeof(int64_t) * (P + 1), hipMemcpyHostToDevice) != hipSuccess ||
       hipStreamCreateWithFlags(&lm->cap, hipStreamNonBlocking) != hipSuccess)
     return QRK_EHIP;

@@ -27,9 +27,12 @@ hipError_t launch_lmbd_eval(int P, int64_t M, int64_t N, int w, bool jac, const 
 
 // stage 0: pred = p^T (lam D^2 p - J^T f) / 2 per problem.  stage 1: gain ratio, damping
 // update, accept flags, log row of this iteration, iteration counter, x += p where accepted.
-hipError_t launch_lm_control(int P, const int64_t* noff, const double* p, const double* d, const double* gJ,
-                             double* lam, double* nu, const double* F, const double* Fnew, double* pred, int* acc,
-                             int* iter, double* log, int max_log, double* x, hipStream_t st, int stage);
+// workgroups per problem of the predicted-decrease sum (its partials buffer holds P of them)
+int lm_pred_blocks(int64_t maxN);
+hipError_t launch_lm_control(int P, int64_t maxN, const int64_t* noff, const double* p, const double* d,
+                             const double* gJ, double* lam, double* nu, const double* F, const double* Fnew,
+                             double* pred, double* predpart, int* acc, int* iter, double* log, int max_log, double* x,
+                             hipStream_t st, int stage);
 
 // nu = 2 for every problem, iteration counter = 0.
 hipError_t launch_lm_init(int P, double* nu, int* iter, hipStream_t st);
