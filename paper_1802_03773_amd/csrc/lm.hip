@@ -27,7 +27,10 @@ __device__ __forceinline__ double lm_dphi(double t, double c) { return 1.0 + 3.0
 
 // ---------------------------------------------------------------------------------------
 // Block-angular model evaluation: workgroup w serves the packs of problem wg_prob[w] (the
-// refinement's assignment), one wave per pack of whole blocks, one row per lane.
+// refinement's assignment), one wave per pack of whole blocks.  The pack's rows of B0 are read
+// once, 16 rows at a time with coalesced loads (lane = column), and staged in the wave's LDS
+// tile; each row's B0 phi(u_B) is summed from the tile by four lanes, and J's B rows and their
+// column sums come from the registers the rows were loaded into.
 // JAC: writes A = A0 diag(phi'(u_blk)), B = B0 diag(phi'(u_B)), b = -f, the block columns'
 //      d and J^T f, and per-workgroup partials of sum_r B_rj^2, sum_r B_rj f_r and sum_r f_r^2.
 // !JAC: only the partial of sum_r f_r^2, at u = x + p.
@@ -40,6 +43,9 @@ k_lmba_eval(const ProbDesc* __restrict__ probs, const int32_t* __restrict__ wg_p
             const double* __restrict__ x, const double* __restrict__ pstep, T* __restrict__ A,
             T* __restrict__ B, T* __restrict__ b, double* __restrict__ d, double* __restrict__ gJ,
             double* __restrict__ part, double* __restrict__ fpart) {
+  constexpr int CH = 16;      // rows per staged chunk
+  constexpr int LS = CH + 1;  // column stride of the staged tile
+  __shared__ T tile_all[4][kMaxDense * LS];
   __shared__ double phB[kMaxDense], dphB[kMaxDense];
   __shared__ double rr[4][64];
   __shared__ double av[4][64][8];
@@ -55,14 +61,22 @@ k_lmba_eval(const ProbDesc* __restrict__ probs, const int32_t* __restrict__ wg_p
   const int64_t offB = noff + P.K * n;
   const T* B0p = B0 + P.boff;
   T* Bp = B + P.boff;
-  for (int j = threadIdx.x; j < nB; j += blockDim.x) {
-    const double u = x[offB + j] + (JAC ? 0.0 : pstep[offB + j]);
-    phB[j] = lm_phi(u, c);
-    dphB[j] = lm_dphi(u, c);
+  T* tile = tile_all[wv];
+  for (int j = threadIdx.x; j < kMaxDense; j += blockDim.x) {
+    double ph = 0.0, dph = 0.0;  // zero past nB: the staged tile is zero there too
+    if (j < nB) {
+      const double u = x[offB + j] + (JAC ? 0.0 : pstep[offB + j]);
+      ph = lm_phi(u, c);
+      dph = lm_dphi(u, c);
+    }
+    phB[j] = ph;
+    dphB[j] = dph;
   }
   __syncthreads();
   double s2a = 0.0, s2b = 0.0, sfa = 0.0, sfb = 0.0;  // columns lane, lane + 64
   double fsq = 0.0;
+  const int qi = lane & 15, qq = lane >> 4;  // row pass: row qi of the chunk, columns 4t + qq
+  const bool c0ok = lane < nB, c1ok = lane + 64 < nB;
   const int64_t lw = blockIdx.x - P.wg0;
   const int64_t pend = P.pack0 + P.npacks;
   for (int64_t pk = P.pack0 + lw * 4 + wv; pk < pend; pk += (int64_t)P.nwg * 4) {
@@ -75,55 +89,85 @@ k_lmba_eval(const ProbDesc* __restrict__ probs, const int32_t* __restrict__ wg_p
       for (int r = lo; r < hi; ++r) rowblk[wv][r] = lane;
     }
     wave_lds_sync();
-    if (lane < prows) {
-      const int64_t row = pr0 + lane;
-      const int64_t lb = b0 - koff + rowblk[wv][lane];
-      double f = 0.0;
+    for (int c0 = 0; c0 < prows; c0 += CH) {
+      const int last = prows - 1 - c0;  // rows past the pack re-read its last row and are skipped
+      // stage the chunk's rows of B0, coalesced across lanes (lane = column)
+      T v0[CH], v1[CH];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        if (k < n) {
-          const double u = x[noff + lb * n + k] + (JAC ? 0.0 : pstep[noff + lb * n + k]);
-          const double a0 = (double)A0[row * n + k];
-          f += a0 * lm_phi(u, c);
-          if (JAC) {
-            const T a = (T)(a0 * lm_dphi(u, c));
-            A[row * n + k] = a;
-            av[wv][lane][k] = (double)a;
+      for (int i = 0; i < CH; ++i) {
+        const int ri = i < last ? i : last;
+        const int64_t roff = (pr0 + c0 + ri - moff) * ldb;
+        v0[i] = c0ok ? B0p[roff + lane] : T(0);
+        v1[i] = c1ok ? B0p[roff + lane + 64] : T(0);
+      }
+#pragma unroll
+      for (int i = 0; i < CH; ++i) {
+        tile[lane * LS + i] = v0[i];
+        tile[(lane + 64) * LS + i] = v1[i];
+      }
+      wave_lds_sync();
+      // B0 phi(u_B) for row c0 + qi: lanes qi, qi + 16, qi + 32, qi + 48 split the columns
+      double acc = 0.0;
+      auto tier = [&](auto t_begin) {
+        constexpr int tb = decltype(t_begin)::value;
+#pragma unroll
+        for (int t = tb; t < tb + 8; ++t) acc += (double)tile[(4 * t + qq) * LS + qi] * phB[4 * t + qq];
+      };
+      tier(std::integral_constant<int, 0>{});
+      if (nB > 32) tier(std::integral_constant<int, 8>{});
+      if (nB > 64) tier(std::integral_constant<int, 16>{});
+      if (nB > 96) tier(std::integral_constant<int, 24>{});
+      acc += __shfl_xor(acc, 16, 64);
+      acc += __shfl_xor(acc, 32, 64);
+      if (qq == 0 && qi <= last) {
+        const int r = c0 + qi;
+        const int64_t row = pr0 + r;
+        const int64_t lb = b0 - koff + rowblk[wv][r];
+        double f = 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          if (k < n) {
+            const double u = x[noff + lb * n + k] + (JAC ? 0.0 : pstep[noff + lb * n + k]);
+            const double a0 = (double)A0[row * n + k];
+            f += a0 * lm_phi(u, c);
+            if (JAC) {
+              const T a = (T)(a0 * lm_dphi(u, c));
+              A[row * n + k] = a;
+              av[wv][r][k] = (double)a;
+            }
+          }
+        }
+        f += acc - (double)y[row];
+        rr[wv][r] = f;
+        fsq += f * f;
+        if (JAC) b[row] = (T)(-f);
+      }
+      wave_lds_sync();
+      if (JAC) {
+        // J's B rows from the staged registers: scale, store (coalesced), column sums
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+          if (i <= last) {
+            const int64_t roff = (pr0 + c0 + i - moff) * ldb;
+            const double fr = rr[wv][c0 + i];
+            if (c0ok) {
+              const T v = (T)((double)v0[i] * dphB[lane]);
+              Bp[roff + lane] = v;
+              s2a += (double)v * (double)v;
+              sfa += (double)v * fr;
+            }
+            if (c1ok) {
+              const T v = (T)((double)v1[i] * dphB[lane + 64]);
+              Bp[roff + lane + 64] = v;
+              s2b += (double)v * (double)v;
+              sfb += (double)v * fr;
+            }
           }
         }
       }
-      const T* Brow = B0p + (row - moff) * ldb;
-      double f0 = 0.0, f1 = 0.0;
-      int j = 0;
-      for (; j + 1 < nB; j += 2) {
-        f0 += (double)Brow[j] * phB[j];
-        f1 += (double)Brow[j + 1] * phB[j + 1];
-      }
-      if (j < nB) f0 += (double)Brow[j] * phB[j];
-      f += (f0 + f1) - (double)y[row];
-      rr[wv][lane] = f;
-      fsq += f * f;
-      if (JAC) b[row] = (T)(-f);
+      wave_lds_sync();  // the next chunk overwrites the tile
     }
-    wave_lds_sync();
     if (JAC) {
-      // B rows of the pack, coalesced across lanes: scale, store, accumulate column sums
-      for (int r = 0; r < prows; ++r) {
-        const int64_t roff = (pr0 + r - moff) * ldb;
-        const double fr = rr[wv][r];
-        if (lane < nB) {
-          const T v = (T)((double)B0p[roff + lane] * dphB[lane]);
-          Bp[roff + lane] = v;
-          s2a += (double)v * (double)v;
-          sfa += (double)v * fr;
-        }
-        if (lane + 64 < nB) {
-          const T v = (T)((double)B0p[roff + lane + 64] * dphB[lane + 64]);
-          Bp[roff + lane + 64] = v;
-          s2b += (double)v * (double)v;
-          sfb += (double)v * fr;
-        }
-      }
       // block columns: lane per block
       if (lane < nb) {
         const int64_t lb = b0 - koff + lane;
