@@ -75,6 +75,78 @@ __device__ __forceinline__ float read_lane(float x, int lane) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), lane));
 }
 
+// Lane (g, c) receives lane (G, c)'s x: row G of the wave copied to all four rows (a
+// cross-lane fetch through the LDS crossbar, no LDS storage; every lane must be active).
+template <int G>
+__device__ __forceinline__ float rows_from(float x, int c) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute((G * 16 + c) * 4, __builtin_bit_cast(int, x)));
+}
+
+// Householder factorisation of one 16-column panel [Rd; X[0..RBN-1]] (paper Section 2: one
+// reflector per column, the compact-WY factor T built alongside).  Rd is the 16x16 diagonal
+// block of the triangle, X the panel's tile blocks, both in the accumulator layout; lane
+// (g, c) owns column c.  Step j:
+//   G_c   = x_j^T x_c over the tile rows (one pass, all columns; G_j = sigma_j = ||x_j||^2)
+//   beta  = -sign(alpha) sqrt(alpha^2 + sigma), alpha = R[j][j]; tau = (beta - alpha) / beta;
+//           the reflector is [1; s_j x_j] with s_j = 1 / (alpha - beta) (the tile column stays
+//           unscaled in place)
+//   pd_c  = R[j][c] + s_j G_c   (= [e_j; w_j]^T [R[:, c]; x_c])
+//   R[j][c] -= tau pd_c, x_c -= x_j s_j tau pd_c   (c > j);  R[j][j] = beta
+//   T[0:j, j] = -tau T[0:j, 0:j] (W[:, 0:j]^T w_j), T[j][j] = tau, with w_k^T w_j = s_k s_j G_k.
+// sigma below the smallest normal float counts as zero (identity reflector).  A leaf that
+// starts from a zero triangle reflects the roundoff left in the columns beyond the rank of its
+// first tiles; that residue shrinks by about eps per tile height and can reach the subnormal
+// range, where the hardware square root returns 0 and the scale would be infinite.  Selects,
+// not branches, for the reflector itself: the panel stays one straight-line block the scheduler
+// can interleave with the matrix-core updates around it.
+// On return lane (g, c) holds row c of T in trow and s_c in sc.
+template <int RBN>
+__device__ __forceinline__ void panel_factor(f4& Rd, f4 (&X)[RBN], float (&trow)[16], float& sc, int lane) {
+  const int g = lane >> 4;
+  const int c = lane & 15;
+  sc = 0.f;
+  static_for<0, 16>([&](auto JJ) {
+    constexpr int j = decltype(JJ)::value;
+    // R's row j in every row of the wave; the steps before j leave that row unchanged
+    const float rrow = rows_from<(j >> 2)>(Rd[j & 3], c);
+    float pr0 = 0.f, pr1 = 0.f;
+#pragma unroll
+    for (int rb = 0; rb < RBN; ++rb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        if (v & 1)
+          pr1 += row_bcast<j>(X[rb][v]) * X[rb][v];
+        else
+          pr0 += row_bcast<j>(X[rb][v]) * X[rb][v];
+      }
+    const float gram = sum_rows4(pr0 + pr1);  // x_j^T x_c
+    const float sigma = row_bcast<j>(gram);
+    const float alpha = read_lane(Rd[j & 3], (j >> 2) * 16 + j);
+    const bool refl = sigma >= 0x1p-126f;
+    const float nrm = __builtin_amdgcn_sqrtf(alpha * alpha + sigma);
+    const float bneg = alpha >= 0.f ? -nrm : nrm;
+    const float beta = refl ? bneg : alpha;
+    const float tau = refl ? (bneg - alpha) * __builtin_amdgcn_rcpf(bneg) : 0.f;
+    const float scale = refl ? __builtin_amdgcn_rcpf(alpha - bneg) : 0.f;
+    const float pd = gram * scale + rrow;  // R[j][c] + w_j^T x_c
+    const float s = tau * pd;
+    const float nf = (c > j) ? -scale * s : 0.f;
+#pragma unroll
+    for (int rb = 0; rb < RBN; ++rb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) X[rb][v] += row_bcast<j>(X[rb][v]) * nf;
+    if (g == (j >> 2)) Rd[j & 3] = (c > j) ? Rd[j & 3] - s : (c == j ? beta : Rd[j & 3]);
+    const float gk = sc * pd;  // at lane k < j: s_k s_j x_j^T x_k = w_k^T w_j
+    float t = 0.f;
+    static_for<0, j>([&](auto KK) {
+      constexpr int k = decltype(KK)::value;
+      t += trow[k] * row_bcast<k>(gk);
+    });
+    trow[j] = (c < j) ? -tau * t : (c == j ? tau : 0.f);
+    if (c == j) sc = scale;
+  });
+}
+
 __device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
@@ -137,65 +209,15 @@ __device__ __forceinline__ void merge_tile(f4 (&R)[Tri<NCB>::count], f4 (&X)[NRB
 
     // ---- panel factorisation of [R[P][P]; X[:, P]] (and T alongside) -------------------
     float trow[16];  // lane (g, c) builds row c of T
-    float sc = 0.f;  // scale of this lane's column once it has been reduced
-    static_for<0, 16>([&](auto JJ) {
-      constexpr int j = decltype(JJ)::value;
-      float ps0 = 0.f, ps1 = 0.f;
+    float sc;        // scale of this lane's column
+    {
+      f4 Xp[RBN];
 #pragma unroll
-      for (int rb = 0; rb < RBN; ++rb)
+      for (int rb = 0; rb < RBN; ++rb) Xp[rb] = X[rb][P];
+      panel_factor<RBN>(R[rp], Xp, trow, sc, lane);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          if (v & 1)
-            ps1 += X[rb][P][v] * X[rb][P][v];
-          else
-            ps0 += X[rb][P][v] * X[rb][P][v];
-        }
-      const float ps = sum_rows4(ps0 + ps1);
-      const float sigma = row_bcast<j>(ps);  // every row of the wave holds column j's sum
-      const float alpha = read_lane(R[rp][j & 3], (j >> 2) * 16 + j);
-      // sigma below the smallest normal float counts as zero (identity reflector).  A leaf
-      // that starts from a zero triangle reflects the roundoff left in the columns beyond the
-      // rank of its first tiles; that residue shrinks by about eps per tile height and can
-      // reach the subnormal range, where the hardware square root returns 0 and the scale
-      // 1 / (alpha - beta) would be infinite.  Selects, not a branch: the whole panel stays
-      // one straight-line block the scheduler can interleave with the matrix-core updates.
-      const bool refl = sigma >= 0x1p-126f;
-      const float nrm = __builtin_amdgcn_sqrtf(alpha * alpha + sigma);
-      const float bneg = alpha >= 0.f ? -nrm : nrm;
-      const float beta = refl ? bneg : alpha;
-      const float tau = refl ? (bneg - alpha) * __builtin_amdgcn_rcpf(bneg) : 0.f;
-      const float scale = refl ? __builtin_amdgcn_rcpf(alpha - bneg) : 0.f;
-      // x_j^T x_c for every lane's column c
-      float pr0 = 0.f, pr1 = 0.f;
-#pragma unroll
-      for (int rb = 0; rb < RBN; ++rb)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          if (v & 1)
-            pr1 += row_bcast<j>(X[rb][P][v]) * X[rb][P][v];
-          else
-            pr0 += row_bcast<j>(X[rb][P][v]) * X[rb][P][v];
-        }
-      const float rj = (g == (j >> 2)) ? R[rp][j & 3] : 0.f;
-      const float pd = sum_rows4((pr0 + pr1) * scale + rj);  // R[j][c] + w_j^T x_c
-      const float s = tau * pd;
-      const float nf = (c > j) ? -scale * s : 0.f;             // x_c -= x_j * (scale s_c)
-#pragma unroll
-      for (int rb = 0; rb < RBN; ++rb)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) X[rb][P][v] += row_bcast<j>(X[rb][P][v]) * nf;
-      if (g == (j >> 2)) R[rp][j & 3] = (c > j) ? R[rp][j & 3] - s : (c == j ? beta : R[rp][j & 3]);
-      // T column j: T[c][j] = -tau_j sum_{k<j} T[c][k] (w_k^T w_j), T[j][j] = tau_j, where
-      // w_k^T w_j = s_k * (pd at lane k) for k < j.
-      const float gk = sc * pd;
-      float t = 0.f;
-      static_for<0, j>([&](auto KK) {
-        constexpr int k = decltype(KK)::value;
-        t += trow[k] * row_bcast<k>(gk);
-      });
-      trow[j] = (c < j) ? -tau * t : (c == j ? tau : 0.f);
-      if (c == j) sc = scale;
-    });
+      for (int rb = 0; rb < RBN; ++rb) X[rb][P] = Xp[rb];
+    }
 
     // ---- re-lay out T (rows -> accumulator layout), scales and W^T through LDS ------------
     if (g == 0) {

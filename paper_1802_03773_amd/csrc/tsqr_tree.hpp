@@ -51,58 +51,15 @@ __device__ __forceinline__ void tree_panel_factor(f4& Rd, f4* X, float* __restri
   const int g = lane >> 4;
   const int c = lane & 15;
   float trow[16];  // lane (g, c) builds row c of T
-  float sc = 0.f;  // scale of this lane's column once it has been reduced
-  static_for<0, 16>([&](auto JJ) {
-    constexpr int j = decltype(JJ)::value;
-    float ps0 = 0.f, ps1 = 0.f;
+  float sc;        // scale of this lane's column
+  {
+    f4 Xp[RBN];
 #pragma unroll
-    for (int rb = 0; rb < RBN; ++rb)
+    for (int rb = 0; rb < RBN; ++rb) Xp[rb] = X[rb];
+    panel_factor<RBN>(Rd, Xp, trow, sc, lane);
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        if (v & 1)
-          ps1 += X[rb][v] * X[rb][v];
-        else
-          ps0 += X[rb][v] * X[rb][v];
-      }
-    const float ps = sum_rows4(ps0 + ps1);
-    const float sigma = row_bcast<j>(ps);
-    const float alpha = read_lane(Rd[j & 3], (j >> 2) * 16 + j);
-    // sigma below the smallest normal float counts as zero (identity reflector): the
-    // hardware square root would return 0 for it
-    const bool refl = sigma >= 0x1p-126f;
-    const float nrm = __builtin_amdgcn_sqrtf(alpha * alpha + sigma);
-    const float bneg = alpha >= 0.f ? -nrm : nrm;
-    const float beta = refl ? bneg : alpha;
-    const float tau = refl ? (bneg - alpha) * __builtin_amdgcn_rcpf(bneg) : 0.f;
-    const float scale = refl ? __builtin_amdgcn_rcpf(alpha - bneg) : 0.f;
-    float pr0 = 0.f, pr1 = 0.f;
-#pragma unroll
-    for (int rb = 0; rb < RBN; ++rb)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        if (v & 1)
-          pr1 += row_bcast<j>(X[rb][v]) * X[rb][v];
-        else
-          pr0 += row_bcast<j>(X[rb][v]) * X[rb][v];
-      }
-    const float rj = (g == (j >> 2)) ? Rd[j & 3] : 0.f;
-    const float pd = sum_rows4((pr0 + pr1) * scale + rj);  // R[j][c] + w_j^T x_c
-    const float s = tau * pd;
-    const float nf = (c > j) ? -scale * s : 0.f;
-#pragma unroll
-    for (int rb = 0; rb < RBN; ++rb)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) X[rb][v] += row_bcast<j>(X[rb][v]) * nf;
-    if (g == (j >> 2)) Rd[j & 3] = (c > j) ? Rd[j & 3] - s : (c == j ? beta : Rd[j & 3]);
-    const float gk = sc * pd;
-    float t = 0.f;
-    static_for<0, j>([&](auto KK) {
-      constexpr int k = decltype(KK)::value;
-      t += trow[k] * row_bcast<k>(gk);
-    });
-    trow[j] = (c < j) ? -tau * t : (c == j ? tau : 0.f);
-    if (c == j) sc = scale;
-  });
+    for (int rb = 0; rb < RBN; ++rb) X[rb] = Xp[rb];
+  }
   float* Tl = keep;
   float* Sl = keep + 256;
   float* Wl = keep + 320;
