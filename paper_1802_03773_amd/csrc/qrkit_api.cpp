@@ -282,7 +282,7 @@ qrk_status assign_leaves(qrk_handle h) {
       D.tree_sep = sep ? 1 : 0;
       if (sep) {
         slot += (int64_t)(D.leaves + h->nnodes) * tsqr_mfma_slot_floats(D.L);
-        ctr += std::max<int64_t>(1, (int64_t)h->nnodes * ((D.L + 15) / 16));
+        ctr += std::max<int64_t>(1, (int64_t)h->nnodes * ((D.L + 15) / 16) * 2);  // two flags per column block
       } else {
         const TreeSize ts = tree_size(D.leaves);
         slot += ts.slots * tsqr_mfma_slot_floats(D.L);

@@ -5,13 +5,17 @@
 //
 // Organisation.  The leaves (k_tsqr_mfma with the problem's tree_sep set) store their
 // triangles and exit.  Here one wave per merge node works left-looking over column blocks of
-// 16: for column block q it waits until both children have published their column block q,
-// loads it, applies the reflectors of its own panels 0..q-1 (compact WY, kept in LDS),
-// factors panel q, keeps that panel's reflectors (T, column scales, raw tile columns W) for
-// the later column blocks, and publishes its column block q (stores, then a per-node,
-// per-block flag).  A parent starts on column block 0 while its children are still
-// on later ones, so the root trails the leaves by about (tree depth + column blocks) panel
-// times rather than (tree depth) whole merges.
+// 16.  Column block q is published in two parts, each with a flag of its own: the blocks above
+// the diagonal (block rows 0..q-1), which are final once the node's panels 0..q-1 have been
+// applied, and then the diagonal block, final once panel q is factored.  For column block q a
+// node waits until both children have published the part above the diagonal, loads it and
+// applies the reflectors of its own panels 0..q-1 to it (compact WY, kept in LDS; panel p
+// touches block rows 0..p only), publishes that part, then waits for the children's diagonal
+// blocks, factors panel q, keeps that panel's reflectors (T, column scales, raw tile columns W)
+// for the later column blocks and publishes its diagonal block.  The applications thus overlap
+// the children's factorisation of the same column block, and a parent starts on column block
+// 0 while its children are still on later ones, so the root trails the leaves by about
+// (tree depth + column blocks) panel times rather than (tree depth) whole merges.
 //
 // Memory ordering.  A node's published blocks are written and read with device-coherent
 // accesses (through the L2 to memory and back); the producer waits for its block stores to
@@ -153,8 +157,9 @@ __device__ __forceinline__ bool tree_wait(const int* flag, int lane) {
 
 // One wave per inner node of the (single) problem's tree.  node_l / node_r: child references,
 // r >= 0 an inner node, r < 0 leaf -1 - r.  Leaf triangles are at slots 0 .. leaves-1 of the
-// problem, node outputs at slots leaves + node; flags[node * NCB + q] marks column block q of
-// a node's output as published.  The root (the last node) writes R_B | c_B row-major.
+// problem, node outputs at slots leaves + node; flags[(node * NCB + q) * 2] marks column block
+// q of a node's output as published above the diagonal, flags[(node * NCB + q) * 2 + 1] its
+// diagonal block.  The root (the last node) writes R_B | c_B row-major.
 template <int NCB>
 __global__ void __launch_bounds__(256)
 k_tsqr_tree(const ProbDesc* __restrict__ probs, const int32_t* __restrict__ node_l,
@@ -182,24 +187,46 @@ k_tsqr_tree(const ProbDesc* __restrict__ probs, const int32_t* __restrict__ node
   bool stalled = false;
   f4 a[NCB];  // column block q: R part (left child), block rows 0..q
   f4 x[NCB];  // column block q: tile (right child), block rows 0..q
+  // block (p, q) of the left (a) or right (x) child's triangle: published node outputs are read
+  // past the L2, leaf triangles come from the previous launch (plain loads)
+  auto load_blocks = [&](int p, int q, f4& av, f4& xv) {
+    const float* ls = lsrc + Tri<NCB>::idx(p, q) * 256;
+    const float* rs = rsrc + Tri<NCB>::idx(p, q) * 256;
+    av = lref >= 0 ? tree_load_block(ls, lane) : __builtin_nontemporal_load(reinterpret_cast<const f4*>(ls + lane * 4));
+    xv = rref >= 0 ? tree_load_block(rs, lane) : __builtin_nontemporal_load(reinterpret_cast<const f4*>(rs + lane * 4));
+  };
+  // flag k (0: above the diagonal, 1: diagonal block) of column block q, once the stores before
+  // it have completed
+  auto publish = [&](int q, int k) {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    if (lane == 0)
+      __hip_atomic_store(pflags + ((int64_t)node * NCB + q) * 2 + k, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  };
+  auto wait_children = [&](int q, int k) {
+    if (!stalled && lref >= 0) stalled = !tree_wait(pflags + ((int64_t)lref * NCB + q) * 2 + k, lane);
+    if (!stalled && rref >= 0) stalled = !tree_wait(pflags + ((int64_t)rref * NCB + q) * 2 + k, lane);
+    asm volatile("" ::: "memory");  // the block's loads stay after the flags were seen
+  };
   static_for<0, NCB>([&](auto QQ) {
     constexpr int q = decltype(QQ)::value;
-    if (!stalled && lref >= 0) stalled = !tree_wait(pflags + (int64_t)lref * NCB + q, lane);
-    if (!stalled && rref >= 0) stalled = !tree_wait(pflags + (int64_t)rref * NCB + q, lane);
-    asm volatile("" ::: "memory");  // the block's loads stay after the flags were seen
-    // leaf triangles come from the previous launch (plain loads); node outputs are read past
-    // the L2
+    if constexpr (q > 0) {
+      // above the diagonal: panels 0..q-1 applied, then published
+      wait_children(q, 0);
 #pragma unroll
-    for (int p = 0; p <= q; ++p) {
-      const float* ls = lsrc + Tri<NCB>::idx(p, q) * 256;
-      const float* rs = rsrc + Tri<NCB>::idx(p, q) * 256;
-      a[p] = lref >= 0 ? tree_load_block(ls, lane) : __builtin_nontemporal_load(reinterpret_cast<const f4*>(ls + lane * 4));
-      x[p] = rref >= 0 ? tree_load_block(rs, lane) : __builtin_nontemporal_load(reinterpret_cast<const f4*>(rs + lane * 4));
+      for (int p = 0; p < q; ++p) load_blocks(p, q, a[p], x[p]);
+      static_for<0, q>([&](auto PP) {
+        constexpr int p = decltype(PP)::value;
+        tree_panel_apply<p + 1>(keep + TreeKeep<NCB>::off(p), a[p], x, lane);
+      });
+      if (!root) {
+#pragma unroll
+        for (int p = 0; p < q; ++p) tree_store_block(out + Tri<NCB>::idx(p, q) * 256, a[p], lane);
+        publish(q, 0);
+      }
     }
-    static_for<0, q>([&](auto PP) {
-      constexpr int p = decltype(PP)::value;
-      tree_panel_apply<p + 1>(keep + TreeKeep<NCB>::off(p), a[p], x, lane);
-    });
+    // the diagonal block: panel q factored, then published
+    wait_children(q, 1);
+    load_blocks(q, q, a[q], x[q]);
     tree_panel_factor<q + 1>(a[q], x, keep + TreeKeep<NCB>::off(q), lane);
     if (root) {
       // column block q of R_B | c_B, row-major L x L (zeros below the diagonal)
@@ -217,11 +244,8 @@ k_tsqr_tree(const ProbDesc* __restrict__ probs, const int32_t* __restrict__ node
         }
       });
     } else {
-#pragma unroll
-      for (int p = 0; p <= q; ++p) tree_store_block(out + Tri<NCB>::idx(p, q) * 256, a[p], lane);
-      // the flag store follows the completion of the block's stores
-      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-      if (lane == 0) __hip_atomic_store(pflags + (int64_t)node * NCB + q, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      tree_store_block(out + Tri<NCB>::idx(q, q) * 256, a[q], lane);
+      publish(q, 1);
     }
   });
   if (stalled) set_status(status, ST_STALL);

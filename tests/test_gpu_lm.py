@@ -11,14 +11,14 @@ from workloads import generators as gen
 pytestmark = pytest.mark.gpu
 
 
-def _setup(problems, dtype, c, sweeps=2, max_log=32):
+def _setup(problems, dtype, c, sweeps=2, max_log=32, mode="plain"):
     """problems: list of (inst0, y, x0); returns (driver, batch-or-solver, device arrays)."""
     import torch
     from paper_1802_03773_amd import BlockAngularBatch, LMDriver
     insts = [p[0] for p in problems]
     st = gen.stack_batch(insts)
     td = torch.float32 if dtype == np.float32 else torch.float64
-    bt = BlockAngularBatch(st["K"], st["nB"], st["row_off"], st["n"], dtype=np.dtype(dtype).name)
+    bt = BlockAngularBatch(st["K"], st["nB"], st["row_off"], st["n"], dtype=np.dtype(dtype).name, mode=mode)
     A0 = torch.from_numpy(st["A"]).cuda()
     B0 = torch.from_numpy(st["B"]).cuda() if st["B"].size else None
     y = torch.from_numpy(np.concatenate([p[1] for p in problems]).astype(dtype)).cuda()
@@ -59,13 +59,14 @@ def test_lm_float64_single_problem_matches_oracle():
     assert rel_err(x.cpu().numpy(), xo) <= 1e-9
 
 
-def test_lm_float32_batch_matches_oracle():
+@pytest.mark.parametrize("mode", ["plain", "bf16x3"])
+def test_lm_float32_batch_matches_oracle(mode):
     import torch
     probs = []
     for k, (K, nB) in enumerate([(60, 30), (25, 6), (40, 0)]):
         inst0, y, x0, _ = gen.lm_blockangular(410 + k, K=K, m=10, n=3, nB=nB, c=0.1, dtype=np.float32)
         probs.append((inst0, y, x0))
-    drv, bt, x0d, _ = _setup(probs, np.float32, 0.1)
+    drv, bt, x0d, _ = _setup(probs, np.float32, 0.1, mode=mode)
     iters = 10
     lam0 = np.array([1e-2, 1e-1, 1.0])
     drv.reset(x0d, torch.from_numpy(lam0).cuda())
@@ -77,7 +78,7 @@ def test_lm_float32_batch_matches_oracle():
     for q, prob in enumerate(probs):
         xo, _, lgo = _oracle_run(prob, 0.1, lam0[q], iters, np.float32)
         k = _significant(lgo)
-        log(f"float32 LM problem {q}: {k} significant iterations")
+        log(f"float32 LM ({mode}) problem {q}: {k} significant iterations")
         assert k >= 2
         np.testing.assert_allclose(lg[:k, q, :3], lgo[:k, :3], rtol=1e-5)
         assert np.array_equal(lg[:k, q, 3], lgo[:k, 3])
