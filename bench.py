@@ -34,7 +34,8 @@ PEAK_FP64_VECTOR_TFLOPS = 78.6
 # and while the kernels' sources hash to the recorded digest.
 _TSQR_SOURCES = ["paper_1802_03773_amd/csrc/tsqr_mfma.hpp", "paper_1802_03773_amd/csrc/tsqr_mfma.hip",
                  "paper_1802_03773_amd/csrc/tsqr_mfma_ncb6.hip", "paper_1802_03773_amd/csrc/qrk_device.hpp",
-                 "paper_1802_03773_amd/csrc/tsqr_tree.hpp", "paper_1802_03773_amd/csrc/tsqr_tree.hip"]
+                 "paper_1802_03773_amd/csrc/tsqr_tree.hpp", "paper_1802_03773_amd/csrc/tsqr_tree.hip",
+                 "paper_1802_03773_amd/csrc/qrkit_api.cpp"]  # the host side sets the reduced-row stride
 _TSQR_DIGEST = "2e21b80a54aff74ef821598b3ff7ea3765c3755ee6f79e21fb31df23eb12f77e"
 _TREE_KIB = 22611.9 * 2.000 + 21845.8
 MEASURED_TRAFFIC = {

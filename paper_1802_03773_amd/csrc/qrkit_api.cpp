@@ -202,6 +202,16 @@ void dfree(qrk_handle h, void* ptr) {
     }
 }
 
+// Row stride (elements) of the reduced rows for L columns of es-byte elements: a multiple of 128
+// bytes when that costs at most 1/16 more than the smallest multiple of 4, so that no two blocks'
+// rows share a cache line and the per-block QR writes whole lines; else a multiple of 4.
+int64_t reduced_row_stride(int64_t L, int64_t es) {
+  const int64_t line = 128 / es;
+  const int64_t s4 = ((L + 3) / 4) * 4;
+  const int64_t sl = ((L + line - 1) / line) * line;
+  return sl * 16 <= s4 * 17 ? sl : s4;
+}
+
 // Slots and arrival counters a merge tree over `leaves` leaves touches: level k has n_k
 // nodes (n_0 = leaves, n_{k+1} = ceil(n_k / 2)); its stored triangles sit at slots
 // [sum_{j<k} n_j, sum_{j<=k} n_j) and its counters at [sum_{j<k} n_{j+1}, ...).
@@ -454,7 +464,7 @@ qrk_status create_ba(int32_t P, int32_t n, const int32_t* Kp, const int32_t* nBp
   h->M = row_off_host[Ktot];
   h->max_rows = max_m + n;
   h->ldb = ldb_single >= 0 ? ldb_single : nBp[0];
-  h->ldr = ((nBp[0] + 1 + 3) / 4) * 4;
+  h->ldr = reduced_row_stride(nBp[0] + 1, dtype == QRK_F32 ? 4 : 8);
   const size_t es = dtype == QRK_F32 ? 4 : 8;
 
   // per-problem descriptors and packs
@@ -476,7 +486,7 @@ qrk_status create_ba(int32_t P, int32_t n, const int32_t* Kp, const int32_t* nBp
     D.boff = boff;
     D.ldb = ldb_single >= 0 ? ldb_single : D.nB;
     D.soff = soff;
-    D.ldr = ((D.L + 3) / 4) * 4;
+    D.ldr = reduced_row_stride(D.L, dtype == QRK_F32 ? 4 : 8);
     D.redoff = redoff;
     D.rboff = rboff;
     D.pack0 = (int64_t)packs.size() - 1;
