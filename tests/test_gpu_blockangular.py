@@ -114,6 +114,27 @@ def test_wide_dense_part_multi_leaf_trees(nB):
         assert rel_err(p, p_ref) <= 1e-5
 
 
+@pytest.mark.parametrize("mode", ["plain", "bf16x3"])
+@pytest.mark.parametrize("nB", [5, 20, 40, 60, 75, 90])
+def test_pipelined_tree_every_width(nB, mode):
+    """Single float32 problems of 1..6 column blocks, whose leaf triangles are merged by the
+    pipelined tree launch (each column block published above the diagonal first, then its
+    diagonal block): even and odd leaf counts (a node without a sibling carries its triangle
+    up a level), the factor R_B | c_B against the oracle up to row signs, and p."""
+    K = 300
+    inst = gen.make_blockangular(700 + nB, K=K, m=(np.arange(K) % 7) + 6, n=3, nB=nB, lam=1e-2,
+                                 dtype=np.float32)
+    p_ref, f = refine.reference_solution(inst)
+    for leaves in [2, 3, 7, 16, 33]:
+        log(f"pipelined tree nB={nB} mode={mode} leaves={leaves}")
+        p, st, solver, _ = gpu_solve_blockangular(inst, mode=mode, leaves=leaves, return_solver=True)
+        assert st[0] == 0, st
+        assert rel_err(p, p_ref) <= 1e-5
+        _check_factor(inst, solver, f, 5e-5)
+        p2, st = gpu_solve_blockangular(inst, mode=mode, leaves=leaves, sweeps=2)
+        assert rel_err(p2, p_ref) <= 1e-10
+
+
 @pytest.mark.parametrize("lam", [1e-2, 0.0])
 @pytest.mark.parametrize("nB", [47, 90, 127])
 def test_few_rows_per_leaf(nB, lam):
