@@ -189,6 +189,24 @@ qrk_status qrk_factor_banded(qrk_handle h, const int32_t* row_start, const void*
 qrk_status qrk_solve(qrk_handle h, double* p, int32_t sweeps, void* stream);
 
 /* ------------------------------------------------------------------------------
+ * qrk_solve_rhs
+ *   The step for a new right-hand side with the stored factor (the paper applies the kept
+ *   Q^T to each new b, Section 5.1; here Q is not stored): p = argmin
+ *   || [J; sqrt(lambda) D] p - [b; 0] || for the J, d and lambda of the last qrk_factor_*
+ *   call and the given b, by `sweeps` (1..8) corrected semi-normal sweeps from p = 0:
+ *       r = b - J p,  g = J^T r - lambda D^2 p,  R^T R delta = g,  p <- p + delta.
+ *   The first sweep gives the semi-normal solution R^{-1} R^{-T} J^T b; each further sweep
+ *   reduces the error by about cond(J) times the factor's relative accuracy (float32
+ *   factors: two to four sweeps reach 1e-10 at cond(J) <= 1e3).
+ *   b: device, the layout and type of the factor call's b (block-angular [M] stacked over
+ *   the problems, banded [P][M]); p [N] double (block-angular: sum_p N_p; banded: P * N),
+ *   written.  Neither the handle's borrowed b nor its factor is changed: qrk_solve still
+ *   solves for the factor call's b.  Errors: QRK_EINVAL for a NULL handle, b or p, a
+ *   handle without a factor, or sweeps outside 1..8.
+ * ------------------------------------------------------------------------------ */
+qrk_status qrk_solve_rhs(qrk_handle h, const void* b, double* p, int32_t sweeps, void* stream);
+
+/* ------------------------------------------------------------------------------
  * qrk_solve_adjoint
  *   For a loss L(p) of the step p (from qrk_solve on this handle) and g = dL/dp,
  *   with u = (R^T R)^{-1} g (two triangular solves with the stored R; R^T R =

@@ -20,6 +20,9 @@ namespace {
 inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 template <typename T>
+qrk_status banded_refine_t(qrk_handle h, double* p, int sweeps, const T* b, hipStream_t st);
+
+template <typename T>
 qrk_status banded_solve_t(qrk_handle h, double* p, int sweeps, hipStream_t st) {
   const T* R = static_cast<const T*>(h->bandR);
   const T* c = static_cast<const T*>(h->bandc);
@@ -28,11 +31,19 @@ qrk_status banded_solve_t(qrk_handle h, double* p, int sweeps, hipStream_t st) {
   if (launch_banded_backsub<T>(h->P, h->N, h->w, R, R16, h->bandinv, c, p, h->status, st) != hipSuccess)
     return QRK_EHIP;
   prof_end(h, pr, st);
-  pr = sweeps > 0 ? prof_begin(h, 4, st) : -1;
+  return banded_refine_t<T>(h, p, sweeps, static_cast<const T*>(h->b), st);
+}
+
+// `sweeps` corrected semi-normal sweeps for the right-hand side b.
+template <typename T>
+qrk_status banded_refine_t(qrk_handle h, double* p, int sweeps, const T* b, hipStream_t st) {
+  const T* R = static_cast<const T*>(h->bandR);
+  const T* R16 = static_cast<const T*>(h->bandR16);
+  int pr = sweeps > 0 ? prof_begin(h, 4, st) : -1;
   for (int s = 0; s < sweeps; ++s) {
     // r = b - J p; g = J^T r - lam D^2 p; y = R^{-T} g; p += R^{-1} y
-    if (launch_banded_apply<T>(h->P, h->M, h->N, h->w, h->row_start, static_cast<const T*>(h->A),
-                               static_cast<const T*>(h->b), p, h->rbuf, st) != hipSuccess ||
+    if (launch_banded_apply<T>(h->P, h->M, h->N, h->w, h->row_start, static_cast<const T*>(h->A), b, p, h->rbuf,
+                               st) != hipSuccess ||
         launch_banded_jt<T>(h->P, h->M, h->N, h->w, h->row_start, h->bandfr, static_cast<const T*>(h->A), h->rbuf,
                             h->d, h->lam_ptr, p, h->gbuf, st) != hipSuccess ||
         launch_banded_fwd<T>(h->P, h->N, h->w, R, R16, h->bandinv, h->gbuf, h->gbuf, st) != hipSuccess ||
@@ -135,6 +146,11 @@ qrk_status create_banded(int32_t P, int64_t M, int64_t N, int32_t w, qrk_dtype d
 
 qrk_status banded_solve(qrk_handle h, double* p, int sweeps, hipStream_t st) {
   return h->dtype == QRK_F32 ? banded_solve_t<float>(h, p, sweeps, st) : banded_solve_t<double>(h, p, sweeps, st);
+}
+
+qrk_status banded_refine(qrk_handle h, double* p, int sweeps, const void* b, hipStream_t st) {
+  return h->dtype == QRK_F32 ? banded_refine_t<float>(h, p, sweeps, static_cast<const float*>(b), st)
+                             : banded_refine_t<double>(h, p, sweeps, static_cast<const double*>(b), st);
 }
 
 qrk_status banded_adjoint(qrk_handle h, const double* p, const double* g, void* dvals, void* db,

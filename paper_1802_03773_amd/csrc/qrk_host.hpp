@@ -146,6 +146,7 @@ qrk::BatchView blockangular_view(qrk_handle h);
 // Banded factor / solve on the handle's current inputs and damping ([P] at h->lam_ptr).
 qrk_status banded_factor(qrk_handle h, hipStream_t st);
 qrk_status banded_solve(qrk_handle h, double* p, int sweeps, hipStream_t st);
+qrk_status banded_refine(qrk_handle h, double* p, int sweeps, const void* b, hipStream_t st);
 
 // Workspace allocation shared by the create functions (records the allocation in h).
 qrk_status handle_alloc(qrk_handle h, void** out, size_t bytes);

@@ -137,6 +137,26 @@ qrk_status factor_ba(qrk_handle h, hipStream_t st, const double* lam_host = null
   return QRK_OK;
 }
 
+// `sweeps` corrected semi-normal sweeps for the right-hand side b: r = b - J p,
+// g = J^T r - lam D^2 p, p += (R^T R)^{-1} g.
+template <typename T>
+qrk_status refine_ba(qrk_handle h, double* p, int sweeps, const T* b, hipStream_t st) {
+  const T* Rblk = static_cast<const T*>(h->Rblk);
+  const T* Sc = static_cast<const T*>(h->Sc);
+  const T* RB = static_cast<const T*>(h->RB);
+  const BatchView bv = view(h);
+  int pr = sweeps > 0 ? prof_begin(h, 4, st) : -1;
+  for (int s = 0; s < sweeps; ++s) {
+    if (launch_refine_residual<T>(bv, static_cast<const T*>(h->A), static_cast<const T*>(h->B), b, h->d, Rblk,
+                                  Sc, p, h->ybuf, h->refpart, st) != hipSuccess ||
+        launch_refine_dense<T>(bv, h->refpart, RB, h->d, p, h->deltaB, st) != hipSuccess ||
+        launch_refine_blocks<T>(bv, Rblk, Sc, h->ybuf, h->deltaB, p, st) != hipSuccess)
+      return QRK_EHIP;
+  }
+  prof_end(h, pr, st);
+  return QRK_OK;
+}
+
 template <typename T>
 qrk_status solve_ba(qrk_handle h, double* p, int sweeps, hipStream_t st) {
   const T* Rblk = static_cast<const T*>(h->Rblk);
@@ -147,17 +167,7 @@ qrk_status solve_ba(qrk_handle h, double* p, int sweeps, hipStream_t st) {
   if (launch_backsub_dense<T>(bv, RB, p, h->status, st) != hipSuccess) return QRK_EHIP;
   if (launch_backsub_blocks<T>(bv, Rblk, Sc, p, h->status, st) != hipSuccess) return QRK_EHIP;
   prof_end(h, pr, st);
-  pr = sweeps > 0 ? prof_begin(h, 4, st) : -1;
-  for (int s = 0; s < sweeps; ++s) {
-    if (launch_refine_residual<T>(bv, static_cast<const T*>(h->A), static_cast<const T*>(h->B),
-                                  static_cast<const T*>(h->b), h->d, Rblk, Sc, p, h->ybuf, h->refpart, st) !=
-            hipSuccess ||
-        launch_refine_dense<T>(bv, h->refpart, RB, h->d, p, h->deltaB, st) != hipSuccess ||
-        launch_refine_blocks<T>(bv, Rblk, Sc, h->ybuf, h->deltaB, p, st) != hipSuccess)
-      return QRK_EHIP;
-  }
-  prof_end(h, pr, st);
-  return QRK_OK;
+  return refine_ba<T>(h, p, sweeps, static_cast<const T*>(h->b), st);
 }
 
 void prof_free(qrk_handle h) {
@@ -736,6 +746,17 @@ qrk_status qrk_solve(qrk_handle h, double* p, int32_t sweeps, void* stream) {
     return h->dtype == QRK_F32 ? solve_ba<float>(h, p, sweeps, S(stream))
                                : solve_ba<double>(h, p, sweeps, S(stream));
   return banded_solve(h, p, sweeps, S(stream));
+}
+
+qrk_status qrk_solve_rhs(qrk_handle h, const void* b, double* p, int32_t sweeps, void* stream) {
+  if (!h || !b || !p || sweeps < 1 || sweeps > 8 || !h->factored) return QRK_EINVAL;
+  hipStream_t st = S(stream);
+  const int64_t np = h->kind == KIND_BLOCKANGULAR ? h->N : (int64_t)h->P * h->N;
+  if (launch_fill_double(p, np, 0.0, st) != hipSuccess) return QRK_EHIP;
+  if (h->kind == KIND_BLOCKANGULAR)
+    return h->dtype == QRK_F32 ? refine_ba<float>(h, p, sweeps, static_cast<const float*>(b), st)
+                               : refine_ba<double>(h, p, sweeps, static_cast<const double*>(b), st);
+  return banded_refine(h, p, sweeps, b, st);
 }
 
 qrk_status qrk_solve_adjoint(qrk_handle h, const double* p, const double* g, void* dA, void* dB,

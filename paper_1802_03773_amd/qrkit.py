@@ -52,6 +52,7 @@ _SIGS = {
     "qrk_create_banded_batched": (_c_i32, [_c_i32, _c_i64, _c_i64, _c_i32, _c_i32, ctypes.POINTER(_c_vp)]),
     "qrk_factor_banded": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_dbl, _c_vp]),
     "qrk_solve": (_c_i32, [_c_vp, _c_vp, _c_i32, _c_vp]),
+    "qrk_solve_rhs": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_i32, _c_vp]),
     "qrk_solve_adjoint": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp]),
     "qrk_colnorms_blockangular": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_vp]),
     "qrk_get_factor": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_vp]),
@@ -160,6 +161,20 @@ class Factor:
         _check(lib().qrk_solve(self._h, _dev_ptr(out, torch.float64, "p", self.N), int(sweeps),
                                _stream_ptr(stream)), "qrk_solve")
         return out
+
+    def solve_rhs(self, b, sweeps: int = 3, out=None, stream=None):
+        """The step for a new right-hand side b (same J, d, lambda as the last factor), by
+        `sweeps` corrected semi-normal sweeps from p = 0 with the stored R; p float64 [N]."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty(self.N, dtype=torch.float64, device="cuda")
+        _check(lib().qrk_solve_rhs(self._h, _dev_ptr(b, _torch_dtype(self.qdtype), "b", self._rhs_rows()),
+                                   _dev_ptr(out, torch.float64, "p", self.N), int(sweeps), _stream_ptr(stream)),
+               "qrk_solve_rhs")
+        return out
+
+    def _rhs_rows(self) -> int:
+        return int(self.P) * int(self.M) if self.kind == "banded" else int(self.M)
 
     def status(self, stream=None) -> tuple[int, int]:
         detail = ctypes.c_int32(0)

@@ -70,6 +70,7 @@ def test_null_handle_calls_are_rejected():
     assert L.qrk_solve_adjoint(None, None, None, None, None, None, None, None, None) == qrkit.QRK_EINVAL
     assert L.qrk_set_tsqr_shape(None, 0, 0) == qrkit.QRK_EINVAL
     assert L.qrk_factor_lambda(None, 1e-2, None) == qrkit.QRK_EINVAL
+    assert L.qrk_solve_rhs(None, None, None, 1, None) == qrkit.QRK_EINVAL
     assert L.qrk_workspace_bytes(None) == 0
     L.qrk_destroy(None)
 
