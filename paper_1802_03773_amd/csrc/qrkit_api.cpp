@@ -18,6 +18,7 @@
 #include "qrk_device.hpp"
 #include "block_classes.hpp"
 #include "qrk_host.hpp"
+#include "qrk_layout.hpp"
 
 using namespace qrk;
 
@@ -210,16 +211,6 @@ void dfree(qrk_handle h, void* ptr) {
       h->allocs.erase(h->allocs.begin() + (long)i);
       return;
     }
-}
-
-// Row stride (elements) of the reduced rows for L columns of es-byte elements: a multiple of 128
-// bytes when that costs at most 1/16 more than the smallest multiple of 4, so that no two blocks'
-// rows share a cache line and the per-block QR writes whole lines; else a multiple of 4.
-int64_t reduced_row_stride(int64_t L, int64_t es) {
-  const int64_t line = 128 / es;
-  const int64_t s4 = ((L + 3) / 4) * 4;
-  const int64_t sl = ((L + line - 1) / line) * line;
-  return sl * 16 <= s4 * 17 ? sl : s4;
 }
 
 // Slots and arrival counters a merge tree over `leaves` leaves touches: level k has n_k
