@@ -528,8 +528,9 @@ qrk_status create_ba(int32_t P, int32_t n, const int32_t* Kp, const int32_t* nBp
   }
   h->blk_list_n = (int64_t)bq.list.size();
   const std::vector<int32_t>& blk_list = bq.list;
-  // refinement workgroups, in proportion to each problem's packs
-  const int64_t target = std::min<int64_t>(ceil_div(h->npacks, 4), 1024);
+  // refinement workgroups, in proportion to each problem's packs: 512 in all (two waves per SIMD
+  // in one round at the refinement's register use), and about eight per problem for batches
+  const int64_t target = std::min<int64_t>(ceil_div(h->npacks, 4), std::max<int64_t>(512, 8 * (int64_t)P));
   std::vector<int32_t> wg_prob;
   for (int32_t q = 0; q < P; ++q) {
     ProbDesc& D = pd[q];
