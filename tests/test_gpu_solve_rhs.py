@@ -101,3 +101,24 @@ def test_rejects_bad_arguments():
     for sweeps in (0, 9):
         with pytest.raises(QRKError):
             s.solve_rhs(b2, sweeps=sweeps)
+
+
+def test_new_rhs_after_two_stage_factor():
+    """J factored at lambda = 0, then the two-stage factor of [R; sqrt(lambda) D]: a new right-hand
+    side is solved with that lambda."""
+    import torch
+    from paper_1802_03773_amd import BlockAngularSolver
+    inst = gen.make_blockangular(960, K=300, m=(np.arange(300) % 7) + 6, n=3, nB=30, lam=0.0, dtype=np.float32)
+    lam = 1e-2
+    b2 = _new_b(inst, 961)
+    p_ref, _ = refine.reference_solution(dataclasses.replace(inst, b=b2, lam=lam))
+    A, B, b, d = to_device(inst)
+    s = BlockAngularSolver(inst.row_off, inst.n, inst.nB, dtype="float32")
+    s.factor(A, B, b, d, 0.0)
+    s.factor_lambda(lam)
+    p2 = s.solve_rhs(torch.from_numpy(b2).cuda(), sweeps=4)
+    torch.cuda.synchronize()
+    e = rel_err(p2.cpu().numpy(), p_ref)
+    log(f"two-stage factor, new right-hand side: {e:.2e}")
+    assert s.status()[0] == 0
+    assert e <= 1e-10
