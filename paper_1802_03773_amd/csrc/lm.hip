@@ -36,7 +36,7 @@ __device__ __forceinline__ double lm_dphi(double t, double c) { return 1.0 + 3.0
 // !JAC: only the partial of sum_r f_r^2, at u = x + p.
 // ---------------------------------------------------------------------------------------
 template <typename T, bool JAC>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(JAC ? 256 : 512)
 k_lmba_eval(const ProbDesc* __restrict__ probs, const int32_t* __restrict__ wg_prob,
             const int64_t* __restrict__ pack_blk, int n, const int64_t* __restrict__ row_off,
             const T* __restrict__ A0, const T* __restrict__ B0, const T* __restrict__ y, double c,
@@ -45,13 +45,15 @@ k_lmba_eval(const ProbDesc* __restrict__ probs, const int32_t* __restrict__ wg_p
             double* __restrict__ part, double* __restrict__ fpart) {
   constexpr int CH = 16;      // rows per staged chunk
   constexpr int LS = CH + 1;  // column stride of the staged tile
-  __shared__ T tile_all[4][kMaxDense * LS];
+  // waves per workgroup: the residual-only pass keeps less per wave, so eight fit the LDS
+  constexpr int WG = JAC ? 4 : 8;
+  __shared__ T tile_all[WG][kMaxDense * LS];
   __shared__ double phB[kMaxDense], dphB[kMaxDense];
-  __shared__ double rr[4][64];
-  __shared__ double av[4][64][8];
-  __shared__ int rowblk[4][64];
-  __shared__ double red2[4][kMaxDense], redf[4][kMaxDense];
-  __shared__ double fred[4];
+  __shared__ double rr[WG][64];
+  __shared__ double av[JAC ? WG : 1][64][8];
+  __shared__ int rowblk[WG][64];
+  __shared__ double red2[JAC ? WG : 1][kMaxDense], redf[JAC ? WG : 1][kMaxDense];
+  __shared__ double fred[WG];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int pi = wg_prob[blockIdx.x];
@@ -79,7 +81,7 @@ k_lmba_eval(const ProbDesc* __restrict__ probs, const int32_t* __restrict__ wg_p
   const bool c0ok = lane < nB, c1ok = lane + 64 < nB;
   const int64_t lw = blockIdx.x - P.wg0;
   const int64_t pend = P.pack0 + P.npacks;
-  for (int64_t pk = P.pack0 + lw * 4 + wv; pk < pend; pk += (int64_t)P.nwg * 4) {
+  for (int64_t pk = P.pack0 + lw * WG + wv; pk < pend; pk += (int64_t)P.nwg * WG) {
     const int64_t b0 = pack_blk[pk];
     const int nb = (int)(pack_blk[pk + 1] - b0);
     const int64_t pr0 = row_off[b0];
@@ -130,7 +132,7 @@ k_lmba_eval(const ProbDesc* __restrict__ probs, const int32_t* __restrict__ wg_p
             const double u = x[noff + lb * n + k] + (JAC ? 0.0 : pstep[noff + lb * n + k]);
             const double a0 = (double)A0[row * n + k];
             f += a0 * lm_phi(u, c);
-            if (JAC) {
+            if constexpr (JAC) {
               const T a = (T)(a0 * lm_dphi(u, c));
               A[row * n + k] = a;
               av[wv][r][k] = (double)a;
@@ -167,7 +169,7 @@ k_lmba_eval(const ProbDesc* __restrict__ probs, const int32_t* __restrict__ wg_p
       }
       wave_lds_sync();  // the next chunk overwrites the tile
     }
-    if (JAC) {
+    if constexpr (JAC) {
       // block columns: lane per block
       if (lane < nb) {
         const int64_t lb = b0 - koff + lane;
@@ -189,25 +191,36 @@ k_lmba_eval(const ProbDesc* __restrict__ probs, const int32_t* __restrict__ wg_p
     }
     wave_lds_sync();
   }
-  // fixed-order reductions: across the wave (butterfly), then the four waves in order
+  // fixed-order reductions: across the wave (butterfly), then the workgroup's waves in order
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) fsq += __shfl_xor(fsq, off, 64);
   if (lane == 0) fred[wv] = fsq;
-  if (JAC) {
+  if constexpr (JAC) {
     red2[wv][lane] = s2a;
     red2[wv][lane + 64] = s2b;
     redf[wv][lane] = sfa;
     redf[wv][lane + 64] = sfb;
   }
   __syncthreads();
-  if (JAC) {
+  if constexpr (JAC) {
     double* pw = part + (int64_t)blockIdx.x * 2 * kMaxDense;
     for (int j = threadIdx.x; j < nB; j += blockDim.x) {
-      pw[j] = ((red2[0][j] + red2[1][j]) + red2[2][j]) + red2[3][j];
-      pw[kMaxDense + j] = ((redf[0][j] + redf[1][j]) + redf[2][j]) + redf[3][j];
+      double a2 = red2[0][j], af = redf[0][j];
+#pragma unroll
+      for (int w = 1; w < WG; ++w) {
+        a2 += red2[w][j];
+        af += redf[w][j];
+      }
+      pw[j] = a2;
+      pw[kMaxDense + j] = af;
     }
   }
-  if (threadIdx.x == 0) fpart[blockIdx.x] = ((fred[0] + fred[1]) + fred[2]) + fred[3];
+  if (threadIdx.x == 0) {
+    double fs = fred[0];
+#pragma unroll
+    for (int w = 1; w < WG; ++w) fs += fred[w];
+    fpart[blockIdx.x] = fs;
+  }
 }
 
 // Per problem (one workgroup each): the dense columns' d and J^T f from the workgroup
@@ -597,7 +610,7 @@ hipError_t launch_lmba_eval(const BatchView& bv, bool jac, const T* A0, const T*
     hipLaunchKernelGGL((k_lmba_eval<T, true>), dim3(bv.nwg), dim3(256), 0, st, bv.probs, bv.wg_prob, bv.pack_blk,
                        bv.n, bv.row_off, A0, B0, y, c, x, p, A, B, b, d, gJ, part, fpart);
   else
-    hipLaunchKernelGGL((k_lmba_eval<T, false>), dim3(bv.nwg), dim3(256), 0, st, bv.probs, bv.wg_prob,
+    hipLaunchKernelGGL((k_lmba_eval<T, false>), dim3(bv.nwg), dim3(512), 0, st, bv.probs, bv.wg_prob,
                        bv.pack_blk, bv.n, bv.row_off, A0, B0, y, c, x, p, A, B, b, d, gJ, part, fpart);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
