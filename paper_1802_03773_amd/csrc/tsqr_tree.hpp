@@ -143,13 +143,18 @@ __device__ __forceinline__ f4 tree_load_block(const float* src, int lane) {
   return __builtin_amdgcn_raw_buffer_load_b128(rs, lane * 16, 0, kCoherent);
 }
 
-// Wait (bounded) until *flag is set; false on timeout.  Lane 0 polls with relaxed
-// device-scope loads (no cache invalidation per poll).
-__device__ __forceinline__ bool tree_wait(const int* flag, int lane) {
+// Wait (bounded) until both *fa and *fb are set (a null flag counts as set); false on
+// timeout.  Lane 0 polls with relaxed device-scope loads (no cache invalidation per poll),
+// both flags in the same round trip.
+__device__ __forceinline__ bool tree_wait2(const int* fa, const int* fb, int lane) {
   for (int it = 0; it < (1 << 20); ++it) {
-    int v = 0;
-    if (lane == 0) v = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (__builtin_amdgcn_readfirstlane(v) != 0) return true;
+    int ready = 1;
+    if (lane == 0) {
+      const int va = fa ? __hip_atomic_load(fa, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 1;
+      const int vb = fb ? __hip_atomic_load(fb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 1;
+      ready = (va != 0) && (vb != 0);
+    }
+    if (__builtin_amdgcn_readfirstlane(ready) != 0) return true;
     __builtin_amdgcn_s_sleep(2);
   }
   return false;
@@ -203,8 +208,9 @@ k_tsqr_tree(const ProbDesc* __restrict__ probs, const int32_t* __restrict__ node
       __hip_atomic_store(pflags + ((int64_t)node * NCB + q) * 2 + k, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   };
   auto wait_children = [&](int q, int k) {
-    if (!stalled && lref >= 0) stalled = !tree_wait(pflags + ((int64_t)lref * NCB + q) * 2 + k, lane);
-    if (!stalled && rref >= 0) stalled = !tree_wait(pflags + ((int64_t)rref * NCB + q) * 2 + k, lane);
+    if (!stalled && (lref >= 0 || rref >= 0))
+      stalled = !tree_wait2(lref >= 0 ? pflags + ((int64_t)lref * NCB + q) * 2 + k : nullptr,
+                            rref >= 0 ? pflags + ((int64_t)rref * NCB + q) * 2 + k : nullptr, lane);
     asm volatile("" ::: "memory");  // the block's loads stay after the flags were seen
   };
   static_for<0, NCB>([&](auto QQ) {
