@@ -19,15 +19,16 @@
  * The paper's interface is compute(A); Q^T b; R.solve(Q^T b) (Section 5.1).  Because
  * the step always knows b, "compute" and "Q^T b" are fused into qrk_factor_*: b rides
  * through the factorisation as one more column and Q is never stored.
- * "R.solve" (plus optional refinement) is qrk_solve.
+ * "R.solve" (plus optional refinement) is qrk_solve; a new right-hand side with the same
+ * factor is qrk_solve_rhs (with J and the kept R, since Q is not stored).
  *
  * Conventions for every function below
  *   - Array arguments are DEVICE pointers unless marked [host].  The caller owns
  *     every buffer it passes.  The handle owns its workspace (R factors, coupling
  *     rows, TSQR partials, refinement scratch, status word).
  *   - A handle BORROWS the J, b and d buffers given to qrk_factor_*: qrk_solve with
- *     sweeps > 0 and qrk_solve_adjoint read them again, so they must stay alive and
- *     unchanged until the next factor call or qrk_destroy.
+ *     sweeps > 0, qrk_solve_rhs and qrk_solve_adjoint read them again, so they must stay
+ *     alive and unchanged until the next factor call or qrk_destroy.
  *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).  Calls
  *     after create only enqueue work on that stream and never synchronise, except
  *     qrk_status_get and qrk_get_factor.
