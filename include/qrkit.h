@@ -198,7 +198,7 @@ qrk_status qrk_solve(qrk_handle h, double* p, int32_t sweeps, void* stream);
  *       r = b - J p,  g = J^T r - lambda D^2 p,  R^T R delta = g,  p <- p + delta.
  *   The first sweep gives the semi-normal solution R^{-1} R^{-T} J^T b; each further sweep
  *   reduces the error by about cond(J) times the factor's relative accuracy (float32
- *   factors: two to four sweeps reach 1e-10 at cond(J) <= 1e3).
+ *   factors, fp32 or BF16x3 updates: four sweeps reach 1e-10 at cond(J) <= 1e3).
  *   b: device, the layout and type of the factor call's b (block-angular [M] stacked over
  *   the problems, banded [P][M]); p [N] double (block-angular: sum_p N_p; banded: P * N),
  *   written.  Neither the handle's borrowed b nor its factor is changed: qrk_solve still
@@ -251,8 +251,10 @@ qrk_status qrk_status_get(qrk_handle h, int32_t* detail_host, void* stream);
 /* Set the launch shape of the dense-part leaves of a single-problem handle (0 = library
  * default): number of leaves (at most 4096 for float32 handles, 1024 for float64 ones) and,
  * for float64 handles, the tree fan-in.
- * Not capturable (it may reallocate the merge-tree workspace).  QRK_EINVAL for
- * out-of-range values or a batched handle. */
+ * Not capturable (it may reallocate the merge-tree workspace).  Synchronises the device
+ * first (no earlier work on any stream may still read the leaf tables it rewrites).  An LM
+ * driver graph captured on this handle before the call is captured again at its next
+ * qrk_lm_run.  QRK_EINVAL for out-of-range values or a batched handle. */
 qrk_status qrk_set_tsqr_shape(qrk_handle h, int32_t leaves, int32_t fanin);
 
 /* ------------------------------------------------------------------------------
@@ -263,7 +265,9 @@ qrk_status qrk_set_tsqr_shape(qrk_handle h, int32_t leaves, int32_t fanin);
  *   handle is left factored with the chosen shape.  Choices are remembered in the
  *   process by batch shape (sum of rows, P, n, widest dense part), so a later handle of
  *   the same shape starts from the remembered choice.  *scale_host [host, may be NULL]
- *   receives the chosen scale.  QRK_EINVAL before any factor call.
+ *   receives the chosen scale.  Synchronises the device first, like qrk_set_tsqr_shape, and
+ *   an LM driver graph captured on this handle before the call is captured again at its
+ *   next qrk_lm_run.  QRK_EINVAL before any factor call.
  * ------------------------------------------------------------------------------ */
 qrk_status qrk_autotune_blockangular(qrk_handle h, double* scale_host, void* stream);
 
@@ -318,6 +322,23 @@ void qrk_lm_destroy(qrk_lm lm);
 #define QRK_NPHASES 6
 qrk_status qrk_profile_enable(qrk_handle h, int32_t max_calls);
 qrk_status qrk_profile_read(qrk_handle h, double* ms_host, int32_t* count_host, int32_t nphase);
+
+/* ------------------------------------------------------------------------------
+ * Self-check entry points (for parity tests of the BF16x3 mode).  They expose, one at a
+ * time, the device primitives of the dense-part trailing updates C <- C - V (T^T (V^T C))
+ * (Section 2, compact WY) in QRK_BF16X3 mode, where every fp32 operand x is split as
+ * hi = bf16(x), lo = bf16(x - hi) (round to nearest even) and a*b is formed as
+ * hi*hi' + hi*lo' + lo*hi' on the bf16 matrix cores with fp32 accumulation.
+ * qrk_check_bf16_split: x [n] float (device, read); hi, lo [n] float (device, written; the
+ *   bf16 values widened exactly to float).  n >= 0.  QRK_EINVAL for n < 0 or null pointers.
+ * qrk_check_bf16x3_product: C = A B with A [16 x k] and B [k x 16] float row-major (device,
+ *   read) and C [16 x 16] float (device, written), with the kernels' operand layout and
+ *   product order (hi*hi' in one accumulator, hi*lo' then lo*hi' in a second, summed at the
+ *   end).  32 <= k <= 4096, k a multiple of 32, else QRK_EINVAL.
+ * Both are stream-ordered and allocate nothing; the caller owns every buffer.
+ * ------------------------------------------------------------------------------ */
+qrk_status qrk_check_bf16_split(const float* x, float* hi, float* lo, int64_t n, void* stream);
+qrk_status qrk_check_bf16x3_product(const float* A, const float* B, float* C, int32_t k, void* stream);
 
 /* Device workspace held by the handle, in bytes. */
 int64_t qrk_workspace_bytes(qrk_handle h);

@@ -34,6 +34,8 @@ __device__ __forceinline__ double lm_dphi(double t, double c) { return 1.0 + 3.0
 // JAC: writes A = A0 diag(phi'(u_blk)), B = B0 diag(phi'(u_B)), b = -f, the block columns'
 //      d and J^T f, and per-workgroup partials of sum_r B_rj^2, sum_r B_rj f_r and sum_r f_r^2.
 // !JAC: only the partial of sum_r f_r^2, at u = x + p.
+// sum_r f_r^2 is written per pack (fpart[pack]), in the same order in both passes whatever the
+// waves per workgroup, so that F and F_new of the same point agree bit for bit.
 // ---------------------------------------------------------------------------------------
 template <typename T, bool JAC>
 __global__ void __launch_bounds__(JAC ? 256 : 512)
@@ -53,7 +55,6 @@ k_lmba_eval(const ProbDesc* __restrict__ probs, const int32_t* __restrict__ wg_p
   __shared__ double av[JAC ? WG : 1][64][8];
   __shared__ int rowblk[WG][64];
   __shared__ double red2[JAC ? WG : 1][kMaxDense], redf[JAC ? WG : 1][kMaxDense];
-  __shared__ double fred[WG];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int pi = wg_prob[blockIdx.x];
@@ -141,7 +142,7 @@ k_lmba_eval(const ProbDesc* __restrict__ probs, const int32_t* __restrict__ wg_p
         }
         f += acc - (double)y[row];
         rr[wv][r] = f;
-        fsq += f * f;
+        fsq += f * f;  // lane qi: rows qi, qi + 16, ... of this pack, in order
         if (JAC) b[row] = (T)(-f);
       }
       wave_lds_sync();
@@ -189,12 +190,14 @@ k_lmba_eval(const ProbDesc* __restrict__ probs, const int32_t* __restrict__ wg_p
         }
       }
     }
+    // the pack's sum of f^2: butterfly across the wave (every lane ends with the same bits)
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) fsq += __shfl_xor(fsq, off, 64);
+    if (lane == 0) fpart[pk] = fsq;
+    fsq = 0.0;
     wave_lds_sync();
   }
-  // fixed-order reductions: across the wave (butterfly), then the workgroup's waves in order
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) fsq += __shfl_xor(fsq, off, 64);
-  if (lane == 0) fred[wv] = fsq;
+  // fixed-order reduction of the column sums: the workgroup's waves in order
   if constexpr (JAC) {
     red2[wv][lane] = s2a;
     red2[wv][lane + 64] = s2b;
@@ -215,16 +218,10 @@ k_lmba_eval(const ProbDesc* __restrict__ probs, const int32_t* __restrict__ wg_p
       pw[kMaxDense + j] = af;
     }
   }
-  if (threadIdx.x == 0) {
-    double fs = fred[0];
-#pragma unroll
-    for (int w = 1; w < WG; ++w) fs += fred[w];
-    fpart[blockIdx.x] = fs;
-  }
 }
 
 // Per problem (one workgroup each): the dense columns' d and J^T f from the workgroup
-// partials (JAC), and F = sum f^2 / 2 into Fout[p].
+// partials (JAC), and F = sum f^2 / 2 into Fout[p] from the per-pack partials.
 template <bool JAC>
 __global__ void __launch_bounds__(1024)
 k_lmba_reduce(const ProbDesc* __restrict__ probs, int n, const double* __restrict__ part,
@@ -267,7 +264,7 @@ k_lmba_reduce(const ProbDesc* __restrict__ probs, int n, const double* __restric
     sf_all[seg][j] = sf;
   }
   double fs = 0.0;
-  for (int64_t w = w0 + t; w < w0 + nw; w += 1024) fs += fpart[w];
+  for (int64_t k = P.pack0 + t; k < P.pack0 + P.npacks; k += 1024) fs += fpart[k];
   red[t] = fs;
   __syncthreads();
   if (JAC && seg == 0 && j < P.nB) {

@@ -41,6 +41,7 @@ struct qrk_lm_s {
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  uint64_t shape_gen = 0;  // the handle's leaf-layout generation the graph was captured with
 };
 
 namespace {
@@ -206,7 +207,7 @@ qrk_status qrk_lm_create_blockangular(qrk_handle h, const void* A0, const void* 
       (s = lm_alloc(lm, &lm->B, es * (size_t)btot)) != QRK_OK ||
       (s = lm_alloc(lm, &lm->b, es * (size_t)h->M)) != QRK_OK ||
       (s = lm_alloc(lm, &lm->part, sizeof(double) * (size_t)h->nwg * 2 * kMaxDense)) != QRK_OK ||
-      (s = lm_alloc(lm, &lm->fpart, sizeof(double) * (size_t)h->nwg)) != QRK_OK ||
+      (s = lm_alloc(lm, &lm->fpart, sizeof(double) * (size_t)std::max<int64_t>(h->npacks, 1))) != QRK_OK ||
       (s = lm_alloc_common(lm, noff)) != QRK_OK) {
     lm_free(lm);
     delete lm;
@@ -273,8 +274,18 @@ qrk_status qrk_lm_run(qrk_lm lm, int32_t iters, int32_t use_graph, void* stream)
     }
     return QRK_OK;
   }
+  if (lm->exec && lm->shape_gen != h->shape_gen) {
+    // the leaf layout changed since the capture (qrk_set_tsqr_shape / qrk_autotune_blockangular):
+    // the graph holds the old launch geometry and workspace pointers, so capture again
+    if (hipStreamSynchronize(st) != hipSuccess) return QRK_EHIP;
+    (void)hipGraphExecDestroy(lm->exec);
+    (void)hipGraphDestroy(lm->graph);
+    lm->exec = nullptr;
+    lm->graph = nullptr;
+  }
   if (!lm->exec) {
     // capture one iteration on the driver's own stream (phase timing off: no event nodes)
+    lm->shape_gen = h->shape_gen;
     const bool prof = h->prof_on;
     h->prof_on = false;
     if (hipStreamBeginCapture(lm->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {

@@ -66,7 +66,9 @@ struct qrk_handle_s {
   double* lam_d = nullptr;       // owned damping of a single-problem factor call
   const double* lam_ptr = nullptr;  // damping the kernels read ([P], device)
 
-  // launch shape
+  // launch shape; shape_gen counts the changes of the dense-part leaf layout (device tables and
+  // workspace pointers), so that a graph captured before a change is re-captured
+  uint64_t shape_gen = 0;
   int grid_blocks = 1;
   int refine_grid = 1;
   int leaves = 1;

@@ -348,6 +348,7 @@ qrk_status assign_leaves(qrk_handle h) {
   }
   if (hipMemcpy(h->probs_d, pd.data(), sizeof(ProbDesc) * P, hipMemcpyHostToDevice) != hipSuccess)
     return QRK_EHIP;
+  ++h->shape_gen;
   return QRK_OK;
 }
 
@@ -834,6 +835,9 @@ qrk_status qrk_status_get_problems(qrk_handle h, int32_t* bits_host, void* strea
 qrk_status qrk_set_tsqr_shape(qrk_handle h, int32_t leaves, int32_t fanin) {
   if (!h || leaves < 0 || fanin < 0 || fanin == 1 || fanin > 64) return QRK_EINVAL;
   if (h->kind != KIND_BLOCKANGULAR || h->P != 1 || leaves > h->max_leaves) return QRK_EINVAL;
+  // the leaf tables and the merge-tree workspace are rewritten (and may be reallocated) below,
+  // so nothing that reads them may still be in flight on any stream
+  if (hipDeviceSynchronize() != hipSuccess) return QRK_EHIP;
   h->leaves = leaves;
   h->fanin = fanin ? fanin : 8;
   return assign_leaves(h);
@@ -842,6 +846,8 @@ qrk_status qrk_set_tsqr_shape(qrk_handle h, int32_t leaves, int32_t fanin) {
 qrk_status qrk_autotune_blockangular(qrk_handle h, double* scale_host, void* stream) {
   if (!h || h->kind != KIND_BLOCKANGULAR || !h->factored || h->dtype != QRK_F32) return QRK_EINVAL;
   hipStream_t st = S(stream);
+  // as in qrk_set_tsqr_shape: no earlier work on any stream may still read the leaf tables
+  if (hipDeviceSynchronize() != hipSuccess) return QRK_EHIP;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return QRK_EHIP;
   if (hipEventCreate(&e1) != hipSuccess) {

@@ -61,6 +61,8 @@ _SIGS = {
     "qrk_workspace_bytes": (_c_i64, [_c_vp]),
     "qrk_profile_enable": (_c_i32, [_c_vp, _c_i32]),
     "qrk_profile_read": (_c_i32, [_c_vp, ctypes.POINTER(_c_dbl), _c_i32p, _c_i32]),
+    "qrk_check_bf16_split": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_i64, _c_vp]),
+    "qrk_check_bf16x3_product": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_i32, _c_vp]),
     "qrk_destroy": (None, [_c_vp]),
     "qrk_strerror": (ctypes.c_char_p, [_c_i32]),
 }
@@ -162,9 +164,10 @@ class Factor:
                                _stream_ptr(stream)), "qrk_solve")
         return out
 
-    def solve_rhs(self, b, sweeps: int = 3, out=None, stream=None):
+    def solve_rhs(self, b, sweeps: int = 4, out=None, stream=None):
         """The step for a new right-hand side b (same J, d, lambda as the last factor), by
-        `sweeps` corrected semi-normal sweeps from p = 0 with the stored R; p float64 [N]."""
+        `sweeps` corrected semi-normal sweeps from p = 0 with the stored R; p float64 [N].
+        Four sweeps reach 1e-10 for float32 factors at cond(J) <= 1e3."""
         torch = _torch()
         if out is None:
             out = torch.empty(self.N, dtype=torch.float64, device="cuda")
@@ -475,3 +478,30 @@ class LMDriver:
                                 _dev_ptr(log, torch.float64, "log"), ctypes.byref(it), _stream_ptr(stream)),
                "qrk_lm_get")
         return x, lam, log[:self.max_log], int(it.value)
+
+
+def check_bf16_split(x, stream=None):
+    """(hi, lo) of every float32 element of x by the dense-part kernels' BF16x3 split
+    (qrk_check_bf16_split)."""
+    torch = _torch()
+    n = x.numel()
+    hi = torch.empty_like(x)
+    lo = torch.empty_like(x)
+    _check(lib().qrk_check_bf16_split(_dev_ptr(x, torch.float32, "x"), _dev_ptr(hi, torch.float32, "hi"),
+                                      _dev_ptr(lo, torch.float32, "lo"), n, _stream_ptr(stream)),
+           "qrk_check_bf16_split")
+    return hi, lo
+
+
+def check_bf16x3_product(A, B, stream=None):
+    """C = A B (A 16 x k, B k x 16, float32) by the dense-part kernels' BF16x3 matrix-core
+    product (qrk_check_bf16x3_product)."""
+    torch = _torch()
+    k = A.shape[1]
+    if A.shape != (16, k) or B.shape != (k, 16):
+        raise ValueError("A must be 16 x k and B k x 16")
+    C = torch.empty((16, 16), dtype=torch.float32, device=A.device)
+    _check(lib().qrk_check_bf16x3_product(_dev_ptr(A, torch.float32, "A"), _dev_ptr(B, torch.float32, "B"),
+                                          _dev_ptr(C, torch.float32, "C"), k, _stream_ptr(stream)),
+           "qrk_check_bf16x3_product")
+    return C

@@ -44,6 +44,23 @@ def rel_err(p, p_ref):
     return float(np.linalg.norm(p - p_ref) / np.linalg.norm(p_ref))
 
 
+def scaled_err(p, p_ref, d):
+    """Largest componentwise error with each unknown weighted by its column scale d_j
+    (the column 2-norm of J): max_j d_j |p_j - p_ref_j| / max_j d_j |p_ref_j|.  Under
+    column scalings of 10^(k t) the unknowns with large scales are tiny, so the 2-norm error
+    alone could miss them; weighted by d they count as much as the others."""
+    p = np.asarray(p, np.float64)
+    p_ref = np.asarray(p_ref, np.float64)
+    d = np.asarray(d, np.float64)
+    return float(np.max(d * np.abs(p - p_ref)) / np.max(d * np.abs(p_ref)))
+
+
+def p_err(p, p_ref, d):
+    """The larger of the relative 2-norm error and the column-scaled componentwise error;
+    a parity bound on p holds for both measures."""
+    return max(rel_err(p, p_ref), scaled_err(p, p_ref, d))
+
+
 def sign_fix_rows(R, *extra):
     """Flip rows of R (and of the extra arrays) so that diag(R) >= 0."""
     R = np.asarray(R, np.float64)

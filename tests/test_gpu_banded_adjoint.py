@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 from oracle import adjoint, banded, dense, refine, structured
-from tests.gpu_util import log, rel_err, sign_fix_rows, to_device
+from tests.gpu_util import p_err, log, rel_err, sign_fix_rows, to_device
 from workloads import generators as gen
 
 pytestmark = pytest.mark.gpu
@@ -40,7 +40,7 @@ def test_banded_small(w, dtype):
     p, st, solver, _ = _banded_solve([inst])
     assert st[0] == 0, st
     tol = 1e-12 if dtype == np.float64 else 1e-5
-    assert rel_err(p[0], p_ref) <= tol
+    assert p_err(p[0], p_ref, inst.d) <= tol
     Rb, c = [t.cpu().numpy().astype(np.float64) for t in solver.get_factor()]
     R = np.zeros((inst.N, inst.N))
     for j in range(inst.N):
@@ -52,7 +52,7 @@ def test_banded_small(w, dtype):
     assert np.abs(Rg - Ro).max() <= ftol * np.abs(Ro).max()
     assert np.abs(cg - co).max() <= ftol * max(np.abs(co).max(), np.abs(Ro).max())
     p2, st, _, _ = _banded_solve([inst], sweeps=2)
-    assert rel_err(p2[0], p_ref) <= 1e-10
+    assert p_err(p2[0], p_ref, inst.d) <= 1e-10
 
 
 def test_banded_batch_and_refine():
@@ -63,8 +63,8 @@ def test_banded_batch_and_refine():
     p2, st, _, _ = _banded_solve(insts, sweeps=2)
     for k, inst in enumerate(insts):
         p_ref, _, _ = banded.reference_solution(inst)
-        assert rel_err(p0[k], p_ref) <= 1e-5
-        assert rel_err(p2[k], p_ref) <= 1e-10
+        assert p_err(p0[k], p_ref, inst.d) <= 1e-5
+        assert p_err(p2[k], p_ref, inst.d) <= 1e-10
 
 
 def test_banded_full_size_sampled():
@@ -78,8 +78,8 @@ def test_banded_full_size_sampled():
     for k in (0, 777, 2047):
         log(f"banded full size: oracle problem {k}")
         p_ref, _, _ = banded.reference_solution(insts[k])
-        assert rel_err(p0[k], p_ref) <= 1e-5
-        assert rel_err(p1[k], p_ref) <= 1e-10
+        assert p_err(p0[k], p_ref, insts[k].d) <= 1e-5
+        assert p_err(p1[k], p_ref, insts[k].d) <= 1e-10
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
@@ -96,8 +96,8 @@ def test_banded_row_patterns(rows_per_col, w, dtype):
     tol = 1e-12 if dtype == np.float64 else 1e-5
     for k, inst in enumerate(insts):
         p_ref, _, _ = banded.reference_solution(inst)
-        assert rel_err(p0[k], p_ref) <= tol
-        assert rel_err(p2[k], p_ref) <= 1e-10
+        assert p_err(p0[k], p_ref, inst.d) <= tol
+        assert p_err(p2[k], p_ref, inst.d) <= 1e-10
 
 
 def _custom_banded(seed, N, w, row_start, lam, dtype):
@@ -135,8 +135,8 @@ def test_banded_edge_shapes(case, dtype):
     tol = 1e-12 if dtype == np.float64 else 1e-5
     for k, inst in enumerate(insts):
         p_ref, _, _ = banded.reference_solution(inst)
-        assert rel_err(p0[k], p_ref) <= tol
-        assert rel_err(p2[k], p_ref) <= 1e-10
+        assert p_err(p0[k], p_ref, inst.d) <= tol
+        assert p_err(p2[k], p_ref, inst.d) <= 1e-10
 
 
 def test_banded_many_small_problems():
@@ -148,8 +148,8 @@ def test_banded_many_small_problems():
     p1 = solver.solve(sweeps=1).cpu().numpy().reshape(4100, -1)
     for k in (0, 1, 2049, 4099):
         p_ref, _, _ = banded.reference_solution(insts[k])
-        assert rel_err(p0[k], p_ref) <= 1e-5
-        assert rel_err(p1[k], p_ref) <= 1e-10
+        assert p_err(p0[k], p_ref, insts[k].d) <= 1e-5
+        assert p_err(p1[k], p_ref, insts[k].d) <= 1e-10
 
 
 def test_banded_bad_row_start_is_reported():

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from oracle import refine, structured
-from tests.gpu_util import gpu_solve_blockangular, log, rel_err, sign_fix_rows
+from tests.gpu_util import p_err, gpu_solve_blockangular, log, rel_err, sign_fix_rows
 from workloads import generators as gen
 
 pytestmark = pytest.mark.gpu
@@ -37,7 +37,7 @@ def test_tiny_float64(seed):
     p_ref, f = refine.reference_solution(inst)
     p, st, solver, _ = gpu_solve_blockangular(inst, return_solver=True)
     assert st[0] == 0
-    assert rel_err(p, p_ref) <= 1e-12
+    assert p_err(p, p_ref, inst.d) <= 1e-12
     _check_factor(inst, solver, f, 1e-12)
 
 
@@ -48,10 +48,10 @@ def test_tiny_float32_unrefined_and_refined(seed):
     p_ref, f = refine.reference_solution(inst)
     p0, st, solver, _ = gpu_solve_blockangular(inst, return_solver=True)
     assert st[0] == 0
-    assert rel_err(p0, p_ref) <= 1e-5
+    assert p_err(p0, p_ref, inst.d) <= 1e-5
     _check_factor(inst, solver, f, 2e-5)
     p2, st = gpu_solve_blockangular(inst, sweeps=2)
-    assert rel_err(p2, p_ref) <= 1e-10
+    assert p_err(p2, p_ref, inst.d) <= 1e-10
 
 
 SHAPES = [
@@ -84,10 +84,10 @@ def test_shapes(shape, dtype):
     p, st, solver, _ = gpu_solve_blockangular(inst, return_solver=True)
     assert st[0] == 0, st
     tol = 1e-11 if dtype == np.float64 else 1e-5
-    assert rel_err(p, p_ref) <= tol
+    assert p_err(p, p_ref, inst.d) <= tol
     _check_factor(inst, solver, f, 1e-11 if dtype == np.float64 else 5e-5)
     p2, st = gpu_solve_blockangular(inst, sweeps=2)
-    assert rel_err(p2, p_ref) <= 1e-10
+    assert p_err(p2, p_ref, inst.d) <= 1e-10
 
 
 def test_tsqr_launch_shapes_agree():
@@ -98,7 +98,7 @@ def test_tsqr_launch_shapes_agree():
         log(f"tsqr leaves={leaves} fanin={fanin}")
         p, st = gpu_solve_blockangular(inst, leaves=leaves, fanin=fanin)
         assert st[0] == 0
-        assert rel_err(p, p_ref) <= 1e-12
+        assert p_err(p, p_ref, inst.d) <= 1e-12
 
 
 @pytest.mark.parametrize("nB", [95, 100, 111, 112, 120, 127])
@@ -111,7 +111,7 @@ def test_wide_dense_part_multi_leaf_trees(nB):
         log(f"nB={nB} leaves={leaves}")
         p, st = gpu_solve_blockangular(inst, leaves=leaves)
         assert st[0] == 0, st
-        assert rel_err(p, p_ref) <= 1e-5
+        assert p_err(p, p_ref, inst.d) <= 1e-5
 
 
 @pytest.mark.parametrize("mode", ["plain", "bf16x3"])
@@ -129,10 +129,10 @@ def test_pipelined_tree_every_width(nB, mode):
         log(f"pipelined tree nB={nB} mode={mode} leaves={leaves}")
         p, st, solver, _ = gpu_solve_blockangular(inst, mode=mode, leaves=leaves, return_solver=True)
         assert st[0] == 0, st
-        assert rel_err(p, p_ref) <= 1e-5
+        assert p_err(p, p_ref, inst.d) <= 1e-5
         _check_factor(inst, solver, f, 5e-5)
         p2, st = gpu_solve_blockangular(inst, mode=mode, leaves=leaves, sweeps=2)
-        assert rel_err(p2, p_ref) <= 1e-10
+        assert p_err(p2, p_ref, inst.d) <= 1e-10
 
 
 @pytest.mark.parametrize("lam", [1e-2, 0.0])
@@ -151,9 +151,11 @@ def test_few_rows_per_leaf(nB, lam):
         p, st = gpu_solve_blockangular(inst, leaves=leaves)
         assert st[0] == 0, st
         assert np.isfinite(p).all()
-        assert rel_err(p, p_ref) <= 1e-4
+        e0 = p_err(p, p_ref, inst.d)
+        log(f"  unrefined error {e0:.2e} (rel {rel_err(p, p_ref):.2e})")
+        assert e0 <= 1e-5
         p1, st = gpu_solve_blockangular(inst, leaves=leaves, sweeps=2)
-        assert rel_err(p1, p_ref) <= 1e-10
+        assert p_err(p1, p_ref, inst.d) <= 1e-10
 
 
 def test_lambda_zero_gauss_newton():
@@ -163,7 +165,7 @@ def test_lambda_zero_gauss_newton():
     p_ref, _ = refine.reference_solution(inst)
     p, st = gpu_solve_blockangular(inst)
     assert st[0] == 0
-    assert rel_err(p, p_ref) <= 1e-11
+    assert p_err(p, p_ref, inst.d) <= 1e-11
 
 
 def test_singular_block_is_reported():
@@ -192,7 +194,7 @@ def test_deterministic_repeat():
     assert np.array_equal(p1, p2)
 
 
-@pytest.mark.parametrize("lam", [1e-2, 0.0])
+@pytest.mark.parametrize("lam", [1e-2, 0.0, 1e-4, 1.0])
 def test_scale_workload_full_size(lam):
     """50,000 blocks of 12x3 with a 600,000 x 90 dense part (column scales 10^(3t)), in the
     launch configuration the benchmark times: unrefined <= 1e-5, one sweep <= 1e-10."""
@@ -203,15 +205,15 @@ def test_scale_workload_full_size(lam):
     log("gpu")
     p0, st, solver, dev = gpu_solve_blockangular(inst, return_solver=True)
     assert st[0] == 0
-    e0 = rel_err(p0, p_ref)
+    e0 = p_err(p0, p_ref, inst.d)
     log(f"unrefined rel err {e0:.3e}")
     assert e0 <= 1e-5
     p1 = solver.solve(sweeps=1).cpu().numpy()
-    e1 = rel_err(p1, p_ref)
+    e1 = p_err(p1, p_ref, inst.d)
     log(f"1 sweep rel err {e1:.3e}")
     assert e1 <= 1e-10
     p2 = solver.solve(sweeps=2).cpu().numpy()
-    assert rel_err(p2, p_ref) <= 1e-10
+    assert p_err(p2, p_ref, inst.d) <= 1e-10
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
@@ -232,6 +234,6 @@ def test_every_block_width(n, dtype):
         p, st = gpu_solve_blockangular(inst)
         assert st[0] == 0, st
         tol = 1e-11 if dtype == np.float64 else 1e-5
-        assert rel_err(p, p_ref) <= tol
+        assert p_err(p, p_ref, inst.d) <= tol
         p1, _ = gpu_solve_blockangular(inst, sweeps=2)
-        assert rel_err(p1, p_ref) <= 1e-10
+        assert p_err(p1, p_ref, inst.d) <= 1e-10

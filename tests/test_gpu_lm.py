@@ -113,6 +113,60 @@ def test_lm_graph_replays_match_eager():
     assert np.all(lg_e[:iters, :, 3] >= 0)
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_lm_cost_at_unchanged_point_is_bit_identical(dtype):
+    """With a damping so large that x + p == x in float64, F_new is the cost at the same point
+    as F: the two passes (with and without the Jacobian) sum f^2 in the same order, so the
+    values agree bit for bit and the gain ratio's numerator is exactly zero."""
+    import torch
+    probs = [gen.lm_blockangular(440 + k, K=K, m=10, n=3, nB=nB, c=0.1, dtype=dtype)[:3]
+             for k, (K, nB) in enumerate([(300, 40), (70, 90)])]
+    drv, bt, x0d, _ = _setup(probs, dtype, 0.1, sweeps=1)
+    drv.reset(x0d, torch.tensor([1e30, 1e30], dtype=torch.float64, device="cuda"))
+    drv.run(1)
+    x, _, lg, done = drv.get()
+    lg = lg.cpu().numpy()
+    assert done == 1
+    assert np.array_equal(x.cpu().numpy(), x0d.cpu().numpy())  # rejected: x unchanged
+    for q in range(2):
+        log(f"problem {q}: F = {lg[0, q, 0]!r}, F_new = {lg[0, q, 1]!r}")
+        assert lg[0, q, 0] == lg[0, q, 1]
+        assert lg[0, q, 3] == 0.0
+
+
+def test_lm_graph_recaptured_after_leaf_shape_change():
+    """A graph captured with one dense-part leaf layout, then qrk_set_tsqr_shape moves to another
+    (new leaf tables, possibly new merge-tree workspace): the next graph run captures again, and
+    its iterations match eager iterations under the new layout bit for bit."""
+    import torch
+    from paper_1802_03773_amd import BlockAngularSolver, LMDriver
+    inst0, y, x0, _ = gen.lm_blockangular(430, K=120, m=10, n=3, nB=40, c=0.1, dtype=np.float32)
+    A0 = torch.from_numpy(inst0.A).cuda()
+    B0 = torch.from_numpy(inst0.B).cuda()
+    yd = torch.from_numpy(y).cuda()
+    x0d = torch.from_numpy(x0).cuda()
+    lam0 = torch.tensor([1e-2], dtype=torch.float64, device="cuda")
+    s = BlockAngularSolver(inst0.row_off, inst0.n, inst0.nB, dtype="float32")
+    s.set_tsqr_shape(2)
+    drv = LMDriver(s, A0, B0, yd, 0.1, sweeps=1, max_log=8)
+    drv.reset(x0d, lam0)
+    drv.run(3, graph=True)  # captured with two leaves
+    torch.cuda.synchronize()
+    s.set_tsqr_shape(9)  # more leaves: more slots, counters and tree nodes
+    drv.reset(x0d, lam0)
+    drv.run(4, graph=True)
+    x_g, lam_g, lg_g, done = drv.get()
+    assert done == 4
+    drv.reset(x0d, lam0)
+    drv.run(4, graph=False)
+    x_e, lam_e, lg_e, _ = drv.get()
+    assert np.array_equal(x_g.cpu().numpy(), x_e.cpu().numpy())
+    assert np.array_equal(lg_g.cpu().numpy(), lg_e.cpu().numpy())
+    xo, _, lgo = _oracle_run((inst0, y, x0), 0.1, 1e-2, 4, np.float32)
+    k = _significant(lgo)
+    np.testing.assert_allclose(lg_g.cpu().numpy()[:k, 0, :3], lgo[:k, :3], rtol=1e-5)
+
+
 def _setup_banded(problems, dtype, c, sweeps=2, max_log=32):
     import torch
     from paper_1802_03773_amd import BandedSolver, LMDriver
