@@ -56,7 +56,9 @@ typedef enum {
   QRK_EHIP = 3,          /* a HIP runtime call failed                              */
   QRK_ESINGULAR = 4,     /* a pivot of R is (numerically) zero; p is undefined     */
   QRK_ENONFINITE = 5,    /* NaN or Inf met in the inputs or the factor             */
-  QRK_ENODEVICE = 6      /* no usable gfx950 device                                */
+  QRK_ENODEVICE = 6,     /* no usable gfx950 device                                */
+  QRK_ETOOLARGE = 7      /* the request does not fit the fixed scratch array of
+                            qrk_solve_banded_noalloc; nothing was enqueued          */
 } qrk_status;
 
 typedef enum { QRK_F32 = 0, QRK_F64 = 1 } qrk_dtype;
@@ -322,6 +324,31 @@ void qrk_lm_destroy(qrk_lm lm);
 #define QRK_NPHASES 6
 qrk_status qrk_profile_enable(qrk_handle h, int32_t max_calls);
 qrk_status qrk_profile_read(qrk_handle h, double* ms_host, int32_t* count_host, int32_t nphase);
+
+/* ------------------------------------------------------------------------------
+ * qrk_solve_banded_noalloc  (for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc)
+ *   The banded step of qrk_create_banded_batched + qrk_factor_banded + qrk_solve in one call
+ *   without a handle: Givens QR of [J; sqrt(lambda) D] for P stacked problems (M rows, N
+ *   columns, w values per row), back-substitution and `sweeps` (0..8) float64-residual
+ *   sweeps, with the same kernels and the same results.  Arguments as for those calls:
+ *   row_start [P][M] int32, vals [P][M][w] T, b [P][M] T, d [P][N] double, lambda >= 0 (one
+ *   value for every problem), p [P][N] double (written); status_dev [device, int32, 1, may be
+ *   NULL] receives the status bits of qrk_status_get (1 singular, 2 non-finite, 4 bad row
+ *   start).  The caller owns every buffer.
+ *   No memory is allocated: the factor, the sweep buffers and the status word live in one
+ *   fixed device array of QRK_NOALLOC_SCRATCH_BYTES per GPU, held from the library's first
+ *   call on that GPU until the process ends.  A request whose workspace (about
+ *   P N ((w + 17) sizeof(T) + 20) + 8 P M bytes) does not fit returns QRK_ETOOLARGE before
+ *   anything is enqueued.  All calls on one GPU share the array: calls that overlap in time
+ *   on that GPU (different streams or threads) race and must be serialised by the caller.
+ *   Stream-ordered; never synchronises.  QRK_EINVAL for the argument errors of the calls it
+ *   replaces; QRK_ENODEVICE on a device that is not gfx950.
+ * ------------------------------------------------------------------------------ */
+#define QRK_NOALLOC_SCRATCH_BYTES (32ll << 20)
+qrk_status qrk_solve_banded_noalloc(int32_t P, int64_t M, int64_t N, int32_t w, qrk_dtype dtype,
+                                    const int32_t* row_start, const void* vals, const void* b, const double* d,
+                                    double lambda, double* p, int32_t sweeps, int32_t* status_dev, void* stream);
 
 /* ------------------------------------------------------------------------------
  * Self-check entry points (for parity tests of the BF16x3 mode).  They expose, one at a

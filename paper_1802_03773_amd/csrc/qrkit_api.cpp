@@ -608,6 +608,7 @@ const char* qrk_strerror(qrk_status s) {
     case QRK_ESINGULAR: return "R has a numerically zero pivot";
     case QRK_ENONFINITE: return "non-finite value in inputs or factor";
     case QRK_ENODEVICE: return "no gfx950 device available";
+    case QRK_ETOOLARGE: return "request exceeds the fixed scratch array of the no-allocation entry point";
   }
   return "unknown status";
 }

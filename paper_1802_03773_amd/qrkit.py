@@ -22,7 +22,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "lib", "libqrkit.so")
 HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "qrkit.h")
 
-QRK_OK, QRK_EINVAL, QRK_ENOMEM, QRK_EHIP, QRK_ESINGULAR, QRK_ENONFINITE, QRK_ENODEVICE = range(7)
+QRK_OK, QRK_EINVAL, QRK_ENOMEM, QRK_EHIP, QRK_ESINGULAR, QRK_ENONFINITE, QRK_ENODEVICE, QRK_ETOOLARGE = range(8)
+NOALLOC_SCRATCH_BYTES = 32 << 20
 QRK_F32, QRK_F64 = 0, 1
 QRK_PLAIN, QRK_BF16X3 = 0, 1
 MAX_BLOCK_COLS, MAX_BLOCK_ROWS, MAX_DENSE_COLS, MAX_BAND = 8, 56, 127, 31
@@ -63,6 +64,8 @@ _SIGS = {
     "qrk_profile_read": (_c_i32, [_c_vp, ctypes.POINTER(_c_dbl), _c_i32p, _c_i32]),
     "qrk_check_bf16_split": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_i64, _c_vp]),
     "qrk_check_bf16x3_product": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_i32, _c_vp]),
+    "qrk_solve_banded_noalloc": (_c_i32, [_c_i32, _c_i64, _c_i64, _c_i32, _c_i32, _c_vp, _c_vp, _c_vp, _c_vp,
+                                          _c_dbl, _c_vp, _c_i32, _c_vp, _c_vp]),
     "qrk_destroy": (None, [_c_vp]),
     "qrk_strerror": (ctypes.c_char_p, [_c_i32]),
 }
@@ -505,3 +508,24 @@ def check_bf16x3_product(A, B, stream=None):
                                           _dev_ptr(C, torch.float32, "C"), k, _stream_ptr(stream)),
            "qrk_check_bf16x3_product")
     return C
+
+
+def solve_banded_noalloc(row_start, vals, b, d, lam: float, N: int, sweeps: int = 0, p=None, status=None,
+                         stream=None):
+    """The banded step of factor_banded + solve in one call that allocates no device memory
+    (qrk_solve_banded_noalloc).  row_start [P, M] int32, vals [P, M, w], b [P, M], d [P, N]
+    float64; p [P * N] float64 and status [1] int32 may be given (device tensors)."""
+    torch = _torch()
+    P, M = int(row_start.shape[0]), int(row_start.shape[1])
+    w = int(vals.shape[-1])
+    qd = QRK_F32 if vals.dtype == torch.float32 else QRK_F64
+    td = _torch_dtype(qd)
+    if p is None:
+        p = torch.empty(P * int(N), dtype=torch.float64, device=vals.device)
+    _check(lib().qrk_solve_banded_noalloc(
+        P, M, int(N), w, qd, _dev_ptr(row_start, torch.int32, "row_start", P * M), _dev_ptr(vals, td, "vals", P * M * w),
+        _dev_ptr(b, td, "b", P * M), _dev_ptr(d, torch.float64, "d", P * int(N)), float(lam),
+        _dev_ptr(p, torch.float64, "p", P * int(N)), int(sweeps),
+        _dev_ptr(status, torch.int32, "status", 1) if status is not None else None, _stream_ptr(stream)),
+        "qrk_solve_banded_noalloc")
+    return p
