@@ -19,6 +19,8 @@ Modules
   refine     - O-ext: extended-precision (numpy.longdouble) residual refinement
                of an O1/O2 solution; the reference for all parity numbers.
   banded     - banded J (Section 4.4 problem class): dense assembly + O1 / LAPACK.
+  block_banded - the block-banded factorisation of Section 4.4: dense steps over column
+               blocks, each applied in the compressed WY form (Eq. blockBandedYTY).
   adjoint    - gradient of a loss of p* with respect to J, b, lam, d (closed
                form from differentiating Eq. 1).
   bf16       - bit-level emulation of bf16 rounding and the three-product split.
