@@ -79,6 +79,9 @@ def _parse():
                          "problems in one batch; banded-batch: 2,048 banded problems in one batch")
     ap.add_argument("--problems", type=int, default=0, help="batch workloads: problems (0 = the recipe's count)")
     ap.add_argument("--autotune", action="store_true", help="ragged-batch: autotune the leaf shape first")
+    ap.add_argument("--banded-method", default="auto", choices=["auto", "givens", "blockwy", "blockwy-bf16x3"],
+                    help="banded-batch: factorisation (Givens rotations or the block-banded compact-WY steps); "
+                         "auto times every method and reports the fastest")
     return ap.parse_args()
 
 
@@ -152,6 +155,8 @@ def run_batch(args):
         N_p = [i.N for i in insts]
         mode = "plain"
         solver = BandedSolver(i0.M, i0.N, i0.w, dtype="float32", P=P)
+        methods = (["givens", "blockwy", "blockwy-bf16x3"] if args.banded_method == "auto"
+                   else [args.banded_method])
 
         def factor():
             solver.factor(dev["rs"], dev["vals"], dev["b"], dev["d"], args.lam)
@@ -191,22 +196,58 @@ def run_batch(args):
         if args.autotune and ragged:
             factor()
             print(f"[bench] autotune: leaf scale {solver.autotune()}", file=sys.stderr, flush=True)
-        for s_ in range(0, 4):
-            step(s_)
-            torch.cuda.synchronize()
-            x = p.cpu().numpy()
-            errors[s_] = max(float(np.linalg.norm(x[offs[q]:offs[q + 1]] - refs[q]) / np.linalg.norm(refs[q]))
-                             for q in sample)
-    st_ = solver.status()
-    if st_[0] != 0:
-        raise RuntimeError(f"device status {st_}")
-    if args.sweeps >= 0:
-        sweeps = args.sweeps
-    elif errors:
-        ok = [s_ for s_ in sorted(errors) if errors[s_] <= 1e-10]
-        sweeps = ok[0] if ok else 3
-    else:
-        sweeps = 1
+
+    def measure_errors():
+        errs = {}
+        if refs_ok:
+            for s_ in range(0, 4):
+                step(s_)
+                torch.cuda.synchronize()
+                x = p.cpu().numpy()
+                errs[s_] = max(float(np.linalg.norm(x[offs[q]:offs[q + 1]] - refs[q]) / np.linalg.norm(refs[q]))
+                               for q in sample)
+        st_ = solver.status()
+        if st_[0] != 0:
+            raise RuntimeError(f"device status {st_}")
+        if args.sweeps >= 0:
+            sw = args.sweeps
+        elif errs:
+            ok = [s_ for s_ in sorted(errs) if errs[s_] <= 1e-10]
+            sw = ok[0] if ok else 3
+        else:
+            sw = 1
+        return errs, sw
+
+    def time_steps(sw):
+        for _ in range(args.warmup):
+            step(sw)
+        torch.cuda.synchronize()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(args.steps):
+            step(sw)
+        t1.record()
+        torch.cuda.synchronize()
+        return t0.elapsed_time(t1) / args.steps
+
+    refs_ok = not args.no_cpu
+    method_rows = None
+    if not ragged:
+        # every banded method: its errors, sweep count and step time; the fastest is reported
+        method_rows = {}
+        for meth in methods:
+            solver.set_method(meth)
+            errs_m, sw_m = measure_errors()
+            ms_m = time_steps(sw_m)
+            method_rows[meth] = {"ms_per_step": ms_m, "value": P * 1000.0 / ms_m, "refine_sweeps": sw_m,
+                                 "max_rel_err_sampled": errs_m.get(sw_m), "by_sweeps": errs_m}
+            print(f"[bench] banded {meth}: {ms_m:.3f} ms per batched step ({sw_m} sweeps)", file=sys.stderr,
+                  flush=True)
+        best = min(method_rows, key=lambda k: method_rows[k]["ms_per_step"])
+        solver.set_method(best)
+        desc["method"] = best
+        mode = "bf16x3" if best.endswith("bf16x3") else "plain"
+    errors, sweeps = measure_errors()
     for _ in range(args.warmup):
         step(sweeps)
     torch.cuda.synchronize()
@@ -239,7 +280,7 @@ def run_batch(args):
         work = {k: ((b_, a_, PEAK_FP32_VECTOR_TFLOPS, "TFLOP/s", 1e12) if b_ == "alu" else
                     (b_, a_, PEAK_HBM_GBS, "GB/s", 1e9)) for k, (b_, a_) in work.items()}
     else:
-        # Givens factor: J, b, d in; R (N x w) and c out.  One refinement sweep: J, row starts,
+        # banded factor: J, b, d in; R (N x w) and c out.  One refinement sweep: J, row starts,
         # b, d, p in; R read by both triangular solves; p out
         fbytes = sum(i.M * i.w * 4 + i.M * 4 + i.M * 4 + i.N * 8 + i.N * i.w * 4 + i.N * 4 for i in insts)
         rbytes = sum(i.M * i.w * 4 + i.M * 4 + i.M * 4 + i.N * 8 + i.N * 8 + 2 * i.N * i.w * 4 + i.N * 8
@@ -262,6 +303,8 @@ def run_batch(args):
            "config": desc, "accuracy": {"max_rel_err_sampled": errors.get(sweeps), "by_sweeps": errors,
                                         "sampled_problems": sample},
            "roofline": roofline, "phases": phase_out, "cpu_baseline": cpu_baseline}
+    if method_rows is not None:
+        out["methods"] = method_rows
     print(json.dumps(out))
     return 0
 
@@ -286,11 +329,13 @@ def run_lm(args):
         probs = [gen.lm_banded(320 + k, N=2048, w=12, c=c)[:3] for k in range(P)]
         i0 = probs[0][0]
         solver = BandedSolver(i0.M, i0.N, i0.w, dtype="float32", P=P)
+        # the block-banded compact-WY factor is the faster one on this batch (auto picks it)
+        solver.set_method("blockwy-bf16x3" if args.banded_method == "auto" else args.banded_method)
         A0 = torch.from_numpy(np.concatenate([q[0].row_start for q in probs]).astype(np.int32)).cuda()
         B0 = torch.from_numpy(np.concatenate([q[0].vals for q in probs])).cuda()
         desc = {"workload": "LM on a banded batch: %d problems of n = %d unknowns, %d rows, %d values per row, "
                             "f(x) = J0 (x + %g x^3) - y, float32 factor, %d float64 sweep" % (P, i0.N, i0.M, i0.w, c, sweeps),
-                "problems": P, "rows": P * i0.M, "unknowns": P * i0.N}
+                "problems": P, "rows": P * i0.M, "unknowns": P * i0.N, "method": solver.method}
     else:
         probs = [gen.lm_blockangular(310, K=50_000, m=12, n=3, nB=90, c=c)[:3]]
         i0 = probs[0][0]

@@ -181,6 +181,25 @@ qrk_status qrk_factor_banded(qrk_handle h, const int32_t* row_start, const void*
                              const void* b, const double* d, double lambda, void* stream);
 
 /* ------------------------------------------------------------------------------
+ * qrk_set_banded_method
+ *   How qrk_factor_banded (and the LM driver on this handle) factorises:
+ *     QRK_BANDED_GIVENS (0, the default): Givens rotations row by row.
+ *     QRK_BANDED_BLOCKWY (1): the block-banded factorisation of Section 4.4 (Eq.
+ *       blockBandedYTY): columns in blocks of 16, each step a dense QR of the rows carried from
+ *       the previous step, the next block's damping rows and the rows whose first nonzero lies
+ *       in the block, over two column blocks and the right-hand side, its Householder
+ *       vectors local to those rows and applied in the compact WY form on the matrix cores.
+ *     QRK_BANDED_BLOCKWY_BF16X3 (2): the same with BF16x3 products in the WY updates.
+ *   The factor's outputs (R, c) and every later call are the same for all methods (R is
+ *   unique up to row signs).  Methods 1 and 2 need a QRK_F32 handle with w <= 15
+ *   (QRK_EINVAL otherwise, or for a block-angular handle).  Takes effect at the next factor.
+ * ------------------------------------------------------------------------------ */
+#define QRK_BANDED_GIVENS 0
+#define QRK_BANDED_BLOCKWY 1
+#define QRK_BANDED_BLOCKWY_BF16X3 2
+qrk_status qrk_set_banded_method(qrk_handle h, int32_t method);
+
+/* ------------------------------------------------------------------------------
  * qrk_solve
  *   Back-substitution through the stored R (Section 4.2: R = [[blkdiag(R_i), S],
  *   [0, R_B]] for block-angular J, banded R otherwise), then `sweeps` (0..8) sweeps of

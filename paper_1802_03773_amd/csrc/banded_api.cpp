@@ -170,6 +170,13 @@ qrk_status qrk_create_banded_batched(int32_t P, int64_t M, int64_t N, int32_t w,
   return create_banded(P, M, N, w, dtype, out);
 }
 
+qrk_status qrk_set_banded_method(qrk_handle h, int32_t method) {
+  if (!h || h->kind != KIND_BANDED || method < 0 || method > 2) return QRK_EINVAL;
+  if (method != 0 && (h->dtype != QRK_F32 || h->w > 15)) return QRK_EINVAL;
+  h->band_method = method;
+  return QRK_OK;
+}
+
 qrk_status qrk_factor_banded(qrk_handle h, const int32_t* row_start, const void* vals, const void* b,
                              const double* d, double lambda, void* stream) {
   if (!h || h->kind != KIND_BANDED) return QRK_EINVAL;
@@ -199,6 +206,14 @@ qrk_status banded_factor(qrk_handle h, hipStream_t st) {
   const double* d = h->d;
   int pr = prof_begin(h, 5, st);
   if (launch_band_first_row(h->P, h->M, h->N, h->w, row_start, h->bandfr, st) != hipSuccess) return QRK_EHIP;
+  if (h->band_method != 0) {
+    const hipError_t ew = launch_bwy<float>(h->band_method == 2, h->P, h->M, h->N, h->w, row_start,
+                                            static_cast<const float*>(vals), static_cast<const float*>(b), d,
+                                            h->lam_ptr, static_cast<float*>(h->bandR), static_cast<float*>(h->bandc),
+                                            h->bandinv, static_cast<float*>(h->bandR16), h->status, st);
+    prof_end(h, pr, st);
+    return ew == hipSuccess ? QRK_OK : QRK_EHIP;
+  }
   hipError_t e = h->dtype == QRK_F32
                      ? launch_banded_givens<float>(h->P, h->M, h->N, h->w, row_start,
                                                    static_cast<const float*>(vals),

@@ -41,6 +41,13 @@ template <typename T>
 hipError_t launch_banded_dvals(int P, int64_t M, int64_t N, int w, const int32_t* row_start, const double* r,
                                const double* Ju, const double* u, const double* p, T* dvals, hipStream_t st);
 
+// Block-banded QR on the matrix cores (w <= 15, float32 only; banded_wy.hip): the same outputs
+// as launch_banded_givens; bf16x3 selects BF16x3 products for the compact-WY updates.
+template <typename T>
+hipError_t launch_bwy(bool bf16x3, int P, int64_t M, int64_t N, int w, const int32_t* row_start, const T* vals,
+                      const T* b, const double* d, const double* lam, T* Rb, T* cb, double* binv, T* R16,
+                      int* status, hipStream_t st);
+
 // Rows of padding before and after the sweep copy of the band (R16), and the band sizes the
 // compile-time-width sweeps accept (their per-lane offsets into R16 are 32-bit).
 constexpr int kBandPad = 128;

@@ -37,6 +37,7 @@ struct qrk_handle_s {
   int64_t ldb = 0;
   int max_rows = 0;    // max_i m_i + n
   int w = 0;           // banded: values per row
+  int band_method = 0; // banded: 0 Givens, 1 block-banded compact WY (fp32), 2 (BF16x3)
   int P = 1;           // problems stacked in the handle
 
   // block-angular batch layout (a single problem is the batch of one)

@@ -192,7 +192,9 @@ struct Tri {
 // The Householder vectors are kept unscaled: the tile column x_j stays in place and the
 // reflector's tile part is w_j = s_j x_j with s_j = 1/(alpha_j - beta_j); the scales are
 // applied once per row of the small Z products instead of once per tile element.
-template <int NCB, int NRB, bool TRI, bool BF = false>
+// Only the first NPANEL panels are factored; their reflectors are still applied to every
+// column block (the later blocks then hold columns that are carried, not factored).
+template <int NCB, int NRB, bool TRI, bool BF = false, int NPANEL = NCB>
 __device__ __forceinline__ void merge_tile(f4 (&R)[Tri<NCB>::count], f4 (&X)[NRB][NCB], int pstart,
                                            float* __restrict__ lds, int lane) {
   const int g = lane >> 4;
@@ -206,6 +208,7 @@ __device__ __forceinline__ void merge_tile(f4 (&R)[Tri<NCB>::count], f4 (&X)[NRB
     constexpr int rp = Tri<NCB>::idx(P, P);
     constexpr int RBN = TRI ? (P + 1 < NRB ? P + 1 : NRB) : NRB;  // active block rows
     if (!TRI && P < pstart) return;
+    if constexpr (P >= NPANEL) return;
 
     // ---- panel factorisation of [R[P][P]; X[:, P]] (and T alongside) -------------------
     float trow[16];  // lane (g, c) builds row c of T

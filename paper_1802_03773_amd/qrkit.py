@@ -52,6 +52,7 @@ _SIGS = {
     "qrk_create_banded": (_c_i32, [_c_i64, _c_i64, _c_i32, _c_i32, ctypes.POINTER(_c_vp)]),
     "qrk_create_banded_batched": (_c_i32, [_c_i32, _c_i64, _c_i64, _c_i32, _c_i32, ctypes.POINTER(_c_vp)]),
     "qrk_factor_banded": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_dbl, _c_vp]),
+    "qrk_set_banded_method": (_c_i32, [_c_vp, _c_i32]),
     "qrk_solve": (_c_i32, [_c_vp, _c_vp, _c_i32, _c_vp]),
     "qrk_solve_rhs": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_i32, _c_vp]),
     "qrk_solve_adjoint": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp]),
@@ -374,6 +375,16 @@ class BandedSolver(Factor):
                    "qrk_create_banded_batched")
         super().__init__(h, "banded", qd, int(P) * int(N))
         self.M, self.w, self.P, self.Nper = int(M), int(w), int(P), int(N)
+        self.method = "givens"
+
+    METHODS = {"givens": 0, "blockwy": 1, "blockwy-bf16x3": 2}
+
+    def set_method(self, method: str):
+        """Factorisation of the next factor call: "givens" (rotations row by row), "blockwy"
+        (block-banded compact-WY steps on the matrix cores, Section 4.4) or "blockwy-bf16x3"."""
+        _check(lib().qrk_set_banded_method(self._h, self.METHODS[method]), "qrk_set_banded_method")
+        self.method = method
+        return self
 
     def factor(self, row_start, vals, b, d, lam: float, stream=None):
         torch = _torch()
