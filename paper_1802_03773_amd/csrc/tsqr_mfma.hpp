@@ -71,6 +71,39 @@ __device__ __forceinline__ float row_bcast(float x) {
                                                             0xF, 0xF, false));
 }
 
+// Fused forms of acc += row_bcast<J>(x) * y: the broadcast is the DPP modifier of the FMA
+// itself (v_fmac_f32 with row_newbcast on its first source), one instruction instead of a DPP
+// move and an FMA.  Each group starts with s_nop 1: a DPP source must not have been written by
+// the VALU in the two preceding cycles, and the compiler does not track that hazard across an
+// asm statement.  Inside a group no instruction reads, through DPP, a register that an earlier
+// instruction of the group wrote.
+// Gram terms of one 4-row block: pr0 += b(x0) x0 + b(x2) x2, pr1 += b(x1) x1 + b(x3) x3.
+template <int J>
+__device__ __forceinline__ void gram4_bcast(float& pr0, float& pr1, const f4& x) {
+  asm(
+      "s_nop 1\n\t"
+      "v_fmac_f32_dpp %0, %2, %2 row_newbcast:%6 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %1, %3, %3 row_newbcast:%6 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %0, %4, %4 row_newbcast:%6 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %1, %5, %5 row_newbcast:%6 row_mask:0xf bank_mask:0xf"
+      : "+v"(pr0), "+v"(pr1)
+      : "v"(x[0]), "v"(x[1]), "v"(x[2]), "v"(x[3]), "n"(J));
+}
+// x_v += b(x_v) * f for the four components of one 4-row block.
+template <int J>
+__device__ __forceinline__ void axpy4_bcast(f4& x, float f) {
+  float x0 = x[0], x1 = x[1], x2 = x[2], x3 = x[3];
+  asm(
+      "s_nop 1\n\t"
+      "v_fmac_f32_dpp %0, %0, %4 row_newbcast:%5 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %1, %1, %4 row_newbcast:%5 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %2, %2, %4 row_newbcast:%5 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %3, %3, %4 row_newbcast:%5 row_mask:0xf bank_mask:0xf"
+      : "+v"(x0), "+v"(x1), "+v"(x2), "+v"(x3)
+      : "v"(f), "n"(J));
+  x = f4{x0, x1, x2, x3};
+}
+
 __device__ __forceinline__ float read_lane(float x, int lane) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), lane));
 }
@@ -109,16 +142,25 @@ __device__ __forceinline__ void panel_factor(f4& Rd, f4 (&X)[RBN], float (&trow)
     constexpr int j = decltype(JJ)::value;
     // R's row j in every row of the wave; the steps before j leave that row unchanged
     const float rrow = rows_from<(j >> 2)>(Rd[j & 3], c);
+    // Column 0 of the panel reads tile values that the matrix cores may have just written (the
+    // previous panel's trailing update); that read goes through compiler-generated code, which
+    // keeps the matrix-core result hazard.  From column 1 on every tile value was last written
+    // by column j-1's update on the VALU, which the fused groups' s_nop covers.
     float pr0 = 0.f, pr1 = 0.f;
+    if constexpr (j == 0) {
 #pragma unroll
-    for (int rb = 0; rb < RBN; ++rb)
+      for (int rb = 0; rb < RBN; ++rb)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        if (v & 1)
-          pr1 += row_bcast<j>(X[rb][v]) * X[rb][v];
-        else
-          pr0 += row_bcast<j>(X[rb][v]) * X[rb][v];
-      }
+        for (int v = 0; v < 4; ++v) {
+          if (v & 1)
+            pr1 += row_bcast<j>(X[rb][v]) * X[rb][v];
+          else
+            pr0 += row_bcast<j>(X[rb][v]) * X[rb][v];
+        }
+    } else {
+#pragma unroll
+      for (int rb = 0; rb < RBN; ++rb) gram4_bcast<j>(pr0, pr1, X[rb]);
+    }
     const float gram = sum_rows4(pr0 + pr1);  // x_j^T x_c
     const float sigma = row_bcast<j>(gram);
     const float alpha = read_lane(Rd[j & 3], (j >> 2) * 16 + j);
@@ -131,10 +173,15 @@ __device__ __forceinline__ void panel_factor(f4& Rd, f4 (&X)[RBN], float (&trow)
     const float pd = gram * scale + rrow;  // R[j][c] + w_j^T x_c
     const float s = tau * pd;
     const float nf = (c > j) ? -scale * s : 0.f;
+    if constexpr (j == 0) {
 #pragma unroll
-    for (int rb = 0; rb < RBN; ++rb)
+      for (int rb = 0; rb < RBN; ++rb)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) X[rb][v] += row_bcast<j>(X[rb][v]) * nf;
+        for (int v = 0; v < 4; ++v) X[rb][v] += row_bcast<j>(X[rb][v]) * nf;
+    } else {
+#pragma unroll
+      for (int rb = 0; rb < RBN; ++rb) axpy4_bcast<j>(X[rb], nf);
+    }
     if (g == (j >> 2)) Rd[j & 3] = (c > j) ? Rd[j & 3] - s : (c == j ? beta : Rd[j & 3]);
     const float gk = sc * pd;  // at lane k < j: s_k s_j x_j^T x_k = w_k^T w_j
     float t = 0.f;
