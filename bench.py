@@ -33,7 +33,8 @@ PEAK_FP64_VECTOR_TFLOPS = 78.6
 # leaf launch plus the merge-tree launch.  A figure holds only for the workload it was taken on
 # and while the kernels' sources hash to the recorded digest.
 _TSQR_SOURCES = ["paper_1802_03773_amd/csrc/tsqr_mfma.hpp", "paper_1802_03773_amd/csrc/tsqr_mfma.hip",
-                 "paper_1802_03773_amd/csrc/tsqr_mfma_ncb6.hip", "paper_1802_03773_amd/csrc/qrk_device.hpp",
+                 "paper_1802_03773_amd/csrc/tsqr_queue_fp32.hip", "paper_1802_03773_amd/csrc/tsqr_queue_bf16x3.hip",
+                 "paper_1802_03773_amd/csrc/qrk_device.hpp",
                  "paper_1802_03773_amd/csrc/tsqr_tree.hpp", "paper_1802_03773_amd/csrc/tsqr_tree.hip",
                  "paper_1802_03773_amd/csrc/qrk_layout.hpp"]  # the reduced-row stride
 _TSQR_DIGEST = "5ceeb35246f3c8185b571da2097a8959a53abfe8779c79513fed8ad90a360173"
@@ -55,7 +56,10 @@ def measured_traffic(phase, lam, mode):
     root = os.path.dirname(os.path.abspath(__file__))
     h = hashlib.sha256()
     for src in rec["sources"]:
-        with open(os.path.join(root, src), "rb") as f:
+        path = os.path.join(root, src)
+        if not os.path.exists(path):
+            return None
+        with open(path, "rb") as f:
             h.update(f.read())
     return rec["bytes"] if h.hexdigest() == rec["sha256"] else None
 
@@ -78,7 +82,9 @@ def _parse():
                     help="scale: one block-angular problem (the headline); ragged-batch: 512 block-angular "
                          "problems in one batch; banded-batch: 2,048 banded problems in one batch")
     ap.add_argument("--problems", type=int, default=0, help="batch workloads: problems (0 = the recipe's count)")
-    ap.add_argument("--autotune", action="store_true", help="ragged-batch: autotune the leaf shape first")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="block-angular workloads: skip the library's autotuner (leaf height, leaf queue, "
+                         "refinement workgroups) and run the default launch shape")
     ap.add_argument("--banded-method", default="auto", choices=["auto", "givens", "blockwy", "blockwy-bf16x3"],
                     help="banded-batch: factorisation (Givens rotations or the block-banded compact-WY steps); "
                          "auto times every method and reports the fastest")
@@ -193,9 +199,6 @@ def run_batch(args):
                         "sample": "float64 oracle solves of problems %s of the batch (%s), %.2f s" % (
                             sample, "structured LAPACK per block and dense part" if ragged else
                             "LAPACK QR of the assembled band", t_cpu)}
-        if args.autotune and ragged:
-            factor()
-            print(f"[bench] autotune: leaf scale {solver.autotune()}", file=sys.stderr, flush=True)
 
     def measure_errors():
         errs = {}
@@ -232,6 +235,12 @@ def run_batch(args):
 
     refs_ok = not args.no_cpu
     method_rows = None
+    if ragged and not args.no_autotune:
+        from paper_1802_03773_amd import qrkit
+        factor()
+        solver.autotune()
+        desc["autotune"] = qrkit.tune_choice(solver)
+        print(f"[bench] autotune: {desc['autotune']}", file=sys.stderr, flush=True)
     if not ragged:
         # every banded method: its errors, sweep count and step time; the fastest is reported
         method_rows = {}
@@ -547,11 +556,18 @@ def main():
         return float(np.linalg.norm(x - p_ref) / np.linalg.norm(p_ref))
 
     def measure(mode):
+        from paper_1802_03773_amd import qrkit
         solver = BlockAngularSolver(inst.row_off, inst.n, inst.nB, dtype="float32", mode=mode)
 
         def step(sweeps):
             solver.factor(A, B, b, d, args.lam)
             solver.solve(sweeps=sweeps, out=p)
+
+        if not args.no_autotune:
+            solver.factor(A, B, b, d, args.lam)
+            solver.autotune()
+        tune = qrkit.tune_choice(solver)
+        print(f"[bench] {mode}: launch shape {tune}", file=sys.stderr, flush=True)
 
         errors = {}
         if p_ref is not None:
@@ -596,7 +612,7 @@ def main():
         ms_, _ = timed(sweeps, args.steps, 1, False)
         ms_unref, _ = timed(0, args.steps, 1, False)
         return dict(mode=mode, sweeps=sweeps, errors=errors, ms=ms_, ms_profiled=ms_prof, phases=phases_,
-                    ms_unrefined=ms_unref)
+                    ms_unrefined=ms_unref, tune=tune)
 
     modes = ["plain", "bf16x3"] if args.mode == "auto" else [args.mode]
     runs = {m: measure(m) for m in modes}
@@ -642,7 +658,8 @@ def main():
     plain = runs.get("plain")
     mode_rows = {m: {"value": 1000.0 / r["ms"], "ms_per_step": r["ms"], "ms_per_step_with_phase_events":
                      r["ms_profiled"], "refine_sweeps": r["sweeps"],
-                     "rel_err_vs_oracle": r["errors"].get(r["sweeps"]), "by_sweeps": r["errors"]}
+                     "rel_err_vs_oracle": r["errors"].get(r["sweeps"]), "by_sweeps": r["errors"],
+                     "autotune": r["tune"]}
                  for m, r in runs.items()}
 
     out = {
@@ -663,7 +680,7 @@ def main():
                         "column scales 10^(3t), D = column norms, lambda = %g" % args.lam,
             "K": inst.K, "block_rows": 12, "block_cols": 3, "dense_cols": inst.nB, "rows": inst.M,
             "unknowns": inst.N, "lambda": args.lam, "mode": best["mode"], "refine_sweeps": sweeps,
-            "refine_dtype": "f64",
+            "refine_dtype": "f64", "autotune": best["tune"],
         },
         "accuracy": {"rel_err_vs_oracle": errors.get(sweeps), "by_sweeps": errors},
         "plain_fp32": ({"value": 1000.0 / plain["ms_unrefined"], "ms_per_step": plain["ms_unrefined"],

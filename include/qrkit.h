@@ -279,18 +279,33 @@ qrk_status qrk_status_get(qrk_handle h, int32_t* detail_host, void* stream);
 qrk_status qrk_set_tsqr_shape(qrk_handle h, int32_t leaves, int32_t fanin);
 
 /* ------------------------------------------------------------------------------
- * qrk_autotune_blockangular (float32 handles; not capturable; synchronises `stream`)
- *   Times the factorisation of the inputs of the last qrk_factor_* call on this handle
- *   for a few dense-part leaf shapes (rows per leaf scaled by 1/2, 1, 2 and 4 from the
- *   library default, capped at 1024 leaves per problem) and keeps the fastest; the
- *   handle is left factored with the chosen shape.  Choices are remembered in the
- *   process by batch shape (sum of rows, P, n, widest dense part), so a later handle of
- *   the same shape starts from the remembered choice.  *scale_host [host, may be NULL]
- *   receives the chosen scale.  Synchronises the device first, like qrk_set_tsqr_shape, and
- *   an LM driver graph captured on this handle before the call is captured again at its
- *   next qrk_lm_run.  QRK_EINVAL before any factor call.
+ * qrk_autotune_blockangular (float32 handles; not capturable; synchronises the device)
+ *   Times the factorisation plus a one-sweep solve of the inputs of the last qrk_factor_*
+ *   call on this handle over three launch-shape knobs, by coordinate search, and keeps the
+ *   fastest: the rows per dense-part leaf (1/2, 1, 2 or 4 times the library default, capped
+ *   at 1024 leaves per problem), for batches whose dense parts have several widths of at most
+ *   6 column blocks one persistent leaf launch over all of them or one launch per width, and
+ *   the number of refinement workgroups (1/2, 1 or 2 times the default).  The handle is left
+ *   factored with the chosen shape.  The choice is remembered in the process, and in the
+ *   cache file when one is set (qrk_tune_cache_file), under a key of the device architecture,
+ *   dtype, mode, block width, widest dense part, number of dense-part widths, and the problem
+ *   and row counts rounded up to powers of two; a handle created later for a matching key
+ *   starts from it.  *scale_host [host, may be NULL] receives the chosen leaf scale.  Like
+ *   qrk_set_tsqr_shape it may rewrite the leaf and refinement tables, so an LM driver graph
+ *   captured on this handle is captured again at its next qrk_lm_run.  QRK_EINVAL before any
+ *   factor call.
  * ------------------------------------------------------------------------------ */
 qrk_status qrk_autotune_blockangular(qrk_handle h, double* scale_host, void* stream);
+
+/* The launch-shape knobs a block-angular handle uses (from qrk_autotune_blockangular, the cache,
+ * or the defaults 1, 1, 1); any pointer [host] may be NULL.  QRK_EINVAL for a banded handle. */
+qrk_status qrk_tune_get(qrk_handle h, double* leaf_scale, int32_t* leaf_queue, double* refine_scale);
+
+/* Sets the autotuner's cache file [host path, NULL: none] for the process and loads the choices
+ * it holds (JSON; written again after every qrk_autotune_blockangular, best effort).  Without a
+ * call, the QRK_TUNE_CACHE environment variable names the file.  QRK_EINVAL if an existing file
+ * cannot be parsed. */
+qrk_status qrk_tune_cache_file(const char* path);
 
 /* ------------------------------------------------------------------------------
  * Levenberg-Marquardt driver (Backtrack LM of Section 5.2) for the synthetic model

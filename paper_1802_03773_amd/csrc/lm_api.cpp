@@ -206,7 +206,7 @@ qrk_status qrk_lm_create_blockangular(qrk_handle h, const void* A0, const void* 
   if ((s = lm_alloc(lm, &lm->A, es * (size_t)h->M * h->n)) != QRK_OK ||
       (s = lm_alloc(lm, &lm->B, es * (size_t)btot)) != QRK_OK ||
       (s = lm_alloc(lm, &lm->b, es * (size_t)h->M)) != QRK_OK ||
-      (s = lm_alloc(lm, &lm->part, sizeof(double) * (size_t)h->nwg * 2 * kMaxDense)) != QRK_OK ||
+      (s = lm_alloc(lm, &lm->part, sizeof(double) * (size_t)h->nwg_cap * 2 * kMaxDense)) != QRK_OK ||
       (s = lm_alloc(lm, &lm->fpart, sizeof(double) * (size_t)std::max<int64_t>(h->npacks, 1))) != QRK_OK ||
       (s = lm_alloc_common(lm, noff)) != QRK_OK) {
     lm_free(lm);

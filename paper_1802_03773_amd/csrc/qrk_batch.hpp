@@ -13,6 +13,9 @@
 namespace qrk {
 
 constexpr int kMaxDense = 128;  // nB + 1 <= 128
+// Dense parts of at most this many 16-column blocks run their leaves in one persistent launch
+// (a device work queue of leaves, widest problems first); wider ones have a launch per width.
+constexpr int kQueueNCB = 6;
 
 struct ProbDesc {
   int64_t koff, K;        // first global block, blocks

@@ -59,7 +59,17 @@ struct qrk_handle_s {
   int32_t* node_r = nullptr;     //   child references of the inner nodes, level order
   int64_t node_cap = 0;
   int nnodes = 0;                //   0: the merges run inside the leaf launch
-  int cls_begin[9] = {0};        // float32 leaves grouped by 16-column-block count
+  int cls_begin[9] = {0};        // float32 leaves grouped by 16-column-block count, widest first
+  int queue_begin = 0;           // first leaf of the persistent launch (classes 6 .. 1)
+  int64_t qhead_off = 0;         // its queue head among the counters
+  int cus = 256;                 // compute units of the device
+  char arch[32] = {0};           // its architecture name (autotuner cache key)
+  // autotuner knobs (tune_cache.hpp): leaf queue on or off, refinement workgroups scale; nwg_cap
+  // is the refinement workgroup capacity reserved at create (the count at the largest scale)
+  int leaf_queue = 1;
+  double refine_scale = 1.0;
+  int nwg_cap = 1;
+  int widths = 1;                // float32 leaf classes of at most kQueueNCB column blocks present
   int cls_count[9] = {0};
   int nwg = 1;                   // refinement workgroups over the batch
   int max_L = 1;

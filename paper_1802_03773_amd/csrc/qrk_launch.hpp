@@ -52,10 +52,15 @@ hipError_t launch_zero_ints(int* p, int64_t n, hipStream_t st);
 // flags[nnodes * ncb] cleared beforehand; ncb <= 6.  The root writes R_B | c_B.
 hipError_t launch_tsqr_tree(int ncb, const ProbDesc* probs, const int32_t* node_l, const int32_t* node_r,
                             int nnodes, float* slots, int* flags, float* RB, int* status, hipStream_t st);
-hipError_t launch_tsqr_mfma(bool bf16x3, const int* cls_begin, const int* cls_count, const int32_t* leaf_prob,
-                            const int32_t* leaf_idx, const ProbDesc* probs, int n, const float* Red,
-                            const double* d, const double* lam, float* slots, int* counters, int64_t nctr,
-                            float* RB, hipStream_t st);
+// Leaves of classes 8 and 7 by their launches; the leaves from queue_begin on (classes
+// kQueueNCB .. 1, listed widest first) by one persistent launch of at most `cus` workgroups
+// that takes them from the device counter *qhead (cleared with the counters) when use_queue is
+// set and more than one of those classes is present, else by a launch per class.
+hipError_t launch_tsqr_mfma(bool bf16x3, const int* cls_begin, const int* cls_count, int queue_begin, bool use_queue,
+                            int cus,
+                            const int32_t* leaf_prob, const int32_t* leaf_idx, const ProbDesc* probs, int n,
+                            const float* Red, const double* d, const double* lam, float* slots, int* counters,
+                            int64_t nctr, int* qhead, float* RB, hipStream_t st);
 
 // R_B p_B = c_B for every problem (RB_p is L x L with c_B in column L-1); writes p_B.
 template <typename T>

@@ -10,6 +10,7 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <string>
 #include <tuple>
 #include <type_traits>
 #include <vector>
@@ -19,6 +20,7 @@
 #include "block_classes.hpp"
 #include "qrk_host.hpp"
 #include "qrk_layout.hpp"
+#include "tune_cache.hpp"
 
 using namespace qrk;
 
@@ -28,12 +30,22 @@ inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-qrk_status check_device() {
+qrk_status check_device(int* cus = nullptr, char* arch = nullptr, size_t arch_len = 0) {
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess) return QRK_ENODEVICE;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return QRK_ENODEVICE;
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return QRK_ENODEVICE;
+  if (cus) *cus = prop.multiProcessorCount;
+  if (arch && arch_len) {
+    // the base name (gfx950), without the feature suffixes
+    size_t i = 0;
+    while (i + 1 < arch_len && prop.gcnArchName[i] && prop.gcnArchName[i] != ':') {
+      arch[i] = prop.gcnArchName[i];
+      ++i;
+    }
+    arch[i] = 0;
+  }
   return QRK_OK;
 }
 
@@ -94,8 +106,9 @@ qrk_status factor_ba(qrk_handle h, hipStream_t st, const double* lam_host = null
   if constexpr (std::is_same<T, float>::value) {
     // dense parts on the matrix cores: leaves and merge trees, one launch per column-block count
     pr = prof_begin(h, 1, st);
-    if (launch_tsqr_mfma(h->mode == QRK_BF16X3, h->cls_begin, h->cls_count, h->leaf_prob, h->leaf_idx, h->probs_d, h->n, Red, h->d,
-                         h->lam_ptr, h->slots, h->counters, h->nctr, RB, st) != hipSuccess)
+    if (launch_tsqr_mfma(h->mode == QRK_BF16X3, h->cls_begin, h->cls_count, h->queue_begin, h->leaf_queue != 0, h->cus,
+                         h->leaf_prob, h->leaf_idx, h->probs_d, h->n, Red, h->d, h->lam_ptr, h->slots, h->counters,
+                         h->nctr, h->counters + h->qhead_off, RB, st) != hipSuccess)
       return QRK_EHIP;
     if (h->nnodes > 0 &&
         launch_tsqr_tree((h->probs_h[0].L + 15) / 16, h->probs_d, h->node_l, h->node_r, h->nnodes, h->slots,
@@ -256,8 +269,10 @@ qrk_status assign_leaves(qrk_handle h) {
       D.leaves = (int)(h->leaves > 0 ? h->leaves : def);
       D.rows_per_leaf = std::max<int64_t>(1, ceil_div(D.M, D.leaves));
     }
+    // widest classes first: classes 8 and 7 have launches of their own, classes 6 .. 1 form the
+    // persistent queue launch's item list (the suffix starting at cls_begin of the widest of them)
     std::vector<int32_t> lp, li;
-    for (int c = 1; c <= 8; ++c) {
+    for (int c = 8; c >= 1; --c) {
       h->cls_begin[c] = (int)lp.size();
       for (int q = 0; q < P; ++q)
         if ((pd[q].L + 15) / 16 == c)
@@ -300,7 +315,12 @@ qrk_status assign_leaves(qrk_handle h) {
         ctr += ts.counters;
       }
     }
+    h->qhead_off = ctr;  // the persistent leaf launch's queue head, cleared with the counters
+    ctr += 1;
     h->nctr = ctr;
+    h->queue_begin = (int)lp.size();
+    for (int c = kQueueNCB; c >= 1; --c)
+      if (h->cls_count[c] > 0) h->queue_begin = std::min(h->queue_begin, h->cls_begin[c]);
     if (h->nnodes > h->node_cap) {
       dfree(h, h->node_l);
       dfree(h, h->node_r);
@@ -409,23 +429,41 @@ void prof_end(qrk_handle h, int rec, hipStream_t st) {
   if (rec >= 0) (void)hipEventRecord(h->prof_pool[rec].stop, st);
 }
 
-// Leaf-shape choices of the autotuner, remembered in the process by batch shape.
-struct TuneKey {
-  int64_t rows;
-  int P, n, max_L, dtype;
-  bool operator<(const TuneKey& o) const {
-    return std::tie(rows, P, n, max_L, dtype) < std::tie(o.rows, o.P, o.n, o.max_L, o.dtype);
+// Largest refinement workgroup scale the autotuner tries (its buffers are sized for it).
+constexpr double kMaxRefineScale = 2.0;
+
+// The handle's key in the autotuner cache.
+std::string handle_tune_key(qrk_handle h) {
+  return tune_key(h->arch, (int)h->dtype, (int)h->mode, h->P, h->n, h->M, h->max_L, h->widths);
+}
+
+// Refinement workgroups of every problem, in proportion to its packs: 512 in all (two waves per
+// SIMD in one round at the refinement's register use), about eight per problem for batches,
+// times refine_scale; never more than the capacity reserved at create.
+qrk_status assign_refine(qrk_handle h, bool upload) {
+  std::vector<ProbDesc>& pd = h->probs_h;
+  const int P = h->P;
+  const double base = (double)std::min<int64_t>(ceil_div(h->npacks, 4), std::max<int64_t>(512, 8 * (int64_t)P));
+  const int64_t target = std::max<int64_t>(1, (int64_t)std::llround(base * h->refine_scale));
+  std::vector<int32_t> wg_prob;
+  for (int32_t q = 0; q < P; ++q) {
+    ProbDesc& D = pd[q];
+    int64_t w = (int64_t)std::llround((double)D.npacks * (double)target / (double)h->npacks);
+    w = std::max<int64_t>(1, std::min<int64_t>(w, ceil_div(D.npacks, 4)));
+    D.wg0 = (int32_t)wg_prob.size();
+    D.nwg = (int32_t)w;
+    for (int64_t k = 0; k < w; ++k) wg_prob.push_back(q);
   }
-};
-std::mutex g_tune_mu;
-std::map<TuneKey, double> g_tune;
-
-TuneKey tune_key(qrk_handle h) { return TuneKey{h->M, h->P, h->n, h->max_L, (int)h->dtype}; }
-
-double remembered_leaf_scale(qrk_handle h) {
-  std::lock_guard<std::mutex> lk(g_tune_mu);
-  auto it = g_tune.find(tune_key(h));
-  return it == g_tune.end() ? 1.0 : it->second;
+  if ((int64_t)wg_prob.size() > h->nwg_cap) return QRK_EINVAL;
+  h->nwg = (int)wg_prob.size();
+  h->refine_grid = h->nwg;
+  if (upload) {
+    if (hipMemcpy(h->wg_prob, wg_prob.data(), sizeof(int32_t) * wg_prob.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->probs_d, pd.data(), sizeof(ProbDesc) * P, hipMemcpyHostToDevice) != hipSuccess)
+      return QRK_EHIP;
+    ++h->shape_gen;
+  }
+  return QRK_OK;
 }
 
 // Validate a batch description and build the handle: per-problem descriptors, the
@@ -451,12 +489,16 @@ qrk_status create_ba(int32_t P, int32_t n, const int32_t* Kp, const int32_t* nBp
     if (m < 0 || m > QRK_MAX_BLOCK_ROWS) return QRK_EINVAL;
     max_m = std::max<int>(max_m, (int)m);
   }
-  qrk_status ds = check_device();
+  int cus = 256;
+  char arch[32] = {0};
+  qrk_status ds = check_device(&cus, arch, sizeof(arch));
   if (ds != QRK_OK) return ds;
 
   qrk_handle h = new (std::nothrow) qrk_handle_s();
   if (!h) return QRK_ENOMEM;
   h->kind = KIND_BLOCKANGULAR;
+  h->cus = cus;
+  std::memcpy(h->arch, arch, sizeof(arch));
   h->dtype = dtype;
   h->mode = mode;
   h->P = P;
@@ -529,25 +571,45 @@ qrk_status create_ba(int32_t P, int32_t n, const int32_t* Kp, const int32_t* nBp
   }
   h->blk_list_n = (int64_t)bq.list.size();
   const std::vector<int32_t>& blk_list = bq.list;
-  // refinement workgroups, in proportion to each problem's packs: 512 in all (two waves per SIMD
-  // in one round at the refinement's register use), and about eight per problem for batches
-  const int64_t target = std::min<int64_t>(ceil_div(h->npacks, 4), std::max<int64_t>(512, 8 * (int64_t)P));
-  std::vector<int32_t> wg_prob;
-  for (int32_t q = 0; q < P; ++q) {
-    ProbDesc& D = pd[q];
-    int64_t w = (int64_t)std::llround((double)D.npacks * (double)target / (double)h->npacks);
-    w = std::max<int64_t>(1, std::min<int64_t>(w, ceil_div(D.npacks, 4)));
-    D.wg0 = (int32_t)wg_prob.size();
-    D.nwg = (int32_t)w;
-    for (int64_t k = 0; k < w; ++k) wg_prob.push_back(q);
+  // float32 leaf widths present (for the cache key and the leaf queue)
+  {
+    bool seen[9] = {false};
+    for (auto& D : pd) seen[(D.L + 15) / 16] = true;
+    h->widths = 0;
+    for (int c = 1; c <= kQueueNCB; ++c) h->widths += seen[c];
   }
-  h->nwg = (int)wg_prob.size();
-  h->refine_grid = h->nwg;
+  // launch-shape knobs: a remembered autotuner choice for this shape, else the defaults; the
+  // refinement workgroup buffers are sized for the largest scale the autotuner tries
+  {
+    TuneChoice tc;
+    if (tune_lookup(handle_tune_key(h), &tc)) {
+      h->leaf_scale = tc.leaf_scale;
+      h->leaf_queue = tc.leaf_queue;
+      h->refine_scale = tc.refine_scale;
+    }
+    const double keep = h->refine_scale;
+    h->nwg_cap = 1 << 30;
+    h->refine_scale = std::max(keep, kMaxRefineScale);
+    qrk_status s0 = assign_refine(h, false);
+    if (s0 != QRK_OK) {
+      delete h;
+      return s0;
+    }
+    h->nwg_cap = h->nwg;
+    h->refine_scale = keep;
+    s0 = assign_refine(h, false);
+    if (s0 != QRK_OK) {
+      delete h;
+      return s0;
+    }
+  }
+  std::vector<int32_t> wg_prob;
+  for (int32_t q = 0; q < P; ++q)
+    for (int32_t k = 0; k < pd[q].nwg; ++k) wg_prob.push_back(q);
   h->grid_blocks = (int)std::min<int64_t>(ceil_div(Ktot, 4), 2048);
   h->max_leaves = dtype == QRK_F32 ? 4096 : 1024;
   h->leaves = 0;
   h->fanin = 8;
-  h->leaf_scale = remembered_leaf_scale(h);
 
   qrk_status s = QRK_OK;
   const int Lm = h->max_L;
@@ -555,7 +617,7 @@ qrk_status create_ba(int32_t P, int32_t n, const int32_t* Kp, const int32_t* nBp
       (s = dalloc(h, &h->pack_blk, sizeof(int64_t) * packs.size())) != QRK_OK ||
       (s = dalloc(h, &h->blk_prob, sizeof(int32_t) * Ktot)) != QRK_OK ||
       (!blk_list.empty() && (s = dalloc(h, &h->blk_list, sizeof(int32_t) * blk_list.size())) != QRK_OK) ||
-      (s = dalloc(h, &h->wg_prob, sizeof(int32_t) * wg_prob.size())) != QRK_OK ||
+      (s = dalloc(h, &h->wg_prob, sizeof(int32_t) * (size_t)h->nwg_cap)) != QRK_OK ||
       (s = dalloc(h, &h->probs_d, sizeof(ProbDesc) * P)) != QRK_OK ||
       (s = dalloc(h, &h->Rblk, es * (size_t)Ktot * n * n)) != QRK_OK ||
       (s = dalloc(h, &h->Sc, es * (size_t)soff)) != QRK_OK ||
@@ -566,7 +628,7 @@ qrk_status create_ba(int32_t P, int32_t n, const int32_t* Kp, const int32_t* nBp
       (s = dalloc(h, &h->ybuf, sizeof(double) * (size_t)Ktot * n)) != QRK_OK ||
       (s = dalloc(h, &h->ubuf, sizeof(double) * (size_t)h->N)) != QRK_OK ||
       (s = dalloc(h, &h->vecpart, sizeof(double) * (size_t)1024 * std::max(Lm - 1, 1))) != QRK_OK ||
-      (s = dalloc(h, &h->refpart, sizeof(double) * (size_t)h->nwg * kMaxDense)) != QRK_OK ||
+      (s = dalloc(h, &h->refpart, sizeof(double) * (size_t)h->nwg_cap * kMaxDense)) != QRK_OK ||
       (s = dalloc(h, &h->deltaB, sizeof(double) * (size_t)P * kMaxDense)) != QRK_OK ||
       (s = dalloc(h, &h->lam_d, sizeof(double) * (size_t)P)) != QRK_OK ||
       (s = dalloc(h, &h->status, sizeof(int) * (size_t)std::max(P, 4))) != QRK_OK) {
@@ -847,7 +909,7 @@ qrk_status qrk_set_tsqr_shape(qrk_handle h, int32_t leaves, int32_t fanin) {
 qrk_status qrk_autotune_blockangular(qrk_handle h, double* scale_host, void* stream) {
   if (!h || h->kind != KIND_BLOCKANGULAR || !h->factored || h->dtype != QRK_F32) return QRK_EINVAL;
   hipStream_t st = S(stream);
-  // as in qrk_set_tsqr_shape: no earlier work on any stream may still read the leaf tables
+  // as in qrk_set_tsqr_shape: no earlier work on any stream may still read the tables rewritten
   if (hipDeviceSynchronize() != hipSuccess) return QRK_EHIP;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return QRK_EHIP;
@@ -859,41 +921,74 @@ qrk_status qrk_autotune_blockangular(qrk_handle h, double* scale_host, void* str
   h->leaves = 0;
   const bool prof = h->prof_on;
   h->prof_on = false;
-  double best_ms = 1e300, best = 1.0;
   qrk_status s = QRK_OK;
-  for (double scale : {0.5, 1.0, 2.0, 4.0}) {
-    h->leaf_scale = scale;
-    if ((s = assign_leaves(h)) != QRK_OK) break;
-    float ms_min = 1e30f;
-    for (int rep = 0; rep < 3 && s == QRK_OK; ++rep) {  // the first run warms up
-      if (hipEventRecord(e0, st) != hipSuccess) s = QRK_EHIP;
-      if (s == QRK_OK) s = factor_ba<float>(h, st);
-      if (s == QRK_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
-        s = QRK_EHIP;
+  // one timed configuration: the factor and a one-sweep solve (the step the LM loop takes),
+  // best of two after a warm-up; p goes to the adjoint's scratch vector
+  auto time_config = [&](double* ms_out) -> qrk_status {
+    qrk_status r;
+    if ((r = assign_leaves(h)) != QRK_OK || (r = assign_refine(h, true)) != QRK_OK) return r;
+    float best = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {
+      if (hipEventRecord(e0, st) != hipSuccess) return QRK_EHIP;
+      if ((r = factor_ba<float>(h, st)) != QRK_OK) return r;
+      if ((r = blockangular_solve(h, h->ubuf, 1, st)) != QRK_OK) return r;
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return QRK_EHIP;
       float ms = 0.f;
-      if (s == QRK_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) s = QRK_EHIP;
-      if (rep > 0) ms_min = std::min(ms_min, ms);
+      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return QRK_EHIP;
+      if (rep > 0) best = std::min(best, ms);
     }
-    if (s != QRK_OK) break;
-    if (ms_min < best_ms) {
-      best_ms = ms_min;
-      best = scale;
+    *ms_out = best;
+    return QRK_OK;
+  };
+  // coordinate search: rows per leaf, then the leaf queue (batches of several widths), then the
+  // refinement workgroups, each from the best of the previous ones
+  TuneChoice best;
+  best.leaf_scale = h->leaf_scale;
+  best.leaf_queue = h->leaf_queue;
+  best.refine_scale = h->refine_scale;
+  best.ms = 1e300;
+  auto try_config = [&](double ls, int lq, double rs) {
+    if (s != QRK_OK) return;
+    h->leaf_scale = ls;
+    h->leaf_queue = lq;
+    h->refine_scale = rs;
+    double ms = 0.0;
+    s = time_config(&ms);
+    if (s == QRK_OK && ms < best.ms) {
+      best.leaf_scale = ls;
+      best.leaf_queue = lq;
+      best.refine_scale = rs;
+      best.ms = ms;
     }
-  }
+  };
+  for (double ls : {0.5, 1.0, 2.0, 4.0}) try_config(ls, best.leaf_queue, best.refine_scale);
+  if (h->widths > 1)
+    for (int lq : {1, 0}) try_config(best.leaf_scale, lq, best.refine_scale);
+  for (double rs : {0.5, 1.0, kMaxRefineScale}) try_config(best.leaf_scale, best.leaf_queue, rs);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   h->prof_on = prof;
-  h->leaf_scale = best;
+  h->leaf_scale = best.leaf_scale;
+  h->leaf_queue = best.leaf_queue;
+  h->refine_scale = best.refine_scale;
   h->leaves = fixed;
   if (s == QRK_OK) s = assign_leaves(h);
+  if (s == QRK_OK) s = assign_refine(h, true);
   if (s == QRK_OK) s = factor_ba<float>(h, st);
-  if (s == QRK_OK) {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune[tune_key(h)] = best;
-  }
-  if (scale_host) *scale_host = best;
+  if (s == QRK_OK) (void)tune_store(handle_tune_key(h), best);  // the file is best effort
+  if (scale_host) *scale_host = best.leaf_scale;
   return s;
 }
+
+qrk_status qrk_tune_get(qrk_handle h, double* leaf_scale, int32_t* leaf_queue, double* refine_scale) {
+  if (!h || h->kind != KIND_BLOCKANGULAR) return QRK_EINVAL;
+  if (leaf_scale) *leaf_scale = h->leaf_scale;
+  if (leaf_queue) *leaf_queue = h->leaf_queue;
+  if (refine_scale) *refine_scale = h->refine_scale;
+  return QRK_OK;
+}
+
+qrk_status qrk_tune_cache_file(const char* path) { return tune_set_file(path) ? QRK_OK : QRK_EINVAL; }
 
 qrk_status qrk_profile_enable(qrk_handle h, int32_t max_calls) {
   if (!h || max_calls < 0 || max_calls > 100000) return QRK_EINVAL;

@@ -420,24 +420,17 @@ __device__ __forceinline__ void merge_stored_tri(f4 (&R)[Tri<NCB>::count], const
   merge_tile<NCB, NCB, true, BF>(R, X, 0, lds, lane);
 }
 
-// One launch per column-block count NCB: wave w is global leaf leaf_begin + w.  Leaf li of
-// problem p streams rows [li * rows_per_leaf, ...) of the problem's reduced rows into its
-// triangle (leaf 0 starts from diag(sqrt(lam_p) d_B)); the leaves of each problem are then
-// merged pairwise in the same launch (the problem's own slots and arrival counters) and the
-// root is written row-major to the problem's R_B | c_B.
+// One leaf of the dense part, by one wave: leaf li of problem p streams rows
+// [li * rows_per_leaf, ...) of the problem's reduced rows into its triangle (leaf 0 starts from
+// diag(sqrt(lam_p) d_B)); the leaves of each problem are then merged pairwise (the problem's own
+// slots and arrival counters: the second wave of a pair to finish merges) and the root is
+// written row-major to the problem's R_B | c_B.
 template <int NCB, int NRB, bool BF>
-__global__ void __launch_bounds__(256)
-k_tsqr_mfma(int leaf_begin, int nleaves_cls, const int32_t* __restrict__ leaf_prob,
-            const int32_t* __restrict__ leaf_idx, const ProbDesc* __restrict__ probs, int n,
-            const float* __restrict__ Red, const double* __restrict__ d, const double* __restrict__ lamv,
-            float* __restrict__ slots, int* __restrict__ counters, float* __restrict__ RBall) {
-  __shared__ float lds_all[4][kWaveLds];
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  const int wl = blockIdx.x * 4 + wv;
-  if (wl >= nleaves_cls) return;
-  const int pi = leaf_prob[leaf_begin + wl];
-  const int leaf = leaf_idx[leaf_begin + wl];
+__device__ __forceinline__ void tsqr_leaf(int pi, int leaf, const ProbDesc* __restrict__ probs, int n,
+                                          const float* __restrict__ Red, const double* __restrict__ d,
+                                          const double* __restrict__ lamv, float* __restrict__ slots,
+                                          int* __restrict__ counters, float* __restrict__ RBall, float* lds,
+                                          int lane) {
   const ProbDesc& P = probs[pi];
   const float* Xg = Red + P.redoff;
   const int64_t ldx = P.ldr;
@@ -445,7 +438,6 @@ k_tsqr_mfma(int leaf_begin, int nleaves_cls, const int32_t* __restrict__ leaf_pr
   const int L = P.L;
   const int nleaves = P.leaves;
   const int64_t rows_per_leaf = P.rows_per_leaf;
-  float* lds = lds_all[wv];
   const int g = lane >> 4;
   const int c = lane & 15;
   constexpr int NT = Tri<NCB>::count;
@@ -540,6 +532,79 @@ k_tsqr_mfma(int leaf_begin, int nleaves_cls, const int32_t* __restrict__ leaf_pr
       }
     });
   });
+}
+
+// One launch per column-block count NCB: wave w is global leaf leaf_begin + w.
+template <int NCB, int NRB, bool BF>
+__global__ void __launch_bounds__(256)
+k_tsqr_mfma(int leaf_begin, int nleaves_cls, const int32_t* __restrict__ leaf_prob,
+            const int32_t* __restrict__ leaf_idx, const ProbDesc* __restrict__ probs, int n,
+            const float* __restrict__ Red, const double* __restrict__ d, const double* __restrict__ lamv,
+            float* __restrict__ slots, int* __restrict__ counters, float* __restrict__ RBall) {
+  __shared__ float lds_all[4][kWaveLds];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int wl = blockIdx.x * 4 + wv;
+  if (wl >= nleaves_cls) return;
+  tsqr_leaf<NCB, NRB, BF>(leaf_prob[leaf_begin + wl], leaf_idx[leaf_begin + wl], probs, n, Red, d, lamv, slots,
+                          counters, RBall, lds_all[wv], lane);
+}
+
+// Leaf rows per tile for each column-block count: 128 up to 4 column blocks, 64 beyond
+// (taller tiles no longer fit the register file there).
+template <int NCB>
+struct LeafTile {
+  static constexpr int nrb = NCB <= 4 ? 8 : 4;
+};
+
+// The leaves of every problem with at most kQueueNCB column blocks in one persistent launch:
+// each wave takes the next item of the leaf list (widest problems first) from a device-scope
+// counter until the list is exhausted, and runs that leaf with the body instantiated for its
+// problem's column-block count.  A wave that finds its merge partner still running goes on to
+// the next item.  Every leaf body needs the whole register file (one wave per SIMD), so one
+// launch over all widths costs no occupancy against one launch per width, and the narrow
+// problems' leaves fill the SIMDs that the wide ones leave idle at the end.  kQueueNCB (the
+// widest count in the queue) is in qrk_batch.hpp.
+
+// The queue kernel calls each width's body as a function of its own, so that every body keeps
+// the register allocation it has in a kernel by itself (inlined side by side, the six bodies
+// exceed the register file and spill).
+template <int NCB, bool BF>
+__device__ __noinline__ void tsqr_leaf_call(int pi, int leaf, const ProbDesc* __restrict__ probs, int n,
+                                            const float* __restrict__ Red, const double* __restrict__ d,
+                                            const double* __restrict__ lamv, float* __restrict__ slots,
+                                            int* __restrict__ counters, float* __restrict__ RBall, float* lds,
+                                            int lane) {
+  tsqr_leaf<NCB, LeafTile<NCB>::nrb, BF>(pi, leaf, probs, n, Red, d, lamv, slots, counters, RBall, lds, lane);
+}
+
+template <bool BF>
+__global__ void __launch_bounds__(256)
+k_tsqr_queue(int nitems, const int32_t* __restrict__ leaf_prob, const int32_t* __restrict__ leaf_idx,
+             const ProbDesc* __restrict__ probs, int n, const float* __restrict__ Red, const double* __restrict__ d,
+             const double* __restrict__ lamv, float* __restrict__ slots, int* __restrict__ counters,
+             int* __restrict__ qhead, float* __restrict__ RBall) {
+  __shared__ float lds_all[4][kWaveLds];
+  const int lane = threadIdx.x & 63;
+  float* lds = lds_all[threadIdx.x >> 6];
+  for (;;) {
+    int item = 0;
+    if (lane == 0) item = atomicAdd(qhead, 1);
+    item = __builtin_amdgcn_readfirstlane(item);
+    if (item >= nitems) return;
+    const int pi = leaf_prob[item];
+    const int leaf = leaf_idx[item];
+    switch ((probs[pi].L + 15) >> 4) {
+#define QRK_QLEAF(C)                                                                                   \
+  case C:                                                                                              \
+    tsqr_leaf_call<C, BF>(pi, leaf, probs, n, Red, d, lamv, slots, counters, RBall, lds, lane);        \
+    break;
+      QRK_QLEAF(1) QRK_QLEAF(2) QRK_QLEAF(3) QRK_QLEAF(4) QRK_QLEAF(5) QRK_QLEAF(6)
+#undef QRK_QLEAF
+      default:
+        break;
+    }
+  }
 }
 
 template <int NCB, int NRB>

@@ -42,6 +42,8 @@ _SIGS = {
     "qrk_factor_blockangular_batched": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp]),
     "qrk_status_get_problems": (_c_i32, [_c_vp, _c_i32p, _c_vp]),
     "qrk_autotune_blockangular": (_c_i32, [_c_vp, ctypes.POINTER(_c_dbl), _c_vp]),
+    "qrk_tune_get": (_c_i32, [_c_vp, ctypes.POINTER(_c_dbl), _c_i32p, ctypes.POINTER(_c_dbl)]),
+    "qrk_tune_cache_file": (_c_i32, [ctypes.c_char_p]),
     "qrk_lm_create_blockangular": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_dbl, _c_i32, _c_i32,
                                             ctypes.POINTER(_c_vp)]),
     "qrk_lm_create_banded": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_dbl, _c_i32, _c_i32, ctypes.POINTER(_c_vp)]),
@@ -540,3 +542,15 @@ def solve_banded_noalloc(row_start, vals, b, d, lam: float, N: int, sweeps: int 
         _dev_ptr(status, torch.int32, "status", 1) if status is not None else None, _stream_ptr(stream)),
         "qrk_solve_banded_noalloc")
     return p
+
+
+def set_tune_cache(path):
+    """Autotuner cache file for the process (None: none); loads the choices it holds."""
+    _check(lib().qrk_tune_cache_file(None if path is None else str(path).encode()), "qrk_tune_cache_file")
+
+
+def tune_choice(solver) -> dict:
+    """The launch-shape knobs a block-angular solver or batch uses."""
+    ls, lq, rs = _c_dbl(0.0), _c_i32(0), _c_dbl(0.0)
+    _check(lib().qrk_tune_get(solver.handle, ctypes.byref(ls), ctypes.byref(lq), ctypes.byref(rs)), "qrk_tune_get")
+    return {"leaf_scale": float(ls.value), "leaf_queue": int(lq.value), "refine_scale": float(rs.value)}

@@ -127,3 +127,18 @@ def test_stack_batch_layout():
     assert st["B"].size == 15 * 4 + 20 * 7
     assert np.array_equal(st["B"][60:].reshape(20, 7), insts[2].B)
     assert st["d"].size == sum(i.N for i in insts)
+
+
+def test_tune_cache_file_parsing(tmp_path):
+    """qrk_tune_cache_file loads the autotuner's JSON cache: a file of the library's own layout
+    (and a missing file) is accepted, a malformed one is refused; no device is touched."""
+    L = qrkit.lib()
+    good = tmp_path / "tune.json"
+    good.write_text('{"version": 1, "entries": {\n  "gfx950/f32/bf16x3/P512/n3/rows67108864/L91/w3": '
+                    '{"leaf_scale": 2, "leaf_queue": 1, "refine_scale": 0.5, "ms": 25.1}\n}}\n')
+    assert L.qrk_tune_cache_file(str(good).encode()) == qrkit.QRK_OK
+    assert L.qrk_tune_cache_file(str(tmp_path / "absent.json").encode()) == qrkit.QRK_OK
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"version": 1, "entries": {"k": {"leaf_scale": 2}}}')
+    assert L.qrk_tune_cache_file(str(bad).encode()) == qrkit.QRK_EINVAL
+    assert L.qrk_tune_cache_file(None) == qrkit.QRK_OK

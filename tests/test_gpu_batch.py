@@ -101,6 +101,45 @@ def test_batch_autotune_keeps_results():
         assert p_err(p[q], p_ref, inst.d) <= 1e-10, q
 
 
+def test_autotune_cache_file_round_trip(tmp_path):
+    """The autotuner's choice is written to the cache file under the batch's shape key, and a new
+    handle of the same shape starts from it (in a process that reads the file afresh the key
+    and the file are the same; here the file is re-read into the process map)."""
+    import json
+    import torch
+    from paper_1802_03773_amd import BlockAngularBatch, qrkit
+    path = tmp_path / "tune.json"
+    qrkit.set_tune_cache(path)
+    try:
+        insts = _batch_problems(np.float32, seed=4)
+        st = gen.stack_batch(insts)
+        dev = _to_dev(st)
+        bt = BlockAngularBatch(st["K"], st["nB"], st["row_off"], st["n"], dtype="float32")
+        bt.factor(dev["A"], dev["B"], dev["b"], dev["d"], dev["lam"])
+        scale = bt.autotune()
+        chosen = qrkit.tune_choice(bt)
+        log(f"autotune choice {chosen}")
+        assert chosen["leaf_scale"] == scale
+        data = json.loads(path.read_text())
+        entries = data["entries"]
+        assert len(entries) == 1
+        (key, rec), = entries.items()
+        assert key.startswith("gfx950/f32/plain/P8/n3/")
+        assert rec["leaf_scale"] == chosen["leaf_scale"] and rec["refine_scale"] == chosen["refine_scale"]
+        assert rec["leaf_queue"] == chosen["leaf_queue"]
+        qrkit.set_tune_cache(path)  # reload
+        bt2 = BlockAngularBatch(st["K"], st["nB"], st["row_off"], st["n"], dtype="float32")
+        assert qrkit.tune_choice(bt2) == chosen
+        bt2.factor(dev["A"], dev["B"], dev["b"], dev["d"], dev["lam"])
+        p = np.split(bt2.solve(sweeps=2).cpu().numpy(), np.cumsum([i.N for i in insts])[:-1])
+        torch.cuda.synchronize()
+        for q in (0, 4, 7):
+            p_ref, _ = refine.reference_solution(insts[q])
+            assert p_err(p[q], p_ref, insts[q].d) <= 1e-10, q
+    finally:
+        qrkit.set_tune_cache(None)
+
+
 def test_ragged_batch_sampled():
     """32 problems of the ragged-batch recipe (K ~ U{500..8000}, m_i ~ U{4,6,..,40},
     nB ~ U{6,30,90}); problems 0, 13 and 31 checked against the oracle."""
