@@ -28,40 +28,68 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3
 PEAK_FP64_VECTOR_TFLOPS = 78.6
 
 # HBM bytes per launch of a phase's kernels, from two rocprofv3 PMC runs of this script
-# (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, factors read off a 256 MiB device copy; the runs
-# and figures are in profiles/blockangular_scale_pmc_traffic.md).  The dense-part phase is the
-# leaf launch plus the merge-tree launch.  A figure holds only for the workload it was taken on
-# and while the kernels' sources hash to the recorded digest.
+# (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, factors read off a 256 MiB device copy), and the
+# matrix-core work of the same launches (SQ_INSTS_VALU_MFMA_MOPS_BF16 / _F32 x 512 flops, and
+# SQ_VALU_MFMA_BUSY_CYCLES per SIMD); runs and figures in
+# profiles/blockangular_scale_pmc_counters.md.  The dense-part phase is the leaf launch plus the
+# merge-tree launch.  A figure holds only for the workload it was taken on and while the
+# kernels' sources hash to the recorded digest.
 _TSQR_SOURCES = ["paper_1802_03773_amd/csrc/tsqr_mfma.hpp", "paper_1802_03773_amd/csrc/tsqr_mfma.hip",
-                 "paper_1802_03773_amd/csrc/tsqr_queue_fp32.hip", "paper_1802_03773_amd/csrc/tsqr_queue_bf16x3.hip",
-                 "paper_1802_03773_amd/csrc/qrk_device.hpp",
+                 "paper_1802_03773_amd/csrc/tsqr_mfma_ncb6.hip", "paper_1802_03773_amd/csrc/qrk_device.hpp",
                  "paper_1802_03773_amd/csrc/tsqr_tree.hpp", "paper_1802_03773_amd/csrc/tsqr_tree.hip",
                  "paper_1802_03773_amd/csrc/qrk_layout.hpp"]  # the reduced-row stride
-_TSQR_DIGEST = "5ceeb35246f3c8185b571da2097a8959a53abfe8779c79513fed8ad90a360173"
-_TREE_KIB = 22599.7 * 2.000 + 21845.9
+_TSQR_DIGEST = "32b2fef12e8504e104d63e24ec3ea3951d264874a442a60ca820dec27ef429dd"
 MEASURED_TRAFFIC = {
-    ("dense_leaves", "plain"): {"bytes": (113410.5 * 2.000 + 21504.0 + _TREE_KIB) * 1024.0, "lam": 1e-2,
-                                "sources": _TSQR_SOURCES, "sha256": _TSQR_DIGEST},
-    ("dense_leaves", "bf16x3"): {"bytes": (113627.1 * 2.000 + 21504.0 + _TREE_KIB) * 1024.0, "lam": 1e-2,
-                                 "sources": _TSQR_SOURCES, "sha256": _TSQR_DIGEST},
+    ("dense_leaves", "bf16x3"): {"bytes": (114598.0 * 2.000 + 23808.0 + 22614.0 * 2.000 + 21845.7) * 1024.0,
+                                 "lam": 1e-2, "sources": _TSQR_SOURCES, "sha256": _TSQR_DIGEST},
 }
+# matrix-core flops per launch (leaves + tree) and the SIMDs' matrix-core busy cycles per launch
+MEASURED_MFMA = {
+    ("dense_leaves", "bf16x3"): {"bf16_flops": 88464960.0 * 512, "f32_flops": (2457360.0 + 1391280.0) * 512,
+                                 "busy_cycles_per_simd": (63891360.0 + 11130240.0) / 1024.0,
+                                 "lam": 1e-2, "sources": _TSQR_SOURCES, "sha256": _TSQR_DIGEST},
+    ("dense_leaves", "plain"): {"bf16_flops": 0.0, "f32_flops": (22116240.0 + 1391280.0) * 512,
+                                "busy_cycles_per_simd": (176929920.0 + 11130240.0) / 1024.0,
+                                "lam": 1e-2, "sources": _TSQR_SOURCES, "sha256": _TSQR_DIGEST},
+}
+PEAK_BF16_MFMA_TFLOPS = 2500.0
+PEAK_FP32_MFMA_TFLOPS = 157.3
+CLOCK_GHZ = 2.4
 
 
-def measured_traffic(phase, lam, mode):
-    """Bytes per launch for `phase` if a PMC figure matches this workload and these sources."""
+def _sources_match(rec):
     import hashlib
-    rec = MEASURED_TRAFFIC.get((phase, mode))
-    if rec is None or rec["lam"] != lam:
-        return None
     root = os.path.dirname(os.path.abspath(__file__))
     h = hashlib.sha256()
     for src in rec["sources"]:
         path = os.path.join(root, src)
         if not os.path.exists(path):
-            return None
+            return False
         with open(path, "rb") as f:
             h.update(f.read())
-    return rec["bytes"] if h.hexdigest() == rec["sha256"] else None
+    return h.hexdigest() == rec["sha256"]
+
+
+def measured_mfma(phase, lam, mode, avg_ms):
+    """Matrix-core utilisation of `phase` at this run's duration, if a PMC figure matches."""
+    rec = MEASURED_MFMA.get((phase, mode))
+    if rec is None or rec["lam"] != lam or not _sources_match(rec):
+        return None
+    sec = avg_ms * 1e-3
+    bf = rec["bf16_flops"] / sec / 1e12
+    f32 = rec["f32_flops"] / sec / 1e12
+    return {"bf16_tflops": bf, "bf16_peak": PEAK_BF16_MFMA_TFLOPS, "bf16_frac": bf / PEAK_BF16_MFMA_TFLOPS,
+            "f32_tflops": f32, "f32_peak": PEAK_FP32_MFMA_TFLOPS, "f32_frac": f32 / PEAK_FP32_MFMA_TFLOPS,
+            "busy_frac": rec["busy_cycles_per_simd"] / (sec * CLOCK_GHZ * 1e9),
+            "flops_basis": "SQ_INSTS_VALU_MFMA_MOPS_* x 512 per launch (leaves + tree)"}
+
+
+def measured_traffic(phase, lam, mode):
+    """Bytes per launch for `phase` if a PMC figure matches this workload and these sources."""
+    rec = MEASURED_TRAFFIC.get((phase, mode))
+    if rec is None or rec["lam"] != lam:
+        return None
+    return rec["bytes"] if _sources_match(rec) else None
 
 
 def _parse():
@@ -100,6 +128,17 @@ def _cpu_threads() -> int:
     except Exception:
         pass
     return len(os.sched_getaffinity(0))
+
+
+def _blas_build() -> str:
+    """NumPy version and the BLAS it was built against (numpy.show_config)."""
+    import numpy as np
+    try:
+        cfg = np.show_config(mode="dicts")
+        blas = cfg.get("Build Dependencies", {}).get("blas", {})
+        return "numpy %s, %s %s" % (np.__version__, blas.get("name", "?"), blas.get("version", "?"))
+    except Exception:
+        return "numpy %s" % np.__version__
 
 
 def algorithmic_work(inst):
@@ -540,15 +579,31 @@ def main():
     if not args.no_cpu:
         from oracle import refine, structured
         print("[bench] oracle (cpu_baseline leg)", file=sys.stderr, flush=True)
-        t0 = time.perf_counter()
-        p0, fac = structured.solve_blockangular(inst)
-        t_oracle = time.perf_counter() - t0
+
+        def oracle_time():
+            t0 = time.perf_counter()
+            out = structured.solve_blockangular(inst)
+            return time.perf_counter() - t0, out
+
+        # the oracle as it stands, on the host's cores and on one core: the median of three runs
+        # after one warm-up (whose solution seeds the refined reference)
+        _, (p0, fac) = oracle_time()
         p_ref = refine.refine(inst, fac, p0, sweeps=2).astype(np.float64)
+        t_all = sorted(oracle_time()[0] for _ in range(3))[1]
+        try:
+            from threadpoolctl import threadpool_limits
+            with threadpool_limits(limits=1):
+                t_one = sorted(oracle_time()[0] for _ in range(3))[1]
+        except ImportError:
+            t_one = None
         cpu_baseline = {
-            "value": 1.0 / t_oracle, "unit": "steps/s", "cores": _cpu_threads(), "kind": "oracle",
+            "value": 1.0 / t_all, "unit": "steps/s", "cores": _cpu_threads(), "kind": "oracle",
             "sample": "one structured float64 oracle solve of the full workload (per-block LAPACK QR, "
                       "Q_i^T applied to B and b, LAPACK QR of the 600,090 x 91 reduced rows, "
-                      "back-substitution); %.2f s" % t_oracle,
+                      "back-substitution): median of 3 after one warm-up, %.2f s on %d threads%s" % (
+                          t_all, _cpu_threads(), "" if t_one is None else ", %.2f s on 1 thread" % t_one),
+            "one_core_value": None if t_one is None else 1.0 / t_one,
+            "blas": _blas_build(),
         }
 
     def rel_err(x):
@@ -646,7 +701,10 @@ def main():
     dom = phase_out[dominant]
     roofline = {"kernel": dominant, "bound": dom.get("bound"), "achieved": dom.get("achieved"),
                 "peak": dom.get("peak"), "unit": dom.get("unit"), "frac": dom.get("frac"),
-                "traffic": measured_traffic(dominant, args.lam, best["mode"])}
+                "traffic": measured_traffic(dominant, args.lam, best["mode"]),
+                # `frac` prices the algorithmic flops against the fp32 vector peak: the Householder
+                # panels run on the VALU, which bounds the phase; the matrix-core share is below
+                "mfma": measured_mfma(dominant, args.lam, best["mode"], dom["avg_ms"])}
 
     if args.copy_calibration:
         x = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda")  # 256 MiB

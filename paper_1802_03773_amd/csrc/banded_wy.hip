@@ -102,7 +102,7 @@ k_bwy(int P, int64_t M, int64_t N, int w, const int32_t* __restrict__ row_start,
           }
           X[rb][2][v] = (live && c == 0) ? bb[row] : 0.f;
         }
-      merge_tile<NCB, NRB, false, BF, 2>(T, X, 0, lds, lane);
+      merge_tile<NCB, NRB, false, BF, 2, true>(T, X, 0, lds, lane);
       i += cnt;
       if (cnt < KT) break;
     }

@@ -133,7 +133,10 @@ __device__ __forceinline__ float rows_from(float x, int c) {
 // not branches, for the reflector itself: the panel stays one straight-line block the scheduler
 // can interleave with the matrix-core updates around it.
 // On return lane (g, c) holds row c of T in trow and s_c in sc.
-template <int RBN>
+// FUSE selects the fused broadcast-FMA groups from a panel's second column on (faster for the
+// two-block tiles of the banded kernel; the dense-part leaves and tree measured a little slower
+// with them and keep the compiler's DPP moves).
+template <int RBN, bool FUSE = false>
 __device__ __forceinline__ void panel_factor(f4& Rd, f4 (&X)[RBN], float (&trow)[16], float& sc, int lane) {
   const int g = lane >> 4;
   const int c = lane & 15;
@@ -147,7 +150,7 @@ __device__ __forceinline__ void panel_factor(f4& Rd, f4 (&X)[RBN], float (&trow)
     // keeps the matrix-core result hazard.  From column 1 on every tile value was last written
     // by column j-1's update on the VALU, which the fused groups' s_nop covers.
     float pr0 = 0.f, pr1 = 0.f;
-    if constexpr (j == 0) {
+    if constexpr (j == 0 || !FUSE) {
 #pragma unroll
       for (int rb = 0; rb < RBN; ++rb)
 #pragma unroll
@@ -173,7 +176,7 @@ __device__ __forceinline__ void panel_factor(f4& Rd, f4 (&X)[RBN], float (&trow)
     const float pd = gram * scale + rrow;  // R[j][c] + w_j^T x_c
     const float s = tau * pd;
     const float nf = (c > j) ? -scale * s : 0.f;
-    if constexpr (j == 0) {
+    if constexpr (j == 0 || !FUSE) {
 #pragma unroll
       for (int rb = 0; rb < RBN; ++rb)
 #pragma unroll
@@ -241,7 +244,7 @@ struct Tri {
 // applied once per row of the small Z products instead of once per tile element.
 // Only the first NPANEL panels are factored; their reflectors are still applied to every
 // column block (the later blocks then hold columns that are carried, not factored).
-template <int NCB, int NRB, bool TRI, bool BF = false, int NPANEL = NCB>
+template <int NCB, int NRB, bool TRI, bool BF = false, int NPANEL = NCB, bool FUSE = false>
 __device__ __forceinline__ void merge_tile(f4 (&R)[Tri<NCB>::count], f4 (&X)[NRB][NCB], int pstart,
                                            float* __restrict__ lds, int lane) {
   const int g = lane >> 4;
@@ -264,7 +267,7 @@ __device__ __forceinline__ void merge_tile(f4 (&R)[Tri<NCB>::count], f4 (&X)[NRB
       f4 Xp[RBN];
 #pragma unroll
       for (int rb = 0; rb < RBN; ++rb) Xp[rb] = X[rb][P];
-      panel_factor<RBN>(R[rp], Xp, trow, sc, lane);
+      panel_factor<RBN, FUSE>(R[rp], Xp, trow, sc, lane);
 #pragma unroll
       for (int rb = 0; rb < RBN; ++rb) X[rb][P] = Xp[rb];
     }
