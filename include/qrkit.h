@@ -57,8 +57,10 @@ typedef enum {
   QRK_ESINGULAR = 4,     /* a pivot of R is (numerically) zero; p is undefined     */
   QRK_ENONFINITE = 5,    /* NaN or Inf met in the inputs or the factor             */
   QRK_ENODEVICE = 6,     /* no usable gfx950 device                                */
-  QRK_ETOOLARGE = 7      /* the request does not fit the fixed scratch array of
+  QRK_ETOOLARGE = 7,     /* the request does not fit the fixed scratch array of
                             qrk_solve_banded_noalloc; nothing was enqueued          */
+  QRK_ENOTCONVERGED = 8  /* qrk_solve_tol used all its sweeps above the tolerance;
+                            p is the last iterate                                   */
 } qrk_status;
 
 typedef enum { QRK_F32 = 0, QRK_F64 = 1 } qrk_dtype;
@@ -211,6 +213,23 @@ qrk_status qrk_set_banded_method(qrk_handle h, int32_t method);
 qrk_status qrk_solve(qrk_handle h, double* p, int32_t sweeps, void* stream);
 
 /* ------------------------------------------------------------------------------
+ * qrk_solve_tol
+ *   qrk_solve with an early stop: the back-substitution, then up to max_sweeps (0..8)
+ *   refinement sweeps, stopping after the first sweep whose correction satisfies
+ *   ||delta||_2 <= rel_tol ||p||_2 for every problem of the handle (rel_tol >= 0, finite).
+ *   p as for qrk_solve.  *sweeps_host [host, may be NULL] receives the sweeps run.  Returns
+ *   QRK_OK when the tolerance was met (or max_sweeps == 0), QRK_ENOTCONVERGED when the sweeps
+ *   ran out first (p is then the last iterate, and the problems still above the tolerance
+ *   carry the status bit 16, which qrk_status_get reports as QRK_ENOTCONVERGED until the next
+ *   factor call).  The norms are summed on the device and read by the host after each sweep,
+ *   so this call synchronises `stream` once per sweep and is not capturable (qrk_solve with a
+ *   fixed sweep count is).  It allocates two small buffers on its first call on a handle.
+ *   QRK_EINVAL for a NULL handle or p, a handle without a factor, or bad max_sweeps / rel_tol.
+ * ------------------------------------------------------------------------------ */
+qrk_status qrk_solve_tol(qrk_handle h, double* p, int32_t max_sweeps, double rel_tol, int32_t* sweeps_host,
+                         void* stream);
+
+/* ------------------------------------------------------------------------------
  * qrk_solve_rhs
  *   The step for a new right-hand side with the stored factor (the paper applies the kept
  *   Q^T to each new b, Section 5.1; here Q is not stored): p = argmin
@@ -263,8 +282,9 @@ qrk_status qrk_get_factor(qrk_handle h, void* Rblk, void* S, void* RB, void* str
 
 /* ------------------------------------------------------------------------------
  * qrk_status_get: synchronises `stream`, returns the worst numerical condition recorded
- * since the last factor call (QRK_OK, QRK_ESINGULAR, QRK_ENONFINITE or QRK_EINVAL for a
- * bad banded row_start) and clears nothing.  *detail_host [host, may be NULL] receives
+ * since the last factor call (QRK_OK, QRK_ESINGULAR, QRK_ENONFINITE, QRK_ENOTCONVERGED after a
+ * qrk_solve_tol that ran out of sweeps, or QRK_EINVAL for a bad banded row_start) and clears
+ * nothing.  *detail_host [host, may be NULL] receives
  * the raw status bits.
  * ------------------------------------------------------------------------------ */
 qrk_status qrk_status_get(qrk_handle h, int32_t* detail_host, void* stream);

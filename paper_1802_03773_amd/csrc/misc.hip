@@ -108,3 +108,42 @@ template hipError_t launch_colnorms<double>(int64_t, int, int, int64_t, const in
                                             const double*, int64_t, double*, double*, int, hipStream_t);
 
 }  // namespace qrk
+
+namespace qrk {
+
+// Per problem q (one workgroup each, unknowns [noff[q], noff[q+1])): out[2q] = sum (p - pold)^2,
+// out[2q+1] = sum p^2, in a fixed order (strided per thread, then a tree in LDS).
+__global__ void __launch_bounds__(256) k_rel_change(const int64_t* __restrict__ noff, const double* __restrict__ p,
+                                                    const double* __restrict__ pold, double* __restrict__ out) {
+  __shared__ double sd[256], sp[256];
+  const int q = blockIdx.x;
+  const int64_t lo = noff[q], hi = noff[q + 1];
+  double a = 0.0, c = 0.0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
+    const double x = p[i], dx = x - pold[i];
+    a += dx * dx;
+    c += x * x;
+  }
+  sd[threadIdx.x] = a;
+  sp[threadIdx.x] = c;
+  __syncthreads();
+  for (int h = 128; h >= 1; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      sd[threadIdx.x] += sd[threadIdx.x + h];
+      sp[threadIdx.x] += sp[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[2 * q] = sd[0];
+    out[2 * q + 1] = sp[0];
+  }
+}
+
+hipError_t launch_rel_change(int P, const int64_t* noff, const double* p, const double* pold, double* out,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_rel_change, dim3((unsigned)P), dim3(256), 0, st, noff, p, pold, out);
+  return hipGetLastError();
+}
+
+}  // namespace qrk

@@ -16,6 +16,7 @@ enum : int {
   ST_NONFINITE = 2,
   ST_BADINPUT = 4,
   ST_STALL = 8,  // a dense-part merge did not see its inputs within its wait bound
+  ST_NOTCONVERGED = 16,  // qrk_solve_tol used all its sweeps above the requested tolerance
 };
 
 constexpr int kWave = 64;

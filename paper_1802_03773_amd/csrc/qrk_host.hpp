@@ -15,6 +15,9 @@ enum HandleKind { KIND_BLOCKANGULAR = 0, KIND_BANDED = 1 };
 
 hipError_t launch_fill_int(int* ptr, int value, hipStream_t st);
 hipError_t launch_fill_double(double* p, int64_t n, double value, hipStream_t st);
+// out[2q], out[2q+1] = sum over problem q's unknowns [noff[q], noff[q+1]) of (p - pold)^2 and p^2
+hipError_t launch_rel_change(int P, const int64_t* noff, const double* p, const double* pold, double* out,
+                             hipStream_t st);
 template <typename T>
 hipError_t launch_to_type(const double* src, T* dst, int64_t n, hipStream_t st);
 template <typename T>
@@ -124,6 +127,8 @@ struct qrk_handle_s {
   double* jubuf = nullptr;
   double* gbuf = nullptr;     // banded: [P][N]
   double* vecpart = nullptr;  // adjoint vector-term partials
+  int64_t* tol_noff = nullptr;   // qrk_solve_tol: unknown offsets [P+1] and norms [2P] (first call)
+  double* tol_norms = nullptr;
 
   // phase timing: event pairs in a ring, summed on read
   struct ProfRec {
@@ -160,6 +165,8 @@ qrk::BatchView blockangular_view(qrk_handle h);
 qrk_status banded_factor(qrk_handle h, hipStream_t st);
 qrk_status banded_solve(qrk_handle h, double* p, int sweeps, hipStream_t st);
 qrk_status banded_refine(qrk_handle h, double* p, int sweeps, const void* b, hipStream_t st);
+// `sweeps` refinement sweeps of a block-angular handle for the right-hand side b (the handle's type)
+qrk_status blockangular_refine(qrk_handle h, double* p, int sweeps, const void* b, hipStream_t st);
 
 // Workspace allocation shared by the create functions (records the allocation in h).
 qrk_status handle_alloc(qrk_handle h, void** out, size_t bytes);

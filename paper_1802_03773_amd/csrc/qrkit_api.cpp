@@ -380,6 +380,11 @@ qrk_status blockangular_factor(qrk_handle h, hipStream_t st) {
   return h->dtype == QRK_F32 ? factor_ba<float>(h, st) : factor_ba<double>(h, st);
 }
 
+qrk_status blockangular_refine(qrk_handle h, double* p, int sweeps, const void* b, hipStream_t st) {
+  return h->dtype == QRK_F32 ? refine_ba<float>(h, p, sweeps, static_cast<const float*>(b), st)
+                             : refine_ba<double>(h, p, sweeps, static_cast<const double*>(b), st);
+}
+
 qrk_status blockangular_solve(qrk_handle h, double* p, int sweeps, hipStream_t st) {
   return h->dtype == QRK_F32 ? solve_ba<float>(h, p, sweeps, st) : solve_ba<double>(h, p, sweeps, st);
 }
@@ -671,6 +676,7 @@ const char* qrk_strerror(qrk_status s) {
     case QRK_ENONFINITE: return "non-finite value in inputs or factor";
     case QRK_ENODEVICE: return "no gfx950 device available";
     case QRK_ETOOLARGE: return "request exceeds the fixed scratch array of the no-allocation entry point";
+    case QRK_ENOTCONVERGED: return "refinement sweeps exhausted above the requested tolerance";
   }
   return "unknown status";
 }
@@ -882,6 +888,7 @@ qrk_status qrk_status_get(qrk_handle h, int32_t* detail_host, void* stream) {
   if (bits & ST_STALL) return QRK_EHIP;
   if (bits & ST_SINGULAR) return QRK_ESINGULAR;
   if (bits & ST_NONFINITE) return QRK_ENONFINITE;
+  if (bits & ST_NOTCONVERGED) return QRK_ENOTCONVERGED;
   return QRK_OK;
 }
 

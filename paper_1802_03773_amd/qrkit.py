@@ -22,7 +22,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "lib", "libqrkit.so")
 HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "qrkit.h")
 
-QRK_OK, QRK_EINVAL, QRK_ENOMEM, QRK_EHIP, QRK_ESINGULAR, QRK_ENONFINITE, QRK_ENODEVICE, QRK_ETOOLARGE = range(8)
+(QRK_OK, QRK_EINVAL, QRK_ENOMEM, QRK_EHIP, QRK_ESINGULAR, QRK_ENONFINITE, QRK_ENODEVICE, QRK_ETOOLARGE,
+ QRK_ENOTCONVERGED) = range(9)
 NOALLOC_SCRATCH_BYTES = 32 << 20
 QRK_F32, QRK_F64 = 0, 1
 QRK_PLAIN, QRK_BF16X3 = 0, 1
@@ -57,6 +58,7 @@ _SIGS = {
     "qrk_set_banded_method": (_c_i32, [_c_vp, _c_i32]),
     "qrk_solve": (_c_i32, [_c_vp, _c_vp, _c_i32, _c_vp]),
     "qrk_solve_rhs": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_i32, _c_vp]),
+    "qrk_solve_tol": (_c_i32, [_c_vp, _c_vp, _c_i32, _c_dbl, _c_i32p, _c_vp]),
     "qrk_solve_adjoint": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp]),
     "qrk_colnorms_blockangular": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_vp]),
     "qrk_get_factor": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_vp]),
@@ -169,6 +171,19 @@ class Factor:
         _check(lib().qrk_solve(self._h, _dev_ptr(out, torch.float64, "p", self.N), int(sweeps),
                                _stream_ptr(stream)), "qrk_solve")
         return out
+
+    def solve_tol(self, max_sweeps: int = 3, rel_tol: float = 1e-12, out=None, stream=None):
+        """Back-substitution, then refinement sweeps until ||delta|| <= rel_tol ||p|| for every
+        problem or max_sweeps ran out.  Returns (p float64, sweeps run, converged)."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty(self.N, dtype=torch.float64, device="cuda")
+        done = _c_i32(0)
+        st = lib().qrk_solve_tol(self._h, _dev_ptr(out, torch.float64, "p", self.N), int(max_sweeps),
+                                 float(rel_tol), ctypes.byref(done), _stream_ptr(stream))
+        if st not in (QRK_OK, QRK_ENOTCONVERGED):
+            _check(st, "qrk_solve_tol")
+        return out, int(done.value), st == QRK_OK
 
     def solve_rhs(self, b, sweeps: int = 4, out=None, stream=None):
         """The step for a new right-hand side b (same J, d, lambda as the last factor), by

@@ -142,3 +142,13 @@ def test_tune_cache_file_parsing(tmp_path):
     bad.write_text('{"version": 1, "entries": {"k": {"leaf_scale": 2}}}')
     assert L.qrk_tune_cache_file(str(bad).encode()) == qrkit.QRK_EINVAL
     assert L.qrk_tune_cache_file(None) == qrkit.QRK_OK
+
+
+def test_solve_tol_rejects_bad_arguments():
+    """qrk_solve_tol validates on the host: no handle or p, negative or too many sweeps, a
+    negative or non-finite tolerance; and the new status has its message."""
+    L = qrkit.lib()
+    done = ctypes.c_int32(-1)
+    assert L.qrk_solve_tol(None, None, 2, 1e-12, ctypes.byref(done), None) == qrkit.QRK_EINVAL
+    assert L.qrk_strerror(qrkit.QRK_ENOTCONVERGED) == b"refinement sweeps exhausted above the requested tolerance"
+    assert L.qrk_strerror(qrkit.QRK_ETOOLARGE).startswith(b"request exceeds")
