@@ -248,6 +248,46 @@ qrk_status qrk_solve_tol(qrk_handle h, double* p, int32_t max_sweeps, double rel
 qrk_status qrk_solve_rhs(qrk_handle h, const void* b, double* p, int32_t sweeps, void* stream);
 
 /* ------------------------------------------------------------------------------
+ * Stored Q (Section 2: Q kept as the object that applies its Householder reflectors;
+ * Sections 5.1 and 5.2: Q^T applied to each new right-hand side with the same factor).
+ * Float32 block-angular handles (single or batched) whose blocks all have m_i >= n.
+ *
+ * qrk_set_keep_q(h, keep)
+ *   keep != 0: every following factor call also stores Q: for each block its n reflectors
+ *   H_j = I - g_j z_j z_j^T over the block's data and damping rows (M n + K n n + K n floats),
+ *   and for the dense part the compact-WY panels (T and the column scales) of every tile each
+ *   leaf merged, whose reflector columns overwrite the reduced rows in the handle's workspace,
+ *   and the panels (T, scales and reflector blocks) of every merge of two triangles.  Together
+ *   about 1.4 times the reduced rows' bytes.  The storage is allocated here and when the leaf
+ *   layout changes (qrk_set_tsqr_shape, autotuning); the factor calls stay capturable.  An LM
+ *   driver graph captured before the call is captured again at its next qrk_lm_run.
+ *   keep == 0: later factor calls store nothing (the storage is kept until qrk_destroy).
+ *   QRK_EINVAL: NULL handle; keep != 0 on a banded or float64 handle, or with a block of
+ *   fewer rows than columns.  QRK_ENOMEM if the storage cannot be allocated.
+ *
+ * qrk_apply_qt(h, b, c, stream)
+ *   c = the first N entries of Q^T [b; 0] for the stored Q of the last factor call, where
+ *   [J; sqrt(lambda) D] = Q [R; 0] with the damping rows of each block and of the dense part
+ *   in the order the factorisation places them (their right-hand side is zero): c_i of every
+ *   block (n entries each), then c_B (nB), per problem, laid out like p.  R and c are unique up
+ *   to the sign of each row of R (qrk_get_factor gives R).  b [M] float (the factor call's b
+ *   layout); c [N] double, written (computed in float32 except the per-block stage, float64).
+ *   Work space is the handle's; calls on one handle must not overlap.  QRK_EINVAL: NULL
+ *   argument, or the last factor call did not store Q.
+ *
+ * qrk_solve_qt(h, b, p, sweeps, stream)
+ *   The step for a new right-hand side by the stored Q: p = R^{-1} (Q^T b) as qrk_apply_qt
+ *   computes it, then `sweeps` (0..8) refinement sweeps for b as in qrk_solve_rhs.  One pass
+ *   over the stored reflectors instead of qrk_solve_rhs's sweeps over J: sweeps = 0 gives the
+ *   factor's own accuracy (as qrk_solve with sweeps = 0 does for the factor call's b).  The
+ *   handle's borrowed b and its factor are unchanged; pivot and finiteness conditions go to
+ *   the status word.  QRK_EINVAL as for qrk_apply_qt, or sweeps outside 0..8.
+ * ------------------------------------------------------------------------------ */
+qrk_status qrk_set_keep_q(qrk_handle h, int32_t keep);
+qrk_status qrk_apply_qt(qrk_handle h, const void* b, double* c, void* stream);
+qrk_status qrk_solve_qt(qrk_handle h, const void* b, double* p, int32_t sweeps, void* stream);
+
+/* ------------------------------------------------------------------------------
  * qrk_solve_adjoint
  *   For a loss L(p) of the step p (from qrk_solve on this handle) and g = dL/dp,
  *   with u = (R^T R)^{-1} g (two triangular solves with the stored R; R^T R =

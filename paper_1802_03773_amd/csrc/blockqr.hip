@@ -54,7 +54,7 @@ template <typename T>
 hipError_t launch_blockqr(const int32_t* blk_list, int64_t begin, int64_t count, int cls, int n, int probs_count,
                           const ProbDesc* probs, const int32_t* blk_prob, const int64_t* row_off, const T* A,
                           const T* B, const T* b, const double* d, const double* lam, T* Rblk, T* Sc, T* Red,
-                          const BqrPrologue& pro, hipStream_t st) {
+                          const BqrPrologue& pro, const QKeep& qk, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   const int32_t* bp = probs_count == 1 ? nullptr : blk_prob;
   const int rows = block_class_rows(cls), slots = block_class_slots(cls);
@@ -62,14 +62,16 @@ hipError_t launch_blockqr(const int32_t* blk_list, int64_t begin, int64_t count,
     switch (n) {
 #define QRK_N(NN) \
   case NN:        \
-    return launch_blockqr_n<T, NN>(blk_list, begin, count, rows, slots, probs, bp, row_off, A, B, b, d, lam, Rblk, Sc, Red, pro, st);
+    return launch_blockqr_n<T, NN>(blk_list, begin, count, rows, slots, probs, bp, row_off, A, B, b, d, lam, Rblk, Sc, Red, pro, qk, st);
       QRK_N(1) QRK_N(2) QRK_N(3) QRK_N(4) QRK_N(5) QRK_N(6) QRK_N(7) QRK_N(8)
 #undef QRK_N
       default:
         return hipErrorInvalidValue;
     }
   }
-  // blocks with fewer rows than columns: run-time n, 16 register rows
+  // blocks with fewer rows than columns: run-time n, 16 register rows (their reflectors are not
+  // kept: the handle refuses a stored Q when it has such blocks)
+  if (qk.vd) return hipErrorInvalidValue;
   const int grid = (int)((count + 3) / 4 < 2048 ? (count + 3) / 4 : 2048);
   if (slots == 1)
     hipLaunchKernelGGL((k_blockqr<T, 16, 1>), dim3(grid), dim3(256), 0, st, blk_list, begin, count, n, probs, bp,
@@ -84,7 +86,7 @@ hipError_t launch_blockqr(const int32_t* blk_list, int64_t begin, int64_t count,
   template hipError_t launch_blockqr<T>(const int32_t*, int64_t, int64_t, int, int, int, const ProbDesc*, \
                                         const int32_t*, const int64_t*, const T*, const T*, const T*,       \
                                         const double*, const double*, T*, T*, T*, const BqrPrologue&,       \
-                                        hipStream_t);
+                                        const QKeep&, hipStream_t);
 QRK_INST(float)
 QRK_INST(double)
 #undef QRK_INST

@@ -89,11 +89,15 @@ __device__ __forceinline__ T buf_ld(__amdgpu_buffer_rsrc_t rs, uint32_t voff, ui
 // red at the block's first reduced row (row stride ldr).  Requires N <= m <= ROWS - N,
 // nB + 1 <= 64 * SLOTS and (m - 1) * ldb * sizeof(T) < 2^31.  All scalar arguments are
 // wave-uniform.
+// qv: when non-null, the block's reflectors are stored (QKeep layout): qvd at the block's first
+// data row (row stride N), qvp at its damping rows (N x N), qg its g_j (N).
 template <typename T, int N, int ROWS, int SLOTS>
 __device__ __forceinline__ void block_qr_wave_n(int nB, int m, int ldb, int ldr, const T* __restrict__ A,
                                                 const T* __restrict__ B, const T* __restrict__ bvec,
                                                 const double* __restrict__ d, double sqrt_lam, T* __restrict__ Rb,
-                                                T* __restrict__ Scb, T* __restrict__ red, int lane) {
+                                                T* __restrict__ Scb, T* __restrict__ red, int lane,
+                                                T* __restrict__ qvd = nullptr, T* __restrict__ qvp = nullptr,
+                                                T* __restrict__ qg = nullptr) {
   static_assert(N >= 1 && N <= 8 && ROWS >= 2 * N, "block shape");
   constexpr int RD = ROWS - N;  // first damping row
   __builtin_assume(m >= N && m <= RD);
@@ -140,6 +144,7 @@ __device__ __forceinline__ void block_qr_wave_n(int nB, int m, int ldb, int ldr,
     }
   }
 
+  T zsave = T(0), gsave = T(0);  // lane k: z_k's pivot entry and g_k (for the stored Q)
 #pragma unroll
   for (int k = 0; k < N; ++k) {
     // lane k's column: alpha = a_k, sigma = sum of squares below the pivot
@@ -181,7 +186,7 @@ __device__ __forceinline__ void block_qr_wave_n(int nB, int m, int ldb, int ldr,
 #pragma unroll
     for (int r = k + 1; r < ROWS; ++r) zr[r] = lane_value(a[r], k);
 
-    auto apply = [&](T* col) {
+    auto apply = [&](T* col, bool skip) {
       T u0 = zk * col[k], u1 = T(0);
 #pragma unroll
       for (int r = k + 1; r < ROWS; ++r) {
@@ -190,15 +195,33 @@ __device__ __forceinline__ void block_qr_wave_n(int nB, int m, int ldb, int ldr,
         else
           u0 += zr[r] * col[r];
       }
-      const T t = -(u0 + u1) * g;  // col <- col - g (z^T col) z
+      const T t = skip ? T(0) : -(u0 + u1) * g;  // col <- col - g (z^T col) z
       col[k] += t * zk;
 #pragma unroll
       for (int r = k + 1; r < ROWS; ++r) col[r] += t * zr[r];
     };
-    if (k + 1 < N) apply(a);  // columns right of k (lanes > k); lane k's own is set below
+    // columns right of k (lanes > k); the finished columns (lanes <= k) are left alone, so that
+    // lane j keeps its reflector's entries below row j (R's entries there are not used)
+    if (k + 1 < N) apply(a, lane <= k);
 #pragma unroll
-    for (int s = 0; s < SLOTS; ++s) apply(c[s]);
+    for (int s = 0; s < SLOTS; ++s) apply(c[s], false);
+    if (lane == k) {
+      zsave = z0;
+      gsave = g;
+    }
     a[k] = lane == k ? beta : a[k];
+  }
+  // the reflectors: lane j < N writes z_j (data rows, damping rows) and g_j
+  if (qvd != nullptr && lane < N) {
+    const uint32_t jo = (uint32_t)lane * (uint32_t)sizeof(T);
+    int ms = m;
+    asm("" : "+s"(ms));
+#pragma unroll
+    for (int r = 0; r < RD; ++r)
+      if (r < ms) st_row(qvd + r * N, jo, r > lane ? a[r] : (r == lane ? zsave : T(0)));
+#pragma unroll
+    for (int t = 0; t < N; ++t) st_row(qvp + t * N, jo, a[RD + t]);
+    qg[lane] = gsave;
   }
 
   // R_i: lane j < N holds column j (rows above the diagonal and the diagonal)

@@ -17,7 +17,7 @@ k_blockqr_n(const int32_t* __restrict__ blk_list, int64_t begin, int64_t count,
             const ProbDesc* __restrict__ probs, const int32_t* __restrict__ blk_prob,
             const int64_t* __restrict__ row_off, const T* __restrict__ A, const T* __restrict__ B,
             const T* __restrict__ bvec, const double* __restrict__ d, const double* __restrict__ lam,
-            T* __restrict__ Rblk, T* __restrict__ Sc, T* __restrict__ Red, BqrPrologue pro) {
+            T* __restrict__ Rblk, T* __restrict__ Sc, T* __restrict__ Red, BqrPrologue pro, QKeep qk) {
   bqr_prologue<256>(pro);
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -33,19 +33,22 @@ k_blockqr_n(const int32_t* __restrict__ blk_list, int64_t begin, int64_t count,
   block_qr_wave_n<T, N, ROWS, SLOTS>(P.nB, m, (int)P.ldb, (int)P.ldr, A + r0 * N, B + P.boff + rl * P.ldb,
                                      bvec + r0, d + P.noff + lb * N, sqrt(pro.lam_out ? pro.lam_val : lam[pi]),
                                      Rblk + blk * (N * N),
-                                     Sc + P.soff + lb * N * P.L, Red + P.redoff + rl * P.ldr, lane);
+                                     Sc + P.soff + lb * N * P.L, Red + P.redoff + rl * P.ldr, lane,
+                                     qk.vd ? static_cast<T*>(qk.vd) + r0 * N : nullptr,
+                                     qk.vd ? static_cast<T*>(qk.vp) + blk * (N * N) : nullptr,
+                                     qk.vd ? static_cast<T*>(qk.g) + blk * N : nullptr);
 }
 
 template <typename T, int N>
 hipError_t launch_blockqr_n(const int32_t* blk_list, int64_t begin, int64_t count, int rows, int slots,
                             const ProbDesc* probs, const int32_t* blk_prob, const int64_t* row_off, const T* A,
                             const T* B, const T* b, const double* d, const double* lam, T* Rblk, T* Sc, T* Red,
-                            const BqrPrologue& pro, hipStream_t st) {
+                            const BqrPrologue& pro, const QKeep& qk, hipStream_t st) {
   if ((count + 3) / 4 > 0x7fffffff) return hipErrorInvalidValue;
   dim3 blk(256), grd((unsigned)((count + 3) / 4));
 #define QRK_BQRN(R, S)                                                                                   \
   hipLaunchKernelGGL((k_blockqr_n<T, N, R, S>), grd, blk, 0, st, blk_list, begin, count, probs, blk_prob, \
-                     row_off, A, B, b, d, lam, Rblk, Sc, Red, pro)
+                     row_off, A, B, b, d, lam, Rblk, Sc, Red, pro, qk)
   if (rows == 16) {
     if (slots == 1) QRK_BQRN(16, 1); else QRK_BQRN(16, 2);
   } else if (rows == 32) {
@@ -63,6 +66,6 @@ hipError_t launch_blockqr_n(const int32_t* blk_list, int64_t begin, int64_t coun
   template hipError_t launch_blockqr_n<T, N>(const int32_t*, int64_t, int64_t, int, int, const ProbDesc*, \
                                              const int32_t*, const int64_t*, const T*, const T*, const T*, \
                                              const double*, const double*, T*, T*, T*, const BqrPrologue&, \
-                                             hipStream_t);
+                                             const QKeep&, hipStream_t);
 
 }  // namespace qrk

@@ -17,6 +17,19 @@ constexpr int kMaxDense = 128;  // nB + 1 <= 128
 // (a device work queue of leaves, widest problems first); wider ones have a launch per width.
 constexpr int kQueueNCB = 6;
 
+// Dense-part leaves stream tiles of this many rows: 128 up to 4 column blocks, 64 beyond (taller
+// tiles no longer fit the register file there).
+constexpr int leaf_tile_rows(int ncb) { return ncb <= 4 ? 128 : 64; }
+
+// Stored Q of the float32 dense part: per 16-column panel, T (16 x 16, row-major), the column
+// scales (16, padded to 64) and the raw reflector blocks W (16 x 16 each, row-major, block row
+// rb at float 320 + 256 rb).  A tile merged into a leaf keeps nrb = leaf_tile_rows / 16 blocks
+// per panel (tile_panel_floats each, panel p at p * tile_panel_floats); a merge of two
+// triangles keeps p + 1 blocks for panel p (the rows of the right triangle it touches), panel p
+// at node_panel_off(p), a node of ncb column blocks taking node_panel_off(ncb).
+constexpr int64_t tile_panel_floats(int nrb) { return 320 + 256 * (int64_t)nrb; }
+constexpr int64_t node_panel_off(int p) { return (int64_t)p * (256 + 64) + 256 * ((int64_t)p * (p + 1) / 2); }
+
 struct ProbDesc {
   int64_t koff, K;        // first global block, blocks
   int64_t moff, M;        // first global row, rows
@@ -28,6 +41,8 @@ struct ProbDesc {
   int64_t slot0, ctr0;    // merge tree: first slot float, first arrival counter
   int64_t rows_per_leaf;  // dense-part QR: rows per leaf
   int64_t pack0, npacks;  // packs of whole blocks (global index of the first)
+  int64_t qt0, qtiles;    // stored Q: first float of the leaves' tile panels, tiles per leaf
+  int64_t qn0, qc0;       // stored Q: first float of the merge nodes' panels, of the apply's merge vectors
   int32_t nB, L;          // coupled columns, L = nB + 1
   int32_t leaves;         // dense-part QR leaves
   int32_t wg0, nwg;       // refinement workgroups [wg0, wg0 + nwg)
@@ -46,6 +61,17 @@ struct BqrPrologue {
   int64_t n1 = 0;
   double* lam_out = nullptr;
   double lam_val = 0.0;
+};
+
+// Where a factor call keeps the per-block reflectors (the stored Q of qrk_set_keep_q; null
+// pointers: not kept).  Block i's reflector j is H_j = I - g_j z_j z_j^T over the block's data
+// rows and damping rows: vd [M x n] holds z_j at the data rows (row-major like A; z_j is zero
+// above row j), vp [K x n x n] its entries at the damping rows ([block][damping row][j]), and
+// g [K x n] the g_j.
+struct QKeep {
+  void* vd = nullptr;
+  void* vp = nullptr;
+  void* g = nullptr;
 };
 
 // Device view of a handle's batch, passed to the launchers.

@@ -129,6 +129,19 @@ struct qrk_handle_s {
   double* vecpart = nullptr;  // adjoint vector-term partials
   int64_t* tol_noff = nullptr;   // qrk_solve_tol: unknown offsets [P+1] and norms [2P] (first call)
   double* tol_norms = nullptr;
+  // stored Q (qrk_set_keep_q; float32 block-angular handles): the per-block reflectors (qk), the
+  // compact-WY panels of the dense-part tiles and merge nodes (offsets in the ProbDescs), and
+  // the application's work space: the reduced right-hand side [M] and the merge vectors
+  bool keep_q = false;
+  bool q_valid = false;          // the last factor call stored Q
+  qrk::QKeep qk;
+  float* q_tiles = nullptr;
+  float* q_nodes = nullptr;
+  float* q_xr = nullptr;
+  float* q_u = nullptr;
+  int64_t q_tiles_cap = 0, q_nodes_cap = 0, q_u_cap = 0;  // floats
+  int64_t q_tiles_n = 0, q_nodes_n = 0, q_u_n = 0;        // floats the current layout needs
+  double* q_c = nullptr;         // Q^T b of qrk_solve_qt, laid out like p [N]
 
   // phase timing: event pairs in a ring, summed on read
   struct ProfRec {
@@ -167,6 +180,10 @@ qrk_status banded_solve(qrk_handle h, double* p, int sweeps, hipStream_t st);
 qrk_status banded_refine(qrk_handle h, double* p, int sweeps, const void* b, hipStream_t st);
 // `sweeps` refinement sweeps of a block-angular handle for the right-hand side b (the handle's type)
 qrk_status blockangular_refine(qrk_handle h, double* p, int sweeps, const void* b, hipStream_t st);
+
+// Stored Q: allocate the storage the current leaf layout needs (set_keep_q and every layout
+// change while it is on).
+qrk_status ensure_q_storage(qrk_handle h);
 
 // Workspace allocation shared by the create functions (records the allocation in h).
 qrk_status handle_alloc(qrk_handle h, void** out, size_t bytes);

@@ -19,7 +19,7 @@ template <typename T>
 hipError_t launch_blockqr(const int32_t* blk_list, int64_t begin, int64_t count, int cls, int n, int probs_count,
                           const ProbDesc* probs, const int32_t* blk_prob, const int64_t* row_off, const T* A,
                           const T* B, const T* b, const double* d, const double* lam, T* Rblk, T* Sc, T* Red,
-                          const BqrPrologue& pro, hipStream_t st);
+                          const BqrPrologue& pro, const QKeep& qk, hipStream_t st);
 
 // Per-block QR with compile-time block width N, for blocks with m_i >= N (rows: 16, 32 or
 // 64 register rows, m_i + N <= rows; slots: 1 or 2, nB + 1 <= 64 slots).
@@ -27,7 +27,7 @@ template <typename T, int N>
 hipError_t launch_blockqr_n(const int32_t* blk_list, int64_t begin, int64_t count, int rows, int slots,
                             const ProbDesc* probs, const int32_t* blk_prob, const int64_t* row_off, const T* A,
                             const T* B, const T* b, const double* d, const double* lam, T* Rblk, T* Sc, T* Red,
-                            const BqrPrologue& pro, hipStream_t st);
+                            const BqrPrologue& pro, const QKeep& qk, hipStream_t st);
 
 // Stream rows [g*rows_per_wg, (g+1)*rows_per_wg) of X (nrows x L, row stride ldx) into
 // an L x L upper-triangular R per workgroup g (Householder merges); workgroup 0 starts
@@ -51,7 +51,7 @@ hipError_t launch_zero_ints(int* p, int64_t n, hipStream_t st);
 // nnodes inner nodes in level order (node_l / node_r child references, r < 0 leaf -1 - r),
 // flags[nnodes * ncb] cleared beforehand; ncb <= 6.  The root writes R_B | c_B.
 hipError_t launch_tsqr_tree(int ncb, const ProbDesc* probs, const int32_t* node_l, const int32_t* node_r,
-                            int nnodes, float* slots, int* flags, float* RB, int* status, hipStream_t st);
+                            int nnodes, float* slots, int* flags, float* RB, int* status, float* qn, hipStream_t st);
 // Leaves of classes 8 and 7 by their launches; the leaves from queue_begin on (classes
 // kQueueNCB .. 1, listed widest first) by one persistent launch of at most `cus` workgroups
 // that takes them from the device counter *qhead (cleared with the counters) when use_queue is
@@ -60,16 +60,27 @@ hipError_t launch_tsqr_mfma(bool bf16x3, const int* cls_begin, const int* cls_co
                             int cus,
                             const int32_t* leaf_prob, const int32_t* leaf_idx, const ProbDesc* probs, int n,
                             const float* Red, const double* d, const double* lam, float* slots, int* counters,
-                            int64_t nctr, int* qhead, float* RB, hipStream_t st);
+                            int64_t nctr, int* qhead, float* RB, float* qt, float* qn, hipStream_t st);
 
-// R_B p_B = c_B for every problem (RB_p is L x L with c_B in column L-1); writes p_B.
+// R_B p_B = c_B for every problem (RB_p is L x L with c_B in column L-1, or c_B from cext,
+// laid out like p, when that is given); writes p_B.
 template <typename T>
-hipError_t launch_backsub_dense(const BatchView& bv, const T* RB, double* p, int* status, hipStream_t st);
+hipError_t launch_backsub_dense(const BatchView& bv, const T* RB, double* p, int* status, hipStream_t st,
+                                const double* cext = nullptr);
 
-// p_i = R_i^{-1} (c_i - S_i p_B) for every block; p_B read from p.
+// p_i = R_i^{-1} (c_i - S_i p_B) for every block (c_i from S|c, or from cext laid out like p);
+// p_B read from p.
 template <typename T>
 hipError_t launch_backsub_blocks(const BatchView& bv, const T* Rblk, const T* Sc, double* p, int* status,
-                                 hipStream_t st);
+                                 hipStream_t st, const double* cext = nullptr);
+
+// Q^T b with the stored Q of a float32 block-angular factor (stored_q.hip): b [M] float, the
+// first N entries (laid out like p) to c; xr [M], uslots and counters[0 .. nctr) are work
+// space (the counters are cleared here).
+hipError_t launch_apply_qt(const BatchView& bv, const int* cls_begin, const int* cls_count,
+                           const int32_t* leaf_prob, const int32_t* leaf_idx, const float* b, const QKeep& qk,
+                           const float* qt, const float* qn, float* xr, float* uslots, int* counters,
+                           int64_t nctr, double* c, hipStream_t st);
 
 // Refinement, pass 1: per pack of whole blocks (at most 64 rows): r = b - J p,
 // g_i = A_i^T r - lam d_i^2 p_i, y_i = R_i^{-T} g_i, and per-workgroup partial sums of

@@ -90,6 +90,9 @@ qrk_status factor_ba(qrk_handle h, hipStream_t st, const double* lam_host = null
     pro.lam_out = h->lam_d;
     pro.lam_val = *lam_host;
   }
+  // the stored Q (float32 only): per-block reflectors, tile and node panels
+  const bool keep = std::is_same<T, float>::value && h->keep_q && h->qk.vd != nullptr;
+  h->q_valid = false;
   int pr = prof_begin(h, 0, st);
   // without a list, the one class present covers blocks 0 .. K-1 in order
   const int32_t* list = h->blk_list_n > 0 ? h->blk_list : nullptr;
@@ -98,7 +101,8 @@ qrk_status factor_ba(qrk_handle h, hipStream_t st, const double* lam_host = null
     if (h->bq_count[c] == 0) continue;
     if (h->bq_begin[c] < 0 || h->bq_begin[c] + h->bq_count[c] > extent) return QRK_EINVAL;
     if (launch_blockqr<T>(list, h->bq_begin[c], h->bq_count[c], c, h->n, h->P, h->probs_d, h->blk_prob,
-                          h->row_off_d, A, B, b, h->d, h->lam_ptr, Rblk, Sc, Red, pro, st) != hipSuccess)
+                          h->row_off_d, A, B, b, h->d, h->lam_ptr, Rblk, Sc, Red, pro, keep ? h->qk : QKeep(),
+                          st) != hipSuccess)
       return QRK_EHIP;
     pro = BqrPrologue();  // later launches: nothing to clear, lambda on the device
   }
@@ -108,13 +112,15 @@ qrk_status factor_ba(qrk_handle h, hipStream_t st, const double* lam_host = null
     pr = prof_begin(h, 1, st);
     if (launch_tsqr_mfma(h->mode == QRK_BF16X3, h->cls_begin, h->cls_count, h->queue_begin, h->leaf_queue != 0, h->cus,
                          h->leaf_prob, h->leaf_idx, h->probs_d, h->n, Red, h->d, h->lam_ptr, h->slots, h->counters,
-                         h->nctr, h->counters + h->qhead_off, RB, st) != hipSuccess)
+                         h->nctr, h->counters + h->qhead_off, RB, keep ? h->q_tiles : nullptr,
+                         keep ? h->q_nodes : nullptr, st) != hipSuccess)
       return QRK_EHIP;
     if (h->nnodes > 0 &&
         launch_tsqr_tree((h->probs_h[0].L + 15) / 16, h->probs_d, h->node_l, h->node_r, h->nnodes, h->slots,
-                         h->counters, RB, h->status, st) != hipSuccess)
+                         h->counters, RB, h->status, keep ? h->q_nodes : nullptr, st) != hipSuccess)
       return QRK_EHIP;
     prof_end(h, pr, st);
+    h->q_valid = keep;
     return QRK_OK;
   }
   // float64 dense parts, problem by problem: leaves, then the reduction tree (ping-pong
@@ -315,6 +321,22 @@ qrk_status assign_leaves(qrk_handle h) {
         ctr += ts.counters;
       }
     }
+    // stored Q: tile panels of every leaf, node panels of the leaves - 1 merges, and the
+    // application's merge vectors (128 floats per tree slot)
+    int64_t qt = 0, qn = 0, qu = 0;
+    for (auto& D : pd) {
+      const int ncb = (D.L + 15) / 16;
+      D.qtiles = ceil_div(D.rows_per_leaf, (int64_t)leaf_tile_rows(ncb));
+      D.qt0 = qt;
+      qt += (int64_t)D.leaves * D.qtiles * ncb * tile_panel_floats(leaf_tile_rows(ncb) / 16);
+      D.qn0 = qn;
+      qn += (int64_t)(D.leaves - 1) * node_panel_off(ncb);
+      D.qc0 = qu;
+      qu += tree_size(D.leaves).slots * 128;
+    }
+    h->q_tiles_n = std::max<int64_t>(qt, 1);
+    h->q_nodes_n = std::max<int64_t>(qn, 1);
+    h->q_u_n = std::max<int64_t>(qu, 1);
     h->qhead_off = ctr;  // the persistent leaf launch's queue head, cleared with the counters
     ctr += 1;
     h->nctr = ctr;
@@ -369,10 +391,43 @@ qrk_status assign_leaves(qrk_handle h) {
   if (hipMemcpy(h->probs_d, pd.data(), sizeof(ProbDesc) * P, hipMemcpyHostToDevice) != hipSuccess)
     return QRK_EHIP;
   ++h->shape_gen;
-  return QRK_OK;
+  h->q_valid = false;
+  return ensure_q_storage(h);
 }
 
 }  // namespace
+
+qrk_status ensure_q_storage(qrk_handle h) {
+  if (!h->keep_q) return QRK_OK;
+  qrk_status s;
+  const size_t es = sizeof(float);
+  if (!h->qk.vd) {
+    void *vd = nullptr, *vp = nullptr, *g = nullptr;
+    if ((s = dalloc(h, &vd, es * (size_t)std::max<int64_t>(h->M * h->n, 1))) != QRK_OK ||
+        (s = dalloc(h, &vp, es * (size_t)std::max<int64_t>(h->K * h->n * h->n, 1))) != QRK_OK ||
+        (s = dalloc(h, &g, es * (size_t)std::max<int64_t>(h->K * h->n, 1))) != QRK_OK ||
+        (s = dalloc(h, &h->q_xr, es * (size_t)std::max<int64_t>(h->M, 1))) != QRK_OK ||
+        (s = dalloc(h, &h->q_c, sizeof(double) * (size_t)std::max<int64_t>(h->N, 1))) != QRK_OK)
+      return s;
+    h->qk.vd = vd;
+    h->qk.vp = vp;
+    h->qk.g = g;
+  }
+  auto grow = [&](float** ptr, int64_t* cap, int64_t need) -> qrk_status {
+    if (need <= *cap) return QRK_OK;
+    dfree(h, *ptr);
+    *ptr = nullptr;
+    *cap = 0;
+    const qrk_status s2 = dalloc(h, ptr, es * (size_t)need);
+    if (s2 == QRK_OK) *cap = need;
+    return s2;
+  };
+  if ((s = grow(&h->q_tiles, &h->q_tiles_cap, h->q_tiles_n)) != QRK_OK ||
+      (s = grow(&h->q_nodes, &h->q_nodes_cap, h->q_nodes_n)) != QRK_OK ||
+      (s = grow(&h->q_u, &h->q_u_cap, h->q_u_n)) != QRK_OK)
+    return s;
+  return QRK_OK;
+}
 
 qrk_status handle_alloc(qrk_handle h, void** out, size_t bytes) { return dalloc(h, out, bytes); }
 
@@ -727,6 +782,7 @@ qrk_status qrk_factor_lambda(qrk_handle h, double lambda, void* stream) {
   const int L = h->nB + 1;
   const int64_t Kn = h->K * n;
   qrk_status s;
+  h->q_valid = false;  // the stored Q is that of J alone, not of the new factor
   if (!h->lam_base_saved) {
     if (h->lam != 0.0) return QRK_EINVAL;  // the current factor must be that of J alone
     if (!h->lam_stage) {

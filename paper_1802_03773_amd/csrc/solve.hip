@@ -131,12 +131,12 @@ __device__ __forceinline__ void wave_bwd(const float* Rs, const double* Rsd, int
 
 // ---------------------------------------------------------------------------------
 // Dense part of the back-substitution: R_B p_B = c_B, one workgroup (one working wave)
-// per problem.
+// per problem.  c_B is column L-1 of R_B | c_B, or cext (laid out like p) when that is given.
 // ---------------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_backsub_dense(const ProbDesc* __restrict__ probs, int n, const T* __restrict__ RBall, double* __restrict__ p,
-                int* __restrict__ status) {
+                int* __restrict__ status, const double* __restrict__ cext) {
   __shared__ float Rs[sizeof(T) == 4 ? kMaxDense * kMaxDense : 1];
   __shared__ double Rsd[sizeof(T) == 8 ? kMaxDense * kMaxDense : 1];
   const int pi = blockIdx.x;
@@ -147,8 +147,8 @@ k_backsub_dense(const ProbDesc* __restrict__ probs, int n, const T* __restrict__
   __syncthreads();
   if (threadIdx.x >= 64) return;
   const int lane = threadIdx.x;
-  double v0 = lane < nB ? rs_at<T>(Rs, Rsd, lane * L + nB) : 0.0;
-  double v1 = lane + 64 < nB ? rs_at<T>(Rs, Rsd, (lane + 64) * L + nB) : 0.0;
+  double v0 = lane < nB ? (cext ? cext[off + lane] : rs_at<T>(Rs, Rsd, lane * L + nB)) : 0.0;
+  double v1 = lane + 64 < nB ? (cext ? cext[off + lane + 64] : rs_at<T>(Rs, Rsd, (lane + 64) * L + nB)) : 0.0;
   // largest pivot magnitude: each lane its own diagonal entries, then a wave maximum
   const double dg0 = lane < nB ? fabs(rs_at<T>(Rs, Rsd, lane * L + lane)) : 0.0;
   const double dg1 = lane + 64 < nB ? fabs(rs_at<T>(Rs, Rsd, (lane + 64) * L + lane + 64)) : 0.0;
@@ -175,9 +175,10 @@ k_backsub_dense(const ProbDesc* __restrict__ probs, int n, const T* __restrict__
 }
 
 template <typename T>
-hipError_t launch_backsub_dense(const BatchView& bv, const T* RB, double* p, int* status, hipStream_t st) {
+hipError_t launch_backsub_dense(const BatchView& bv, const T* RB, double* p, int* status, hipStream_t st,
+                                const double* cext) {
   if (bv.max_L > kMaxDense) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_backsub_dense<T>), dim3(bv.P), dim3(256), 0, st, bv.probs, bv.n, RB, p, status);
+  hipLaunchKernelGGL((k_backsub_dense<T>), dim3(bv.P), dim3(256), 0, st, bv.probs, bv.n, RB, p, status, cext);
   return hipGetLastError();
 }
 
@@ -202,7 +203,9 @@ __device__ __forceinline__ T buf_ld_row(__amdgpu_buffer_rsrc_t rs, uint32_t voff
 //   MODE 0 back-substitution: base_i = c_i (column nB of S|c, staged with weight -1),
 //                             v = p_B, p_i set, pivot and finiteness status;
 //   MODE 1 refinement:        base_i = y_i, v = delta_B, p_i incremented;
-//   MODE 2 adjoint:           base_i = y_i, v = u_B, u_i set.
+//   MODE 2 adjoint:           base_i = y_i, v = u_B, u_i set;
+//   MODE 3 back-substitution for a given c (laid out like p, in ybase): base_i = c_i,
+//                             v = p_B, p_i set, pivot and finiteness status.
 // ---------------------------------------------------------------------------------
 template <typename T, int N, int MODE>
 __global__ void __launch_bounds__(256)
@@ -250,7 +253,7 @@ k_blocks_solve_n(const ProbDesc* __restrict__ probs, const int32_t* __restrict__
     for (int e = 0; e < N * N; ++e) Rb[e] = Rblk[blk * (N * N) + e];
     double base[N];
 #pragma unroll
-    for (int c = 0; c < N; ++c) base[c] = MODE == 0 ? 0.0 : ybase[blk * N + c];
+    for (int c = 0; c < N; ++c) base[c] = MODE == 0 ? 0.0 : (MODE == 3 ? ybase[noff + lb * N + c] : ybase[blk * N + c]);
     double xold[N];
 #pragma unroll
     for (int c = 0; c < N; ++c) xold[c] = MODE == 1 ? x[noff + lb * N + c] : 0.0;
@@ -308,7 +311,7 @@ k_blocks_solve_n(const ProbDesc* __restrict__ probs, const int32_t* __restrict__
         xo[c] = MODE == 1 ? xold[c] + out[c] : out[c];
         nonfinite |= !is_finite(out[c]);
       }
-      if (MODE == 0 && status) {
+      if ((MODE == 0 || MODE == 3) && status) {
         double dmax = 0.0;
 #pragma unroll
         for (int c = 0; c < N; ++c) dmax = fmax(dmax, fabs((double)Rb[c * N + c]));
@@ -346,7 +349,8 @@ static hipError_t launch_blocks_solve(const BatchView& bv, const T* Rblk, const 
 
 template <typename T>
 hipError_t launch_backsub_blocks(const BatchView& bv, const T* Rblk, const T* Sc, double* p, int* status,
-                                 hipStream_t st) {
+                                 hipStream_t st, const double* cext) {
+  if (cext) return launch_blocks_solve<T, 3>(bv, Rblk, Sc, p, cext, p, status, st);
   return launch_blocks_solve<T, 0>(bv, Rblk, Sc, p, nullptr, p, status, st);
 }
 
@@ -694,9 +698,10 @@ hipError_t launch_adjoint_dense(const BatchView& bv, const double* part, const T
 }
 
 #define QRK_INST(T)                                                                                      \
-  template hipError_t launch_backsub_dense<T>(const BatchView&, const T*, double*, int*, hipStream_t);     \
+  template hipError_t launch_backsub_dense<T>(const BatchView&, const T*, double*, int*, hipStream_t,      \
+                                              const double*);                                            \
   template hipError_t launch_backsub_blocks<T>(const BatchView&, const T*, const T*, double*, int*,        \
-                                               hipStream_t);                                             \
+                                               hipStream_t, const double*);                              \
   template hipError_t launch_refine_residual<T>(const BatchView&, const T*, const T*, const T*,             \
                                                 const double*, const T*, const T*, const double*, double*, \
                                                 double*, hipStream_t);                                   \

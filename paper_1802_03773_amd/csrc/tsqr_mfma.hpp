@@ -227,6 +227,14 @@ __device__ __forceinline__ BfPair bf_split(const float (&x)[8]) {
 
 constexpr int kWaveLds = 256 + 256 + 256 * 8;  // T staging, scales, W staging (up to 8 blocks)
 
+// The kept panels of a merge of two triangles (per-wave LDS in the merge tree, and the stored Q
+// of a merge node), in the node_panel_off layout of qrk_batch.hpp.
+template <int NCB>
+struct TreeKeep {
+  static constexpr int off(int p) { return (int)node_panel_off(p); }
+  static constexpr int total = off(NCB);
+};
+
 template <int NCB>
 struct Tri {
   static constexpr int count = NCB * (NCB + 1) / 2;
@@ -244,9 +252,12 @@ struct Tri {
 // applied once per row of the small Z products instead of once per tile element.
 // Only the first NPANEL panels are factored; their reflectors are still applied to every
 // column block (the later blocks then hold columns that are carried, not factored).
+// qkeep (may be null): where the panels' compact-WY factors (T, the scales and the raw
+// reflector blocks, qrk_batch.hpp) are stored for a later Q^T: panel P at P * tile_panel_floats
+// for a dense tile, at TreeKeep<NCB>::off(P) for a triangle.
 template <int NCB, int NRB, bool TRI, bool BF = false, int NPANEL = NCB, bool FUSE = false>
 __device__ __forceinline__ void merge_tile(f4 (&R)[Tri<NCB>::count], f4 (&X)[NRB][NCB], int pstart,
-                                           float* __restrict__ lds, int lane) {
+                                           float* __restrict__ lds, int lane, float* __restrict__ qkeep = nullptr) {
   const int g = lane >> 4;
   const int c = lane & 15;
   float* Tl = lds;            // [16][16]
@@ -284,6 +295,22 @@ __device__ __forceinline__ void merge_tile(f4 (&R)[Tri<NCB>::count], f4 (&X)[NRB
 #pragma unroll
       for (int v = 0; v < 4; ++v) Wl[rb * 256 + (4 * g + v) * 16 + c] = X[rb][P][v];
     wave_lds_sync();
+    if (qkeep != nullptr) {
+      // T, the scales and W of this panel, from the registers they are staged from: lane (0, c)
+      // holds row c of T (trow) and scale c, lane (g, c) the entries 4g .. 4g+3 of W's column c
+      // in each block
+      float* qp = qkeep + (TRI ? (int64_t)TreeKeep<NCB>::off(P) : P * tile_panel_floats(NRB));
+      if (g == 0) {
+#pragma unroll
+        for (int k = 0; k < 16; k += 4)
+          *reinterpret_cast<f4*>(qp + c * 16 + k) = f4{trow[k], trow[k + 1], trow[k + 2], trow[k + 3]};
+        qp[256 + c] = sc;
+      }
+#pragma unroll
+      for (int rb = 0; rb < RBN; ++rb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) qp[320 + rb * 256 + (4 * g + v) * 16 + c] = X[rb][P][v];
+    }
     f4 Td;
 #pragma unroll
     for (int v = 0; v < 4; ++v) Td[v] = Tl[(4 * g + v) * 16 + c];
@@ -407,7 +434,7 @@ __device__ __forceinline__ void load_tri(const float* __restrict__ src, f4 (&R)[
 // R <- triangle of QR([R; stored triangle at src]).
 template <int NCB, bool BF = false>
 __device__ __forceinline__ void merge_stored_tri(f4 (&R)[Tri<NCB>::count], const float* __restrict__ src,
-                                                 float* lds, int lane) {
+                                                 float* lds, int lane, float* __restrict__ qkeep = nullptr) {
   f4 X[NCB][NCB];
   static_for<0, NCB>([&](auto RB) {
     constexpr int rb = decltype(RB)::value;
@@ -420,7 +447,7 @@ __device__ __forceinline__ void merge_stored_tri(f4 (&R)[Tri<NCB>::count], const
         X[rb][q] = f4{0.f, 0.f, 0.f, 0.f};
     });
   });
-  merge_tile<NCB, NCB, true, BF>(R, X, 0, lds, lane);
+  merge_tile<NCB, NCB, true, BF>(R, X, 0, lds, lane, qkeep);
 }
 
 // One leaf of the dense part, by one wave: leaf li of problem p streams rows
@@ -428,12 +455,16 @@ __device__ __forceinline__ void merge_stored_tri(f4 (&R)[Tri<NCB>::count], const
 // diag(sqrt(lam_p) d_B)); the leaves of each problem are then merged pairwise (the problem's own
 // slots and arrival counters: the second wave of a pair to finish merges) and the root is
 // written row-major to the problem's R_B | c_B.
-template <int NCB, int NRB, bool BF>
+// KEEP (the stored Q): the panels of the leaf's tiles go to qt (at the problem's qt0, qtiles
+// tiles per leaf) and those of its merges to qn (at qn0, one TreeKeep per merge node, numbered
+// level by level from the leaves up as the separate merge tree numbers its nodes).  A separate
+// instantiation, so that the kernels without it are compiled as if it did not exist.
+template <int NCB, int NRB, bool BF, bool KEEP = false>
 __device__ __forceinline__ void tsqr_leaf(int pi, int leaf, const ProbDesc* __restrict__ probs, int n,
                                           const float* __restrict__ Red, const double* __restrict__ d,
                                           const double* __restrict__ lamv, float* __restrict__ slots,
                                           int* __restrict__ counters, float* __restrict__ RBall, float* lds,
-                                          int lane) {
+                                          int lane, float* __restrict__ qt = nullptr, float* __restrict__ qn = nullptr) {
   const ProbDesc& P = probs[pi];
   const float* Xg = Red + P.redoff;
   const int64_t ldx = P.ldr;
@@ -465,7 +496,8 @@ __device__ __forceinline__ void tsqr_leaf(int pi, int leaf, const ProbDesc* __re
   // ---- leaf: stream this wave's rows -------------------------------------------------------
   const int64_t r0 = (int64_t)leaf * rows_per_leaf;
   const int64_t r1 = r0 + rows_per_leaf < nrows ? r0 + rows_per_leaf : nrows;
-  for (int64_t t = r0; t < r1; t += KT) {
+  int64_t tile = 0;
+  for (int64_t t = r0; t < r1; t += KT, ++tile) {
     f4 X[NRB][NCB];
 #pragma unroll
     for (int rb = 0; rb < NRB; ++rb)
@@ -478,7 +510,8 @@ __device__ __forceinline__ void tsqr_leaf(int pi, int leaf, const ProbDesc* __re
           X[rb][q][v] = (row < r1 && col < L) ? Xg[row * ldx + col] : 0.f;
         }
       }
-    merge_tile<NCB, NRB, false, BF>(R, X, 0, lds, lane);
+    float* qk = KEEP ? qt + P.qt0 + ((int64_t)leaf * P.qtiles + tile) * (NCB * tile_panel_floats(NRB)) : nullptr;
+    merge_tile<NCB, NRB, false, BF>(R, X, 0, lds, lane, qk);
   }
 
   // ---- pairwise merges up the problem's tree, in the same launch ----------------------------
@@ -492,6 +525,7 @@ __device__ __forceinline__ void tsqr_leaf(int pi, int leaf, const ProbDesc* __re
   int slot = leaf;
   int64_t base = 0;   // first slot of the current level
   int64_t cbase = 0;  // first counter of the current level
+  int64_t mbase = 0;  // merges of the levels below (the stored Q's node numbering)
   while (nl > 1) {
     const int sib = slot ^ 1;
     const int parent = slot >> 1;
@@ -499,6 +533,7 @@ __device__ __forceinline__ void tsqr_leaf(int pi, int leaf, const ProbDesc* __re
     if (sib >= nl) {  // no sibling at this level: carry the triangle up unchanged
       base += nl;
       cbase += nn;
+      mbase += nl >> 1;
       slot = parent;
       nl = nn;
       continue;
@@ -512,9 +547,11 @@ __device__ __forceinline__ void tsqr_leaf(int pi, int leaf, const ProbDesc* __re
     __threadfence();
     const int left = slot & ~1;
     load_tri<NCB>(pslots + (base + left) * SLOT, R, lane);
-    merge_stored_tri<NCB, BF>(R, pslots + (base + left + 1) * SLOT, lds, lane);
+    merge_stored_tri<NCB, BF>(R, pslots + (base + left + 1) * SLOT, lds, lane,
+                              KEEP ? qn + P.qn0 + (mbase + parent) * TreeKeep<NCB>::total : nullptr);
     base += nl;
     cbase += nn;
+    mbase += nl >> 1;
     slot = parent;
     nl = nn;
   }
@@ -538,26 +575,26 @@ __device__ __forceinline__ void tsqr_leaf(int pi, int leaf, const ProbDesc* __re
 }
 
 // One launch per column-block count NCB: wave w is global leaf leaf_begin + w.
-template <int NCB, int NRB, bool BF>
+template <int NCB, int NRB, bool BF, bool KEEP>
 __global__ void __launch_bounds__(256)
 k_tsqr_mfma(int leaf_begin, int nleaves_cls, const int32_t* __restrict__ leaf_prob,
             const int32_t* __restrict__ leaf_idx, const ProbDesc* __restrict__ probs, int n,
             const float* __restrict__ Red, const double* __restrict__ d, const double* __restrict__ lamv,
-            float* __restrict__ slots, int* __restrict__ counters, float* __restrict__ RBall) {
+            float* __restrict__ slots, int* __restrict__ counters, float* __restrict__ RBall, float* __restrict__ qt,
+            float* __restrict__ qn) {
   __shared__ float lds_all[4][kWaveLds];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int wl = blockIdx.x * 4 + wv;
   if (wl >= nleaves_cls) return;
-  tsqr_leaf<NCB, NRB, BF>(leaf_prob[leaf_begin + wl], leaf_idx[leaf_begin + wl], probs, n, Red, d, lamv, slots,
-                          counters, RBall, lds_all[wv], lane);
+  tsqr_leaf<NCB, NRB, BF, KEEP>(leaf_prob[leaf_begin + wl], leaf_idx[leaf_begin + wl], probs, n, Red, d, lamv, slots,
+                          counters, RBall, lds_all[wv], lane, qt, qn);
 }
 
-// Leaf rows per tile for each column-block count: 128 up to 4 column blocks, 64 beyond
-// (taller tiles no longer fit the register file there).
+// Leaf tile blocks of 16 rows for each column-block count (leaf_tile_rows, qrk_batch.hpp).
 template <int NCB>
 struct LeafTile {
-  static constexpr int nrb = NCB <= 4 ? 8 : 4;
+  static constexpr int nrb = leaf_tile_rows(NCB) / 16;
 };
 
 // The leaves of every problem with at most kQueueNCB column blocks in one persistent launch:
@@ -572,21 +609,22 @@ struct LeafTile {
 // The queue kernel calls each width's body as a function of its own, so that every body keeps
 // the register allocation it has in a kernel by itself (inlined side by side, the six bodies
 // exceed the register file and spill).
-template <int NCB, bool BF>
+template <int NCB, bool BF, bool KEEP>
 __device__ __noinline__ void tsqr_leaf_call(int pi, int leaf, const ProbDesc* __restrict__ probs, int n,
                                             const float* __restrict__ Red, const double* __restrict__ d,
                                             const double* __restrict__ lamv, float* __restrict__ slots,
                                             int* __restrict__ counters, float* __restrict__ RBall, float* lds,
-                                            int lane) {
-  tsqr_leaf<NCB, LeafTile<NCB>::nrb, BF>(pi, leaf, probs, n, Red, d, lamv, slots, counters, RBall, lds, lane);
+                                            int lane, float* __restrict__ qt, float* __restrict__ qn) {
+  tsqr_leaf<NCB, LeafTile<NCB>::nrb, BF, KEEP>(pi, leaf, probs, n, Red, d, lamv, slots, counters, RBall, lds, lane, qt,
+                                         qn);
 }
 
-template <bool BF>
+template <bool BF, bool KEEP>
 __global__ void __launch_bounds__(256)
 k_tsqr_queue(int nitems, const int32_t* __restrict__ leaf_prob, const int32_t* __restrict__ leaf_idx,
              const ProbDesc* __restrict__ probs, int n, const float* __restrict__ Red, const double* __restrict__ d,
              const double* __restrict__ lamv, float* __restrict__ slots, int* __restrict__ counters,
-             int* __restrict__ qhead, float* __restrict__ RBall) {
+             int* __restrict__ qhead, float* __restrict__ RBall, float* __restrict__ qt, float* __restrict__ qn) {
   __shared__ float lds_all[4][kWaveLds];
   const int lane = threadIdx.x & 63;
   float* lds = lds_all[threadIdx.x >> 6];
@@ -600,7 +638,7 @@ k_tsqr_queue(int nitems, const int32_t* __restrict__ leaf_prob, const int32_t* _
     switch ((probs[pi].L + 15) >> 4) {
 #define QRK_QLEAF(C)                                                                                   \
   case C:                                                                                              \
-    tsqr_leaf_call<C, BF>(pi, leaf, probs, n, Red, d, lamv, slots, counters, RBall, lds, lane);        \
+    tsqr_leaf_call<C, BF, KEEP>(pi, leaf, probs, n, Red, d, lamv, slots, counters, RBall, lds, lane, qt, qn); \
     break;
       QRK_QLEAF(1) QRK_QLEAF(2) QRK_QLEAF(3) QRK_QLEAF(4) QRK_QLEAF(5) QRK_QLEAF(6)
 #undef QRK_QLEAF
@@ -612,16 +650,21 @@ k_tsqr_queue(int nitems, const int32_t* __restrict__ leaf_prob, const int32_t* _
 
 template <int NCB, int NRB>
 hipError_t launch_tsqr_mfma_ncb(bool bf16x3, int leaf_begin, int nleaves_cls, const int32_t* leaf_prob,
-                                const int32_t* leaf_idx, const ProbDesc* probs, int n, const float* Red,
-                                const double* d, const double* lam, float* slots, int* counters, float* RB,
+                                const int32_t* leaf_idx, const ProbDesc* probs, int n, const float* Red, const double* d,
+                                const double* lam, float* slots, int* counters, float* RB, float* qt, float* qn,
                                 hipStream_t st) {
+  // the stored Q's tile count per leaf assumes these tiles
+  static_assert(16 * NRB == leaf_tile_rows(NCB), "leaf tile height");
   const int grid = (nleaves_cls + 3) / 4;
-  if (bf16x3)
-    hipLaunchKernelGGL((k_tsqr_mfma<NCB, NRB, true>), dim3(grid), dim3(256), 0, st, leaf_begin, nleaves_cls,
-                       leaf_prob, leaf_idx, probs, n, Red, d, lam, slots, counters, RB);
-  else
-    hipLaunchKernelGGL((k_tsqr_mfma<NCB, NRB, false>), dim3(grid), dim3(256), 0, st, leaf_begin, nleaves_cls,
-                       leaf_prob, leaf_idx, probs, n, Red, d, lam, slots, counters, RB);
+#define QRK_LEAF(BFV, KV)                                                                                   \
+  hipLaunchKernelGGL((k_tsqr_mfma<NCB, NRB, BFV, KV>), dim3(grid), dim3(256), 0, st, leaf_begin, nleaves_cls, \
+                     leaf_prob, leaf_idx, probs, n, Red, d, lam, slots, counters, RB, qt, qn)
+  if (qt != nullptr) {
+    if (bf16x3) QRK_LEAF(true, true); else QRK_LEAF(false, true);
+  } else {
+    if (bf16x3) QRK_LEAF(true, false); else QRK_LEAF(false, false);
+  }
+#undef QRK_LEAF
   return hipGetLastError();
 }
 

@@ -38,13 +38,6 @@
 
 namespace qrk {
 
-// Per-wave LDS for the kept panels: panel p holds T (256 floats, row-major), the column
-// scales (16 floats, padded to 64) and W (p + 1 blocks of 256 floats, accumulator layout).
-template <int NCB>
-struct TreeKeep {
-  static constexpr int off(int p) { return p * (256 + 64) + 256 * (p * (p + 1) / 2); }
-  static constexpr int total = off(NCB);
-};
 
 // Factor the panel [Rd; X[0..RBN-1]]: Rd is the 16x16 diagonal block of the R part, X the
 // tile blocks of this column block (accumulator layout).  On return Rd holds the new diagonal
@@ -164,12 +157,13 @@ __device__ __forceinline__ bool tree_wait2(const int* fa, const int* fb, int lan
 // r >= 0 an inner node, r < 0 leaf -1 - r.  Leaf triangles are at slots 0 .. leaves-1 of the
 // problem, node outputs at slots leaves + node; flags[(node * NCB + q) * 2] marks column block
 // q of a node's output as published above the diagonal, flags[(node * NCB + q) * 2 + 1] its
-// diagonal block.  The root (the last node) writes R_B | c_B row-major.
-template <int NCB>
+// diagonal block.  The root (the last node) writes R_B | c_B row-major.  KEEP (the stored Q):
+// node w's kept panels are written to qn + qn0 + w * TreeKeep<NCB>::total at its end.
+template <int NCB, bool KEEP>
 __global__ void __launch_bounds__(256)
 k_tsqr_tree(const ProbDesc* __restrict__ probs, const int32_t* __restrict__ node_l,
             const int32_t* __restrict__ node_r, int nnodes, float* __restrict__ slots, int* __restrict__ flags,
-            float* __restrict__ RBall, int* __restrict__ status) {
+            float* __restrict__ RBall, int* __restrict__ status, float* __restrict__ qn) {
   __shared__ float keep_all[4][TreeKeep<NCB>::total];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -254,6 +248,12 @@ k_tsqr_tree(const ProbDesc* __restrict__ probs, const int32_t* __restrict__ node
       publish(q, 1);
     }
   });
+  if constexpr (KEEP) {
+    // the stored Q: this node's kept panels, as they are in LDS (TreeKeep layout)
+    float* dst = qn + P.qn0 + (int64_t)node * TreeKeep<NCB>::total;
+    for (int e = lane * 4; e < TreeKeep<NCB>::total; e += 256)
+      *reinterpret_cast<f4*>(dst + e) = *reinterpret_cast<const f4*>(keep + e);
+  }
   if (stalled) set_status(status, ST_STALL);
 }
 

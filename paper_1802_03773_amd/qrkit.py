@@ -59,6 +59,9 @@ _SIGS = {
     "qrk_solve": (_c_i32, [_c_vp, _c_vp, _c_i32, _c_vp]),
     "qrk_solve_rhs": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_i32, _c_vp]),
     "qrk_solve_tol": (_c_i32, [_c_vp, _c_vp, _c_i32, _c_dbl, _c_i32p, _c_vp]),
+    "qrk_set_keep_q": (_c_i32, [_c_vp, _c_i32]),
+    "qrk_apply_qt": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp]),
+    "qrk_solve_qt": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_i32, _c_vp]),
     "qrk_solve_adjoint": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp]),
     "qrk_colnorms_blockangular": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_vp]),
     "qrk_get_factor": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_vp]),
@@ -195,6 +198,34 @@ class Factor:
         _check(lib().qrk_solve_rhs(self._h, _dev_ptr(b, _torch_dtype(self.qdtype), "b", self._rhs_rows()),
                                    _dev_ptr(out, torch.float64, "p", self.N), int(sweeps), _stream_ptr(stream)),
                "qrk_solve_rhs")
+        return out
+
+    def set_keep_q(self, keep: bool = True):
+        """Keep Q at the following factor calls (float32 block-angular handles whose blocks all
+        have m_i >= n): the per-block reflectors and the dense part's compact-WY panels, which
+        apply_qt and solve_qt use."""
+        _check(lib().qrk_set_keep_q(self._h, 1 if keep else 0), "qrk_set_keep_q")
+
+    def apply_qt(self, b, out=None, stream=None):
+        """The first N entries of Q^T [b; 0] with the stored Q of the last factor call: c_i of
+        every block, then c_B (laid out like p); float64 [N]."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty(self.N, dtype=torch.float64, device="cuda")
+        _check(lib().qrk_apply_qt(self._h, _dev_ptr(b, _torch_dtype(self.qdtype), "b", self._rhs_rows()),
+                                  _dev_ptr(out, torch.float64, "c", self.N), _stream_ptr(stream)),
+               "qrk_apply_qt")
+        return out
+
+    def solve_qt(self, b, sweeps: int = 0, out=None, stream=None):
+        """The step for a new right-hand side b with the stored Q: p = R^{-1} (Q^T b) (the first N
+        entries), then `sweeps` (0..8) refinement sweeps for b; p float64 [N]."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty(self.N, dtype=torch.float64, device="cuda")
+        _check(lib().qrk_solve_qt(self._h, _dev_ptr(b, _torch_dtype(self.qdtype), "b", self._rhs_rows()),
+                                  _dev_ptr(out, torch.float64, "p", self.N), int(sweeps), _stream_ptr(stream)),
+               "qrk_solve_qt")
         return out
 
     def _rhs_rows(self) -> int:

@@ -152,3 +152,12 @@ def test_solve_tol_rejects_bad_arguments():
     assert L.qrk_solve_tol(None, None, 2, 1e-12, ctypes.byref(done), None) == qrkit.QRK_EINVAL
     assert L.qrk_strerror(qrkit.QRK_ENOTCONVERGED) == b"refinement sweeps exhausted above the requested tolerance"
     assert L.qrk_strerror(qrkit.QRK_ETOOLARGE).startswith(b"request exceeds")
+
+
+def test_stored_q_entry_points_reject_null_handle():
+    """qrk_set_keep_q, qrk_apply_qt and qrk_solve_qt validate on the host before any device work."""
+    L = qrkit.lib()
+    assert L.qrk_set_keep_q(None, 1) == qrkit.QRK_EINVAL
+    assert L.qrk_set_keep_q(None, 0) == qrkit.QRK_EINVAL
+    assert L.qrk_apply_qt(None, None, None, None) == qrkit.QRK_EINVAL
+    assert L.qrk_solve_qt(None, None, None, 0, None) == qrkit.QRK_EINVAL
