@@ -106,7 +106,8 @@ def _parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for PMC byte scaling)")
     ap.add_argument("--workload", default="scale",
-                    choices=["scale", "ragged-batch", "banded-batch", "lm-scale", "lm-banded-batch", "lambda-retry"],
+                    choices=["scale", "ragged-batch", "banded-batch", "lm-scale", "lm-banded-batch", "lambda-retry",
+                             "new-rhs"],
                     help="scale: one block-angular problem (the headline); ragged-batch: 512 block-angular "
                          "problems in one batch; banded-batch: 2,048 banded problems in one batch")
     ap.add_argument("--problems", type=int, default=0, help="batch workloads: problems (0 = the recipe's count)")
@@ -547,6 +548,81 @@ def run_lambda(args):
     return 0
 
 
+def run_new_rhs(args):
+    """New right-hand sides with the kept factor of the 50,000-block workload (Sections 5.1 and 5.2):
+    J is factored once with the stored Q (untimed); every timed step solves for the next of four
+    right-hand sides: Q^T b from the stored reflectors, the back-substitution and one float64
+    sweep (qrk_solve_qt).  For comparison, the same right-hand sides by corrected semi-normal
+    sweeps from p = 0 with J and R only (qrk_solve_rhs, four sweeps, the count that reaches 1e-10
+    without Q), and the cost of storing Q in the factor call."""
+    import dataclasses
+
+    import numpy as np
+    import torch
+
+    from paper_1802_03773_amd import BlockAngularSolver
+    from workloads import generators as gen
+
+    mode = "bf16x3" if args.mode == "auto" else args.mode
+    print("[bench] generating workload", file=sys.stderr, flush=True)
+    inst = gen.scale_blockangular(args.seed, lam=1e-2)
+    A, B, b, d = (torch.from_numpy(x).cuda() for x in (inst.A, inst.B, inst.b, inst.d))
+    rng = np.random.default_rng(args.seed + 1)
+    rhs = [torch.from_numpy(rng.standard_normal(inst.b.shape[0]).astype(np.float32)).cuda() for _ in range(4)]
+
+    def timed(fn, steps):
+        for k in range(max(args.warmup, 1)):
+            fn(k)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            fn(k)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    s = BlockAngularSolver(inst.row_off, inst.n, inst.nB, dtype="float32", mode=mode)
+    ms_factor = timed(lambda k: s.factor(A, B, b, d, inst.lam), args.steps)
+    s.set_keep_q(True)
+    ms_factor_keep = timed(lambda k: s.factor(A, B, b, d, inst.lam), args.steps)
+    p = torch.empty(inst.N, dtype=torch.float64, device="cuda")
+    c = torch.empty(inst.N, dtype=torch.float64, device="cuda")
+    ms = timed(lambda k: s.solve_qt(rhs[k % 4], sweeps=1, out=p), args.steps)
+    ms_qt0 = timed(lambda k: s.solve_qt(rhs[k % 4], sweeps=0, out=p), args.steps)
+    ms_apply = timed(lambda k: s.apply_qt(rhs[k % 4], out=c), args.steps)
+    ms_rhs4 = timed(lambda k: s.solve_rhs(rhs[k % 4], sweeps=4, out=p), args.steps)
+    s.raise_on_status()
+
+    accuracy, cpu_baseline = None, None
+    if not args.no_cpu:
+        from oracle import refine
+        b2 = rhs[0].cpu().numpy()
+        errs = {"solve_qt_0": s.solve_qt(rhs[0], sweeps=0).cpu().numpy(),
+                "solve_qt_1": s.solve_qt(rhs[0], sweeps=1).cpu().numpy(),
+                "solve_rhs_4": s.solve_rhs(rhs[0], sweeps=4).cpu().numpy()}
+        print("[bench] oracle (cpu_baseline leg)", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        p_ref, _ = refine.reference_solution(dataclasses.replace(inst, b=b2), sweeps=2)
+        t_oracle = time.perf_counter() - t0
+        d_ = inst.d
+        accuracy = {k: float(np.max(d_ * np.abs(v - p_ref)) / np.max(d_ * np.abs(p_ref))) for k, v in errs.items()}
+        cpu_baseline = {"value": 1.0 / t_oracle, "unit": "solves/s", "cores": _cpu_threads(), "kind": "oracle",
+                        "sample": "one float64 oracle solve of the full workload for a new right-hand side "
+                                  "(structured QR with the right-hand side carried, two refinement sweeps); "
+                                  "%.2f s" % t_oracle}
+    out = {"metric": "new right-hand side solves/sec with the kept factor", "value": 1000.0 / ms,
+           "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32" if mode == "plain" else "bf16x3", "data": "synthetic",
+           "config": {"workload": "new right-hand sides with the stored Q: 50,000 blocks of 12x3 + dense "
+                                  "600,000x90, lambda 1e-2, factored once; each step Q^T b, back-substitution "
+                                  "and one float64 sweep", "refine_sweeps": 1, "refine_dtype": "f64"},
+           "ms": {"solve_qt_1sweep": ms, "solve_qt_0sweeps": ms_qt0, "apply_qt": ms_apply,
+                  "solve_rhs_4sweeps": ms_rhs4, "factor": ms_factor, "factor_keep_q": ms_factor_keep},
+           "accuracy": accuracy, "roofline": None, "cpu_baseline": cpu_baseline}
+    print(json.dumps(out))
+    return 0
+
+
 def main():
     args = _parse()
     if args.gpus != 1:
@@ -558,6 +634,8 @@ def main():
         return run_lm(args)
     if args.workload == "lambda-retry":
         return run_lambda(args)
+    if args.workload == "new-rhs":
+        return run_new_rhs(args)
     if args.workload != "scale":
         return run_batch(args)
     import numpy as np

@@ -17,6 +17,7 @@
 #include "qrk_device.hpp"
 #include "qrk_launch.hpp"
 #include "tsqr_mfma.hpp"
+#include "tsqr_tree.hpp"
 
 namespace qrk {
 
@@ -60,12 +61,12 @@ k_qt_blocks(int64_t K, const ProbDesc* __restrict__ probs, const int32_t* __rest
 //   z = u + diag(s) W^T x;  z' = T^T z;  u -= z';  x -= W diag(s) z'
 // u: lane k of every 16-lane row holds entry k of the panel's 16 triangle rows; x: this lane's
 // rows of the tile (row q * 64 + lane); w: those rows' raw reflector entries (zero past the
-// tile); TS: the panel's T (16 x 16, row-major) and column scales; sm: the wave's LDS.
+// tile); tc: column k of T (k = lane % 16), sk: scale k; sm: the wave's LDS.
 constexpr int kSmFloats = 64 * 17 + 16;
 
 template <int RPL>
-__device__ __forceinline__ void qt_panel(const float (&w)[RPL][16], float (&x)[RPL], float& u,
-                                         const float* __restrict__ TS, float* sm, int lane) {
+__device__ __forceinline__ void qt_panel(const float (&w)[RPL][16], float (&x)[RPL], float& u, const float (&tc)[16],
+                                         float sk, float* sm, int lane) {
   const int k = lane & 15;
   const int part = lane >> 4;
   // W^T x: this lane's row products, then the column sums through LDS (lane (part, k) adds
@@ -82,13 +83,12 @@ __device__ __forceinline__ void qt_panel(const float (&w)[RPL][16], float (&x)[R
 #pragma unroll
   for (int i = 0; i < 16; ++i) s += sm[(part * 16 + i) * 17 + k];
   s = sum_rows4(s);
-  const float sk = TS[256 + k];
   const float z = u + sk * s;
   // z'_k = sum_i T[i][k] z_i (T upper triangular), z_i from lane i of the row
   float zp = 0.f;
   static_for<0, 16>([&](auto II) {
     constexpr int i = decltype(II)::value;
-    zp += TS[i * 16 + k] * row_bcast<i>(z);
+    zp += tc[i] * row_bcast<i>(z);
   });
   u -= zp;
   if (lane < 16) sm[64 * 17 + lane] = sk * zp;
@@ -103,6 +103,42 @@ __device__ __forceinline__ void qt_panel(const float (&w)[RPL][16], float (&x)[R
   wave_lds_sync();  // the next panel overwrites sm
 }
 
+// The data of NP kept panels that one application reads, loaded into registers before the
+// first panel's exchange so that the loads of all panels are in flight together.  TS(p): the
+// panel's T and scales; its reflector blocks follow at + 320, row r at + 320 + 16 r, rows at or
+// past `rows` (of this lane's RPL rows) read as zero.
+template <int NP, int RPL>
+struct PanelSet {
+  float w[NP][RPL][16];
+  float tc[NP][16];
+  float sk[NP];
+  template <typename TSof>
+  __device__ __forceinline__ void load(TSof TS, int rows_lim_step, int lane) {
+    const int k = lane & 15;
+    static_for<0, NP>([&](auto PP) {
+      constexpr int p = decltype(PP)::value;
+      const float* ts = TS(p);
+      const int rows = rows_lim_step < 0 ? 64 * RPL : rows_lim_step * (p + 1);
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) {
+        const int row = q * 64 + lane;
+        const bool in = row < rows;
+        const f4* wr = reinterpret_cast<const f4*>(ts + 320 + (in ? row : 0) * 16);  // in bounds
+#pragma unroll
+        for (int j4 = 0; j4 < 4; ++j4) {
+          const f4 l = wr[j4];
+          const f4 v = in ? l : f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) w[p][q][4 * j4 + e] = v[e];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) tc[p][i] = ts[i * 16 + k];
+      sk[p] = ts[256 + k];
+    });
+  }
+};
+
 // One wave per leaf of the problems with NCB column blocks (the factorisation's leaf list):
 // stage 2 over the leaf's tiles, then stage 3 up the problem's tree.  xr: the reduced
 // right-hand side by global row; uslots: 128 floats per tree slot from the problem's qc0;
@@ -116,6 +152,7 @@ k_qt_leaves(int leaf_begin, int nleaves_cls, const int32_t* __restrict__ leaf_pr
   constexpr int KT = leaf_tile_rows(NCB);
   constexpr int RPL = KT / 64;                // tile rows per lane
   constexpr int RPM = (16 * NCB + 63) / 64;   // triangle rows per lane in a merge
+  constexpr int64_t TPF = tile_panel_floats(KT / 16);
   __shared__ float sm_all[4][kSmFloats];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
@@ -131,7 +168,7 @@ k_qt_leaves(int leaf_begin, int nleaves_cls, const int32_t* __restrict__ leaf_pr
 #pragma unroll
   for (int p = 0; p < NCB; ++p) u[p] = 0.f;
 
-  // ---- stage 2: the leaf's tiles ----
+  // ---- stage 2: the leaf's tiles (their reflector blocks are zero past the leaf's rows) ----
   const int64_t r0 = (int64_t)leaf * P.rows_per_leaf;
   const int64_t r1 = r0 + P.rows_per_leaf < P.M ? r0 + P.rows_per_leaf : P.M;
   int64_t tile = 0;
@@ -142,19 +179,12 @@ k_qt_leaves(int leaf_begin, int nleaves_cls, const int32_t* __restrict__ leaf_pr
       const int64_t row = t + q * 64 + lane;
       x[q] = row < r1 ? xp[row] : 0.f;
     }
-    const float* qp = qt + P.qt0 + ((int64_t)leaf * P.qtiles + tile) * (NCB * tile_panel_floats(KT / 16));
+    const float* qp = qt + P.qt0 + ((int64_t)leaf * P.qtiles + tile) * (NCB * TPF);
+    PanelSet<NCB, RPL> ps;
+    ps.load([&](int p) { return qp + p * TPF; }, -1, lane);
     static_for<0, NCB>([&](auto PP) {
       constexpr int p = decltype(PP)::value;
-      const float* TS = qp + p * tile_panel_floats(KT / 16);
-      const float* W = TS + 320;  // KT / 16 blocks of 16 x 16, row-major (zero past the leaf's rows)
-      float w[RPL][16];
-#pragma unroll
-      for (int q = 0; q < RPL; ++q) {
-        const int row = q * 64 + lane;
-#pragma unroll
-        for (int j = 0; j < 16; ++j) w[q][j] = W[(row >> 4) * 256 + (row & 15) * 16 + j];
-      }
-      qt_panel<RPL>(w, x, u[p], TS, sm, lane);
+      qt_panel<RPL>(ps.w[p], x, u[p], ps.tc[p], ps.sk[p], sm, lane);
     });
   }
 
@@ -169,40 +199,41 @@ k_qt_leaves(int leaf_begin, int nleaves_cls, const int32_t* __restrict__ leaf_pr
     const int parent = slot >> 1;
     const int nn = (nl + 1) >> 1;
     if (sib < nl) {
+      // the node's panels (written by the factorisation): their loads overlap the arrival
+      // (panel p of a node reflects rows 0 .. 16 (p + 1) - 1 of the right triangle)
+      const float* nq = qn + P.qn0 + (mbase + parent) * node_panel_off(NCB);
+      PanelSet<NCB, RPM> ps;
+      ps.load([&](int p) { return nq + node_panel_off(p); }, 16, lane);
+      // publish u with device-coherent stores, wait for them, then arrive (as the separate merge
+      // tree of the factorisation publishes its blocks): no cache-wide fence
+      const auto rs_u = __builtin_amdgcn_make_buffer_rsrc(us + (base + slot) * 128, 0, 512, 0x00020000);
       if (lane < 16) {
 #pragma unroll
-        for (int p = 0; p < NCB; ++p) us[(base + slot) * 128 + 16 * p + lane] = u[p];
+        for (int p = 0; p < NCB; ++p)
+          __builtin_amdgcn_raw_buffer_store_b32(u_of(u[p]), rs_u, (16 * p + lane) * 4, 0, kCoherent);
       }
-      __threadfence();
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       int old = 0;
-      if (lane == 0) old = atomicAdd(&pctr[cbase + parent], 1);
+      if (lane == 0)
+        old = __hip_atomic_fetch_add(&pctr[cbase + parent], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       old = __builtin_amdgcn_readfirstlane(old);
       if (old == 0) return;  // the sibling is still running; it will merge
-      __threadfence();
+      asm volatile("" ::: "memory");  // the sibling's vector is read after its arrival was seen
       const int left = slot & ~1;
-      const float* ul = us + (base + left) * 128;
-      const float* ur = us + (base + left + 1) * 128;
+      const auto rs_l = __builtin_amdgcn_make_buffer_rsrc(us + (base + left) * 128, 0, 512, 0x00020000);
+      const auto rs_r = __builtin_amdgcn_make_buffer_rsrc(us + (base + left + 1) * 128, 0, 512, 0x00020000);
 #pragma unroll
-      for (int p = 0; p < NCB; ++p) u[p] = ul[16 * p + k];
+      for (int p = 0; p < NCB; ++p) u[p] = f_of(__builtin_amdgcn_raw_buffer_load_b32(rs_l, (16 * p + k) * 4, 0, kCoherent));
       float x[RPM];
 #pragma unroll
       for (int q = 0; q < RPM; ++q) {
         const int row = q * 64 + lane;
-        x[q] = row < 16 * NCB ? ur[row] : 0.f;
+        const float l = f_of(__builtin_amdgcn_raw_buffer_load_b32(rs_r, (row < 16 * NCB ? row : 0) * 4, 0, kCoherent));
+        x[q] = row < 16 * NCB ? l : 0.f;
       }
-      const float* nq = qn + P.qn0 + (mbase + parent) * node_panel_off(NCB);
       static_for<0, NCB>([&](auto PP) {
         constexpr int p = decltype(PP)::value;
-        const float* TS = nq + node_panel_off(p);
-        const float* W = TS + 320;  // p + 1 blocks of 16 x 16, row-major
-        float w[RPM][16];
-#pragma unroll
-        for (int q = 0; q < RPM; ++q) {
-          const int row = q * 64 + lane;
-#pragma unroll
-          for (int j = 0; j < 16; ++j) w[q][j] = row < 16 * (p + 1) ? W[(row >> 4) * 256 + (row & 15) * 16 + j] : 0.f;
-        }
-        qt_panel<RPM>(w, x, u[p], TS, sm, lane);
+        qt_panel<RPM>(ps.w[p], x, u[p], ps.tc[p], ps.sk[p], sm, lane);
       });
     }
     base += nl;
