@@ -37,11 +37,14 @@ PEAK_FP64_VECTOR_TFLOPS = 78.6
 _TSQR_SOURCES = ["paper_1802_03773_amd/csrc/tsqr_mfma.hpp", "paper_1802_03773_amd/csrc/tsqr_mfma.hip",
                  "paper_1802_03773_amd/csrc/tsqr_mfma_ncb6.hip", "paper_1802_03773_amd/csrc/qrk_device.hpp",
                  "paper_1802_03773_amd/csrc/tsqr_tree.hpp", "paper_1802_03773_amd/csrc/tsqr_tree.hip",
-                 "paper_1802_03773_amd/csrc/qrk_layout.hpp"]  # the reduced-row stride
-_TSQR_DIGEST = "32b2fef12e8504e104d63e24ec3ea3951d264874a442a60ca820dec27ef429dd"
+                 "paper_1802_03773_amd/csrc/qrk_layout.hpp",  # the reduced-row stride
+                 "paper_1802_03773_amd/csrc/qrk_batch.hpp"]   # the batch layout the kernels read
+_TSQR_DIGEST = "40838d407694d4588fc45442e4a079eb5b9f1fd8c9029347be981d3e33876c62"
 MEASURED_TRAFFIC = {
-    ("dense_leaves", "bf16x3"): {"bytes": (114598.0 * 2.000 + 23808.0 + 22614.0 * 2.000 + 21845.7) * 1024.0,
+    ("dense_leaves", "bf16x3"): {"bytes": (117539.5 * 2.000 + 39323.1 + 22597.8 * 2.000 + 21845.8) * 1024.0,
                                  "lam": 1e-2, "sources": _TSQR_SOURCES, "sha256": _TSQR_DIGEST},
+    ("dense_leaves", "plain"): {"bytes": (113438.1 * 2.000 + 21504.0 + 22598.5 * 2.000 + 21845.9) * 1024.0,
+                                "lam": 1e-2, "sources": _TSQR_SOURCES, "sha256": _TSQR_DIGEST},
 }
 # matrix-core flops per launch (leaves + tree) and the SIMDs' matrix-core busy cycles per launch
 MEASURED_MFMA = {

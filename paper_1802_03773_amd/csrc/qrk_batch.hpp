@@ -41,8 +41,6 @@ struct ProbDesc {
   int64_t slot0, ctr0;    // merge tree: first slot float, first arrival counter
   int64_t rows_per_leaf;  // dense-part QR: rows per leaf
   int64_t pack0, npacks;  // packs of whole blocks (global index of the first)
-  int64_t qt0, qtiles;    // stored Q: first float of the leaves' tile panels, tiles per leaf
-  int64_t qn0, qc0;       // stored Q: first float of the merge nodes' panels, of the apply's merge vectors
   int32_t nB, L;          // coupled columns, L = nB + 1
   int32_t leaves;         // dense-part QR leaves
   int32_t wg0, nwg;       // refinement workgroups [wg0, wg0 + nwg)
@@ -61,6 +59,19 @@ struct BqrPrologue {
   int64_t n1 = 0;
   double* lam_out = nullptr;
   double lam_val = 0.0;
+};
+
+// Stored Q of a problem's dense part (in an array of its own, so that the kernels without the
+// stored Q see the batch layout alone): first float of its leaves' tile panels and tiles per
+// leaf, first float of its merge nodes' panels, first float of the application's merge vectors.
+struct QOff {
+  int64_t qt0, qtiles, qn0, qc0;
+};
+// Where the dense-part kernels store Q (all null: not stored).
+struct QStore {
+  float* qt = nullptr;       // tile panels
+  float* qn = nullptr;       // merge-node panels
+  const QOff* qo = nullptr;  // [P]
 };
 
 // Where a factor call keeps the per-block reflectors (the stored Q of qrk_set_keep_q; null

@@ -135,6 +135,8 @@ struct qrk_handle_s {
   bool keep_q = false;
   bool q_valid = false;          // the last factor call stored Q
   qrk::QKeep qk;
+  std::vector<qrk::QOff> qoff_h;  // [P]
+  qrk::QOff* qoff_d = nullptr;
   float* q_tiles = nullptr;
   float* q_nodes = nullptr;
   float* q_xr = nullptr;

@@ -51,7 +51,8 @@ hipError_t launch_zero_ints(int* p, int64_t n, hipStream_t st);
 // nnodes inner nodes in level order (node_l / node_r child references, r < 0 leaf -1 - r),
 // flags[nnodes * ncb] cleared beforehand; ncb <= 6.  The root writes R_B | c_B.
 hipError_t launch_tsqr_tree(int ncb, const ProbDesc* probs, const int32_t* node_l, const int32_t* node_r,
-                            int nnodes, float* slots, int* flags, float* RB, int* status, float* qn, hipStream_t st);
+                            int nnodes, float* slots, int* flags, float* RB, int* status, const QStore& qs,
+                            hipStream_t st);
 // Leaves of classes 8 and 7 by their launches; the leaves from queue_begin on (classes
 // kQueueNCB .. 1, listed widest first) by one persistent launch of at most `cus` workgroups
 // that takes them from the device counter *qhead (cleared with the counters) when use_queue is
@@ -60,7 +61,7 @@ hipError_t launch_tsqr_mfma(bool bf16x3, const int* cls_begin, const int* cls_co
                             int cus,
                             const int32_t* leaf_prob, const int32_t* leaf_idx, const ProbDesc* probs, int n,
                             const float* Red, const double* d, const double* lam, float* slots, int* counters,
-                            int64_t nctr, int* qhead, float* RB, float* qt, float* qn, hipStream_t st);
+                            int64_t nctr, int* qhead, float* RB, const QStore& qs, hipStream_t st);
 
 // R_B p_B = c_B for every problem (RB_p is L x L with c_B in column L-1, or c_B from cext,
 // laid out like p, when that is given); writes p_B.
@@ -79,8 +80,8 @@ hipError_t launch_backsub_blocks(const BatchView& bv, const T* Rblk, const T* Sc
 // space (the counters are cleared here).
 hipError_t launch_apply_qt(const BatchView& bv, const int* cls_begin, const int* cls_count,
                            const int32_t* leaf_prob, const int32_t* leaf_idx, const float* b, const QKeep& qk,
-                           const float* qt, const float* qn, float* xr, float* uslots, int* counters,
-                           int64_t nctr, double* c, hipStream_t st);
+                           const QStore& qs, float* xr, float* uslots, int* counters, int64_t nctr, double* c,
+                           hipStream_t st);
 
 // Refinement, pass 1: per pack of whole blocks (at most 64 rows): r = b - J p,
 // g_i = A_i^T r - lam d_i^2 p_i, y_i = R_i^{-T} g_i, and per-workgroup partial sums of

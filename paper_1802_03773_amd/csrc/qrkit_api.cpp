@@ -92,6 +92,12 @@ qrk_status factor_ba(qrk_handle h, hipStream_t st, const double* lam_host = null
   }
   // the stored Q (float32 only): per-block reflectors, tile and node panels
   const bool keep = std::is_same<T, float>::value && h->keep_q && h->qk.vd != nullptr;
+  QStore qs;
+  if (keep) {
+    qs.qt = h->q_tiles;
+    qs.qn = h->q_nodes;
+    qs.qo = h->qoff_d;
+  }
   h->q_valid = false;
   int pr = prof_begin(h, 0, st);
   // without a list, the one class present covers blocks 0 .. K-1 in order
@@ -112,12 +118,11 @@ qrk_status factor_ba(qrk_handle h, hipStream_t st, const double* lam_host = null
     pr = prof_begin(h, 1, st);
     if (launch_tsqr_mfma(h->mode == QRK_BF16X3, h->cls_begin, h->cls_count, h->queue_begin, h->leaf_queue != 0, h->cus,
                          h->leaf_prob, h->leaf_idx, h->probs_d, h->n, Red, h->d, h->lam_ptr, h->slots, h->counters,
-                         h->nctr, h->counters + h->qhead_off, RB, keep ? h->q_tiles : nullptr,
-                         keep ? h->q_nodes : nullptr, st) != hipSuccess)
+                         h->nctr, h->counters + h->qhead_off, RB, qs, st) != hipSuccess)
       return QRK_EHIP;
     if (h->nnodes > 0 &&
         launch_tsqr_tree((h->probs_h[0].L + 15) / 16, h->probs_d, h->node_l, h->node_r, h->nnodes, h->slots,
-                         h->counters, RB, h->status, keep ? h->q_nodes : nullptr, st) != hipSuccess)
+                         h->counters, RB, h->status, qs, st) != hipSuccess)
       return QRK_EHIP;
     prof_end(h, pr, st);
     h->q_valid = keep;
@@ -324,14 +329,17 @@ qrk_status assign_leaves(qrk_handle h) {
     // stored Q: tile panels of every leaf, node panels of the leaves - 1 merges, and the
     // application's merge vectors (128 floats per tree slot)
     int64_t qt = 0, qn = 0, qu = 0;
-    for (auto& D : pd) {
+    h->qoff_h.resize((size_t)P);
+    for (int q = 0; q < P; ++q) {
+      const ProbDesc& D = pd[(size_t)q];
+      QOff& O = h->qoff_h[(size_t)q];
       const int ncb = (D.L + 15) / 16;
-      D.qtiles = ceil_div(D.rows_per_leaf, (int64_t)leaf_tile_rows(ncb));
-      D.qt0 = qt;
-      qt += (int64_t)D.leaves * D.qtiles * ncb * tile_panel_floats(leaf_tile_rows(ncb) / 16);
-      D.qn0 = qn;
+      O.qtiles = ceil_div(D.rows_per_leaf, (int64_t)leaf_tile_rows(ncb));
+      O.qt0 = qt;
+      qt += (int64_t)D.leaves * O.qtiles * ncb * tile_panel_floats(leaf_tile_rows(ncb) / 16);
+      O.qn0 = qn;
       qn += (int64_t)(D.leaves - 1) * node_panel_off(ncb);
-      D.qc0 = qu;
+      O.qc0 = qu;
       qu += tree_size(D.leaves).slots * 128;
     }
     h->q_tiles_n = std::max<int64_t>(qt, 1);
@@ -403,6 +411,7 @@ qrk_status ensure_q_storage(qrk_handle h) {
   const size_t es = sizeof(float);
   if (!h->qk.vd) {
     void *vd = nullptr, *vp = nullptr, *g = nullptr;
+    if ((s = dalloc(h, &h->qoff_d, sizeof(QOff) * (size_t)h->P)) != QRK_OK) return s;
     if ((s = dalloc(h, &vd, es * (size_t)std::max<int64_t>(h->M * h->n, 1))) != QRK_OK ||
         (s = dalloc(h, &vp, es * (size_t)std::max<int64_t>(h->K * h->n * h->n, 1))) != QRK_OK ||
         (s = dalloc(h, &g, es * (size_t)std::max<int64_t>(h->K * h->n, 1))) != QRK_OK ||
@@ -426,6 +435,9 @@ qrk_status ensure_q_storage(qrk_handle h) {
       (s = grow(&h->q_nodes, &h->q_nodes_cap, h->q_nodes_n)) != QRK_OK ||
       (s = grow(&h->q_u, &h->q_u_cap, h->q_u_n)) != QRK_OK)
     return s;
+  if (h->qoff_h.size() != (size_t)h->P ||
+      hipMemcpy(h->qoff_d, h->qoff_h.data(), sizeof(QOff) * (size_t)h->P, hipMemcpyHostToDevice) != hipSuccess)
+    return QRK_EHIP;
   return QRK_OK;
 }
 

@@ -14,8 +14,8 @@ namespace {
 
 hipError_t apply(qrk_handle h, const void* b, double* c, hipStream_t st) {
   return launch_apply_qt(blockangular_view(h), h->cls_begin, h->cls_count, h->leaf_prob, h->leaf_idx,
-                         static_cast<const float*>(b), h->qk, h->q_tiles, h->q_nodes, h->q_xr, h->q_u,
-                         h->counters, h->nctr, c, st);
+                         static_cast<const float*>(b), h->qk, QStore{h->q_tiles, h->q_nodes, h->qoff_d}, h->q_xr,
+                         h->q_u, h->counters, h->nctr, c, st);
 }
 
 }  // namespace

@@ -141,14 +141,14 @@ struct PanelSet {
 
 // One wave per leaf of the problems with NCB column blocks (the factorisation's leaf list):
 // stage 2 over the leaf's tiles, then stage 3 up the problem's tree.  xr: the reduced
-// right-hand side by global row; uslots: 128 floats per tree slot from the problem's qc0;
+// right-hand side by global row; uslots: 128 floats per tree slot from the problem's qc0 (QOff);
 // counters from ctr0, cleared beforehand.
 template <int NCB>
 __global__ void __launch_bounds__(256)
 k_qt_leaves(int leaf_begin, int nleaves_cls, const int32_t* __restrict__ leaf_prob,
             const int32_t* __restrict__ leaf_idx, const ProbDesc* __restrict__ probs, int n,
-            const float* __restrict__ qt, const float* __restrict__ qn, const float* __restrict__ xr,
-            float* __restrict__ uslots, int* __restrict__ counters, double* __restrict__ c) {
+            const QStore qs, const float* __restrict__ xr, float* __restrict__ uslots, int* __restrict__ counters,
+            double* __restrict__ c) {
   constexpr int KT = leaf_tile_rows(NCB);
   constexpr int RPL = KT / 64;                // tile rows per lane
   constexpr int RPM = (16 * NCB + 63) / 64;   // triangle rows per lane in a merge
@@ -162,6 +162,7 @@ k_qt_leaves(int leaf_begin, int nleaves_cls, const int32_t* __restrict__ leaf_pr
   const int pi = leaf_prob[leaf_begin + wl];
   const int leaf = leaf_idx[leaf_begin + wl];
   const ProbDesc& P = probs[pi];
+  const QOff& Q = qs.qo[pi];
   const int k = lane & 15;
   const float* xp = xr + P.moff;
   float u[NCB];
@@ -179,7 +180,7 @@ k_qt_leaves(int leaf_begin, int nleaves_cls, const int32_t* __restrict__ leaf_pr
       const int64_t row = t + q * 64 + lane;
       x[q] = row < r1 ? xp[row] : 0.f;
     }
-    const float* qp = qt + P.qt0 + ((int64_t)leaf * P.qtiles + tile) * (NCB * TPF);
+    const float* qp = qs.qt + Q.qt0 + ((int64_t)leaf * Q.qtiles + tile) * (NCB * TPF);
     PanelSet<NCB, RPL> ps;
     ps.load([&](int p) { return qp + p * TPF; }, -1, lane);
     static_for<0, NCB>([&](auto PP) {
@@ -189,7 +190,7 @@ k_qt_leaves(int leaf_begin, int nleaves_cls, const int32_t* __restrict__ leaf_pr
   }
 
   // ---- stage 3: merges up the problem's tree (the factorisation's pairing and node order) ----
-  float* us = uslots + P.qc0;
+  float* us = uslots + Q.qc0;
   int* pctr = counters + P.ctr0;
   int nl = P.leaves;
   int slot = leaf;
@@ -201,7 +202,7 @@ k_qt_leaves(int leaf_begin, int nleaves_cls, const int32_t* __restrict__ leaf_pr
     if (sib < nl) {
       // the node's panels (written by the factorisation): their loads overlap the arrival
       // (panel p of a node reflects rows 0 .. 16 (p + 1) - 1 of the right triangle)
-      const float* nq = qn + P.qn0 + (mbase + parent) * node_panel_off(NCB);
+      const float* nq = qs.qn + Q.qn0 + (mbase + parent) * node_panel_off(NCB);
       PanelSet<NCB, RPM> ps;
       ps.load([&](int p) { return nq + node_panel_off(p); }, 16, lane);
       // publish u with device-coherent stores, wait for them, then arrive (as the separate merge
@@ -255,8 +256,8 @@ k_qt_leaves(int leaf_begin, int nleaves_cls, const int32_t* __restrict__ leaf_pr
 
 hipError_t launch_apply_qt(const BatchView& bv, const int* cls_begin, const int* cls_count,
                            const int32_t* leaf_prob, const int32_t* leaf_idx, const float* b, const QKeep& qk,
-                           const float* qt, const float* qn, float* xr, float* uslots, int* counters,
-                           int64_t nctr, double* c, hipStream_t st) {
+                           const QStore& qs, float* xr, float* uslots, int* counters, int64_t nctr, double* c,
+                           hipStream_t st) {
   if (!qk.vd || !qk.vp || !qk.g || bv.max_L > kMaxDense || bv.max_rows > 64) return hipErrorInvalidValue;
   hipError_t e = launch_zero_ints(counters, nctr, st);
   if (e != hipSuccess) return e;
@@ -288,7 +289,7 @@ hipError_t launch_apply_qt(const BatchView& bv, const int* cls_begin, const int*
 #define QRK_QL(C)                                                                                            \
   case C:                                                                                                    \
     hipLaunchKernelGGL((k_qt_leaves<C>), grd, blk, 0, st, cls_begin[cl], nlv, leaf_prob, leaf_idx, bv.probs, \
-                       bv.n, qt, qn, xr, uslots, counters, c);                                               \
+                       bv.n, qs, xr, uslots, counters, c);                                                   \
     break;
       QRK_QL(1) QRK_QL(2) QRK_QL(3) QRK_QL(4) QRK_QL(5) QRK_QL(6) QRK_QL(7) QRK_QL(8)
 #undef QRK_QL

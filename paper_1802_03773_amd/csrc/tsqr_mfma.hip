@@ -16,7 +16,7 @@ namespace qrk {
 template <int NCB>
 hipError_t launch_tsqr_mfma_n(bool bf16x3, int leaf_begin, int nleaves_cls, const int32_t* leaf_prob, const int32_t* leaf_idx,
                               const ProbDesc* probs, int n, const float* Red, const double* d, const double* lam,
-                              float* slots, int* counters, float* RB, float* qt, float* qn, hipStream_t st);
+                              float* slots, int* counters, float* RB, const QStore& qs, hipStream_t st);
 
 __global__ void k_zero_ints(int* __restrict__ p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -37,13 +37,13 @@ int tsqr_mfma_slot_floats(int L) {
 template <bool BF>
 hipError_t launch_tsqr_queue(int nitems, const int32_t* leaf_prob, const int32_t* leaf_idx, const ProbDesc* probs,
                              int n, const float* Red, const double* d, const double* lam, float* slots, int* counters,
-                             int* qhead, float* RB, float* qt, float* qn, int grid, hipStream_t st);
+                             int* qhead, float* RB, const QStore& qs, int grid, hipStream_t st);
 
 hipError_t launch_tsqr_mfma(bool bf16x3, const int* cls_begin, const int* cls_count, int queue_begin, bool use_queue,
                             int cus,
                             const int32_t* leaf_prob, const int32_t* leaf_idx, const ProbDesc* probs, int n,
                             const float* Red, const double* d, const double* lam, float* slots, int* counters,
-                            int64_t nctr, int* qhead, float* RB, float* qt, float* qn, hipStream_t st) {
+                            int64_t nctr, int* qhead, float* RB, const QStore& qs, hipStream_t st) {
   // the arrival counters and the queue head are cleared by the factor call's first per-block
   // QR launch
   if (nctr < 1) return hipErrorInvalidValue;
@@ -57,7 +57,7 @@ hipError_t launch_tsqr_mfma(bool bf16x3, const int* cls_begin, const int* cls_co
     if (k == 0) continue;
 #define QRK_TS(N)                                                                                            \
   case N:                                                                                                    \
-    e = launch_tsqr_mfma_n<N>(bf16x3, b, k, leaf_prob, leaf_idx, probs, n, Red, d, lam, slots, counters, RB, qt, qn, \
+    e = launch_tsqr_mfma_n<N>(bf16x3, b, k, leaf_prob, leaf_idx, probs, n, Red, d, lam, slots, counters, RB, qs,     \
                               st);                                                                          \
     break;
     switch (c) { QRK_TS(1) QRK_TS(2) QRK_TS(3) QRK_TS(4) QRK_TS(5) QRK_TS(6) QRK_TS(7) QRK_TS(8) }
@@ -70,9 +70,9 @@ hipError_t launch_tsqr_mfma(bool bf16x3, const int* cls_begin, const int* cls_co
     // need the whole register file)
     const int grid = std::max(1, std::min((nq + 3) / 4, cus));
     e = bf16x3 ? launch_tsqr_queue<true>(nq, leaf_prob + queue_begin, leaf_idx + queue_begin, probs, n, Red, d, lam,
-                                         slots, counters, qhead, RB, qt, qn, grid, st)
+                                         slots, counters, qhead, RB, qs, grid, st)
                : launch_tsqr_queue<false>(nq, leaf_prob + queue_begin, leaf_idx + queue_begin, probs, n, Red, d, lam,
-                                          slots, counters, qhead, RB, qt, qn, grid, st);
+                                          slots, counters, qhead, RB, qs, grid, st);
   }
   return e;
 }

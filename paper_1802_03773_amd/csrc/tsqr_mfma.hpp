@@ -252,10 +252,10 @@ struct Tri {
 // applied once per row of the small Z products instead of once per tile element.
 // Only the first NPANEL panels are factored; their reflectors are still applied to every
 // column block (the later blocks then hold columns that are carried, not factored).
-// qkeep (may be null): where the panels' compact-WY factors (T, the scales and the raw
-// reflector blocks, qrk_batch.hpp) are stored for a later Q^T: panel P at P * tile_panel_floats
-// for a dense tile, at TreeKeep<NCB>::off(P) for a triangle.
-template <int NCB, int NRB, bool TRI, bool BF = false, int NPANEL = NCB, bool FUSE = false>
+// KEEPQ: the panels' compact-WY factors (T, the scales and the raw reflector blocks,
+// qrk_batch.hpp) are stored at qkeep for a later Q^T: panel P at P * tile_panel_floats for a
+// dense tile, at TreeKeep<NCB>::off(P) for a triangle.
+template <int NCB, int NRB, bool TRI, bool BF = false, int NPANEL = NCB, bool FUSE = false, bool KEEPQ = false>
 __device__ __forceinline__ void merge_tile(f4 (&R)[Tri<NCB>::count], f4 (&X)[NRB][NCB], int pstart,
                                            float* __restrict__ lds, int lane, float* __restrict__ qkeep = nullptr) {
   const int g = lane >> 4;
@@ -295,7 +295,7 @@ __device__ __forceinline__ void merge_tile(f4 (&R)[Tri<NCB>::count], f4 (&X)[NRB
 #pragma unroll
       for (int v = 0; v < 4; ++v) Wl[rb * 256 + (4 * g + v) * 16 + c] = X[rb][P][v];
     wave_lds_sync();
-    if (qkeep != nullptr) {
+    if constexpr (KEEPQ) {
       // T, the scales and W of this panel, from the registers they are staged from: lane (0, c)
       // holds row c of T (trow) and scale c, lane (g, c) the entries 4g .. 4g+3 of W's column c
       // in each block
@@ -432,7 +432,7 @@ __device__ __forceinline__ void load_tri(const float* __restrict__ src, f4 (&R)[
 }
 
 // R <- triangle of QR([R; stored triangle at src]).
-template <int NCB, bool BF = false>
+template <int NCB, bool BF = false, bool KEEPQ = false>
 __device__ __forceinline__ void merge_stored_tri(f4 (&R)[Tri<NCB>::count], const float* __restrict__ src,
                                                  float* lds, int lane, float* __restrict__ qkeep = nullptr) {
   f4 X[NCB][NCB];
@@ -447,7 +447,7 @@ __device__ __forceinline__ void merge_stored_tri(f4 (&R)[Tri<NCB>::count], const
         X[rb][q] = f4{0.f, 0.f, 0.f, 0.f};
     });
   });
-  merge_tile<NCB, NCB, true, BF>(R, X, 0, lds, lane, qkeep);
+  merge_tile<NCB, NCB, true, BF, NCB, false, KEEPQ>(R, X, 0, lds, lane, qkeep);
 }
 
 // One leaf of the dense part, by one wave: leaf li of problem p streams rows
@@ -455,8 +455,8 @@ __device__ __forceinline__ void merge_stored_tri(f4 (&R)[Tri<NCB>::count], const
 // diag(sqrt(lam_p) d_B)); the leaves of each problem are then merged pairwise (the problem's own
 // slots and arrival counters: the second wave of a pair to finish merges) and the root is
 // written row-major to the problem's R_B | c_B.
-// KEEP (the stored Q): the panels of the leaf's tiles go to qt (at the problem's qt0, qtiles
-// tiles per leaf) and those of its merges to qn (at qn0, one TreeKeep per merge node, numbered
+// KEEP (the stored Q): the panels of the leaf's tiles go to qs.qt (at the problem's qt0, qtiles
+// tiles per leaf) and those of its merges to qs.qn (at qn0, one TreeKeep per merge node, numbered
 // level by level from the leaves up as the separate merge tree numbers its nodes).  A separate
 // instantiation, so that the kernels without it are compiled as if it did not exist.
 template <int NCB, int NRB, bool BF, bool KEEP = false>
@@ -464,7 +464,7 @@ __device__ __forceinline__ void tsqr_leaf(int pi, int leaf, const ProbDesc* __re
                                           const float* __restrict__ Red, const double* __restrict__ d,
                                           const double* __restrict__ lamv, float* __restrict__ slots,
                                           int* __restrict__ counters, float* __restrict__ RBall, float* lds,
-                                          int lane, float* __restrict__ qt = nullptr, float* __restrict__ qn = nullptr) {
+                                          int lane, const QStore qs = QStore()) {
   const ProbDesc& P = probs[pi];
   const float* Xg = Red + P.redoff;
   const int64_t ldx = P.ldr;
@@ -496,8 +496,7 @@ __device__ __forceinline__ void tsqr_leaf(int pi, int leaf, const ProbDesc* __re
   // ---- leaf: stream this wave's rows -------------------------------------------------------
   const int64_t r0 = (int64_t)leaf * rows_per_leaf;
   const int64_t r1 = r0 + rows_per_leaf < nrows ? r0 + rows_per_leaf : nrows;
-  int64_t tile = 0;
-  for (int64_t t = r0; t < r1; t += KT, ++tile) {
+  for (int64_t t = r0; t < r1; t += KT) {
     f4 X[NRB][NCB];
 #pragma unroll
     for (int rb = 0; rb < NRB; ++rb)
@@ -510,8 +509,13 @@ __device__ __forceinline__ void tsqr_leaf(int pi, int leaf, const ProbDesc* __re
           X[rb][q][v] = (row < r1 && col < L) ? Xg[row * ldx + col] : 0.f;
         }
       }
-    float* qk = KEEP ? qt + P.qt0 + ((int64_t)leaf * P.qtiles + tile) * (NCB * tile_panel_floats(NRB)) : nullptr;
-    merge_tile<NCB, NRB, false, BF>(R, X, 0, lds, lane, qk);
+    if constexpr (KEEP) {
+      const int64_t tile = (t - r0) / KT;
+      float* qk = qs.qt + qs.qo[pi].qt0 + ((int64_t)leaf * qs.qo[pi].qtiles + tile) * (NCB * tile_panel_floats(NRB));
+      merge_tile<NCB, NRB, false, BF, NCB, false, true>(R, X, 0, lds, lane, qk);
+    } else {
+      merge_tile<NCB, NRB, false, BF>(R, X, 0, lds, lane);
+    }
   }
 
   // ---- pairwise merges up the problem's tree, in the same launch ----------------------------
@@ -533,7 +537,7 @@ __device__ __forceinline__ void tsqr_leaf(int pi, int leaf, const ProbDesc* __re
     if (sib >= nl) {  // no sibling at this level: carry the triangle up unchanged
       base += nl;
       cbase += nn;
-      mbase += nl >> 1;
+      if constexpr (KEEP) mbase += nl >> 1;
       slot = parent;
       nl = nn;
       continue;
@@ -547,11 +551,14 @@ __device__ __forceinline__ void tsqr_leaf(int pi, int leaf, const ProbDesc* __re
     __threadfence();
     const int left = slot & ~1;
     load_tri<NCB>(pslots + (base + left) * SLOT, R, lane);
-    merge_stored_tri<NCB, BF>(R, pslots + (base + left + 1) * SLOT, lds, lane,
-                              KEEP ? qn + P.qn0 + (mbase + parent) * TreeKeep<NCB>::total : nullptr);
+    if constexpr (KEEP)
+      merge_stored_tri<NCB, BF, true>(R, pslots + (base + left + 1) * SLOT, lds, lane,
+                                      qs.qn + qs.qo[pi].qn0 + (mbase + parent) * TreeKeep<NCB>::total);
+    else
+      merge_stored_tri<NCB, BF>(R, pslots + (base + left + 1) * SLOT, lds, lane);
     base += nl;
     cbase += nn;
-    mbase += nl >> 1;
+    if constexpr (KEEP) mbase += nl >> 1;
     slot = parent;
     nl = nn;
   }
@@ -574,21 +581,36 @@ __device__ __forceinline__ void tsqr_leaf(int pi, int leaf, const ProbDesc* __re
   });
 }
 
-// One launch per column-block count NCB: wave w is global leaf leaf_begin + w.
-template <int NCB, int NRB, bool BF, bool KEEP>
+// One launch per column-block count NCB: wave w is global leaf leaf_begin + w.  The launch
+// that stores Q is a kernel of its own with one more argument; the one without it keeps the
+// argument list it had before Q could be stored.
+template <int NCB, int NRB, bool BF>
 __global__ void __launch_bounds__(256)
 k_tsqr_mfma(int leaf_begin, int nleaves_cls, const int32_t* __restrict__ leaf_prob,
             const int32_t* __restrict__ leaf_idx, const ProbDesc* __restrict__ probs, int n,
             const float* __restrict__ Red, const double* __restrict__ d, const double* __restrict__ lamv,
-            float* __restrict__ slots, int* __restrict__ counters, float* __restrict__ RBall, float* __restrict__ qt,
-            float* __restrict__ qn) {
+            float* __restrict__ slots, int* __restrict__ counters, float* __restrict__ RBall) {
   __shared__ float lds_all[4][kWaveLds];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int wl = blockIdx.x * 4 + wv;
   if (wl >= nleaves_cls) return;
-  tsqr_leaf<NCB, NRB, BF, KEEP>(leaf_prob[leaf_begin + wl], leaf_idx[leaf_begin + wl], probs, n, Red, d, lamv, slots,
-                          counters, RBall, lds_all[wv], lane, qt, qn);
+  tsqr_leaf<NCB, NRB, BF>(leaf_prob[leaf_begin + wl], leaf_idx[leaf_begin + wl], probs, n, Red, d, lamv, slots,
+                          counters, RBall, lds_all[wv], lane);
+}
+template <int NCB, int NRB, bool BF>
+__global__ void __launch_bounds__(256)
+k_tsqr_mfma_keep(int leaf_begin, int nleaves_cls, const int32_t* __restrict__ leaf_prob,
+                 const int32_t* __restrict__ leaf_idx, const ProbDesc* __restrict__ probs, int n,
+                 const float* __restrict__ Red, const double* __restrict__ d, const double* __restrict__ lamv,
+                 float* __restrict__ slots, int* __restrict__ counters, float* __restrict__ RBall, const QStore qs) {
+  __shared__ float lds_all[4][kWaveLds];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int wl = blockIdx.x * 4 + wv;
+  if (wl >= nleaves_cls) return;
+  tsqr_leaf<NCB, NRB, BF, true>(leaf_prob[leaf_begin + wl], leaf_idx[leaf_begin + wl], probs, n, Red, d, lamv, slots,
+                                counters, RBall, lds_all[wv], lane, qs);
 }
 
 // Leaf tile blocks of 16 rows for each column-block count (leaf_tile_rows, qrk_batch.hpp).
@@ -609,22 +631,33 @@ struct LeafTile {
 // The queue kernel calls each width's body as a function of its own, so that every body keeps
 // the register allocation it has in a kernel by itself (inlined side by side, the six bodies
 // exceed the register file and spill).
-template <int NCB, bool BF, bool KEEP>
+template <int NCB, bool BF>
 __device__ __noinline__ void tsqr_leaf_call(int pi, int leaf, const ProbDesc* __restrict__ probs, int n,
                                             const float* __restrict__ Red, const double* __restrict__ d,
                                             const double* __restrict__ lamv, float* __restrict__ slots,
                                             int* __restrict__ counters, float* __restrict__ RBall, float* lds,
-                                            int lane, float* __restrict__ qt, float* __restrict__ qn) {
-  tsqr_leaf<NCB, LeafTile<NCB>::nrb, BF, KEEP>(pi, leaf, probs, n, Red, d, lamv, slots, counters, RBall, lds, lane, qt,
-                                         qn);
+                                            int lane) {
+  tsqr_leaf<NCB, LeafTile<NCB>::nrb, BF>(pi, leaf, probs, n, Red, d, lamv, slots, counters, RBall, lds, lane);
+}
+template <int NCB, bool BF>
+__device__ __noinline__ void tsqr_leaf_call_keep(int pi, int leaf, const ProbDesc* __restrict__ probs, int n,
+                                                 const float* __restrict__ Red, const double* __restrict__ d,
+                                                 const double* __restrict__ lamv, float* __restrict__ slots,
+                                                 int* __restrict__ counters, float* __restrict__ RBall, float* lds,
+                                                 int lane, const QStore qs) {
+  tsqr_leaf<NCB, LeafTile<NCB>::nrb, BF, true>(pi, leaf, probs, n, Red, d, lamv, slots, counters, RBall, lds, lane,
+                                               qs);
 }
 
+// The queue's work loop; KEEP: the stored-Q bodies.
 template <bool BF, bool KEEP>
-__global__ void __launch_bounds__(256)
-k_tsqr_queue(int nitems, const int32_t* __restrict__ leaf_prob, const int32_t* __restrict__ leaf_idx,
-             const ProbDesc* __restrict__ probs, int n, const float* __restrict__ Red, const double* __restrict__ d,
-             const double* __restrict__ lamv, float* __restrict__ slots, int* __restrict__ counters,
-             int* __restrict__ qhead, float* __restrict__ RBall, float* __restrict__ qt, float* __restrict__ qn) {
+__device__ __forceinline__ void tsqr_queue_loop(int nitems, const int32_t* __restrict__ leaf_prob,
+                                                const int32_t* __restrict__ leaf_idx,
+                                                const ProbDesc* __restrict__ probs, int n,
+                                                const float* __restrict__ Red, const double* __restrict__ d,
+                                                const double* __restrict__ lamv, float* __restrict__ slots,
+                                                int* __restrict__ counters, int* __restrict__ qhead,
+                                                float* __restrict__ RBall, const QStore& qs) {
   __shared__ float lds_all[4][kWaveLds];
   const int lane = threadIdx.x & 63;
   float* lds = lds_all[threadIdx.x >> 6];
@@ -636,9 +669,12 @@ k_tsqr_queue(int nitems, const int32_t* __restrict__ leaf_prob, const int32_t* _
     const int pi = leaf_prob[item];
     const int leaf = leaf_idx[item];
     switch ((probs[pi].L + 15) >> 4) {
-#define QRK_QLEAF(C)                                                                                   \
-  case C:                                                                                              \
-    tsqr_leaf_call<C, BF, KEEP>(pi, leaf, probs, n, Red, d, lamv, slots, counters, RBall, lds, lane, qt, qn); \
+#define QRK_QLEAF(C)                                                                                          \
+  case C:                                                                                                     \
+    if constexpr (KEEP)                                                                                       \
+      tsqr_leaf_call_keep<C, BF>(pi, leaf, probs, n, Red, d, lamv, slots, counters, RBall, lds, lane, qs);    \
+    else                                                                                                      \
+      tsqr_leaf_call<C, BF>(pi, leaf, probs, n, Red, d, lamv, slots, counters, RBall, lds, lane);             \
     break;
       QRK_QLEAF(1) QRK_QLEAF(2) QRK_QLEAF(3) QRK_QLEAF(4) QRK_QLEAF(5) QRK_QLEAF(6)
 #undef QRK_QLEAF
@@ -648,23 +684,47 @@ k_tsqr_queue(int nitems, const int32_t* __restrict__ leaf_prob, const int32_t* _
   }
 }
 
+template <bool BF>
+__global__ void __launch_bounds__(256)
+k_tsqr_queue(int nitems, const int32_t* __restrict__ leaf_prob, const int32_t* __restrict__ leaf_idx,
+             const ProbDesc* __restrict__ probs, int n, const float* __restrict__ Red, const double* __restrict__ d,
+             const double* __restrict__ lamv, float* __restrict__ slots, int* __restrict__ counters,
+             int* __restrict__ qhead, float* __restrict__ RBall) {
+  tsqr_queue_loop<BF, false>(nitems, leaf_prob, leaf_idx, probs, n, Red, d, lamv, slots, counters, qhead, RBall,
+                             QStore());
+}
+template <bool BF>
+__global__ void __launch_bounds__(256)
+k_tsqr_queue_keep(int nitems, const int32_t* __restrict__ leaf_prob, const int32_t* __restrict__ leaf_idx,
+                  const ProbDesc* __restrict__ probs, int n, const float* __restrict__ Red,
+                  const double* __restrict__ d, const double* __restrict__ lamv, float* __restrict__ slots,
+                  int* __restrict__ counters, int* __restrict__ qhead, float* __restrict__ RBall, const QStore qs) {
+  tsqr_queue_loop<BF, true>(nitems, leaf_prob, leaf_idx, probs, n, Red, d, lamv, slots, counters, qhead, RBall, qs);
+}
+
 template <int NCB, int NRB>
 hipError_t launch_tsqr_mfma_ncb(bool bf16x3, int leaf_begin, int nleaves_cls, const int32_t* leaf_prob,
                                 const int32_t* leaf_idx, const ProbDesc* probs, int n, const float* Red, const double* d,
-                                const double* lam, float* slots, int* counters, float* RB, float* qt, float* qn,
+                                const double* lam, float* slots, int* counters, float* RB, const QStore& qs,
                                 hipStream_t st) {
   // the stored Q's tile count per leaf assumes these tiles
   static_assert(16 * NRB == leaf_tile_rows(NCB), "leaf tile height");
   const int grid = (nleaves_cls + 3) / 4;
-#define QRK_LEAF(BFV, KV)                                                                                   \
-  hipLaunchKernelGGL((k_tsqr_mfma<NCB, NRB, BFV, KV>), dim3(grid), dim3(256), 0, st, leaf_begin, nleaves_cls, \
-                     leaf_prob, leaf_idx, probs, n, Red, d, lam, slots, counters, RB, qt, qn)
-  if (qt != nullptr) {
-    if (bf16x3) QRK_LEAF(true, true); else QRK_LEAF(false, true);
+  if (qs.qt != nullptr) {
+    if (bf16x3)
+      hipLaunchKernelGGL((k_tsqr_mfma_keep<NCB, NRB, true>), dim3(grid), dim3(256), 0, st, leaf_begin, nleaves_cls,
+                         leaf_prob, leaf_idx, probs, n, Red, d, lam, slots, counters, RB, qs);
+    else
+      hipLaunchKernelGGL((k_tsqr_mfma_keep<NCB, NRB, false>), dim3(grid), dim3(256), 0, st, leaf_begin, nleaves_cls,
+                         leaf_prob, leaf_idx, probs, n, Red, d, lam, slots, counters, RB, qs);
   } else {
-    if (bf16x3) QRK_LEAF(true, false); else QRK_LEAF(false, false);
+    if (bf16x3)
+      hipLaunchKernelGGL((k_tsqr_mfma<NCB, NRB, true>), dim3(grid), dim3(256), 0, st, leaf_begin, nleaves_cls,
+                         leaf_prob, leaf_idx, probs, n, Red, d, lam, slots, counters, RB);
+    else
+      hipLaunchKernelGGL((k_tsqr_mfma<NCB, NRB, false>), dim3(grid), dim3(256), 0, st, leaf_begin, nleaves_cls,
+                         leaf_prob, leaf_idx, probs, n, Red, d, lam, slots, counters, RB);
   }
-#undef QRK_LEAF
   return hipGetLastError();
 }
 

@@ -7,15 +7,15 @@ namespace qrk {
 template <int NCB>
 hipError_t launch_tsqr_mfma_n(bool bf16x3, int leaf_begin, int nleaves_cls, const int32_t* leaf_prob, const int32_t* leaf_idx,
                               const ProbDesc* probs, int n, const float* Red, const double* d, const double* lam,
-                              float* slots, int* counters, float* RB, float* qt, float* qn, hipStream_t st);
+                              float* slots, int* counters, float* RB, const QStore& qs, hipStream_t st);
 
 template <>
 hipError_t launch_tsqr_mfma_n<8>(bool bf16x3, int leaf_begin, int nleaves_cls, const int32_t* leaf_prob,
                                  const int32_t* leaf_idx, const ProbDesc* probs, int n, const float* Red,
                                  const double* d, const double* lam, float* slots, int* counters, float* RB,
-                                 float* qt, float* qn, hipStream_t st) {
+                                 const QStore& qs, hipStream_t st) {
   return launch_tsqr_mfma_ncb<8, 4>(bf16x3, leaf_begin, nleaves_cls, leaf_prob, leaf_idx, probs, n, Red, d, lam, slots,
-                                     counters, RB, qt, qn, st);
+                                     counters, RB, qs, st);
 }
 
 }  // namespace qrk

@@ -7,19 +7,19 @@ namespace qrk {
 template <bool BF>
 hipError_t launch_tsqr_queue(int nitems, const int32_t* leaf_prob, const int32_t* leaf_idx, const ProbDesc* probs,
                              int n, const float* Red, const double* d, const double* lam, float* slots, int* counters,
-                             int* qhead, float* RB, float* qt, float* qn, int grid, hipStream_t st);
+                             int* qhead, float* RB, const QStore& qs, int grid, hipStream_t st);
 
 template <>
 hipError_t launch_tsqr_queue<false>(int nitems, const int32_t* leaf_prob, const int32_t* leaf_idx, const ProbDesc* probs,
                                  int n, const float* Red, const double* d, const double* lam, float* slots,
-                                 int* counters, int* qhead, float* RB, float* qt, float* qn, int grid,
+                                 int* counters, int* qhead, float* RB, const QStore& qs, int grid,
                                  hipStream_t st) {
-  if (qt != nullptr)
-    hipLaunchKernelGGL((k_tsqr_queue<false, true>), dim3((unsigned)grid), dim3(256), 0, st, nitems, leaf_prob, leaf_idx,
-                       probs, n, Red, d, lam, slots, counters, qhead, RB, qt, qn);
+  if (qs.qt != nullptr)
+    hipLaunchKernelGGL((k_tsqr_queue_keep<false>), dim3((unsigned)grid), dim3(256), 0, st, nitems, leaf_prob, leaf_idx,
+                       probs, n, Red, d, lam, slots, counters, qhead, RB, qs);
   else
-    hipLaunchKernelGGL((k_tsqr_queue<false, false>), dim3((unsigned)grid), dim3(256), 0, st, nitems, leaf_prob, leaf_idx,
-                       probs, n, Red, d, lam, slots, counters, qhead, RB, qt, qn);
+    hipLaunchKernelGGL((k_tsqr_queue<false>), dim3((unsigned)grid), dim3(256), 0, st, nitems, leaf_prob, leaf_idx, probs,
+                       n, Red, d, lam, slots, counters, qhead, RB);
   return hipGetLastError();
 }
 

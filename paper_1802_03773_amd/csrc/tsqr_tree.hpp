@@ -158,12 +158,11 @@ __device__ __forceinline__ bool tree_wait2(const int* fa, const int* fb, int lan
 // problem, node outputs at slots leaves + node; flags[(node * NCB + q) * 2] marks column block
 // q of a node's output as published above the diagonal, flags[(node * NCB + q) * 2 + 1] its
 // diagonal block.  The root (the last node) writes R_B | c_B row-major.  KEEP (the stored Q):
-// node w's kept panels are written to qn + qn0 + w * TreeKeep<NCB>::total at its end.
+// node w's kept panels are written to qs.qn + qn0 + w * TreeKeep<NCB>::total at its end.
 template <int NCB, bool KEEP>
-__global__ void __launch_bounds__(256)
-k_tsqr_tree(const ProbDesc* __restrict__ probs, const int32_t* __restrict__ node_l,
-            const int32_t* __restrict__ node_r, int nnodes, float* __restrict__ slots, int* __restrict__ flags,
-            float* __restrict__ RBall, int* __restrict__ status, float* __restrict__ qn) {
+__device__ __forceinline__ void tsqr_tree_node(const ProbDesc* probs, const int32_t* node_l, const int32_t* node_r,
+                                               int nnodes, float* slots, int* flags, float* RBall, int* status,
+                                               const QStore& qs) {
   __shared__ float keep_all[4][TreeKeep<NCB>::total];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -250,11 +249,27 @@ k_tsqr_tree(const ProbDesc* __restrict__ probs, const int32_t* __restrict__ node
   });
   if constexpr (KEEP) {
     // the stored Q: this node's kept panels, as they are in LDS (TreeKeep layout)
-    float* dst = qn + P.qn0 + (int64_t)node * TreeKeep<NCB>::total;
+    float* dst = qs.qn + qs.qo[0].qn0 + (int64_t)node * TreeKeep<NCB>::total;
     for (int e = lane * 4; e < TreeKeep<NCB>::total; e += 256)
       *reinterpret_cast<f4*>(dst + e) = *reinterpret_cast<const f4*>(keep + e);
   }
   if (stalled) set_status(status, ST_STALL);
+}
+
+// The launch that stores Q is a kernel of its own with one more argument.
+template <int NCB>
+__global__ void __launch_bounds__(256)
+k_tsqr_tree(const ProbDesc* __restrict__ probs, const int32_t* __restrict__ node_l,
+            const int32_t* __restrict__ node_r, int nnodes, float* __restrict__ slots, int* __restrict__ flags,
+            float* __restrict__ RBall, int* __restrict__ status) {
+  tsqr_tree_node<NCB, false>(probs, node_l, node_r, nnodes, slots, flags, RBall, status, QStore());
+}
+template <int NCB>
+__global__ void __launch_bounds__(256)
+k_tsqr_tree_keep(const ProbDesc* __restrict__ probs, const int32_t* __restrict__ node_l,
+                 const int32_t* __restrict__ node_r, int nnodes, float* __restrict__ slots, int* __restrict__ flags,
+                 float* __restrict__ RBall, int* __restrict__ status, const QStore qs) {
+  tsqr_tree_node<NCB, true>(probs, node_l, node_r, nnodes, slots, flags, RBall, status, qs);
 }
 
 }  // namespace qrk
