@@ -113,6 +113,36 @@ def factor_two_stage(inst, lam: float) -> BlockAngularFactor:
                               float(abs(R2[nB, nB])))
 
 
+def factor_vcat(f1: BlockAngularFactor, f2: BlockAngularFactor) -> BlockAngularFactor:
+    """Vertical concatenation (Section 4.5, Eq. vcatDecomp) of two factored problems over the same
+    columns: [A1; A2] = blkdiag(Q1, Q2) [R1; R2].  [R1; R2] is not triangular; a row permutation P
+    interleaves the two block by block, so that P [R1; R2] is block-angular again: block i is
+    [R1_i; R2_i] (2n x n) with coupled rows [S1_i | c1_i; S2_i | c2_i], and the dense part holds
+    the rows of [R1_B | c1_B] and [R2_B | c2_B] with their residual rows [0 | resid].  The same
+    structured QR (Sections 4.1 and 4.2) then gives Q3 [R3; 0], the factor of [A1; A2]."""
+    K, n = f1.R_blk.shape[0], f1.R_blk.shape[1]
+    nB = f1.R_B.shape[0]
+    Aaug = np.concatenate([f1.R_blk, f2.R_blk], axis=1)                                 # [K, 2n, n]
+    C1 = np.concatenate([f1.S, f1.c_blk[:, :, None]], axis=2)                           # [K, n, nB+1]
+    C2 = np.concatenate([f2.S, f2.c_blk[:, :, None]], axis=2)
+    Caug = np.concatenate([C1, C2], axis=1)                                             # [K, 2n, nB+1]
+    Q, Rr = np.linalg.qr(Aaug, mode="complete")
+    QtC = np.matmul(np.swapaxes(Q, 1, 2), Caug)
+    R_blk, S, c_blk = Rr[:, :n, :], QtC[:, :n, :nB], QtC[:, :n, nB]
+    reduced = QtC[:, n:, :].reshape(-1, nB + 1)
+    tri = []
+    for f in (f1, f2):
+        RBc = np.zeros((nB + 1, nB + 1))
+        RBc[:nB, :nB] = f.R_B
+        RBc[:nB, nB] = f.c_B
+        RBc[nB, nB] = f.resid
+        tri.append(RBc)
+    stack = np.concatenate([reduced] + tri, axis=0)
+    R3 = np.linalg.qr(stack, mode="r")
+    return BlockAngularFactor(R_blk.copy(), S.copy(), c_blk.copy(), R3[:nB, :nB].copy(), R3[:nB, nB].copy(),
+                              float(abs(R3[nB, nB])))
+
+
 def _backsub_batched(R: np.ndarray, c: np.ndarray) -> np.ndarray:
     """Solve R_k x_k = c_k for a stack of small upper-triangular R_k."""
     K, n, _ = R.shape

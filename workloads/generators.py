@@ -214,6 +214,26 @@ def ragged_batch(seed: int = 200, P: int = 512, kmin: int = 500, kmax: int = 800
     return out
 
 
+def stack_rows(insts) -> BlockAngular:
+    """The instance whose least-squares rows are those of all `insts` (same K, n, n_B, d), block i's
+    rows of each instance in turn; the damping (lam) is the first instance's.  Input construction
+    only: the row order of a least-squares problem does not change its solution."""
+    first = insts[0]
+    K, n, nB = first.K, first.n, first.nB
+    assert all(i.K == K and i.n == n and i.nB == nB for i in insts)
+    row_off = np.zeros(K + 1, np.int64)
+    rows = []
+    for k in range(K):
+        for inst in insts:
+            rows.append((inst, int(inst.row_off[k]), int(inst.row_off[k + 1])))
+        row_off[k + 1] = row_off[k] + sum(int(i.row_off[k + 1] - i.row_off[k]) for i in insts)
+    A = np.concatenate([inst.A[a:e] for inst, a, e in rows] or [first.A[:0]], axis=0)
+    B = np.concatenate([inst.B[a:e] for inst, a, e in rows] or [first.B[:0]], axis=0)
+    b = np.concatenate([inst.b[a:e] for inst, a, e in rows] or [first.b[:0]], axis=0)
+    return BlockAngular(row_off, n, np.ascontiguousarray(A), np.ascontiguousarray(B), np.ascontiguousarray(b),
+                        first.d.copy(), first.lam, first.dtype)
+
+
 def stack_batch(insts):
     """Stack block-angular problems (same n and dtype) into the batched layout: K [P], nB [P],
     global row offsets [sum K + 1], A [M_tot, n], B flat (each problem's M_p x nB_p rows packed
