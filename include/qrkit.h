@@ -248,6 +248,27 @@ qrk_status qrk_solve_tol(qrk_handle h, double* p, int32_t max_sweeps, double rel
 qrk_status qrk_solve_rhs(qrk_handle h, const void* b, double* p, int32_t sweeps, void* stream);
 
 /* ------------------------------------------------------------------------------
+ * qrk_factor_vcat (Section 4.5, Eq. vcatDecomp: vertical concatenation)
+ *   Replaces the factor of h by that of the problem with the rows of both handles, from the two
+ *   kept factors alone: [A1; A2] = blkdiag(Q1, Q2) [R1; R2], and the row permutation that
+ *   interleaves R1 and R2 block by block makes P [R1; R2] block-angular again (blocks
+ *   [R1_i; R2_i], coupled rows [S1_i | c1_i; S2_i | c2_i], dense part [R1_B | c1_B; R2_B | c2_B]),
+ *   which the factor call's own kernels factor once more.  The result is the factor of
+ *       min_p || [J1; sqrt(lambda1) D1; J2; sqrt(lambda2) D2] p - [b1; 0; b2; 0] ||
+ *   for the inputs and damping of the two handles' last factor calls (lambda2 = 0 adds rows
+ *   without a second damping).  Both handles single-problem block-angular with equal K, n, n_B and
+ *   dtype (h's mode is used); the rows per block may differ.  h may already hold a concatenation
+ *   (up to 64 added handles); h2 may not.  h2 and its borrowed J, b, d must stay alive and
+ *   unchanged while h holds the concatenation (until h's next factor call): qrk_solve and
+ *   qrk_solve_tol on h refine against every part's rows.  qrk_solve_rhs, qrk_solve_adjoint,
+ *   qrk_factor_lambda and qrk_apply_qt return QRK_EINVAL on a handle holding a concatenation.
+ *   Allocates the merge's workspace on its first call on h (not capturable then), enqueues only
+ *   afterwards.  QRK_EINVAL for mismatched or unfactored handles, h == h2, or h2 itself holding
+ *   a concatenation.
+ * ------------------------------------------------------------------------------ */
+qrk_status qrk_factor_vcat(qrk_handle h, qrk_handle h2, void* stream);
+
+/* ------------------------------------------------------------------------------
  * Stored Q (Section 2: Q kept as the object that applies its Householder reflectors;
  * Sections 5.1 and 5.2: Q^T applied to each new right-hand side with the same factor).
  * Float32 block-angular handles (single or batched) whose blocks all have m_i >= n.

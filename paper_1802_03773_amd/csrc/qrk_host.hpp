@@ -144,6 +144,14 @@ struct qrk_handle_s {
   int64_t q_tiles_cap = 0, q_nodes_cap = 0, q_u_cap = 0;  // floats
   int64_t q_tiles_n = 0, q_nodes_n = 0, q_u_n = 0;        // floats the current layout needs
   double* q_c = nullptr;         // Q^T b of qrk_solve_qt, laid out like p [N]
+  // vertical concatenation (qrk_factor_vcat): the handles whose rows were added to this factor
+  // (borrowed until the next factor call), the stage problem that merges two factors and its
+  // inputs (the interleaved rows of R1, R2)
+  std::vector<qrk_handle_s*> vparts;
+  qrk_handle_s* vcat_stage = nullptr;
+  void* vA = nullptr;
+  void* vB = nullptr;
+  void* vb = nullptr;
 
   // phase timing: event pairs in a ring, summed on read
   struct ProfRec {

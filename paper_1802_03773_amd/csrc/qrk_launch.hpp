@@ -75,6 +75,17 @@ template <typename T>
 hipError_t launch_backsub_blocks(const BatchView& bv, const T* Rblk, const T* Sc, double* p, int* status,
                                  hipStream_t st, const double* cext = nullptr);
 
+// Vertical concatenation (vcat.hip): the stage problem's rows [R1_i; R2_i], [S1_i; S2_i] (row
+// stride L), [c1_i; c2_i] and the two dense triangles (at row red_row of Red, stride ldr).
+template <typename T>
+hipError_t launch_vcat_gather(int64_t K, int n, int L, const T* R1, const T* R2, const T* Sc1, const T* Sc2,
+                              const T* RB1, const T* RB2, T* A, T* B, T* b, T* Red, int64_t red_row, int64_t ldr,
+                              hipStream_t st);
+// y += ypart; part0[j] += sum_w part[w][j] - lam_part d_B,part[j]^2 p_B[j] (j < nB).
+hipError_t launch_vcat_merge(int64_t ny, double* y, const double* ypart, double* part0, const double* part, int nwg,
+                             int nB, const double* lam_part, const double* dB_part, const double* pB,
+                             hipStream_t st);
+
 // Q^T b with the stored Q of a float32 block-angular factor (stored_q.hip): b [M] float, the
 // first N entries (laid out like p) to c; xr [M], uslots and counters[0 .. nctr) are work
 // space (the counters are cleared here).

@@ -90,6 +90,7 @@ qrk_status factor_ba(qrk_handle h, hipStream_t st, const double* lam_host = null
     pro.lam_out = h->lam_d;
     pro.lam_val = *lam_host;
   }
+  h->vparts.clear();  // a new factor of this handle's own rows
   // the stored Q (float32 only): per-block reflectors, tile and node panels
   const bool keep = std::is_same<T, float>::value && h->keep_q && h->qk.vd != nullptr;
   QStore qs;
@@ -171,10 +172,20 @@ qrk_status refine_ba(qrk_handle h, double* p, int sweeps, const T* b, hipStream_
   const T* RB = static_cast<const T*>(h->RB);
   const BatchView bv = view(h);
   int pr = sweeps > 0 ? prof_begin(h, 4, st) : -1;
+  const int64_t Kn = h->K * h->n;
   for (int s = 0; s < sweeps; ++s) {
     if (launch_refine_residual<T>(bv, static_cast<const T*>(h->A), static_cast<const T*>(h->B), b, h->d, Rblk,
-                                  Sc, p, h->ybuf, h->refpart, st) != hipSuccess ||
-        launch_refine_dense<T>(bv, h->refpart, RB, h->d, p, h->deltaB, st) != hipSuccess ||
+                                  Sc, p, h->ybuf, h->refpart, st) != hipSuccess)
+      return QRK_EHIP;
+    // rows added by vertical concatenation: each part's residual terms with the stacked factor
+    for (qrk_handle q : h->vparts)
+      if (launch_refine_residual<T>(view(q), static_cast<const T*>(q->A), static_cast<const T*>(q->B),
+                                    static_cast<const T*>(q->b), q->d, Rblk, Sc, p, q->ybuf, q->refpart,
+                                    st) != hipSuccess ||
+          launch_vcat_merge(Kn, h->ybuf, q->ybuf, h->refpart, q->refpart, q->nwg, h->nB, q->lam_ptr, q->d + Kn,
+                            p + Kn, st) != hipSuccess)
+        return QRK_EHIP;
+    if (launch_refine_dense<T>(bv, h->refpart, RB, h->d, p, h->deltaB, st) != hipSuccess ||
         launch_refine_blocks<T>(bv, Rblk, Sc, h->ybuf, h->deltaB, p, st) != hipSuccess)
       return QRK_EHIP;
   }
@@ -210,6 +221,11 @@ void free_all(qrk_handle h) {
     free_all(h->lam_stage);
     delete h->lam_stage;
     h->lam_stage = nullptr;
+  }
+  if (h->vcat_stage) {
+    free_all(h->vcat_stage);
+    delete h->vcat_stage;
+    h->vcat_stage = nullptr;
   }
   prof_free(h);
   for (void* ptr : h->allocs) (void)hipFree(ptr);
@@ -794,6 +810,7 @@ qrk_status qrk_factor_lambda(qrk_handle h, double lambda, void* stream) {
   const int L = h->nB + 1;
   const int64_t Kn = h->K * n;
   qrk_status s;
+  if (!h->vparts.empty()) return QRK_EINVAL;  // a stacked factor: its base is not J alone
   h->q_valid = false;  // the stored Q is that of J alone, not of the new factor
   if (!h->lam_base_saved) {
     if (h->lam != 0.0) return QRK_EINVAL;  // the current factor must be that of J alone
@@ -857,6 +874,85 @@ qrk_status qrk_factor_lambda(qrk_handle h, double lambda, void* stream) {
   return QRK_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+template <typename T>
+qrk_status factor_vcat(qrk_handle h, qrk_handle h2, hipStream_t st) {
+  const size_t es = sizeof(T);
+  const int n = h->n;
+  const int L = h->nB + 1;
+  const int64_t K = h->K, Kn = K * n;
+  qrk_status s;
+  if (!h->vcat_stage) {
+    // the stage problem: K blocks of 2n rows ([R1_i; R2_i]) with coupled rows of stride L
+    // ([S1_i | c1_i; S2_i | c2_i]); its dense part also takes the 2L rows of the two triangles
+    // R1_B | c1_B and R2_B | c2_B after the blocks' reduced rows (2n per block: n of them are the
+    // block's damping rows, zero here)
+    std::vector<int64_t> ro((size_t)K + 1);
+    for (int64_t i = 0; i <= K; ++i) ro[(size_t)i] = i * 2 * n;
+    const int32_t K32 = (int32_t)K, nB32 = h->nB;
+    qrk_handle hs = nullptr;
+    if ((s = create_ba(1, n, &K32, &nB32, ro.data(), L, h->dtype, h->mode, &hs)) != QRK_OK) return s;
+    hs->probs_h[0].M += 2 * L;
+    hs->M += 2 * L;
+    dfree(hs, hs->Red);
+    hs->Red = nullptr;
+    if ((s = dalloc(hs, &hs->Red, es * (size_t)(2 * Kn + 2 * L) * hs->ldr)) != QRK_OK ||
+        (s = assign_leaves(hs)) != QRK_OK || (s = dalloc(h, &h->vA, es * (size_t)(2 * Kn * n))) != QRK_OK ||
+        (s = dalloc(h, &h->vB, es * (size_t)(2 * Kn * L))) != QRK_OK ||
+        (s = dalloc(h, &h->vb, es * (size_t)(2 * Kn))) != QRK_OK) {
+      free_all(hs);
+      delete hs;
+      return s;
+    }
+    h->vcat_stage = hs;
+  }
+  qrk_handle hs = h->vcat_stage;
+  if (launch_vcat_gather<T>(K, n, L, static_cast<const T*>(h->Rblk), static_cast<const T*>(h2->Rblk),
+                            static_cast<const T*>(h->Sc), static_cast<const T*>(h2->Sc),
+                            static_cast<const T*>(h->RB), static_cast<const T*>(h2->RB), static_cast<T*>(h->vA),
+                            static_cast<T*>(h->vB), static_cast<T*>(h->vb), static_cast<T*>(hs->Red), 2 * Kn,
+                            hs->ldr, st) != hipSuccess)
+    return QRK_EHIP;
+  hs->A = h->vA;
+  hs->B = h->vB;
+  hs->b = h->vb;
+  hs->d = h->d;  // the stage's damping rows are zero (lambda = 0)
+  hs->lam = 0.0;
+  hs->lam_ptr = hs->lam_d;
+  hs->factored = true;
+  const double zero = 0.0;
+  if ((s = factor_ba<T>(hs, st, &zero)) != QRK_OK) return s;
+  // the stage's factor is the factor of the stacked rows
+  if (hipMemcpyAsync(h->Rblk, hs->Rblk, es * (size_t)Kn * n, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(h->Sc, hs->Sc, es * (size_t)Kn * L, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(h->RB, hs->RB, es * (size_t)L * L, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(h->status, hs->status, sizeof(int), hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return QRK_EHIP;
+  return QRK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+qrk_status qrk_factor_vcat(qrk_handle h, qrk_handle h2, void* stream) {
+  if (!h || !h2 || h == h2 || h->kind != KIND_BLOCKANGULAR || h2->kind != KIND_BLOCKANGULAR || h->P != 1 ||
+      h2->P != 1 || !h->factored || !h2->factored || h->K != h2->K || h->n != h2->n || h->nB != h2->nB ||
+      h->dtype != h2->dtype || !h2->vparts.empty() || h->vparts.size() >= 64)
+    return QRK_EINVAL;
+  for (qrk_handle q : h->vparts)
+    if (q == h2) return QRK_EINVAL;
+  hipStream_t st = S(stream);
+  const qrk_status s = h->dtype == QRK_F32 ? factor_vcat<float>(h, h2, st) : factor_vcat<double>(h, h2, st);
+  if (s != QRK_OK) return s;
+  h->vparts.push_back(h2);
+  h->q_valid = false;
+  return QRK_OK;
+}
+
 qrk_status qrk_factor_blockangular_batched(qrk_handle h, const void* A, const void* B, const void* b,
                                            const double* d, const double* lambda_dev, void* stream) {
   if (!h || h->kind != KIND_BLOCKANGULAR || !A || !b || !d || !lambda_dev) return QRK_EINVAL;
@@ -879,7 +975,7 @@ qrk_status qrk_solve(qrk_handle h, double* p, int32_t sweeps, void* stream) {
 }
 
 qrk_status qrk_solve_rhs(qrk_handle h, const void* b, double* p, int32_t sweeps, void* stream) {
-  if (!h || !b || !p || sweeps < 1 || sweeps > 8 || !h->factored) return QRK_EINVAL;
+  if (!h || !b || !p || sweeps < 1 || sweeps > 8 || !h->factored || !h->vparts.empty()) return QRK_EINVAL;
   hipStream_t st = S(stream);
   const int64_t np = h->kind == KIND_BLOCKANGULAR ? h->N : (int64_t)h->P * h->N;
   if (launch_fill_double(p, np, 0.0, st) != hipSuccess) return QRK_EHIP;
@@ -891,7 +987,7 @@ qrk_status qrk_solve_rhs(qrk_handle h, const void* b, double* p, int32_t sweeps,
 
 qrk_status qrk_solve_adjoint(qrk_handle h, const double* p, const double* g, void* dA, void* dB,
                              void* db, double* dlambda, double* dd, void* stream) {
-  if (!h || !h->factored || !p || !g) return QRK_EINVAL;
+  if (!h || !h->factored || !p || !g || !h->vparts.empty()) return QRK_EINVAL;
   if (h->kind == KIND_BLOCKANGULAR) {
     if (h->P != 1 || (dB && h->nB == 0)) return QRK_EINVAL;
     return blockangular_adjoint(h, p, g, dA, dB, db, dlambda, dd, S(stream));

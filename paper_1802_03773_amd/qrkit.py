@@ -59,6 +59,7 @@ _SIGS = {
     "qrk_solve": (_c_i32, [_c_vp, _c_vp, _c_i32, _c_vp]),
     "qrk_solve_rhs": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_i32, _c_vp]),
     "qrk_solve_tol": (_c_i32, [_c_vp, _c_vp, _c_i32, _c_dbl, _c_i32p, _c_vp]),
+    "qrk_factor_vcat": (_c_i32, [_c_vp, _c_vp, _c_vp]),
     "qrk_set_keep_q": (_c_i32, [_c_vp, _c_i32]),
     "qrk_apply_qt": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp]),
     "qrk_solve_qt": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_i32, _c_vp]),
@@ -95,6 +96,14 @@ def lib() -> ctypes.CDLL:
     if _LIB is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1802_03773_amd.build`")
+        # torch's GPU runtime is brought up before the library's first HIP call: started the other
+        # way round, torch found no GPU in the same process
+        try:
+            import torch
+            if torch.cuda.is_available():
+                torch.cuda.init()
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             fn = getattr(L, name)
@@ -275,6 +284,13 @@ class BlockAngularSolver(Factor):
         self.K, self.n, self.nB, self.ldb, self.M = K, int(n), int(nB), ldb, int(row_off[-1])
         self.row_off = row_off
         self.mode = mode
+
+    def factor_vcat(self, other: "BlockAngularSolver", stream=None):
+        """Vertical concatenation (Section 4.5): this handle's factor becomes that of the problem with
+        its rows and `other`'s (both factored, same K, n, nB, dtype); `other` and its inputs must stay
+        alive until this handle's next factor call, since solves refine against both."""
+        _check(lib().qrk_factor_vcat(self._h, other._h, _stream_ptr(stream)), "qrk_factor_vcat")
+        self._keep = tuple(self._keep) + (other,)
 
     def set_tsqr_shape(self, leaves: int = 0, fanin: int = 0):
         _check(lib().qrk_set_tsqr_shape(self._h, int(leaves), int(fanin)), "qrk_set_tsqr_shape")
