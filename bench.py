@@ -110,7 +110,7 @@ def _parse():
                     help="also run a plain device copy of known size (for PMC byte scaling)")
     ap.add_argument("--workload", default="scale",
                     choices=["scale", "ragged-batch", "banded-batch", "lm-scale", "lm-banded-batch", "lambda-retry",
-                             "new-rhs"],
+                             "new-rhs", "configs"],
                     help="scale: one block-angular problem (the headline); ragged-batch: 512 block-angular "
                          "problems in one batch; banded-batch: 2,048 banded problems in one batch")
     ap.add_argument("--problems", type=int, default=0, help="batch workloads: problems (0 = the recipe's count)")
@@ -626,6 +626,131 @@ def run_new_rhs(args):
     return 0
 
 
+def _errs(p, p_ref, d):
+    """(2-norm relative error, largest column-scaled componentwise error) of p against p_ref."""
+    import numpy as np
+    p, p_ref, d = (np.asarray(x, np.float64) for x in (p, p_ref, d))
+    return (float(np.linalg.norm(p - p_ref) / np.linalg.norm(p_ref)),
+            float(np.max(d * np.abs(p - p_ref)) / np.max(d * np.abs(p_ref))))
+
+
+def run_configs(args):
+    """One row per workload configuration of the step solve besides the headline: the tiny
+    100-block problem (latency of one solve, float64 and float32), the 50,000-block problem at
+    lambda 1e-4, 1e-2 and 1 (steps/s, both update modes), the column-scaled precision problems
+    (k = 3, 4, 5: error against the float64 oracle by refinement sweeps, both modes) and the
+    10,000-block adjoint (time of factor + solve + adjoint, gradient against the oracle's)."""
+    import numpy as np
+    import torch
+
+    from paper_1802_03773_amd import BlockAngularSolver
+    from workloads import generators as gen
+
+    def timed(fn, steps):
+        for _ in range(max(args.warmup, 1)):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    def dev(inst):
+        return tuple(torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in (inst.A, inst.B, inst.b, inst.d))
+
+    oracle = not args.no_cpu
+    if oracle:
+        from oracle import adjoint as oadj
+        from oracle import dense as odense
+        from oracle import refine
+    rows = {}
+    # tiny problem: one solve's latency
+    tiny = {}
+    for dt, sweeps in ((np.float64, 0), (np.float32, 1)):
+        inst = gen.tiny_blockangular(args.seed, dtype=dt)
+        A, B, b, d = dev(inst)
+        s = BlockAngularSolver(inst.row_off, inst.n, inst.nB, dtype=np.dtype(dt).name)
+        p = torch.empty(inst.N, dtype=torch.float64, device="cuda")
+        ms = timed(lambda: (s.factor(A, B, b, d, inst.lam), s.solve(sweeps=sweeps, out=p)), max(args.steps, 50))
+        row = {"us_per_solve": ms * 1e3, "refine_sweeps": sweeps}
+        if oracle:
+            p_ref, _ = refine.reference_solution(inst)
+            row["rel_err"], row["scaled_err"] = _errs(p.cpu().numpy(), p_ref, inst.d)
+        tiny[np.dtype(dt).name] = row
+    rows["tiny_100_blocks"] = tiny
+    print("[bench] tiny done", file=sys.stderr, flush=True)
+    # the 50,000-block problem at three damping values
+    lam_rows = {}
+    for lam in (1e-4, 1e-2, 1.0):
+        inst = gen.scale_blockangular(args.seed, lam=lam)
+        A, B, b, d = dev(inst)
+        p = torch.empty(inst.N, dtype=torch.float64, device="cuda")
+        row = {}
+        for mode in ("plain", "bf16x3"):
+            s = BlockAngularSolver(inst.row_off, inst.n, inst.nB, dtype="float32", mode=mode)
+            ms = timed(lambda: (s.factor(A, B, b, d, lam), s.solve(sweeps=1, out=p)), args.steps)
+            row[mode] = {"steps_per_s": 1000.0 / ms, "ms_per_step": ms}
+            if oracle:
+                if "p_ref" not in row:
+                    row["p_ref"], _ = refine.reference_solution(inst, sweeps=2)
+                row[mode]["rel_err"], row[mode]["scaled_err"] = _errs(p.cpu().numpy(), row["p_ref"], inst.d)
+        row.pop("p_ref", None)
+        lam_rows[repr(lam)] = row
+        print(f"[bench] lambda {lam} done", file=sys.stderr, flush=True)
+    rows["scale_by_lambda"] = lam_rows
+    # column-scaled precision problems: error by refinement sweeps
+    if oracle:
+        prec = {}
+        for k in (3.0, 4.0, 5.0):
+            inst = gen.precision_blockangular(args.seed, k)
+            A, B, b, d = dev(inst)
+            p_ref, _ = refine.reference_solution(inst)
+            cond = float(np.linalg.cond(np.vstack([odense.assemble_blockangular(inst),
+                                                   np.sqrt(inst.lam) * np.diag(inst.d)])))
+            row = {"cond": cond}
+            for mode in ("plain", "bf16x3"):
+                s = BlockAngularSolver(inst.row_off, inst.n, inst.nB, dtype="float32", mode=mode)
+                s.factor(A, B, b, d, inst.lam)
+                row[mode] = {str(sw): _errs(s.solve(sweeps=sw).cpu().numpy(), p_ref, inst.d)[1] for sw in range(4)}
+            prec[f"k={int(k)}"] = row
+        rows["precision_scaled_err_by_sweeps"] = prec
+        print("[bench] precision done", file=sys.stderr, flush=True)
+    # the adjoint
+    inst, p_star = gen.adjoint_blockangular(500)
+    A, B, b, d = dev(inst)
+    s = BlockAngularSolver(inst.row_off, inst.n, inst.nB, dtype="float32")
+    ps = torch.from_numpy(p_star).cuda()
+    out = {}
+
+    def adj_step():
+        s.factor(A, B, b, d, inst.lam)
+        p = s.solve(sweeps=1)
+        out["p"] = p
+        out["g"] = s.solve_adjoint(p, p - ps)
+
+    ms = timed(adj_step, args.steps)
+    row = {"ms_factor_solve_adjoint": ms}
+    if oracle:
+        p_ref, f = refine.reference_solution(inst, sweeps=2)
+        ref = oadj.adjoint_blockangular(inst, f, p_ref, p_ref - p_star)
+        g = {k: v.cpu().numpy() for k, v in out["g"].items()}
+        for k in ("dA", "dB", "db", "dd"):
+            row[f"rel_err_{k}"] = float(np.linalg.norm(g[k] - ref[k]) / np.linalg.norm(ref[k]))
+        row["rel_err_dlam"] = float(abs(g["dlam"][0] - ref["dlam"]) / abs(ref["dlam"]))
+    rows["adjoint_10000_blocks"] = row
+    head = rows["scale_by_lambda"]["0.01"]["bf16x3"]
+    out_line = {"metric": METRIC, "value": head["steps_per_s"], "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+                "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
+                "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3", "data": "synthetic",
+                "config": {"workload": "per-configuration rows: the 100-block problem (float64, float32), the "
+                                       "50,000-block problem at lambda 1e-4, 1e-2, 1 (no autotuning), the "
+                                       "column-scaled precision problems k = 3, 4, 5, the 10,000-block adjoint"},
+                "rows": rows, "roofline": None, "cpu_baseline": None}
+    print(json.dumps(out_line))
+    return 0
+
+
 def main():
     args = _parse()
     if args.gpus != 1:
@@ -639,6 +764,8 @@ def main():
         return run_lambda(args)
     if args.workload == "new-rhs":
         return run_new_rhs(args)
+    if args.workload == "configs":
+        return run_configs(args)
     if args.workload != "scale":
         return run_batch(args)
     import numpy as np
