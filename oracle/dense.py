@@ -144,6 +144,26 @@ def assemble_blockangular(inst) -> np.ndarray:
     return J
 
 
+def assemble_blockangular_ncol(inst) -> np.ndarray:
+    """Dense J (M x N) of a block-angular instance whose block i has its own n_i columns
+    (Section 4.1 lets every diagonal block be m_i x n_i): block i's values are its rows
+    row-major, n_i per row, block after block; its columns follow those of the blocks before
+    it, the dense part's columns come last."""
+    K, M, nB = inst.K, inst.M, inst.nB
+    N = int(np.sum(inst.ncol)) + nB
+    J = np.zeros((M, N), dtype=np.float64)
+    A = inst.A.astype(np.float64)
+    pos, col = 0, 0
+    for i in range(K):
+        r0, r1 = int(inst.row_off[i]), int(inst.row_off[i + 1])
+        ni = int(inst.ncol[i])
+        J[r0:r1, col:col + ni] = A[pos:pos + (r1 - r0) * ni].reshape(r1 - r0, ni)
+        pos += (r1 - r0) * ni
+        col += ni
+    J[:, col:] = inst.B.astype(np.float64)
+    return J
+
+
 def solve_blockangular_dense(inst):
     """O1 on an assembled block-angular instance."""
     J = assemble_blockangular(inst)

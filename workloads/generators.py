@@ -160,6 +160,75 @@ def make_blockangular(seed: int, K: int, m, n: int, nB: int, lam: float,
     return BlockAngular(row_off, n, A, B, b, d, float(lam), dtype)
 
 
+@dataclasses.dataclass
+class BlockAngularNcol:
+    """Block-angular instance whose block i has its own column count ncol[i]."""
+
+    row_off: np.ndarray  # int64 [K+1]
+    ncol: np.ndarray     # int32 [K]
+    A: np.ndarray        # [sum_i m_i ncol_i] dtype: block i's rows, ncol_i values each
+    B: np.ndarray        # [M, nB] dtype
+    b: np.ndarray        # [M]     dtype
+    d: np.ndarray        # [N]     float64, > 0 (block i's unknowns, then the dense part's)
+    lam: float
+    dtype: np.dtype
+
+    @property
+    def K(self) -> int:
+        return int(self.row_off.shape[0] - 1)
+
+    @property
+    def M(self) -> int:
+        return int(self.row_off[-1])
+
+    @property
+    def nB(self) -> int:
+        return int(self.B.shape[1])
+
+    @property
+    def N(self) -> int:
+        return int(self.ncol.sum()) + self.nB
+
+    def a_off(self) -> np.ndarray:
+        """First value of block i in A (int64 [K+1])."""
+        out = np.zeros(self.K + 1, dtype=np.int64)
+        np.cumsum(np.diff(self.row_off) * self.ncol, out=out[1:])
+        return out
+
+    def p_off(self) -> np.ndarray:
+        """First unknown of block i (int64 [K+1])."""
+        out = np.zeros(self.K + 1, dtype=np.int64)
+        np.cumsum(self.ncol, out=out[1:])
+        return out
+
+
+def make_blockangular_ncol(seed: int, K: int, m, ncol, nB: int, lam: float,
+                           dtype=np.float64) -> BlockAngularNcol:
+    """Gaussian block-angular instance with per-block column counts (m, ncol: ints or int
+    arrays of length K); d is the column norms of the stored values (1 for a zero column)."""
+    rng = _rng(seed)
+    m_arr = np.full(K, int(m), dtype=np.int64) if np.isscalar(m) else np.asarray(m, np.int64)
+    n_arr = np.full(K, int(ncol), dtype=np.int32) if np.isscalar(ncol) else np.asarray(ncol, np.int32)
+    assert m_arr.shape == (K,) and n_arr.shape == (K,)
+    row_off = np.zeros(K + 1, dtype=np.int64)
+    np.cumsum(m_arr, out=row_off[1:])
+    M = int(row_off[-1])
+    dtype = np.dtype(dtype)
+    A = rng.standard_normal(int((m_arr * n_arr).sum())).astype(dtype)
+    B = rng.standard_normal((M, nB)).astype(dtype)
+    b = rng.standard_normal(M).astype(dtype)
+    dA = []
+    pos = 0
+    for i in range(K):
+        blk = A[pos:pos + m_arr[i] * n_arr[i]].astype(np.float64).reshape(m_arr[i], n_arr[i])
+        dA.append(np.sqrt((blk * blk).sum(axis=0)))
+        pos += m_arr[i] * n_arr[i]
+    B64 = B.astype(np.float64)
+    d = np.concatenate(dA + [np.sqrt((B64 * B64).sum(axis=0))])
+    d[d == 0.0] = 1.0
+    return BlockAngularNcol(row_off, n_arr, A, B, b, d, float(lam), dtype)
+
+
 # ---------------------------------------------------------------------------
 # Named workloads (shapes of the measured configurations)
 # ---------------------------------------------------------------------------
