@@ -98,6 +98,28 @@ qrk_status qrk_create_blockangular(int32_t K, int32_t n, int32_t nB, const int64
                                    int64_t ldb, qrk_dtype dtype, qrk_mode mode, qrk_handle* out);
 
 /* ------------------------------------------------------------------------------
+ * qrk_create_blockangular_ncol
+ *   Block-angular J whose blocks have their own column counts (Section 4.1: block i is
+ *   m_i x n_i): ncol_host [host, int32, K], 1 <= ncol_host[i] <= 8; the other arguments as
+ *   for qrk_create_blockangular.  The handle runs the blocks at n = max_i ncol_host[i]
+ *   columns: block i's columns past n_i are zero in J and their damping values are 1, so for
+ *   lambda > 0 those unknowns decouple from the rest and the solution restricted to the real
+ *   unknowns is that of the problem as given.
+ *   Layouts on such a handle (N' = sum_i n_i + nB unknowns): A [device] holds block i's rows
+ *   row-major with n_i values per row, block after block (block i starts at
+ *   sum_{k<i} m_k n_k); d [device, N' doubles] and p [N' doubles] hold block i's unknowns at
+ *   sum_{k<i} n_k, then the dense part's; B and b as for qrk_create_blockangular.
+ *   qrk_factor_blockangular copies A and d into the handle's layout (lambda > 0 is
+ *   required: QRK_EINVAL otherwise); qrk_solve and qrk_solve_tol write p in the caller's
+ *   layout; qrk_get_factor returns the factor of the handle's n-column layout.  The
+ *   two-stage, batched, new-right-hand-side, adjoint, stored-Q, concatenation, column-norm
+ *   and LM calls return QRK_EINVAL on this handle.
+ * ------------------------------------------------------------------------------ */
+qrk_status qrk_create_blockangular_ncol(int32_t K, const int32_t* ncol_host, int32_t nB,
+                                        const int64_t* row_off_host, int64_t ldb, qrk_dtype dtype,
+                                        qrk_mode mode, qrk_handle* out);
+
+/* ------------------------------------------------------------------------------
  * qrk_factor_blockangular
  *   Structured QR of P_r [J; sqrt(lambda) D] with b carried along (Sections 4.1, 4.2):
  *     per block   [A_i; sqrt(lambda) D_i] = Q_i [R_i; 0]   (Householder, Section 2),

@@ -4,5 +4,5 @@ The hot path lives in libqrkit.so (HIP kernels behind the C ABI of include/qrkit
 `qrkit` is its ctypes binding.
 """
 from . import qrkit  # noqa: F401
-from .qrkit import (BandedSolver, BlockAngularBatch, BlockAngularSolver, LMDriver, QRKError,  # noqa: F401
-                    factor_banded, factor_blockangular)
+from .qrkit import (BandedSolver, BlockAngularBatch, BlockAngularNcolSolver, BlockAngularSolver,  # noqa: F401
+                    LMDriver, QRKError, factor_banded, factor_blockangular)

@@ -20,6 +20,13 @@ hipError_t launch_rel_change(int P, const int64_t* noff, const double* p, const 
                              hipStream_t st);
 template <typename T>
 hipError_t launch_to_type(const double* src, T* dst, int64_t n, hipStream_t st);
+// blocks of their own widths: A and d into the handle's n columns per block, p back out
+template <typename T>
+hipError_t launch_ragged_in(int64_t K, int n, int nB, const int64_t* row_off, const int32_t* ncol,
+                            const int64_t* aoff, const int64_t* poff, const T* Au, const double* du, T* Ap,
+                            double* dp, hipStream_t st);
+hipError_t launch_ragged_out(int64_t K, int n, int nB, const int32_t* ncol, const int64_t* poff, const double* pp,
+                             double* pu, hipStream_t st);
 template <typename T>
 hipError_t launch_colnorms(int64_t K, int n, int nB, int64_t M, const int64_t* row_off, const T* A,
                            const T* B, int64_t ldb, double* d, double* part, int nparts, hipStream_t st);
@@ -147,6 +154,16 @@ struct qrk_handle_s {
   // vertical concatenation (qrk_factor_vcat): the handles whose rows were added to this factor
   // (borrowed until the next factor call), the stage problem that merges two factors and its
   // inputs (the interleaved rows of R1, R2)
+  // blocks of their own widths (qrk_create_blockangular_ncol): the handle runs them at n
+  // columns; A, d and p of the caller's layout are moved in and out around factor and solve
+  bool ragged = false;
+  int64_t rg_N = 0;            // unknowns of the caller's layout: sum of ncol_i, plus nB
+  int32_t* rg_ncol = nullptr;  // [K]
+  int64_t* rg_aoff = nullptr;  // [K + 1] first value of block i in the caller's A
+  int64_t* rg_poff = nullptr;  // [K + 1] first unknown of block i in the caller's d and p
+  void* rg_A = nullptr;        // [M x n]
+  double* rg_d = nullptr;      // [N]
+  double* rg_p = nullptr;      // [N]
   std::vector<qrk_handle_s*> vparts;
   qrk_handle_s* vcat_stage = nullptr;
   void* vA = nullptr;

@@ -772,6 +772,47 @@ qrk_status qrk_create_blockangular(int32_t K, int32_t n, int32_t nB, const int64
   return create_ba(1, n, &K, &nB, row_off_host, ldb, dtype, mode, out);
 }
 
+qrk_status qrk_create_blockangular_ncol(int32_t K, const int32_t* ncol_host, int32_t nB, const int64_t* row_off_host,
+                                        int64_t ldb, qrk_dtype dtype, qrk_mode mode, qrk_handle* out) {
+  if (!out) return QRK_EINVAL;
+  *out = nullptr;
+  if (K < 1 || !ncol_host || !row_off_host) return QRK_EINVAL;
+  int nmax = 0;
+  for (int32_t i = 0; i < K; ++i) {
+    if (ncol_host[i] < 1 || ncol_host[i] > QRK_MAX_BLOCK_COLS) return QRK_EINVAL;
+    nmax = std::max(nmax, (int)ncol_host[i]);
+  }
+  qrk_status s = qrk_create_blockangular(K, nmax, nB, row_off_host, ldb, dtype, mode, out);
+  if (s != QRK_OK) return s;
+  qrk_handle h = *out;
+  std::vector<int64_t> aoff((size_t)K + 1, 0), poff((size_t)K + 1, 0);
+  for (int32_t i = 0; i < K; ++i) {
+    aoff[(size_t)i + 1] = aoff[(size_t)i] + (row_off_host[i + 1] - row_off_host[i]) * ncol_host[i];
+    poff[(size_t)i + 1] = poff[(size_t)i] + ncol_host[i];
+  }
+  const size_t es = dtype == QRK_F32 ? 4 : 8;
+  if ((s = dalloc(h, &h->rg_ncol, sizeof(int32_t) * (size_t)K)) != QRK_OK ||
+      (s = dalloc(h, &h->rg_aoff, sizeof(int64_t) * aoff.size())) != QRK_OK ||
+      (s = dalloc(h, &h->rg_poff, sizeof(int64_t) * poff.size())) != QRK_OK ||
+      (s = dalloc(h, &h->rg_A, es * (size_t)h->M * (size_t)nmax)) != QRK_OK ||
+      (s = dalloc(h, &h->rg_d, sizeof(double) * (size_t)h->N)) != QRK_OK ||
+      (s = dalloc(h, &h->rg_p, sizeof(double) * (size_t)h->N)) != QRK_OK) {
+    qrk_destroy(h);
+    *out = nullptr;
+    return s;
+  }
+  if (hipMemcpy(h->rg_ncol, ncol_host, sizeof(int32_t) * (size_t)K, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(h->rg_aoff, aoff.data(), sizeof(int64_t) * aoff.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(h->rg_poff, poff.data(), sizeof(int64_t) * poff.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    qrk_destroy(h);
+    *out = nullptr;
+    return QRK_EHIP;
+  }
+  h->ragged = true;
+  h->rg_N = poff[(size_t)K] + nB;
+  return QRK_OK;
+}
+
 qrk_status qrk_create_blockangular_batched(int32_t P, int32_t n, const int32_t* K_host, const int32_t* nB_host,
                                            const int64_t* row_off_host, qrk_dtype dtype, qrk_mode mode,
                                            qrk_handle* out) {
@@ -785,6 +826,20 @@ qrk_status qrk_factor_blockangular(qrk_handle h, const void* A, const void* B, c
   if (!h || h->kind != KIND_BLOCKANGULAR || h->P != 1) return QRK_EINVAL;
   if (!A || !b || !d || (h->nB > 0 && !B)) return QRK_EINVAL;
   if (!(lambda >= 0.0) || !std::isfinite(lambda)) return QRK_EINVAL;
+  if (h->ragged) {  // the blocks at n columns: zero columns past n_i with unit damping
+    if (!(lambda > 0.0)) return QRK_EINVAL;
+    const hipError_t e =
+        h->dtype == QRK_F32
+            ? launch_ragged_in<float>(h->K, h->n, h->nB, h->row_off_d, h->rg_ncol, h->rg_aoff, h->rg_poff,
+                                      static_cast<const float*>(A), d, static_cast<float*>(h->rg_A), h->rg_d,
+                                      S(stream))
+            : launch_ragged_in<double>(h->K, h->n, h->nB, h->row_off_d, h->rg_ncol, h->rg_aoff, h->rg_poff,
+                                       static_cast<const double*>(A), d, static_cast<double*>(h->rg_A), h->rg_d,
+                                       S(stream));
+    if (e != hipSuccess) return QRK_EHIP;
+    A = h->rg_A;
+    d = h->rg_d;
+  }
   h->A = A;
   h->B = B;
   h->b = b;
@@ -802,6 +857,7 @@ qrk_status qrk_factor_blockangular(qrk_handle h, const void* A, const void* B, c
 // problem whose blocks are the n rows of R_i (coupled rows S_i | c_i) and whose dense part also
 // takes the rows of R_B | c_B; it runs on an internal handle of that shape.
 qrk_status qrk_factor_lambda(qrk_handle h, double lambda, void* stream) {
+  if (h && h->ragged) return QRK_EINVAL;  // needs the factor at lambda = 0
   if (!h || h->kind != KIND_BLOCKANGULAR || h->P != 1 || !h->factored) return QRK_EINVAL;
   if (!(lambda > 0.0) || !std::isfinite(lambda)) return QRK_EINVAL;
   hipStream_t st = S(stream);
@@ -941,7 +997,7 @@ extern "C" {
 qrk_status qrk_factor_vcat(qrk_handle h, qrk_handle h2, void* stream) {
   if (!h || !h2 || h == h2 || h->kind != KIND_BLOCKANGULAR || h2->kind != KIND_BLOCKANGULAR || h->P != 1 ||
       h2->P != 1 || !h->factored || !h2->factored || h->K != h2->K || h->n != h2->n || h->nB != h2->nB ||
-      h->dtype != h2->dtype || !h2->vparts.empty() || h->vparts.size() >= 64)
+      h->dtype != h2->dtype || !h2->vparts.empty() || h->vparts.size() >= 64 || h->ragged || h2->ragged)
     return QRK_EINVAL;
   for (qrk_handle q : h->vparts)
     if (q == h2) return QRK_EINVAL;
@@ -955,7 +1011,7 @@ qrk_status qrk_factor_vcat(qrk_handle h, qrk_handle h2, void* stream) {
 
 qrk_status qrk_factor_blockangular_batched(qrk_handle h, const void* A, const void* B, const void* b,
                                            const double* d, const double* lambda_dev, void* stream) {
-  if (!h || h->kind != KIND_BLOCKANGULAR || !A || !b || !d || !lambda_dev) return QRK_EINVAL;
+  if (!h || h->kind != KIND_BLOCKANGULAR || h->ragged || !A || !b || !d || !lambda_dev) return QRK_EINVAL;
   if (h->max_L > 1 && !B) return QRK_EINVAL;
   h->A = A;
   h->B = B;
@@ -968,6 +1024,14 @@ qrk_status qrk_factor_blockangular_batched(qrk_handle h, const void* A, const vo
 
 qrk_status qrk_solve(qrk_handle h, double* p, int32_t sweeps, void* stream) {
   if (!h || !p || sweeps < 0 || sweeps > 8 || !h->factored) return QRK_EINVAL;
+  if (h->ragged) {
+    const qrk_status s = h->dtype == QRK_F32 ? solve_ba<float>(h, h->rg_p, sweeps, S(stream))
+                                             : solve_ba<double>(h, h->rg_p, sweeps, S(stream));
+    if (s != QRK_OK) return s;
+    return launch_ragged_out(h->K, h->n, h->nB, h->rg_ncol, h->rg_poff, h->rg_p, p, S(stream)) == hipSuccess
+               ? QRK_OK
+               : QRK_EHIP;
+  }
   if (h->kind == KIND_BLOCKANGULAR)
     return h->dtype == QRK_F32 ? solve_ba<float>(h, p, sweeps, S(stream))
                                : solve_ba<double>(h, p, sweeps, S(stream));
@@ -975,7 +1039,8 @@ qrk_status qrk_solve(qrk_handle h, double* p, int32_t sweeps, void* stream) {
 }
 
 qrk_status qrk_solve_rhs(qrk_handle h, const void* b, double* p, int32_t sweeps, void* stream) {
-  if (!h || !b || !p || sweeps < 1 || sweeps > 8 || !h->factored || !h->vparts.empty()) return QRK_EINVAL;
+  if (!h || !b || !p || sweeps < 1 || sweeps > 8 || !h->factored || !h->vparts.empty() || h->ragged)
+    return QRK_EINVAL;
   hipStream_t st = S(stream);
   const int64_t np = h->kind == KIND_BLOCKANGULAR ? h->N : (int64_t)h->P * h->N;
   if (launch_fill_double(p, np, 0.0, st) != hipSuccess) return QRK_EHIP;
@@ -987,7 +1052,7 @@ qrk_status qrk_solve_rhs(qrk_handle h, const void* b, double* p, int32_t sweeps,
 
 qrk_status qrk_solve_adjoint(qrk_handle h, const double* p, const double* g, void* dA, void* dB,
                              void* db, double* dlambda, double* dd, void* stream) {
-  if (!h || !h->factored || !p || !g || !h->vparts.empty()) return QRK_EINVAL;
+  if (!h || !h->factored || !p || !g || !h->vparts.empty() || h->ragged) return QRK_EINVAL;
   if (h->kind == KIND_BLOCKANGULAR) {
     if (h->P != 1 || (dB && h->nB == 0)) return QRK_EINVAL;
     return blockangular_adjoint(h, p, g, dA, dB, db, dlambda, dd, S(stream));
@@ -997,7 +1062,8 @@ qrk_status qrk_solve_adjoint(qrk_handle h, const double* p, const double* g, voi
 }
 
 qrk_status qrk_colnorms_blockangular(qrk_handle h, const void* A, const void* B, double* d, void* stream) {
-  if (!h || h->kind != KIND_BLOCKANGULAR || h->P != 1 || !A || !d || (h->nB > 0 && !B)) return QRK_EINVAL;
+  if (!h || h->kind != KIND_BLOCKANGULAR || h->P != 1 || h->ragged || !A || !d || (h->nB > 0 && !B))
+    return QRK_EINVAL;
   const int nparts = (int)std::min<int64_t>(std::max<int64_t>(1, ceil_div(h->M, 512)), 1024);
   hipError_t e = h->dtype == QRK_F32
                      ? launch_colnorms<float>(h->K, h->n, h->nB, h->M, h->row_off_d,

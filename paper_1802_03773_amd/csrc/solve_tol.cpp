@@ -36,15 +36,8 @@ qrk_status tol_buffers(qrk_handle h) {
   return QRK_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-qrk_status qrk_solve_tol(qrk_handle h, double* p, int32_t max_sweeps, double rel_tol, int32_t* sweeps_host,
-                         void* stream) {
-  if (!h || !p || !h->factored || max_sweeps < 0 || max_sweeps > 8 || !(rel_tol >= 0.0) || !std::isfinite(rel_tol))
-    return QRK_EINVAL;
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+qrk_status solve_tol(qrk_handle h, double* p, int32_t max_sweeps, double rel_tol, int32_t* sweeps_host,
+                     hipStream_t st) {
   qrk_status s = tol_buffers(h);
   if (s != QRK_OK) return s;
   if ((s = h->kind == KIND_BLOCKANGULAR ? blockangular_solve(h, p, 0, st) : banded_solve(h, p, 0, st)) != QRK_OK)
@@ -88,6 +81,22 @@ qrk_status qrk_solve_tol(qrk_handle h, double* p, int32_t max_sweeps, double rel
       hipStreamSynchronize(st) != hipSuccess)
     return QRK_EHIP;
   return QRK_ENOTCONVERGED;
+}
+
+}  // namespace
+
+extern "C" {
+
+qrk_status qrk_solve_tol(qrk_handle h, double* p, int32_t max_sweeps, double rel_tol, int32_t* sweeps_host,
+                         void* stream) {
+  if (!h || !p || !h->factored || max_sweeps < 0 || max_sweeps > 8 || !(rel_tol >= 0.0) || !std::isfinite(rel_tol))
+    return QRK_EINVAL;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (!h->ragged) return solve_tol(h, p, max_sweeps, rel_tol, sweeps_host, st);
+  // blocks of their own widths: the sweeps run on the handle's layout, p is written back after
+  const qrk_status s = solve_tol(h, h->rg_p, max_sweeps, rel_tol, sweeps_host, st);
+  if (s != QRK_OK && s != QRK_ENOTCONVERGED) return s;
+  return launch_ragged_out(h->K, h->n, h->nB, h->rg_ncol, h->rg_poff, h->rg_p, p, st) == hipSuccess ? s : QRK_EHIP;
 }
 
 }  // extern "C"

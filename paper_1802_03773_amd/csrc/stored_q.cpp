@@ -25,7 +25,7 @@ extern "C" {
 qrk_status qrk_set_keep_q(qrk_handle h, int32_t keep) {
   if (!h) return QRK_EINVAL;
   if (keep) {
-    if (h->kind != KIND_BLOCKANGULAR || h->dtype != QRK_F32 || h->max_rows > 64) return QRK_EINVAL;
+    if (h->kind != KIND_BLOCKANGULAR || h->dtype != QRK_F32 || h->max_rows > 64 || h->ragged) return QRK_EINVAL;
     for (int c = 0; c < kBlockClasses; ++c)
       if (block_class_short(c) && h->bq_count[c] > 0) return QRK_EINVAL;
   }

@@ -36,6 +36,8 @@ _c_i32p = ctypes.POINTER(ctypes.c_int32)
 _SIGS = {
     "qrk_create_blockangular": (_c_i32, [_c_i32, _c_i32, _c_i32, _c_i64p, _c_i64, _c_i32, _c_i32,
                                          ctypes.POINTER(_c_vp)]),
+    "qrk_create_blockangular_ncol": (_c_i32, [_c_i32, _c_i32p, _c_i32, _c_i64p, _c_i64, _c_i32, _c_i32,
+                                              ctypes.POINTER(_c_vp)]),
     "qrk_factor_blockangular": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_dbl, _c_vp]),
     "qrk_factor_lambda": (_c_i32, [_c_vp, _c_dbl, _c_vp]),
     "qrk_create_blockangular_batched": (_c_i32, [_c_i32, _c_i32, _c_i32p, _c_i32p, _c_i64p, _c_i32, _c_i32,
@@ -292,6 +294,9 @@ class BlockAngularSolver(Factor):
         _check(lib().qrk_factor_vcat(self._h, other._h, _stream_ptr(stream)), "qrk_factor_vcat")
         self._keep = tuple(self._keep) + (other,)
 
+    def _a_len(self) -> int:
+        return self.M * self.n
+
     def set_tsqr_shape(self, leaves: int = 0, fanin: int = 0):
         _check(lib().qrk_set_tsqr_shape(self._h, int(leaves), int(fanin)), "qrk_set_tsqr_shape")
 
@@ -305,7 +310,7 @@ class BlockAngularSolver(Factor):
     def factor(self, A, B, b, d, lam: float, stream=None):
         torch = _torch()
         td = _torch_dtype(self.qdtype)
-        pa = _dev_ptr(A, td, "A", self.M * self.n)
+        pa = _dev_ptr(A, td, "A", self._a_len())
         pB = _dev_ptr(B, td, "B", self.M * self.ldb) if self.nB > 0 else (
             _dev_ptr(B, td, "B") if B is not None else None)
         pb = _dev_ptr(b, td, "b", self.M)
@@ -371,6 +376,36 @@ class BlockAngularSolver(Factor):
                "qrk_solve_adjoint")
         return out
 
+
+
+class BlockAngularNcolSolver(BlockAngularSolver):
+    """Block-angular J whose block i has its own column count ncol[i] (1..8): A holds block
+    i's rows row-major with ncol[i] values each, block after block; d and p hold block i's
+    unknowns, then the dense part's (qrk_create_blockangular_ncol).  factor() needs lam > 0;
+    get_factor() returns the factor at max(ncol) columns per block."""
+
+    def __init__(self, row_off, ncol, nB: int, ldb: Optional[int] = None, dtype="float32",
+                 mode: str = "plain"):
+        row_off = np.ascontiguousarray(np.asarray(row_off, dtype=np.int64))
+        ncol = np.ascontiguousarray(np.asarray(ncol, dtype=np.int32))
+        K = int(row_off.shape[0] - 1)
+        if ncol.shape != (K,):
+            raise ValueError(f"ncol has shape {ncol.shape}, needs ({K},)")
+        qd = QRK_F32 if str(dtype).endswith("float32") else QRK_F64
+        qm = {"plain": QRK_PLAIN, "bf16x3": QRK_BF16X3}[mode]
+        ldb = nB if ldb is None else int(ldb)
+        h = _c_vp()
+        st = lib().qrk_create_blockangular_ncol(K, ncol.ctypes.data_as(_c_i32p), int(nB),
+                                                row_off.ctypes.data_as(_c_i64p), ldb, qd, qm, ctypes.byref(h))
+        _check(st, "qrk_create_blockangular_ncol")
+        Factor.__init__(self, h, "blockangular", qd, int(ncol.sum()) + int(nB))
+        self.K, self.n, self.nB, self.ldb, self.M = K, int(ncol.max()), int(nB), ldb, int(row_off[-1])
+        self.row_off = row_off
+        self.ncol = ncol
+        self.mode = mode
+
+    def _a_len(self) -> int:
+        return int((np.diff(self.row_off) * self.ncol).sum())
 
 class BlockAngularBatch(Factor):
     """P independent block-angular problems with the same block width n, factored and solved

@@ -161,3 +161,19 @@ def test_stored_q_entry_points_reject_null_handle():
     assert L.qrk_set_keep_q(None, 0) == qrkit.QRK_EINVAL
     assert L.qrk_apply_qt(None, None, None, None) == qrkit.QRK_EINVAL
     assert L.qrk_solve_qt(None, None, None, 0, None) == qrkit.QRK_EINVAL
+
+
+@pytest.mark.parametrize("ncol", [[3, 0, 2], [3, 9, 2], [1, 2, -1]])
+def test_ncol_create_rejects_bad_widths(ncol):
+    """qrk_create_blockangular_ncol: every block width in 1..8, checked on the host."""
+    L = qrkit.lib()
+    h = ctypes.c_void_p()
+    ro = np.array([0, 4, 8, 12], dtype=np.int64)
+    nc = np.asarray(ncol, dtype=np.int32)
+    st = L.qrk_create_blockangular_ncol(3, nc.ctypes.data_as(qrkit._c_i32p), 5, ro.ctypes.data_as(qrkit._c_i64p), 5,
+                                        0, 0, ctypes.byref(h))
+    assert st == qrkit.QRK_EINVAL and not h.value
+    assert L.qrk_create_blockangular_ncol(3, None, 5, ro.ctypes.data_as(qrkit._c_i64p), 5, 0, 0,
+                                          ctypes.byref(h)) == qrkit.QRK_EINVAL
+    assert L.qrk_create_blockangular_ncol(3, nc.ctypes.data_as(qrkit._c_i32p), 5, ro.ctypes.data_as(qrkit._c_i64p),
+                                          5, 0, 0, None) == qrkit.QRK_EINVAL
