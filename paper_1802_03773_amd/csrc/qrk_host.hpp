@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "qrk_batch.hpp"
+#include "qrk_launch.hpp"
 #include "qrkit.h"
 
 namespace qrk {
@@ -106,8 +107,13 @@ struct qrk_handle_s {
   void* Sc = nullptr;     // [K][n][nB+1]
   void* Red = nullptr;    // [M][ldr]
   void* RB = nullptr;     // [nB+1][nB+1]
-  void* part0 = nullptr;  // TSQR partial triangles (float64 path)
-  void* part1 = nullptr;
+  void* part0 = nullptr;  // TSQR partial triangles (float64 path): even levels
+  void* part1 = nullptr;  // odd levels
+  int64_t part_cap0 = 0, part_cap1 = 0;  // elements
+  // float64 dense part: every level's workgroups (all problems), level by level
+  qrk::TsqrWg* tsqr_wg = nullptr;
+  int64_t tsqr_wg_cap = 0;
+  std::vector<int> tsqr_lvl_begin, tsqr_lvl_count;
   float* slots = nullptr; // TSQR tree slots (float32 matrix-core path)
   int* counters = nullptr;
   int max_leaves = 1;

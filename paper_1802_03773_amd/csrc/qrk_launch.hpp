@@ -29,12 +29,21 @@ hipError_t launch_blockqr_n(const int32_t* blk_list, int64_t begin, int64_t coun
                             const T* B, const T* b, const double* d, const double* lam, T* Rblk, T* Sc, T* Red,
                             const BqrPrologue& pro, const QKeep& qk, hipStream_t st);
 
-// Stream rows [g*rows_per_wg, (g+1)*rows_per_wg) of X (nrows x L, row stride ldx) into
-// an L x L upper-triangular R per workgroup g (Householder merges); workgroup 0 starts
-// from diag(sqrt(*lam) * dB) (dB may be null, then lam is unused).  Rout is [grid][L][L].
+// One workgroup of the float64 tall-skinny QR: stream rows [r0, r1) of its input (row
+// stride ldx, L columns) into an L x L upper-triangular R (Householder merges) written
+// row-major at out_off.  Input buffer: in_buf 0 the reduced rows (x_off from Red), 1 or 2 a
+// partial-triangle buffer; output: out_buf 0 the problem's R_B | c_B (in RB), 1 or 2 a
+// partial buffer.  seed >= 0: the leaf starts from diag(sqrt(lam_q) d_B) of problem q = seed.
+struct TsqrWg {
+  int64_t x_off, r0, r1, out_off;
+  int32_t ldx, L, seed;
+  int8_t in_buf, out_buf;
+};
+// One launch per level (count workgroups from wg): the leaves of every problem, then the
+// fanin-way merges of each problem's triangles, level by level; Lmax: the widest problem.
 template <typename T>
-hipError_t launch_tsqr_stream(const T* X, int64_t ldx, int64_t nrows, int L, int64_t rows_per_wg,
-                              int grid, const double* dB, const double* lam, T* Rout, hipStream_t st);
+hipError_t launch_tsqr_stream(const TsqrWg* wg, int count, int Lmax, const ProbDesc* probs, int n, const T* Red,
+                              const double* d, const double* lam, T* part0, T* part1, T* RB, hipStream_t st);
 
 // Float32 tall-skinny QR on the matrix cores for a batch: the global leaves
 // [cls_begin[c], cls_begin[c] + cls_count[c]) are the leaves of the problems with c

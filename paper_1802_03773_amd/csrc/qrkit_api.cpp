@@ -129,35 +129,15 @@ qrk_status factor_ba(qrk_handle h, hipStream_t st, const double* lam_host = null
     h->q_valid = keep;
     return QRK_OK;
   }
-  // float64 dense parts, problem by problem: leaves, then the reduction tree (ping-pong
-  // buffers, last level -> the problem's R_B)
+  // float64 dense parts: the leaves of every problem in one launch, then one launch per merge
+  // level over every problem still merging (the last level of each writes its R_B | c_B)
   T* P0 = static_cast<T*>(h->part0);
   T* P1 = static_cast<T*>(h->part1);
-  for (int q = 0; q < h->P; ++q) {
-    const ProbDesc& D = h->probs_h[q];
-    const int L = D.L;
-    int G = D.leaves;
-    const int64_t rows_per = std::max<int64_t>(1, ceil_div(D.M, G));
-    T* root = RB + D.rboff;
-    T* out = (G == 1) ? root : P0;
-    pr = prof_begin(h, 1, st);
-    if (launch_tsqr_stream<T>(Red + D.redoff, D.ldr, D.M, L, rows_per, G, h->d + D.noff + D.K * h->n,
-                              h->lam_ptr + q, out, st) != hipSuccess)
+  for (size_t lv = 0; lv < h->tsqr_lvl_begin.size(); ++lv) {
+    pr = prof_begin(h, lv == 0 ? 1 : 2, st);
+    if (launch_tsqr_stream<T>(h->tsqr_wg + h->tsqr_lvl_begin[lv], h->tsqr_lvl_count[lv], h->max_L, h->probs_d,
+                              h->n, Red, h->d, h->lam_ptr, P0, P1, RB, st) != hipSuccess)
       return QRK_EHIP;
-    prof_end(h, pr, st);
-    T* cur = out;
-    T* other = P1;
-    pr = prof_begin(h, 2, st);
-    while (G > 1) {
-      const int Gn = (int)ceil_div(G, h->fanin);
-      T* dst = (Gn == 1) ? root : other;
-      if (launch_tsqr_stream<T>(cur, L, (int64_t)G * L, L, (int64_t)h->fanin * L, Gn, nullptr, nullptr, dst, st) !=
-          hipSuccess)
-        return QRK_EHIP;
-      other = cur;
-      cur = dst;
-      G = Gn;
-    }
     prof_end(h, pr, st);
   }
   return QRK_OK;
@@ -280,11 +260,98 @@ qrk_status assign_leaves(qrk_handle h) {
   std::vector<ProbDesc>& pd = h->probs_h;
   const int P = h->P;
   if (h->dtype == QRK_F64) {
+    // leaves of about 256 rows (at most 1024 per problem; a batch's problems share about 4096
+    // in proportion to their rows)
+    double rows_all = 0.0;
+    for (const auto& D : pd) rows_all += (double)(D.M + D.nB);
     for (auto& D : pd) {
-      const int64_t def = std::max<int64_t>(1, std::min<int64_t>(ceil_div(D.M + D.nB, 256), 1024));
+      int64_t def = std::max<int64_t>(1, std::min<int64_t>(ceil_div(D.M + D.nB, 256), 1024));
+      if (P > 1) def = std::min<int64_t>(def, std::max<int64_t>(1, std::llround(4096.0 * (D.M + D.nB) / rows_all)));
       D.leaves = (int)(h->leaves > 0 ? h->leaves : def);
       D.rows_per_leaf = std::max<int64_t>(1, ceil_div(D.M, D.leaves));
     }
+    // the workgroups of every level, all problems together: level 0 streams each problem's
+    // reduced rows into its leaves' triangles, each later level merges fanin triangles of the
+    // level below (stacked as rows); a problem's last level writes its R_B | c_B.  Levels
+    // alternate between the two partial buffers.
+    std::vector<TsqrWg> wl;
+    h->tsqr_lvl_begin.clear();
+    h->tsqr_lvl_count.clear();
+    std::vector<int64_t> G((size_t)P), in_off((size_t)P, 0);
+    for (int q = 0; q < P; ++q) G[(size_t)q] = pd[(size_t)q].leaves;
+    int64_t need[2] = {0, 0};
+    for (int level = 0;; ++level) {
+      const int buf = 1 + (level & 1);  // this level's output buffer when not the root
+      int64_t off = 0;
+      const int begin = (int)wl.size();
+      bool any = false;
+      for (int q = 0; q < P; ++q) {
+        const ProbDesc& D = pd[(size_t)q];
+        const int64_t L = D.L;
+        if (level > 0 && G[(size_t)q] <= 1) continue;  // done
+        const int64_t nout = level == 0 ? G[(size_t)q] : ceil_div(G[(size_t)q], (int64_t)h->fanin);
+        for (int64_t k = 0; k < nout; ++k) {
+          TsqrWg w{};
+          w.L = (int32_t)L;
+          if (level == 0) {
+            w.x_off = D.redoff;
+            w.ldx = (int32_t)D.ldr;
+            w.r0 = std::min<int64_t>(k * D.rows_per_leaf, D.M);
+            w.r1 = std::min<int64_t>((k + 1) * D.rows_per_leaf, D.M);
+            w.seed = k == 0 ? q : -1;
+            w.in_buf = 0;
+          } else {
+            w.x_off = in_off[(size_t)q];
+            w.ldx = (int32_t)L;
+            w.r0 = k * h->fanin * L;
+            w.r1 = std::min<int64_t>((k + 1) * h->fanin, G[(size_t)q]) * L;
+            w.seed = -1;
+            w.in_buf = (int8_t)(1 + ((level - 1) & 1));
+          }
+          if (nout == 1) {
+            w.out_buf = 0;
+            w.out_off = D.rboff;
+          } else {
+            w.out_buf = (int8_t)buf;
+            w.out_off = off + k * L * L;
+          }
+          wl.push_back(w);
+        }
+        if (nout > 1) {
+          in_off[(size_t)q] = off;
+          off += nout * L * L;
+        }
+        G[(size_t)q] = nout;
+        any = true;
+      }
+      if (!any) break;
+      h->tsqr_lvl_begin.push_back(begin);
+      h->tsqr_lvl_count.push_back((int)wl.size() - begin);
+      need[buf - 1] = std::max(need[buf - 1], off);
+    }
+    qrk_status s;
+    const size_t es = sizeof(double);
+    if ((int64_t)wl.size() > h->tsqr_wg_cap) {
+      dfree(h, h->tsqr_wg);
+      h->tsqr_wg = nullptr;
+      h->tsqr_wg_cap = 0;
+      if ((s = dalloc(h, &h->tsqr_wg, sizeof(TsqrWg) * wl.size())) != QRK_OK) return s;
+      h->tsqr_wg_cap = (int64_t)wl.size();
+    }
+    for (int b = 0; b < 2; ++b) {
+      void*& part = b == 0 ? h->part0 : h->part1;
+      int64_t& cap = b == 0 ? h->part_cap0 : h->part_cap1;
+      if (need[b] > cap) {
+        dfree(h, part);
+        part = nullptr;
+        cap = 0;
+        if ((s = dalloc(h, reinterpret_cast<char**>(&part), es * (size_t)need[b])) != QRK_OK) return s;
+        cap = need[b];
+      }
+    }
+    if (!wl.empty() &&
+        hipMemcpy(h->tsqr_wg, wl.data(), sizeof(TsqrWg) * wl.size(), hipMemcpyHostToDevice) != hipSuccess)
+      return QRK_EHIP;
   } else {
     double rows_cls[9] = {0};
     for (auto& D : pd) rows_cls[(D.L + 15) / 16] += (double)(D.M + D.nB);
@@ -711,8 +778,6 @@ qrk_status create_ba(int32_t P, int32_t n, const int32_t* Kp, const int32_t* nBp
       (s = dalloc(h, &h->Sc, es * (size_t)soff)) != QRK_OK ||
       (s = dalloc(h, &h->Red, es * (size_t)std::max<int64_t>(redoff, 1))) != QRK_OK ||
       (s = dalloc(h, &h->RB, es * (size_t)rboff)) != QRK_OK ||
-      (s = dalloc(h, &h->part0, dtype == QRK_F64 ? es * (size_t)1024 * Lm * Lm : 0)) != QRK_OK ||
-      (s = dalloc(h, &h->part1, dtype == QRK_F64 ? es * (size_t)1024 * Lm * Lm : 0)) != QRK_OK ||
       (s = dalloc(h, &h->ybuf, sizeof(double) * (size_t)Ktot * n)) != QRK_OK ||
       (s = dalloc(h, &h->ubuf, sizeof(double) * (size_t)h->N)) != QRK_OK ||
       (s = dalloc(h, &h->vecpart, sizeof(double) * (size_t)1024 * std::max(Lm - 1, 1))) != QRK_OK ||
