@@ -638,7 +638,8 @@ def run_configs(args):
     """One row per workload configuration of the step solve besides the headline: the tiny
     100-block problem (latency of one solve, float64 and float32), the 50,000-block problem at
     lambda 1e-4, 1e-2 and 1 (steps/s, both update modes), the column-scaled precision problems
-    (k = 3, 4, 5: error against the float64 oracle by refinement sweeps, both modes) and the
+    (k = 3, 4, 5: error against the float64 oracle by refinement sweeps, both modes; also with the
+    scales rotated across B's columns, damped and undamped) and the
     10,000-block adjoint (time of factor + solve + adjoint, gradient against the oracle's)."""
     import numpy as np
     import torch
@@ -715,6 +716,24 @@ def run_configs(args):
                 row[mode] = {str(sw): _errs(s.solve(sweeps=sw).cpu().numpy(), p_ref, inst.d)[1] for sw in range(4)}
             prec[f"k={int(k)}"] = row
         rows["precision_scaled_err_by_sweeps"] = prec
+        # the rotated stress variant (B's column scales rotated by a Haar-orthogonal H): errors
+        # by refinement sweeps, damped and undamped
+        rot = {}
+        for k in (3, 4, 5):
+            for lam in (1e-4, 0.0):
+                inst = gen.precision_rotated(400 + k, k, lam=lam)
+                A, B, b, d = dev(inst)
+                p_ref, _ = refine.reference_solution(inst)
+                Aaug = np.vstack([odense.assemble_blockangular(inst), np.sqrt(lam) * np.diag(inst.d)])
+                row = {"cond": float(np.linalg.cond(Aaug)),
+                       "cond_equilibrated": float(np.linalg.cond(Aaug / np.linalg.norm(Aaug, axis=0)))}
+                for mode in ("plain", "bf16x3"):
+                    s = BlockAngularSolver(inst.row_off, inst.n, inst.nB, dtype="float32", mode=mode)
+                    s.factor(A, B, b, d, lam)
+                    row[mode] = {str(sw): _errs(s.solve(sweeps=sw).cpu().numpy(), p_ref, inst.d)[1]
+                                 for sw in range(9)}
+                rot[f"k={k} lambda={lam}"] = row
+        rows["precision_rotated_scaled_err_by_sweeps"] = rot
         print("[bench] precision done", file=sys.stderr, flush=True)
     # the adjoint
     inst, p_star = gen.adjoint_blockangular(500)

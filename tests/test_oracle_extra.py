@@ -218,3 +218,21 @@ def test_two_stage_small_lambda_reproduces_R():
     s0 = np.sign(np.diag(R0))
     s2 = np.sign(np.diag(R2))
     assert np.abs(s2[:, None] * R2 - s0[:, None] * R0).max() <= 1e-12 * np.abs(R0).max()
+
+
+def test_rotated_precision_generator():
+    """The rotated stress instances: B's column scales 10^(k t) are rotated by an orthogonal H,
+    so B^T B has the scaled spectrum (its singular values are those of B_0 diag(s)) while B's
+    column norms stay within a modest range (unlike the column-scaled variant)."""
+    import numpy as np
+
+    from workloads import generators as gen
+    for k in (3, 5):
+        inst = gen.precision_rotated(400 + k, k, lam=0.0, dtype=np.float64)
+        base = gen.make_blockangular(400 + k, K=100, m=8, n=3, nB=24, lam=0.0, dtype=np.float64)
+        assert np.array_equal(inst.A, base.A) and np.array_equal(inst.b, base.b)
+        sv_rot = np.linalg.svd(inst.B, compute_uv=False)
+        cn = np.linalg.norm(inst.B, axis=0)
+        assert sv_rot.max() / sv_rot.min() > 10.0 ** (k - 1)        # the spread survives the rotation
+        assert cn.max() / cn.min() < 10.0                            # but not along the columns
+        assert np.allclose(inst.d[inst.K * 3:], cn, rtol=1e-14)      # d = column norms of the stored B

@@ -250,6 +250,27 @@ def precision_blockangular(seed: int, k: float, dtype=np.float32, lam: float = 1
     return make_blockangular(seed, K=100, m=8, n=3, nB=24, lam=lam, dtype=dtype, scale_k=k)
 
 
+def precision_rotated(seed: int, k: float, lam: float = 1e-4, dtype=np.float32) -> BlockAngular:
+    """Tiny-workload shapes with B <- B diag(10^(k t_B)) H: t_B a seeded permutation of
+    linspace(0, 1, 24), H a Haar-distributed orthogonal 24 x 24 matrix (QR of a Gaussian with the
+    signs of R's diagonal folded into Q), so the spread of scales is rotated across B's columns
+    and neither column scaling nor a small damping removes it; d is the column norms."""
+    inst = make_blockangular(seed, K=100, m=8, n=3, nB=24, lam=lam, dtype=np.float64)
+    rng = _rng(seed + 7919)
+    nB = inst.nB
+    s = _column_scales(rng, nB, float(k))
+    G = rng.standard_normal((nB, nB))
+    Q, R = np.linalg.qr(G)
+    H = Q * np.sign(np.diag(R))[None, :]
+    B = (inst.B * s[None, :]) @ H
+    dtype = np.dtype(dtype)
+    A = inst.A.astype(dtype)
+    B = B.astype(dtype)
+    b = inst.b.astype(dtype)
+    d = column_norms_blockangular(inst.row_off, inst.n, A, B)
+    return BlockAngular(inst.row_off, inst.n, A, B, b, d, float(lam), dtype)
+
+
 def adjoint_blockangular(seed: int = 500, dtype=np.float32, K: int = 10_000, nB: int = 60,
                          lam: float = 1e-2):
     """10,000 blocks of 12x3, dense part 120,000x60, lambda = 1e-2; also returns p* ~ N(0,1)."""
