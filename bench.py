@@ -678,6 +678,14 @@ def run_configs(args):
         if oracle:
             p_ref, _ = refine.reference_solution(inst)
             row["rel_err"], row["scaled_err"] = _errs(p.cpu().numpy(), p_ref, inst.d)
+        # the same step captured as one HIP graph and replayed (no launch cost per kernel)
+        eager = p.clone()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            s.factor(A, B, b, d, inst.lam)
+            s.solve(sweeps=sweeps, out=p)
+        row["us_per_solve_graph_replay"] = timed(g.replay, max(args.steps, 100)) * 1e3
+        row["graph_replay_bit_identical"] = bool(torch.equal(p, eager))
         tiny[np.dtype(dt).name] = row
     rows["tiny_100_blocks"] = tiny
     print("[bench] tiny done", file=sys.stderr, flush=True)
