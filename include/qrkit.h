@@ -488,6 +488,35 @@ qrk_status qrk_solve_banded_noalloc(int32_t P, int64_t M, int64_t N, int32_t w, 
                                     double lambda, double* p, int32_t sweeps, int32_t* status_dev, void* stream);
 
 /* ------------------------------------------------------------------------------
+ * qrk_discover_blockangular / qrk_discover_banded  [host only: no device, no handle]
+ *   The row and column permutations of Section 4.3 that reveal a structure in a sparse J,
+ *   J' = P_r J P_c, given J's pattern: row_ptr [host, int64, M+1] (row_ptr[0] = 0,
+ *   nondecreasing) and col_idx [host, int32, row_ptr[M]] (each row's columns, 0 <= c < N, any
+ *   order).  Values are not read.  Row k of J' is row row_perm[k] of J; column j of J' is
+ *   column col_perm[j] of J.  All outputs are caller-allocated host arrays.
+ *   Block-angular (for qrk_create_blockangular_ncol): dense_cols [host, int32, nB] are the
+ *   coupled columns (distinct, nB <= 127, nB < N).  Two rows belong to the same block when they
+ *   share a non-dense column, transitively; a block's columns are the non-dense columns of its
+ *   rows (a column no row touches is a block of one column and no rows).  Blocks come in order
+ *   of their smallest column, each block's columns and rows in increasing order, then the dense
+ *   columns in the order given.  Rows that touch only dense columns go to the first blocks with
+ *   fewer than QRK_MAX_BLOCK_ROWS rows.  Outputs: row_perm [M], col_perm [N], ncol [N] (the K
+ *   block widths), row_off [M + 1] (the K + 1 block row offsets of J'), *K.
+ *   Banded (for qrk_create_banded): rows in order of their first column (stable; the paper's
+ *   as-banded-as-possible row order), columns unpermuted.  Outputs: row_perm [M], row_start [M]
+ *   (the start column of each row of J', its first column clamped to N - w so that its w
+ *   values lie in the matrix; nondecreasing), *w (the largest last - first + 1 over the rows).
+ *   QRK_EINVAL: null pointers, bad sizes or indices, repeated dense columns; a block wider than
+ *   QRK_MAX_BLOCK_COLS or taller than QRK_MAX_BLOCK_ROWS; an empty row or w > QRK_MAX_BAND
+ *   (banded).
+ * ------------------------------------------------------------------------------ */
+qrk_status qrk_discover_blockangular(int64_t M, int64_t N, const int64_t* row_ptr, const int32_t* col_idx,
+                                     int32_t nB, const int32_t* dense_cols, int64_t* row_perm,
+                                     int32_t* col_perm, int32_t* ncol, int64_t* row_off, int32_t* K);
+qrk_status qrk_discover_banded(int64_t M, int64_t N, const int64_t* row_ptr, const int32_t* col_idx,
+                               int64_t* row_perm, int32_t* row_start, int32_t* w);
+
+/* ------------------------------------------------------------------------------
  * Self-check entry points (for parity tests of the BF16x3 mode).  They expose, one at a
  * time, the device primitives of the dense-part trailing updates C <- C - V (T^T (V^T C))
  * (Section 2, compact WY) in QRK_BF16X3 mode, where every fp32 operand x is split as

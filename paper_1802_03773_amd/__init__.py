@@ -5,4 +5,5 @@ The hot path lives in libqrkit.so (HIP kernels behind the C ABI of include/qrkit
 """
 from . import qrkit  # noqa: F401
 from .qrkit import (BandedSolver, BlockAngularBatch, BlockAngularNcolSolver, BlockAngularSolver,  # noqa: F401
-                    LMDriver, QRKError, factor_banded, factor_blockangular)
+                    LMDriver, QRKError, discover_banded, discover_blockangular, factor_banded,
+                    factor_blockangular)

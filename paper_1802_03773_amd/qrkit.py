@@ -39,6 +39,9 @@ _SIGS = {
     "qrk_create_blockangular_ncol": (_c_i32, [_c_i32, _c_i32p, _c_i32, _c_i64p, _c_i64, _c_i32, _c_i32,
                                               ctypes.POINTER(_c_vp)]),
     "qrk_factor_blockangular": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_dbl, _c_vp]),
+    "qrk_discover_blockangular": (_c_i32, [_c_i64, _c_i64, _c_i64p, _c_i32p, _c_i32, _c_i32p, _c_i64p, _c_i32p,
+                                           _c_i32p, _c_i64p, _c_i32p]),
+    "qrk_discover_banded": (_c_i32, [_c_i64, _c_i64, _c_i64p, _c_i32p, _c_i64p, _c_i32p, _c_i32p]),
     "qrk_factor_lambda": (_c_i32, [_c_vp, _c_dbl, _c_vp]),
     "qrk_create_blockangular_batched": (_c_i32, [_c_i32, _c_i32, _c_i32p, _c_i32p, _c_i64p, _c_i32, _c_i32,
                                                  ctypes.POINTER(_c_vp)]),
@@ -651,3 +654,44 @@ def tune_choice(solver) -> dict:
     ls, lq, rs = _c_dbl(0.0), _c_i32(0), _c_dbl(0.0)
     _check(lib().qrk_tune_get(solver.handle, ctypes.byref(ls), ctypes.byref(lq), ctypes.byref(rs)), "qrk_tune_get")
     return {"leaf_scale": float(ls.value), "leaf_queue": int(lq.value), "refine_scale": float(rs.value)}
+
+
+def _csr(row_ptr, col_idx):
+    rp = np.ascontiguousarray(np.asarray(row_ptr, dtype=np.int64))
+    ci = np.ascontiguousarray(np.asarray(col_idx, dtype=np.int32))
+    return rp, ci
+
+
+def discover_blockangular(row_ptr, col_idx, N: int, dense_cols) -> dict:
+    """Row and column permutations that bring the sparse pattern (CSR row_ptr, col_idx; N
+    columns) to block-angular form with the given dense columns last (Section 4.3,
+    qrk_discover_blockangular): dict(row_perm, col_perm, ncol, row_off, K), host numpy arrays."""
+    rp, ci = _csr(row_ptr, col_idx)
+    M = int(rp.shape[0] - 1)
+    dc = np.ascontiguousarray(np.asarray(dense_cols, dtype=np.int32))
+    row_perm = np.empty(M, dtype=np.int64)
+    col_perm = np.empty(int(N), dtype=np.int32)
+    ncol = np.empty(int(N), dtype=np.int32)
+    row_off = np.empty(M + 1, dtype=np.int64)
+    K = _c_i32(0)
+    _check(lib().qrk_discover_blockangular(M, int(N), rp.ctypes.data_as(_c_i64p), ci.ctypes.data_as(_c_i32p),
+                                           int(dc.shape[0]), dc.ctypes.data_as(_c_i32p),
+                                           row_perm.ctypes.data_as(_c_i64p), col_perm.ctypes.data_as(_c_i32p),
+                                           ncol.ctypes.data_as(_c_i32p), row_off.ctypes.data_as(_c_i64p),
+                                           ctypes.byref(K)), "qrk_discover_blockangular")
+    k = int(K.value)
+    return dict(row_perm=row_perm, col_perm=col_perm, ncol=ncol[:k].copy(), row_off=row_off[:k + 1].copy(), K=k)
+
+
+def discover_banded(row_ptr, col_idx, N: int) -> dict:
+    """The row order that makes the sparse pattern banded (rows by first column, Section 4.3,
+    qrk_discover_banded): dict(row_perm, row_start, w), host numpy arrays."""
+    rp, ci = _csr(row_ptr, col_idx)
+    M = int(rp.shape[0] - 1)
+    row_perm = np.empty(M, dtype=np.int64)
+    row_start = np.empty(M, dtype=np.int32)
+    w = _c_i32(0)
+    _check(lib().qrk_discover_banded(M, int(N), rp.ctypes.data_as(_c_i64p), ci.ctypes.data_as(_c_i32p),
+                                     row_perm.ctypes.data_as(_c_i64p), row_start.ctypes.data_as(_c_i32p),
+                                     ctypes.byref(w)), "qrk_discover_banded")
+    return dict(row_perm=row_perm, row_start=row_start, w=int(w.value))
