@@ -11,16 +11,22 @@
  *
  *   block-angular  J = [ blkdiag(A_1, ..., A_K) | B ]   (Section 4.2, horizontal
  *                  concatenation of a block-diagonal part, Section 4.1, and a dense
- *                  part B).  The damping rows are permuted next to their blocks as in
- *                  Section 5.2 (Backtrack LM, P_r [J; sqrt(lambda) D] = QR).
+ *                  part B; blocks of one width or of their own widths).  The damping
+ *                  rows are permuted next to their blocks as in Section 5.2 (Backtrack
+ *                  LM, P_r [J; sqrt(lambda) D] = QR).
  *   banded         row i of J holds w values at columns row_start[i] .. row_start[i]+w-1
- *                  (the banded class of Section 4.4), factorised by Givens rotations.
+ *                  (the banded class of Section 4.4), factorised by Givens rotations or
+ *                  by the block-banded compact-WY steps of Section 4.4.
+ * qrk_discover_* find the row and column permutations of Section 4.3 that bring a sparse
+ * J to one of these layouts; qrk_factor_vcat concatenates two factored block-angular
+ * problems vertically (Section 4.5).
  *
  * The paper's interface is compute(A); Q^T b; R.solve(Q^T b) (Section 5.1).  Because
  * the step always knows b, "compute" and "Q^T b" are fused into qrk_factor_*: b rides
- * through the factorisation as one more column and Q is never stored.
- * "R.solve" (plus optional refinement) is qrk_solve; a new right-hand side with the same
- * factor is qrk_solve_rhs (with J and the kept R, since Q is not stored).
+ * through the factorisation as one more column and Q is stored only on request
+ * (qrk_set_keep_q).  "R.solve" (plus optional refinement) is qrk_solve; a new right-hand
+ * side with the same factor is qrk_solve_qt (with the stored Q) or qrk_solve_rhs (with J
+ * and the kept R).
  *
  * Conventions for every function below
  *   - Array arguments are DEVICE pointers unless marked [host].  The caller owns
