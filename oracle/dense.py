@@ -20,6 +20,8 @@ from __future__ import annotations
 
 import numpy as np
 
+from workloads.generators import BlockAngular
+
 
 class SingularError(np.linalg.LinAlgError):
     pass
@@ -162,6 +164,29 @@ def assemble_blockangular_ncol(inst) -> np.ndarray:
         col += ni
     J[:, col:] = inst.B.astype(np.float64)
     return J
+
+
+def camera_columns(inst) -> np.ndarray:
+    """Dense B (M x ncam*cw, float64) of a camera-block instance: row r's cw values go to the
+    columns of its camera cam[r] (cameras in order, cw columns each); a row whose camera is
+    outside [0, ncam) touches no camera (the bundle-adjustment Jacobian of Section 6.2: every
+    observation depends on one point and one camera)."""
+    M, ncam, cw = inst.M, inst.ncam, inst.cw
+    B = np.zeros((M, ncam * cw), dtype=np.float64)
+    Bv = inst.Bv.astype(np.float64)
+    for r in range(M):
+        c = int(inst.cam[r])
+        if 0 <= c < ncam:
+            B[r, c * cw:(c + 1) * cw] = Bv[r]
+    return B
+
+
+def blockangular_from_cam(inst):
+    """The camera-block instance as a block-angular instance with its B stored dense (the
+    values are moved, not rounded, so the stored J is the same)."""
+    B = camera_columns(inst).astype(inst.dtype)
+    return BlockAngular(inst.row_off.copy(), inst.n, inst.A.copy(), B, inst.b.copy(), inst.d.copy(), inst.lam,
+                        inst.dtype)
 
 
 def solve_blockangular_dense(inst):

@@ -229,6 +229,98 @@ def make_blockangular_ncol(seed: int, K: int, m, ncol, nB: int, lam: float,
     return BlockAngularNcol(row_off, n_arr, A, B, b, d, float(lam), dtype)
 
 
+@dataclasses.dataclass
+class BlockAngularCam:
+    """Block-angular instance whose coupled columns are camera blocks (the bundle-adjustment
+    Jacobian of the experiments in Section 6.2, a horizontal concatenation as in Section 4.2:
+    point blocks of n columns, then ncam cameras of cw parameters each).
+
+    Row r of J touches its point block and at most one camera: its coupled entries are
+    Bv[r, :] in the columns cam[r]*cw .. cam[r]*cw + cw - 1 of B and zero elsewhere; a row with
+    cam[r] outside [0, ncam) touches no camera (its Bv row is ignored).  The unknowns are
+    p = [p_1, ..., p_K, p_cam_0, ..., p_cam_{ncam-1}]; N = K*n + ncam*cw.
+    """
+
+    row_off: np.ndarray  # int64 [K+1]
+    n: int               # columns per point block
+    A: np.ndarray        # [M, n]  dtype
+    Bv: np.ndarray       # [M, cw] dtype: each row's values in its camera's columns
+    cam: np.ndarray      # int32 [M]: camera of each row
+    ncam: int
+    b: np.ndarray        # [M] dtype
+    d: np.ndarray        # [N] float64, > 0
+    lam: float
+    dtype: np.dtype
+
+    @property
+    def K(self) -> int:
+        return int(self.row_off.shape[0] - 1)
+
+    @property
+    def M(self) -> int:
+        return int(self.row_off[-1])
+
+    @property
+    def cw(self) -> int:
+        return int(self.Bv.shape[1])
+
+    @property
+    def nB(self) -> int:
+        return self.ncam * self.cw
+
+    @property
+    def N(self) -> int:
+        return self.K * self.n + self.nB
+
+    def with_lambda(self, lam: float) -> "BlockAngularCam":
+        return dataclasses.replace(self, lam=float(lam))
+
+
+def column_norms_cam(row_off, n, A, Bv, cam, ncam) -> np.ndarray:
+    """d_j = ||J e_j||_2 of a camera-block instance in float64; 1 where the column is zero."""
+    K = row_off.shape[0] - 1
+    cw = Bv.shape[1]
+    A64 = A.astype(np.float64)
+    B64 = Bv.astype(np.float64)
+    blk = np.repeat(np.arange(K, dtype=np.int64), np.diff(row_off))
+    dA = np.zeros((K, n), dtype=np.float64)
+    np.add.at(dA, blk, A64 * A64)
+    dC = np.zeros((ncam, cw), dtype=np.float64)
+    seen = (cam >= 0) & (cam < ncam)
+    np.add.at(dC, cam[seen].astype(np.int64), B64[seen] * B64[seen])
+    d = np.sqrt(np.concatenate([dA.reshape(-1), dC.reshape(-1)]))
+    d[d == 0.0] = 1.0
+    return d
+
+
+def make_blockangular_cam(seed: int, K: int, obs, ncam: int, cw: int = 9, n: int = 3, lam: float = 1e-2,
+                          prior_rows: int = 0, dtype=np.float64) -> BlockAngularCam:
+    """Gaussian camera-block instance shaped like bundle adjustment: point i is seen by obs_i
+    distinct cameras (obs: an int or an int array of length K, each <= ncam), drawn uniformly;
+    each observation gives two rows (its x and y residuals) on that camera; prior_rows extra
+    rows per point touch no camera (cam = -1, their Bv rows random and ignored).
+    Draw order: observations' cameras, A, Bv, b."""
+    rng = _rng(seed)
+    o_arr = np.full(K, int(obs), dtype=np.int64) if np.isscalar(obs) else np.asarray(obs, np.int64)
+    assert o_arr.shape == (K,) and int(o_arr.max(initial=0)) <= ncam
+    m_arr = 2 * o_arr + int(prior_rows)
+    row_off = np.zeros(K + 1, dtype=np.int64)
+    np.cumsum(m_arr, out=row_off[1:])
+    M = int(row_off[-1])
+    cam = np.empty(M, dtype=np.int32)
+    for i in range(K):
+        cams = rng.choice(ncam, size=int(o_arr[i]), replace=False)
+        r0 = int(row_off[i])
+        cam[r0:r0 + 2 * o_arr[i]] = np.repeat(cams, 2)
+        cam[r0 + 2 * o_arr[i]:int(row_off[i + 1])] = -1
+    dtype = np.dtype(dtype)
+    A = rng.standard_normal((M, n)).astype(dtype)
+    Bv = rng.standard_normal((M, cw)).astype(dtype)
+    b = rng.standard_normal(M).astype(dtype)
+    d = column_norms_cam(row_off, n, A, Bv, cam, ncam)
+    return BlockAngularCam(row_off, n, A, Bv, cam, int(ncam), b, d, float(lam), dtype)
+
+
 # ---------------------------------------------------------------------------
 # Named workloads (shapes of the measured configurations)
 # ---------------------------------------------------------------------------
