@@ -140,6 +140,33 @@ qrk_status qrk_factor_blockangular(qrk_handle h, const void* A, const void* B, c
                                    const double* d, double lambda, void* stream);
 
 /* ------------------------------------------------------------------------------
+ * qrk_create_blockangular_cam, qrk_factor_blockangular_cam
+ *   Block-angular J whose coupled columns are cameras: the bundle-adjustment Jacobian of the
+ *   experiments of Section 6.2, solved as the horizontal concatenation of Section 4.2, where
+ *   every row depends on one point block (n columns) and at most one camera.  The dense part
+ *   has nB = ncam * cw columns, camera c owning columns c*cw .. c*cw + cw - 1, and is passed
+ *   compressed: Bv [device, M x cw] T holds row r's cw values and cam [device, int32, M] its
+ *   camera, so that B[r, cam[r]*cw + k] = Bv[r*cw + k] and B is zero elsewhere in row r.
+ *   A camera index outside [0, ncam) means the row touches no camera (its Bv row is not
+ *   used).  The per-block QR and the refinement read the compressed rows directly.
+ *   create: ncam >= 1, cw >= 1, ncam * cw <= QRK_MAX_DENSE_COLS; the other arguments as for
+ *   qrk_create_blockangular (QRK_EINVAL otherwise).
+ *   factor: A, b, d, lambda as for qrk_factor_blockangular; Bv and cam are borrowed like A
+ *   (the refinement of qrk_solve, qrk_solve_tol, qrk_solve_rhs and qrk_solve_qt reads them,
+ *   so they must stay valid and unchanged until the next factor).  QRK_EINVAL on null
+ *   pointers, bad lambda or a handle not made by qrk_create_blockangular_cam.
+ *   On such a handle qrk_factor_blockangular, the batched and concatenation calls,
+ *   qrk_solve_adjoint, qrk_colnorms_blockangular and the LM calls return QRK_EINVAL; the
+ *   solve, two-stage, new-right-hand-side, stored-Q, autotuner and factor-readback calls work
+ *   as on a dense-B handle.
+ * ------------------------------------------------------------------------------ */
+qrk_status qrk_create_blockangular_cam(int32_t K, int32_t n, int32_t ncam, int32_t cw,
+                                       const int64_t* row_off_host, qrk_dtype dtype, qrk_mode mode,
+                                       qrk_handle* out);
+qrk_status qrk_factor_blockangular_cam(qrk_handle h, const void* A, const void* Bv, const int32_t* cam,
+                                       const void* b, const double* d, double lambda, void* stream);
+
+/* ------------------------------------------------------------------------------
  * qrk_factor_lambda  (single-problem block-angular handles)
  *   Moré's two-stage damping (Section 5.2, Eq. LMTwoStep): with J = Q R factored once by
  *   qrk_factor_blockangular(h, ..., lambda = 0, ...), each call factors [R; sqrt(lambda) D]
@@ -357,6 +384,14 @@ qrk_status qrk_solve_adjoint(qrk_handle h, const double* p, const double* g, voi
  * ------------------------------------------------------------------------------ */
 qrk_status qrk_colnorms_blockangular(qrk_handle h, const void* A, const void* B, double* d,
                                      void* stream);
+
+/* ------------------------------------------------------------------------------
+ * qrk_colnorms_blockangular_cam
+ *   The same column norms for a handle made by qrk_create_blockangular_cam: A, Bv, cam as for
+ *   qrk_factor_blockangular_cam; d [N].  A camera column no row touches gets d_j = 1.
+ * ------------------------------------------------------------------------------ */
+qrk_status qrk_colnorms_blockangular_cam(qrk_handle h, const void* A, const void* Bv, const int32_t* cam,
+                                         double* d, void* stream);
 
 /* ------------------------------------------------------------------------------
  * qrk_get_factor (inspection; synchronises the stream)

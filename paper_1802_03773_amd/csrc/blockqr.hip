@@ -25,8 +25,9 @@ __global__ void __launch_bounds__(256)
 k_blockqr(const int32_t* __restrict__ blk_list, int64_t begin, int64_t count, int n,
           const ProbDesc* __restrict__ probs, const int32_t* __restrict__ blk_prob,
           const int64_t* __restrict__ row_off, const T* __restrict__ A, const T* __restrict__ B,
-          const T* __restrict__ bvec, const double* __restrict__ d, const double* __restrict__ lam,
-          T* __restrict__ Rblk, T* __restrict__ Sc, T* __restrict__ Red, BqrPrologue pro) {
+          const int32_t* __restrict__ cam, const T* __restrict__ bvec, const double* __restrict__ d,
+          const double* __restrict__ lam, T* __restrict__ Rblk, T* __restrict__ Sc, T* __restrict__ Red,
+          BqrPrologue pro) {
   bqr_prologue<256>(pro);
   __shared__ T vbuf[4][ROWS];
   __shared__ T tbuf[4];
@@ -46,14 +47,14 @@ k_blockqr(const int32_t* __restrict__ blk_list, int64_t begin, int64_t count, in
     block_qr_wave<T, ROWS, SLOTS>(n, P.nB, m, A + r0 * n, B + P.boff + rl * P.ldb, P.ldb, bvec + r0,
                                   d + P.noff + lb * n, sqrt(pro.lam_out ? pro.lam_val : lam[pi]), Rblk + blk * n * n,
                                   Sc + P.soff + lb * n * P.L, vbuf[wv], &tbuf[wv], lane,
-                                  [&](int r, int col, T val) { red[r * ldr + col] = val; });
+                                  [&](int r, int col, T val) { red[r * ldr + col] = val; }, cam ? cam + r0 : nullptr);
   }
 }
 
 template <typename T>
 hipError_t launch_blockqr(const int32_t* blk_list, int64_t begin, int64_t count, int cls, int n, int probs_count,
                           const ProbDesc* probs, const int32_t* blk_prob, const int64_t* row_off, const T* A,
-                          const T* B, const T* b, const double* d, const double* lam, T* Rblk, T* Sc, T* Red,
+                          const T* B, const int32_t* cam, const T* b, const double* d, const double* lam, T* Rblk, T* Sc, T* Red,
                           const BqrPrologue& pro, const QKeep& qk, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   const int32_t* bp = probs_count == 1 ? nullptr : blk_prob;
@@ -62,7 +63,7 @@ hipError_t launch_blockqr(const int32_t* blk_list, int64_t begin, int64_t count,
     switch (n) {
 #define QRK_N(NN) \
   case NN:        \
-    return launch_blockqr_n<T, NN>(blk_list, begin, count, rows, slots, probs, bp, row_off, A, B, b, d, lam, Rblk, Sc, Red, pro, qk, st);
+    return launch_blockqr_n<T, NN>(blk_list, begin, count, rows, slots, probs, bp, row_off, A, B, cam, b, d, lam, Rblk, Sc, Red, pro, qk, st);
       QRK_N(1) QRK_N(2) QRK_N(3) QRK_N(4) QRK_N(5) QRK_N(6) QRK_N(7) QRK_N(8)
 #undef QRK_N
       default:
@@ -75,16 +76,17 @@ hipError_t launch_blockqr(const int32_t* blk_list, int64_t begin, int64_t count,
   const int grid = (int)((count + 3) / 4 < 2048 ? (count + 3) / 4 : 2048);
   if (slots == 1)
     hipLaunchKernelGGL((k_blockqr<T, 16, 1>), dim3(grid), dim3(256), 0, st, blk_list, begin, count, n, probs, bp,
-                       row_off, A, B, b, d, lam, Rblk, Sc, Red, pro);
+                       row_off, A, B, cam, b, d, lam, Rblk, Sc, Red, pro);
   else
     hipLaunchKernelGGL((k_blockqr<T, 16, 2>), dim3(grid), dim3(256), 0, st, blk_list, begin, count, n, probs, bp,
-                       row_off, A, B, b, d, lam, Rblk, Sc, Red, pro);
+                       row_off, A, B, cam, b, d, lam, Rblk, Sc, Red, pro);
   return hipGetLastError();
 }
 
 #define QRK_INST(T)                                                                                   \
   template hipError_t launch_blockqr<T>(const int32_t*, int64_t, int64_t, int, int, int, const ProbDesc*, \
-                                        const int32_t*, const int64_t*, const T*, const T*, const T*,       \
+                                        const int32_t*, const int64_t*, const T*, const T*, const int32_t*, \
+                                        const T*,                                                           \
                                         const double*, const double*, T*, T*, T*, const BqrPrologue&,       \
                                         const QKeep&, hipStream_t);
 QRK_INST(float)

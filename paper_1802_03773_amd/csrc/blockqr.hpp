@@ -17,12 +17,15 @@ namespace qrk {
 
 // A, B, bvec point at the block's first row (of A, of B_p with row stride ldb, of b), d at
 // its first damping entry, Rb and Scb at its R_i (n x n) and S_i | c_i (n x (nB+1)).
+// cam (non-null: camera columns, at the block's first row): B holds each row's ldb values, in
+// the columns of camera cam[r] (cameras of ldb columns, nB = ncam * ldb; a camera outside
+// [0, ncam) is none).
 template <typename T, int ROWS, int SLOTS, typename Emit>
 __device__ __forceinline__ void block_qr_wave(int n, int nB, int m, const T* __restrict__ A,
                                               const T* __restrict__ B, int64_t ldb, const T* __restrict__ bvec,
                                               const double* __restrict__ d, double sqrt_lam, T* __restrict__ Rb,
                                               T* __restrict__ Scb, T* __restrict__ v, T* __restrict__ tb,
-                                              int lane, Emit&& emit) {
+                                              int lane, Emit&& emit, const int32_t* __restrict__ cam = nullptr) {
   const int L = nB + 1;
   const int rows = m + n;
 
@@ -47,10 +50,19 @@ __device__ __forceinline__ void block_qr_wave(int n, int nB, int m, const T* __r
     for (int r = 0; r < ROWS; ++r) {
       T x = T(0);
       if (r < m) {
-        if (col < nB)
-          x = B[r * ldb + col];
-        else if (col == nB)
+        if (col < nB) {
+          if (cam) {
+            const int cr = cam[r];
+            if ((uint32_t)cr < (uint32_t)(nB / ldb)) {
+              const uint32_t k = (uint32_t)(col - cr * (int)ldb);
+              if (k < (uint32_t)ldb) x = B[r * ldb + k];
+            }
+          } else {
+            x = B[r * ldb + col];
+          }
+        } else if (col == nB) {
           x = bvec[r];
+        }
       }
       c[s][r] = x;
     }

@@ -91,13 +91,18 @@ __device__ __forceinline__ T buf_ld(__amdgpu_buffer_rsrc_t rs, uint32_t voff, ui
 // wave-uniform.
 // qv: when non-null, the block's reflectors are stored (QKeep layout): qvd at the block's first
 // data row (row stride N), qvp at its damping rows (N x N), qg its g_j (N).
-template <typename T, int N, int ROWS, int SLOTS>
+// CAM: the coupled columns are cameras of ldb columns each (nB = ncam * ldb, nB > 0): B holds
+// every row's ldb values, cam (at the block's first row) the camera of every row, and row r's
+// values lie in columns cam[r] * ldb .. cam[r] * ldb + ldb - 1; a camera outside [0, ncam) is
+// none (the row's coupled entries are zero).
+template <typename T, int N, int ROWS, int SLOTS, bool CAM = false>
 __device__ __forceinline__ void block_qr_wave_n(int nB, int m, int ldb, int ldr, const T* __restrict__ A,
                                                 const T* __restrict__ B, const T* __restrict__ bvec,
                                                 const double* __restrict__ d, double sqrt_lam, T* __restrict__ Rb,
                                                 T* __restrict__ Scb, T* __restrict__ red, int lane,
                                                 T* __restrict__ qvd = nullptr, T* __restrict__ qvp = nullptr,
-                                                T* __restrict__ qg = nullptr) {
+                                                T* __restrict__ qg = nullptr,
+                                                const int32_t* __restrict__ cam = nullptr) {
   static_assert(N >= 1 && N <= 8 && ROWS >= 2 * N, "block shape");
   constexpr int RD = ROWS - N;  // first damping row
   __builtin_assume(m >= N && m <= RD);
@@ -124,6 +129,7 @@ __device__ __forceinline__ void block_qr_wave_n(int nB, int m, int ldb, int ldr,
     const T* Bb = nB > 0 ? B : bvec;
     const int ldbe = nB > 0 ? ldb : 1;
     const __amdgpu_buffer_rsrc_t rsB = raw_rsrc(Bb);
+    const uint32_t ncam = CAM ? (uint32_t)(nB / ldbe) : 0u;
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
       const int col = s * 64 + lane;
@@ -132,7 +138,17 @@ __device__ __forceinline__ void block_qr_wave_n(int nB, int m, int ldb, int ldr,
 #pragma unroll
       for (int r = 0; r < RD; ++r) {
         const int rr = r < mc ? r : mc;
-        c[s][r] = buf_ld<T>(rsB, co, (uint32_t)(rr * ldbe) * (uint32_t)sizeof(T));
+        if constexpr (CAM) {
+          // the row's camera (wave-uniform): this lane's column within it, if any
+          const int cr = cam[rr];
+          const bool seen = (uint32_t)cr < ncam;
+          const uint32_t k = (uint32_t)(cc - (seen ? cr : 0) * ldbe);
+          const bool on = seen && col < nB && k < (uint32_t)ldbe;
+          const T x = buf_ld<T>(rsB, (on ? k : 0u) * (uint32_t)sizeof(T), (uint32_t)(rr * ldbe) * (uint32_t)sizeof(T));
+          c[s][r] = on ? x : T(0);
+        } else {
+          c[s][r] = buf_ld<T>(rsB, co, (uint32_t)(rr * ldbe) * (uint32_t)sizeof(T));
+        }
       }
 #pragma unroll
       for (int j = 0; j < N; ++j) c[s][RD + j] = T(0);

@@ -183,7 +183,8 @@ qrk_status qrk_lm_create_blockangular(qrk_handle h, const void* A0, const void* 
                                       int32_t sweeps, int32_t max_log, qrk_lm* out) {
   if (!out) return QRK_EINVAL;
   *out = nullptr;
-  if (!h || h->kind != KIND_BLOCKANGULAR || h->ragged || !A0 || !y || (h->max_L > 1 && !B0)) return QRK_EINVAL;
+  if (!h || h->kind != KIND_BLOCKANGULAR || h->ragged || h->camb || !A0 || !y || (h->max_L > 1 && !B0))
+    return QRK_EINVAL;
   if (!std::isfinite(c) || sweeps < 0 || sweeps > 8 || max_log < 0) return QRK_EINVAL;
   qrk_lm lm = new (std::nothrow) qrk_lm_s();
   if (!lm) return QRK_ENOMEM;

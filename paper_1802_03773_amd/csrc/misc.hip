@@ -65,16 +65,30 @@ __global__ void k_colnorms_blocks(int64_t K, int n, const int64_t* __restrict__ 
 
 template <typename T>
 __global__ void __launch_bounds__(128)
-k_colnorms_dense(int64_t M, int nB, const T* __restrict__ B, int64_t ldb, int64_t rows_per,
-                 double* __restrict__ part) {
+k_colnorms_dense(int64_t M, int nB, const T* __restrict__ B, int64_t ldb, const int32_t* __restrict__ cam,
+                 int64_t rows_per, double* __restrict__ part) {
   const int j = threadIdx.x;
   if (j >= nB) return;
   const int64_t r0 = (int64_t)blockIdx.x * rows_per;
   const int64_t r1 = r0 + rows_per < M ? r0 + rows_per : M;
   double s = 0.0;
-  for (int64_t r = r0; r < r1; ++r) {
-    const double b = (double)B[r * ldb + j];
-    s += b * b;
+  if (cam) {
+    // camera columns: row r holds ldb values of camera cam[r] (none outside [0, nB / ldb))
+    const uint32_t ncam = (uint32_t)(nB / ldb);
+    for (int64_t r = r0; r < r1; ++r) {
+      const int cr = cam[r];
+      if ((uint32_t)cr >= ncam) continue;
+      const uint32_t k = (uint32_t)(j - cr * (int)ldb);
+      if (k < (uint32_t)ldb) {
+        const double b = (double)B[r * ldb + k];
+        s += b * b;
+      }
+    }
+  } else {
+    for (int64_t r = r0; r < r1; ++r) {
+      const double b = (double)B[r * ldb + j];
+      s += b * b;
+    }
   }
   part[(int64_t)blockIdx.x * nB + j] = s;
 }
@@ -90,22 +104,26 @@ __global__ void k_colnorms_final(int nparts, int nB, const double* __restrict__ 
 
 template <typename T>
 hipError_t launch_colnorms(int64_t K, int n, int nB, int64_t M, const int64_t* row_off, const T* A,
-                           const T* B, int64_t ldb, double* d, double* part, int nparts, hipStream_t st) {
+                           const T* B, int64_t ldb, const int32_t* cam, double* d, double* part, int nparts,
+                           hipStream_t st) {
   const int64_t kn = K * n;
   if (kn > 0)
     hipLaunchKernelGGL((k_colnorms_blocks<T>), dim3((unsigned)((kn + 255) / 256)), dim3(256), 0, st, K, n,
                        row_off, A, d);
   if (nB > 0) {
     const int64_t rows_per = (M + nparts - 1) / nparts > 0 ? (M + nparts - 1) / nparts : 1;
-    hipLaunchKernelGGL((k_colnorms_dense<T>), dim3(nparts), dim3(128), 0, st, M, nB, B, ldb, rows_per, part);
+    hipLaunchKernelGGL((k_colnorms_dense<T>), dim3(nparts), dim3(128), 0, st, M, nB, B, ldb, cam, rows_per,
+                       part);
     hipLaunchKernelGGL(k_colnorms_final, dim3(1), dim3(128), 0, st, nparts, nB, part, d + kn);
   }
   return hipGetLastError();
 }
 template hipError_t launch_colnorms<float>(int64_t, int, int, int64_t, const int64_t*, const float*,
-                                           const float*, int64_t, double*, double*, int, hipStream_t);
+                                           const float*, int64_t, const int32_t*, double*, double*, int,
+                                           hipStream_t);
 template hipError_t launch_colnorms<double>(int64_t, int, int, int64_t, const int64_t*, const double*,
-                                            const double*, int64_t, double*, double*, int, hipStream_t);
+                                            const double*, int64_t, const int32_t*, double*, double*, int,
+                                            hipStream_t);
 
 }  // namespace qrk
 

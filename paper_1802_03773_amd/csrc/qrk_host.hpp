@@ -30,7 +30,8 @@ hipError_t launch_ragged_out(int64_t K, int n, int nB, const int32_t* ncol, cons
                              double* pu, hipStream_t st);
 template <typename T>
 hipError_t launch_colnorms(int64_t K, int n, int nB, int64_t M, const int64_t* row_off, const T* A,
-                           const T* B, int64_t ldb, double* d, double* part, int nparts, hipStream_t st);
+                           const T* B, int64_t ldb, const int32_t* cam, double* d, double* part, int nparts,
+                           hipStream_t st);
 
 }  // namespace qrk
 
@@ -170,6 +171,11 @@ struct qrk_handle_s {
   void* rg_A = nullptr;        // [M x n]
   double* rg_d = nullptr;      // [N]
   double* rg_p = nullptr;      // [N]
+  // camera columns (qrk_create_blockangular_cam): nB = ncam * cw, B holds cw values per row
+  // (row stride ldb = cw) and cam the camera of every row (the caller's device array)
+  bool camb = false;
+  int32_t ncam = 0, cw = 0;
+  const int32_t* cam = nullptr;
   std::vector<qrk_handle_s*> vparts;
   qrk_handle_s* vcat_stage = nullptr;
   void* vA = nullptr;

@@ -14,20 +14,21 @@ namespace qrk {
 // block order), the coupling rows S_i | c_i (Sc, the problem's slice, row stride L_p) and the
 // m_i reduced rows of every block into the problem's slice of Red (row stride ldr_p).
 // pro: the clearing and lambda store of the factor call's first launch (an empty prologue for
-// the others).
+// the others).  cam non-null: the coupled columns are cameras of ldb columns (nB = ncam *
+// ldb), B holds each row's ldb values and cam[row] (indexed like the rows of A) its camera.
 template <typename T>
 hipError_t launch_blockqr(const int32_t* blk_list, int64_t begin, int64_t count, int cls, int n, int probs_count,
                           const ProbDesc* probs, const int32_t* blk_prob, const int64_t* row_off, const T* A,
-                          const T* B, const T* b, const double* d, const double* lam, T* Rblk, T* Sc, T* Red,
-                          const BqrPrologue& pro, const QKeep& qk, hipStream_t st);
+                          const T* B, const int32_t* cam, const T* b, const double* d, const double* lam, T* Rblk,
+                          T* Sc, T* Red, const BqrPrologue& pro, const QKeep& qk, hipStream_t st);
 
 // Per-block QR with compile-time block width N, for blocks with m_i >= N (rows: 16, 32 or
 // 64 register rows, m_i + N <= rows; slots: 1 or 2, nB + 1 <= 64 slots).
 template <typename T, int N>
 hipError_t launch_blockqr_n(const int32_t* blk_list, int64_t begin, int64_t count, int rows, int slots,
                             const ProbDesc* probs, const int32_t* blk_prob, const int64_t* row_off, const T* A,
-                            const T* B, const T* b, const double* d, const double* lam, T* Rblk, T* Sc, T* Red,
-                            const BqrPrologue& pro, const QKeep& qk, hipStream_t st);
+                            const T* B, const int32_t* cam, const T* b, const double* d, const double* lam, T* Rblk,
+                            T* Sc, T* Red, const BqrPrologue& pro, const QKeep& qk, hipStream_t st);
 
 // One workgroup of the float64 tall-skinny QR: stream rows [r0, r1) of its input (row
 // stride ldx, L columns) into an L x L upper-triangular R (Householder merges) written
@@ -105,11 +106,12 @@ hipError_t launch_apply_qt(const BatchView& bv, const int* cls_begin, const int*
 
 // Refinement, pass 1: per pack of whole blocks (at most 64 rows): r = b - J p,
 // g_i = A_i^T r - lam d_i^2 p_i, y_i = R_i^{-T} g_i, and per-workgroup partial sums of
-// B^T r - S_i^T y_i (part[wg][kMaxDense]).
+// B^T r - S_i^T y_i (part[wg][kMaxDense]).  cam non-null: camera columns, as for
+// launch_blockqr.
 template <typename T>
-hipError_t launch_refine_residual(const BatchView& bv, const T* A, const T* B, const T* b, const double* d,
-                                  const T* Rblk, const T* Sc, const double* p, double* y, double* part,
-                                  hipStream_t st);
+hipError_t launch_refine_residual(const BatchView& bv, const T* A, const T* B, const int32_t* cam, const T* b,
+                                  const double* d, const T* Rblk, const T* Sc, const double* p, double* y,
+                                  double* part, hipStream_t st);
 
 // Refinement, pass 2: g_B = sum(part) - lam d_B^2 p_B; y_B = R_B^{-T} g_B; dB = R_B^{-1} y_B;
 // p_B += dB; dB stored to delta_B[p * kMaxDense ..].

@@ -108,8 +108,8 @@ qrk_status factor_ba(qrk_handle h, hipStream_t st, const double* lam_host = null
     if (h->bq_count[c] == 0) continue;
     if (h->bq_begin[c] < 0 || h->bq_begin[c] + h->bq_count[c] > extent) return QRK_EINVAL;
     if (launch_blockqr<T>(list, h->bq_begin[c], h->bq_count[c], c, h->n, h->P, h->probs_d, h->blk_prob,
-                          h->row_off_d, A, B, b, h->d, h->lam_ptr, Rblk, Sc, Red, pro, keep ? h->qk : QKeep(),
-                          st) != hipSuccess)
+                          h->row_off_d, A, B, h->camb ? h->cam : nullptr, b, h->d, h->lam_ptr, Rblk, Sc, Red, pro,
+                          keep ? h->qk : QKeep(), st) != hipSuccess)
       return QRK_EHIP;
     pro = BqrPrologue();  // later launches: nothing to clear, lambda on the device
   }
@@ -154,12 +154,13 @@ qrk_status refine_ba(qrk_handle h, double* p, int sweeps, const T* b, hipStream_
   int pr = sweeps > 0 ? prof_begin(h, 4, st) : -1;
   const int64_t Kn = h->K * h->n;
   for (int s = 0; s < sweeps; ++s) {
-    if (launch_refine_residual<T>(bv, static_cast<const T*>(h->A), static_cast<const T*>(h->B), b, h->d, Rblk,
-                                  Sc, p, h->ybuf, h->refpart, st) != hipSuccess)
+    if (launch_refine_residual<T>(bv, static_cast<const T*>(h->A), static_cast<const T*>(h->B),
+                                  h->camb ? h->cam : nullptr, b, h->d, Rblk, Sc, p, h->ybuf, h->refpart,
+                                  st) != hipSuccess)
       return QRK_EHIP;
     // rows added by vertical concatenation: each part's residual terms with the stacked factor
     for (qrk_handle q : h->vparts)
-      if (launch_refine_residual<T>(view(q), static_cast<const T*>(q->A), static_cast<const T*>(q->B),
+      if (launch_refine_residual<T>(view(q), static_cast<const T*>(q->A), static_cast<const T*>(q->B), nullptr,
                                     static_cast<const T*>(q->b), q->d, Rblk, Sc, p, q->ybuf, q->refpart,
                                     st) != hipSuccess ||
           launch_vcat_merge(Kn, h->ybuf, q->ybuf, h->refpart, q->refpart, q->nwg, h->nB, q->lam_ptr, q->d + Kn,
@@ -888,7 +889,7 @@ qrk_status qrk_create_blockangular_batched(int32_t P, int32_t n, const int32_t* 
 
 qrk_status qrk_factor_blockangular(qrk_handle h, const void* A, const void* B, const void* b,
                                    const double* d, double lambda, void* stream) {
-  if (!h || h->kind != KIND_BLOCKANGULAR || h->P != 1) return QRK_EINVAL;
+  if (!h || h->kind != KIND_BLOCKANGULAR || h->P != 1 || h->camb) return QRK_EINVAL;
   if (!A || !b || !d || (h->nB > 0 && !B)) return QRK_EINVAL;
   if (!(lambda >= 0.0) || !std::isfinite(lambda)) return QRK_EINVAL;
   if (h->ragged) {  // the blocks at n columns: zero columns past n_i with unit damping
@@ -907,6 +908,39 @@ qrk_status qrk_factor_blockangular(qrk_handle h, const void* A, const void* B, c
   }
   h->A = A;
   h->B = B;
+  h->b = b;
+  h->d = d;
+  h->lam = lambda;
+  h->lam_ptr = h->lam_d;
+  h->factored = true;
+  h->lam_base_saved = false;
+  return h->dtype == QRK_F32 ? factor_ba<float>(h, S(stream), &lambda) : factor_ba<double>(h, S(stream), &lambda);
+}
+
+// Camera columns: B's rows in the compressed form (cw values and a camera index per row); the
+// per-block QR and the refinement read them in place.
+qrk_status qrk_create_blockangular_cam(int32_t K, int32_t n, int32_t ncam, int32_t cw, const int64_t* row_off_host,
+                                       qrk_dtype dtype, qrk_mode mode, qrk_handle* out) {
+  if (!out) return QRK_EINVAL;
+  *out = nullptr;
+  if (ncam < 1 || cw < 1 || (int64_t)ncam * cw > QRK_MAX_DENSE_COLS) return QRK_EINVAL;
+  const int32_t nB = ncam * cw;
+  const qrk_status s = create_ba(1, n, &K, &nB, row_off_host, cw, dtype, mode, out);
+  if (s != QRK_OK) return s;
+  (*out)->camb = true;
+  (*out)->ncam = ncam;
+  (*out)->cw = cw;
+  return QRK_OK;
+}
+
+qrk_status qrk_factor_blockangular_cam(qrk_handle h, const void* A, const void* Bv, const int32_t* cam,
+                                       const void* b, const double* d, double lambda, void* stream) {
+  if (!h || h->kind != KIND_BLOCKANGULAR || h->P != 1 || !h->camb) return QRK_EINVAL;
+  if (!A || !Bv || !cam || !b || !d) return QRK_EINVAL;
+  if (!(lambda >= 0.0) || !std::isfinite(lambda)) return QRK_EINVAL;
+  h->A = A;
+  h->B = Bv;
+  h->cam = cam;
   h->b = b;
   h->d = d;
   h->lam = lambda;
@@ -1062,7 +1096,8 @@ extern "C" {
 qrk_status qrk_factor_vcat(qrk_handle h, qrk_handle h2, void* stream) {
   if (!h || !h2 || h == h2 || h->kind != KIND_BLOCKANGULAR || h2->kind != KIND_BLOCKANGULAR || h->P != 1 ||
       h2->P != 1 || !h->factored || !h2->factored || h->K != h2->K || h->n != h2->n || h->nB != h2->nB ||
-      h->dtype != h2->dtype || !h2->vparts.empty() || h->vparts.size() >= 64 || h->ragged || h2->ragged)
+      h->dtype != h2->dtype || !h2->vparts.empty() || h->vparts.size() >= 64 || h->ragged || h2->ragged ||
+      h->camb || h2->camb)
     return QRK_EINVAL;
   for (qrk_handle q : h->vparts)
     if (q == h2) return QRK_EINVAL;
@@ -1076,7 +1111,8 @@ qrk_status qrk_factor_vcat(qrk_handle h, qrk_handle h2, void* stream) {
 
 qrk_status qrk_factor_blockangular_batched(qrk_handle h, const void* A, const void* B, const void* b,
                                            const double* d, const double* lambda_dev, void* stream) {
-  if (!h || h->kind != KIND_BLOCKANGULAR || h->ragged || !A || !b || !d || !lambda_dev) return QRK_EINVAL;
+  if (!h || h->kind != KIND_BLOCKANGULAR || h->ragged || h->camb || !A || !b || !d || !lambda_dev)
+    return QRK_EINVAL;
   if (h->max_L > 1 && !B) return QRK_EINVAL;
   h->A = A;
   h->B = B;
@@ -1117,7 +1153,7 @@ qrk_status qrk_solve_rhs(qrk_handle h, const void* b, double* p, int32_t sweeps,
 
 qrk_status qrk_solve_adjoint(qrk_handle h, const double* p, const double* g, void* dA, void* dB,
                              void* db, double* dlambda, double* dd, void* stream) {
-  if (!h || !h->factored || !p || !g || !h->vparts.empty() || h->ragged) return QRK_EINVAL;
+  if (!h || !h->factored || !p || !g || !h->vparts.empty() || h->ragged || h->camb) return QRK_EINVAL;
   if (h->kind == KIND_BLOCKANGULAR) {
     if (h->P != 1 || (dB && h->nB == 0)) return QRK_EINVAL;
     return blockangular_adjoint(h, p, g, dA, dB, db, dlambda, dd, S(stream));
@@ -1126,19 +1162,30 @@ qrk_status qrk_solve_adjoint(qrk_handle h, const double* p, const double* g, voi
   return banded_adjoint(h, p, g, dA, db, dlambda, dd, S(stream));
 }
 
-qrk_status qrk_colnorms_blockangular(qrk_handle h, const void* A, const void* B, double* d, void* stream) {
-  if (!h || h->kind != KIND_BLOCKANGULAR || h->P != 1 || h->ragged || !A || !d || (h->nB > 0 && !B))
-    return QRK_EINVAL;
+static qrk_status colnorms_ba(qrk_handle h, const void* A, const void* B, const int32_t* cam, double* d,
+                              void* stream) {
   const int nparts = (int)std::min<int64_t>(std::max<int64_t>(1, ceil_div(h->M, 512)), 1024);
   hipError_t e = h->dtype == QRK_F32
                      ? launch_colnorms<float>(h->K, h->n, h->nB, h->M, h->row_off_d,
                                               static_cast<const float*>(A), static_cast<const float*>(B),
-                                              h->ldb, d, h->vecpart, nparts, S(stream))
+                                              h->ldb, cam, d, h->vecpart, nparts, S(stream))
                      : launch_colnorms<double>(h->K, h->n, h->nB, h->M, h->row_off_d,
                                                static_cast<const double*>(A),
-                                               static_cast<const double*>(B), h->ldb, d, h->vecpart,
+                                               static_cast<const double*>(B), h->ldb, cam, d, h->vecpart,
                                                nparts, S(stream));
   return e == hipSuccess ? QRK_OK : QRK_EHIP;
+}
+
+qrk_status qrk_colnorms_blockangular(qrk_handle h, const void* A, const void* B, double* d, void* stream) {
+  if (!h || h->kind != KIND_BLOCKANGULAR || h->P != 1 || h->ragged || h->camb || !A || !d || (h->nB > 0 && !B))
+    return QRK_EINVAL;
+  return colnorms_ba(h, A, B, nullptr, d, stream);
+}
+
+qrk_status qrk_colnorms_blockangular_cam(qrk_handle h, const void* A, const void* Bv, const int32_t* cam, double* d,
+                                         void* stream) {
+  if (!h || h->kind != KIND_BLOCKANGULAR || h->P != 1 || !h->camb || !A || !Bv || !cam || !d) return QRK_EINVAL;
+  return colnorms_ba(h, A, Bv, cam, d, stream);
 }
 
 qrk_status qrk_get_factor(qrk_handle h, void* Rblk, void* Sc, void* RB, void* stream) {

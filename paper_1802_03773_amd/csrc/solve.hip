@@ -377,13 +377,17 @@ hipError_t launch_adjoint_blocks(const BatchView& bv, const T* Rblk, const T* Sc
 // loaded into.  Every sum runs in a fixed order, so the partials are deterministic.
 // Workgroup w serves problem wg_prob[w] only; its packs are that problem's packs
 // lw*4 + wave, lw*4 + wave + 4*nwg, ... (lw = w - wg0), its partial goes to part[w].
+// CAM: the coupled columns are cameras of ldb columns (nB = ncam * ldb); B holds each row's ldb
+// values and cam[row] its camera (outside [0, ncam): none), so a staged row is zero outside its
+// camera's columns.
 // ---------------------------------------------------------------------------------
 
-template <typename T, int N>
+template <typename T, int N, bool CAM>
 __global__ void __launch_bounds__(256)
 k_refine_pass1(const ProbDesc* __restrict__ probs, const int32_t* __restrict__ wg_prob,
                const int64_t* __restrict__ pack_blk, const int64_t* __restrict__ row_off,
-               const T* __restrict__ A, const T* __restrict__ B, const T* __restrict__ bvec,
+               const T* __restrict__ A, const T* __restrict__ B, const int32_t* __restrict__ cam,
+               const T* __restrict__ bvec,
                const double* __restrict__ d, const double* __restrict__ lamv, const T* __restrict__ Rblk,
                const T* __restrict__ Sc, const double* __restrict__ p, double* __restrict__ y,
                double* __restrict__ part) {
@@ -407,6 +411,7 @@ k_refine_pass1(const ProbDesc* __restrict__ probs, const int32_t* __restrict__ w
   const int nB = P.nB, L = P.L;
   const int64_t koff = P.koff, noff = P.noff, moff = P.moff, soff = P.soff;
   const int ldb = nB > 0 ? (int)P.ldb : 0;
+  const uint32_t ncam = CAM ? (uint32_t)(nB / ldb) : 0u;
   const double lam = lamv[pi];
   const double* pBv = p + noff + P.K * N;
   const int qi = lane & 15, qq = lane >> 4;  // row pass: row qi of the chunk, columns 4t + qq
@@ -456,10 +461,22 @@ k_refine_pass1(const ProbDesc* __restrict__ probs, const int32_t* __restrict__ w
       for (int i = 0; i < CH; ++i) {
         const int ri = i < last ? i : last;
         const uint32_t so = (uint32_t)((c0 + ri) * ldb) * (uint32_t)sizeof(T);
-        const T x0 = buf_ld_row<T>(rsB, co0, so);
-        const T x1 = buf_ld_row<T>(rsB, co1, so);
-        v0[i] = c0ok ? x0 : T(0);
-        v1[i] = c1ok ? x1 : T(0);
+        if constexpr (CAM) {
+          const int cr = cam[pr0 + c0 + ri];
+          const bool seen = (uint32_t)cr < ncam;
+          const int cb = (seen ? cr : 0) * ldb;
+          const uint32_t k0 = (uint32_t)(lane - cb), k1 = (uint32_t)(lane + 64 - cb);
+          const bool on0 = seen && k0 < (uint32_t)ldb, on1 = seen && k1 < (uint32_t)ldb;
+          const T x0 = buf_ld_row<T>(rsB, (on0 ? k0 : 0u) * (uint32_t)sizeof(T), so);
+          const T x1 = buf_ld_row<T>(rsB, (on1 ? k1 : 0u) * (uint32_t)sizeof(T), so);
+          v0[i] = on0 ? x0 : T(0);
+          v1[i] = on1 ? x1 : T(0);
+        } else {
+          const T x0 = buf_ld_row<T>(rsB, co0, so);
+          const T x1 = buf_ld_row<T>(rsB, co1, so);
+          v0[i] = c0ok ? x0 : T(0);
+          v1[i] = c1ok ? x1 : T(0);
+        }
       }
 #pragma unroll
       for (int i = 0; i < CH; ++i) {
@@ -578,15 +595,19 @@ k_refine_pass1(const ProbDesc* __restrict__ probs, const int32_t* __restrict__ w
 }
 
 template <typename T>
-hipError_t launch_refine_residual(const BatchView& bv, const T* A, const T* B, const T* b, const double* d,
-                                  const T* Rblk, const T* Sc, const double* p, double* y, double* part,
-                                  hipStream_t st) {
+hipError_t launch_refine_residual(const BatchView& bv, const T* A, const T* B, const int32_t* cam, const T* b,
+                                  const double* d, const T* Rblk, const T* Sc, const double* p, double* y,
+                                  double* part, hipStream_t st) {
   if (bv.max_L > kMaxDense) return hipErrorInvalidValue;
   switch (bv.n) {
-#define QRK_P1(NN)                                                                                         \
-  case NN:                                                                                                 \
-    hipLaunchKernelGGL((k_refine_pass1<T, NN>), dim3(bv.nwg), dim3(256), 0, st, bv.probs, bv.wg_prob,      \
-                       bv.pack_blk, bv.row_off, A, B, b, d, bv.lam, Rblk, Sc, p, y, part);                \
+#define QRK_P1(NN)                                                                                           \
+  case NN:                                                                                                   \
+    if (cam)                                                                                                 \
+      hipLaunchKernelGGL((k_refine_pass1<T, NN, true>), dim3(bv.nwg), dim3(256), 0, st, bv.probs, bv.wg_prob, \
+                         bv.pack_blk, bv.row_off, A, B, cam, b, d, bv.lam, Rblk, Sc, p, y, part);           \
+    else                                                                                                     \
+      hipLaunchKernelGGL((k_refine_pass1<T, NN, false>), dim3(bv.nwg), dim3(256), 0, st, bv.probs,           \
+                         bv.wg_prob, bv.pack_blk, bv.row_off, A, B, cam, b, d, bv.lam, Rblk, Sc, p, y, part); \
     break;
     QRK_P1(1) QRK_P1(2) QRK_P1(3) QRK_P1(4) QRK_P1(5) QRK_P1(6) QRK_P1(7) QRK_P1(8)
 #undef QRK_P1
@@ -702,9 +723,9 @@ hipError_t launch_adjoint_dense(const BatchView& bv, const double* part, const T
                                               const double*);                                            \
   template hipError_t launch_backsub_blocks<T>(const BatchView&, const T*, const T*, double*, int*,        \
                                                hipStream_t, const double*);                              \
-  template hipError_t launch_refine_residual<T>(const BatchView&, const T*, const T*, const T*,             \
-                                                const double*, const T*, const T*, const double*, double*, \
-                                                double*, hipStream_t);                                   \
+  template hipError_t launch_refine_residual<T>(const BatchView&, const T*, const T*, const int32_t*,       \
+                                                const T*, const double*, const T*, const T*, const double*, \
+                                                double*, double*, hipStream_t);                          \
   template hipError_t launch_refine_dense<T>(const BatchView&, const double*, const T*, const double*,     \
                                              double*, double*, hipStream_t);                             \
   template hipError_t launch_refine_blocks<T>(const BatchView&, const T*, const T*, const double*,         \

@@ -39,6 +39,10 @@ _SIGS = {
     "qrk_create_blockangular_ncol": (_c_i32, [_c_i32, _c_i32p, _c_i32, _c_i64p, _c_i64, _c_i32, _c_i32,
                                               ctypes.POINTER(_c_vp)]),
     "qrk_factor_blockangular": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_dbl, _c_vp]),
+    "qrk_create_blockangular_cam": (_c_i32, [_c_i32, _c_i32, _c_i32, _c_i32, _c_i64p, _c_i32, _c_i32,
+                                             ctypes.POINTER(_c_vp)]),
+    "qrk_factor_blockangular_cam": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_dbl, _c_vp]),
+    "qrk_colnorms_blockangular_cam": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp]),
     "qrk_discover_blockangular": (_c_i32, [_c_i64, _c_i64, _c_i64p, _c_i32p, _c_i32, _c_i32p, _c_i64p, _c_i32p,
                                            _c_i32p, _c_i64p, _c_i32p]),
     "qrk_discover_banded": (_c_i32, [_c_i64, _c_i64, _c_i64p, _c_i32p, _c_i64p, _c_i32p, _c_i32p]),
@@ -409,6 +413,51 @@ class BlockAngularNcolSolver(BlockAngularSolver):
 
     def _a_len(self) -> int:
         return int((np.diff(self.row_off) * self.ncol).sum())
+
+class BlockAngularCamSolver(BlockAngularSolver):
+    """Block-angular J whose nB = ncam * cw coupled columns are cameras of cw columns, every row
+    on at most one camera (qrk_create_blockangular_cam): B is passed compressed as Bv [M, cw]
+    (each row's values) and cam int32 [M] (each row's camera; outside [0, ncam): none)."""
+
+    def __init__(self, row_off, n: int, ncam: int, cw: int, dtype="float32", mode: str = "plain"):
+        row_off = np.ascontiguousarray(np.asarray(row_off, dtype=np.int64))
+        K = int(row_off.shape[0] - 1)
+        qd = QRK_F32 if str(dtype).endswith("float32") else QRK_F64
+        qm = {"plain": QRK_PLAIN, "bf16x3": QRK_BF16X3}[mode]
+        h = _c_vp()
+        _check(lib().qrk_create_blockangular_cam(K, int(n), int(ncam), int(cw), row_off.ctypes.data_as(_c_i64p),
+                                                 qd, qm, ctypes.byref(h)), "qrk_create_blockangular_cam")
+        nB = int(ncam) * int(cw)
+        Factor.__init__(self, h, "blockangular", qd, K * int(n) + nB)
+        self.K, self.n, self.nB, self.ldb, self.M = K, int(n), nB, int(cw), int(row_off[-1])
+        self.ncam, self.cw = int(ncam), int(cw)
+        self.row_off = row_off
+        self.mode = mode
+
+    def factor(self, A, Bv, cam, b, d, lam: float, stream=None):
+        torch = _torch()
+        td = _torch_dtype(self.qdtype)
+        _check(lib().qrk_factor_blockangular_cam(self._h, _dev_ptr(A, td, "A", self.M * self.n),
+                                                 _dev_ptr(Bv, td, "Bv", self.M * self.cw),
+                                                 _dev_ptr(cam, torch.int32, "cam", self.M),
+                                                 _dev_ptr(b, td, "b", self.M), _dev_ptr(d, torch.float64, "d", self.N),
+                                                 float(lam), _stream_ptr(stream)), "qrk_factor_blockangular_cam")
+        self._keep = (A, Bv, cam, b, d)
+        self.lam = float(lam)
+        return self
+
+    def colnorms(self, A, Bv, cam, out=None, stream=None):
+        torch = _torch()
+        td = _torch_dtype(self.qdtype)
+        if out is None:
+            out = torch.empty(self.N, dtype=torch.float64, device="cuda")
+        _check(lib().qrk_colnorms_blockangular_cam(self._h, _dev_ptr(A, td, "A", self.M * self.n),
+                                                   _dev_ptr(Bv, td, "Bv", self.M * self.cw),
+                                                   _dev_ptr(cam, torch.int32, "cam", self.M),
+                                                   _dev_ptr(out, torch.float64, "d", self.N), _stream_ptr(stream)),
+               "qrk_colnorms_blockangular_cam")
+        return out
+
 
 class BlockAngularBatch(Factor):
     """P independent block-angular problems with the same block width n, factored and solved

@@ -177,3 +177,21 @@ def test_ncol_create_rejects_bad_widths(ncol):
                                           ctypes.byref(h)) == qrkit.QRK_EINVAL
     assert L.qrk_create_blockangular_ncol(3, nc.ctypes.data_as(qrkit._c_i32p), 5, ro.ctypes.data_as(qrkit._c_i64p),
                                           5, 0, 0, None) == qrkit.QRK_EINVAL
+
+
+@pytest.mark.parametrize("ncam,cw", [(0, 9), (3, 0), (15, 9), (128, 1), (-1, 4)])
+def test_cam_create_rejects_bad_cameras(ncam, cw):
+    """qrk_create_blockangular_cam: ncam >= 1, cw >= 1 and ncam * cw <= 127, checked on the host."""
+    L = qrkit.lib()
+    h = ctypes.c_void_p()
+    ro = np.array([0, 4, 8, 12], dtype=np.int64)
+    st = L.qrk_create_blockangular_cam(3, 3, ncam, cw, ro.ctypes.data_as(qrkit._c_i64p), 0, 0, ctypes.byref(h))
+    assert st == qrkit.QRK_EINVAL and not h.value
+    assert L.qrk_create_blockangular_cam(3, 3, 4, 9, ro.ctypes.data_as(qrkit._c_i64p), 0, 0,
+                                         None) == qrkit.QRK_EINVAL
+
+
+def test_cam_entry_points_reject_null_handle():
+    L = qrkit.lib()
+    assert L.qrk_factor_blockangular_cam(None, None, None, None, None, None, 1e-2, None) == qrkit.QRK_EINVAL
+    assert L.qrk_colnorms_blockangular_cam(None, None, None, None, None, None) == qrkit.QRK_EINVAL
