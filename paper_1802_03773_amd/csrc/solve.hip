@@ -441,84 +441,99 @@ k_refine_pass1(const ProbDesc* __restrict__ probs, const int32_t* __restrict__ w
     const T* Bbase = nB > 0 ? B + P.boff + (pr0 - moff) * ldb : bvec + pr0;
     const __amdgpu_buffer_rsrc_t rsB =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(Bbase), 0, 0x7fffffff, 0x00020000);
-    for (int c0 = 0; c0 < prows; c0 += CH) {
-      const int last = prows - 1 - c0;  // rows past the pack re-read its last row; their r is 0
-      // this lane's row of the chunk for the r update (lanes 0..15): its A row and p_i
-      const int myrow = c0 + (qi < last ? qi : last);
-      const int64_t grow = pr0 + myrow;
-      const int64_t lbr = b0 - koff + rowblk[myrow];
-      T arow[N];
-      double prow[N];
+    // the pack's rows in chunks; W: the problem has coupled columns past 64 (the second column
+    // slot of each lane holds some), else that slot is left out of the loads and products
+    auto chunks = [&](auto Wc) {
+      constexpr bool W = decltype(Wc)::value;
+      for (int c0 = 0; c0 < prows; c0 += CH) {
+        const int last = prows - 1 - c0;  // rows past the pack re-read its last row; their r is 0
+        // this lane's row of the chunk for the r update (lanes 0..15): its A row and p_i
+        const int myrow = c0 + (qi < last ? qi : last);
+        const int64_t grow = pr0 + myrow;
+        const int64_t lbr = b0 - koff + rowblk[myrow];
+        T arow[N];
+        double prow[N];
 #pragma unroll
-      for (int c = 0; c < N; ++c) {
-        arow[c] = A[grow * N + c];
-        prow[c] = p[noff + lbr * N + c];
-      }
-      const T bval = bvec[grow];
-      // stage rows c0 .. c0 + 15; columns >= nB are zeros
-      T v0[CH], v1[CH];
-#pragma unroll
-      for (int i = 0; i < CH; ++i) {
-        const int ri = i < last ? i : last;
-        const uint32_t so = (uint32_t)((c0 + ri) * ldb) * (uint32_t)sizeof(T);
-        if constexpr (CAM) {
-          const int cr = cam[pr0 + c0 + ri];
-          const bool seen = (uint32_t)cr < ncam;
-          const int cb = (seen ? cr : 0) * ldb;
-          const uint32_t k0 = (uint32_t)(lane - cb), k1 = (uint32_t)(lane + 64 - cb);
-          const bool on0 = seen && k0 < (uint32_t)ldb, on1 = seen && k1 < (uint32_t)ldb;
-          const T x0 = buf_ld_row<T>(rsB, (on0 ? k0 : 0u) * (uint32_t)sizeof(T), so);
-          const T x1 = buf_ld_row<T>(rsB, (on1 ? k1 : 0u) * (uint32_t)sizeof(T), so);
-          v0[i] = on0 ? x0 : T(0);
-          v1[i] = on1 ? x1 : T(0);
-        } else {
-          const T x0 = buf_ld_row<T>(rsB, co0, so);
-          const T x1 = buf_ld_row<T>(rsB, co1, so);
-          v0[i] = c0ok ? x0 : T(0);
-          v1[i] = c1ok ? x1 : T(0);
+        for (int c = 0; c < N; ++c) {
+          arow[c] = A[grow * N + c];
+          prow[c] = p[noff + lbr * N + c];
         }
-      }
+        const T bval = bvec[grow];
+        // stage rows c0 .. c0 + 15; columns >= nB are zeros
+        T v0[CH], v1[W ? CH : 1];
 #pragma unroll
-      for (int i = 0; i < CH; ++i) {
-        tile[lane * LS + i] = v0[i];
-        tile[(lane + 64) * LS + i] = v1[i];
-      }
-      wave_lds_sync();
-      // B p_B for row c0 + qi: lanes qi, qi + 16, qi + 32, qi + 48 split the columns
-      // (32-column tiers; the columns past nB are zeros)
-      double acc = 0.0;
-      auto tier = [&](auto t_begin) {
-        constexpr int tb = decltype(t_begin)::value;
-#pragma unroll
-        for (int t = tb; t < tb + 8; ++t) acc += (double)tile[(4 * t + qq) * LS + qi] * pq[t];
-      };
-      tier(std::integral_constant<int, 0>{});
-      if (nB > 32) tier(std::integral_constant<int, 8>{});
-      if (nB > 64) tier(std::integral_constant<int, 16>{});
-      if (nB > 96) tier(std::integral_constant<int, 24>{});
-      acc += __shfl_xor(acc, 16, 64);
-      acc += __shfl_xor(acc, 32, 64);
-      if (qq == 0) {
-        double dot = 0.0;
-#pragma unroll
-        for (int c = 0; c < N; ++c) dot += (double)arow[c] * prow[c];
-        const double rv = qi <= last ? (double)bval - dot - acc : 0.0;
-        rr[c0 + qi] = rv;
-        if (qi <= last) {
-#pragma unroll
-          for (int c = 0; c < N; ++c) prod[(c0 + qi) * N + c] = (double)arow[c] * rv;
+        for (int i = 0; i < CH; ++i) {
+          const int ri = i < last ? i : last;
+          const uint32_t so = (uint32_t)((c0 + ri) * ldb) * (uint32_t)sizeof(T);
+          if constexpr (CAM) {
+            const int cr = cam[pr0 + c0 + ri];
+            const bool seen = (uint32_t)cr < ncam;
+            const int cb = (seen ? cr : 0) * ldb;
+            const uint32_t k0 = (uint32_t)(lane - cb), k1 = (uint32_t)(lane + 64 - cb);
+            const bool on0 = seen && k0 < (uint32_t)ldb, on1 = seen && k1 < (uint32_t)ldb;
+            const T x0 = buf_ld_row<T>(rsB, (on0 ? k0 : 0u) * (uint32_t)sizeof(T), so);
+            v0[i] = on0 ? x0 : T(0);
+            if constexpr (W) {
+              const T x1 = buf_ld_row<T>(rsB, (on1 ? k1 : 0u) * (uint32_t)sizeof(T), so);
+              v1[i] = on1 ? x1 : T(0);
+            }
+          } else {
+            const T x0 = buf_ld_row<T>(rsB, co0, so);
+            v0[i] = c0ok ? x0 : T(0);
+            if constexpr (W) {
+              const T x1 = buf_ld_row<T>(rsB, co1, so);
+              v1[i] = c1ok ? x1 : T(0);
+            }
+          }
         }
-      }
-      wave_lds_sync();
-      // B^T r over the chunk's rows, from the registers the chunk was loaded into
 #pragma unroll
-      for (int i = 0; i < CH; ++i) {
-        const double rv = rr[c0 + i];
-        t0 += (double)v0[i] * rv;
-        t1 += (double)v1[i] * rv;
+        for (int i = 0; i < CH; ++i) {
+          tile[lane * LS + i] = v0[i];
+          if constexpr (W) tile[(lane + 64) * LS + i] = v1[i];
+        }
+        wave_lds_sync();
+        // B p_B for row c0 + qi: lanes qi, qi + 16, qi + 32, qi + 48 split the columns
+        // (32-column tiers; the columns past nB are zeros)
+        double acc = 0.0;
+        auto tier = [&](auto t_begin) {
+          constexpr int tb = decltype(t_begin)::value;
+#pragma unroll
+          for (int t = tb; t < tb + 8; ++t) acc += (double)tile[(4 * t + qq) * LS + qi] * pq[t];
+        };
+        tier(std::integral_constant<int, 0>{});
+        if (nB > 32) tier(std::integral_constant<int, 8>{});
+        if constexpr (W) {
+          tier(std::integral_constant<int, 16>{});
+          if (nB > 96) tier(std::integral_constant<int, 24>{});
+        }
+        acc += __shfl_xor(acc, 16, 64);
+        acc += __shfl_xor(acc, 32, 64);
+        if (qq == 0) {
+          double dot = 0.0;
+#pragma unroll
+          for (int c = 0; c < N; ++c) dot += (double)arow[c] * prow[c];
+          const double rv = qi <= last ? (double)bval - dot - acc : 0.0;
+          rr[c0 + qi] = rv;
+          if (qi <= last) {
+#pragma unroll
+            for (int c = 0; c < N; ++c) prod[(c0 + qi) * N + c] = (double)arow[c] * rv;
+          }
+        }
+        wave_lds_sync();
+        // B^T r over the chunk's rows, from the registers the chunk was loaded into
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+          const double rv = rr[c0 + i];
+          t0 += (double)v0[i] * rv;
+          if constexpr (W) t1 += (double)v1[i] * rv;
+        }
+        wave_lds_sync();  // the next chunk overwrites the tile
       }
-      wave_lds_sync();  // the next chunk overwrites the tile
-    }
+    };
+    if (nB > 64)
+      chunks(std::true_type{});
+    else
+      chunks(std::false_type{});
     // per block: g_i = A_i^T r - lam d_i^2 p_i, y_i = R_i^{-T} g_i
     if (lane < nb) {
       const int64_t blk = b0 + lane;
