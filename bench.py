@@ -110,7 +110,7 @@ def _parse():
                     help="also run a plain device copy of known size (for PMC byte scaling)")
     ap.add_argument("--workload", default="scale",
                     choices=["scale", "ragged-batch", "banded-batch", "lm-scale", "lm-banded-batch", "lambda-retry",
-                             "new-rhs", "configs"],
+                             "new-rhs", "configs", "camera"],
                     help="scale: one block-angular problem (the headline); ragged-batch: 512 block-angular "
                          "problems in one batch; banded-batch: 2,048 banded problems in one batch")
     ap.add_argument("--problems", type=int, default=0, help="batch workloads: problems (0 = the recipe's count)")
@@ -626,6 +626,109 @@ def run_new_rhs(args):
     return 0
 
 
+def run_camera(args):
+    """Camera columns at bundle-adjustment size (the Jacobian of Section 6.2, each row on one point
+    block and at most one camera): 22,106 points seen by 2..6 of 14 cameras of 9 parameters
+    (176,844 rows, 126 coupled columns), lambda 1e-2, float32.  A step is the factor with B passed
+    compressed (each row's 9 camera values and its camera index) plus the solve with one float64
+    sweep; the same J with B stored dense is timed beside it."""
+    import numpy as np
+    import torch
+
+    from paper_1802_03773_amd import BlockAngularCamSolver, BlockAngularSolver
+    from workloads import generators as gen
+
+    mode = "bf16x3" if args.mode == "auto" else args.mode
+    print("[bench] generating workload", file=sys.stderr, flush=True)
+    K = 22106
+    inst = gen.make_blockangular_cam(args.seed + 7, K=K, obs=2 + (np.arange(K) * 13) % 5, ncam=14, cw=9, n=3,
+                                     lam=1e-2, dtype=np.float32)
+    A, Bv, cam, b, d = (torch.from_numpy(np.ascontiguousarray(x)).cuda()
+                        for x in (inst.A, inst.Bv, inst.cam, inst.b, inst.d))
+    Bdense = np.zeros((inst.M, inst.nB), dtype=np.float32)  # the same rows stored dense (a layout change)
+    for c in range(inst.ncam):
+        sel = inst.cam == c
+        Bdense[sel, c * inst.cw:(c + 1) * inst.cw] = inst.Bv[sel]
+    Bd = torch.from_numpy(Bdense).cuda()
+    p = torch.empty(inst.N, dtype=torch.float64, device="cuda")
+
+    def timed(fn, steps):
+        for _ in range(max(args.warmup, 1)):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    sc = BlockAngularCamSolver(inst.row_off, inst.n, inst.ncam, inst.cw, dtype="float32", mode=mode)
+    sd = BlockAngularSolver(inst.row_off, inst.n, inst.nB, dtype="float32", mode=mode)
+    ms_dense = timed(lambda: (sd.factor(A, Bd, b, d, inst.lam), sd.solve(sweeps=1, out=p)), args.steps)
+    p_dense = p.clone()
+    step = lambda: (sc.factor(A, Bv, cam, b, d, inst.lam), sc.solve(sweeps=1, out=p))  # noqa: E731
+    ms = timed(step, args.steps)
+    sc.raise_on_status()
+    same = bool(torch.equal(p, p_dense))
+    # per-phase times of the timed step, and their rooflines
+    sc.profile_enable(4 * args.steps)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ph = sc.profile_read()
+    M, n, nB, cw = inst.M, inst.n, inst.nB, inst.cw
+    L, N, es = nB + 1, inst.N, 4
+    Bc = M * (cw * es + 4)  # compressed B: values and camera index per row
+    work = {"block_qr": ("hbm", M * n * es + Bc + M * es + N * 8 + (K + 1) * 8
+                         + K * n * n * es + K * n * L * es + M * L * es),
+            "dense_leaves": ("alu", 2.0 * (M + nB) * L * L - (2.0 / 3.0) * L ** 3),
+            "refine": ("hbm", M * n * es + Bc + M * es + N * 8 + (K + 1) * 8 + 2 * N * 8
+                       + K * n * n * es * 2 + K * n * L * es * 2 + 2 * K * n * 8)}
+    phases = {}
+    for k, (bound, amount) in work.items():
+        t_ms, cnt = ph[k]
+        if k == "dense_leaves":
+            t_ms += ph["dense_tree"][0]
+        if cnt == 0:
+            continue
+        avg = t_ms / cnt
+        if bound == "hbm":
+            ach, peak, unit = amount / (avg * 1e-3) / 1e9, 8000.0, "GB/s"
+        else:
+            ach, peak, unit = amount / (avg * 1e-3) / 1e12, 157.3, "TFLOP/s"
+        phases[k] = {"avg_ms": avg, "bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak}
+    dom = max(phases, key=lambda k: phases[k]["avg_ms"])
+    roofline = dict(phases[dom], kernel=dom, traffic=None)
+    roofline.pop("avg_ms")
+    accuracy, cpu_baseline = None, None
+    if not args.no_cpu:
+        from oracle import dense as odense
+        from oracle import structured as ostruct
+        print("[bench] oracle (cpu_baseline leg)", file=sys.stderr, flush=True)
+        ba = odense.blockangular_from_cam(inst)
+        t0 = time.perf_counter()
+        p_ref, _ = ostruct.solve_blockangular(ba)
+        t_oracle = time.perf_counter() - t0
+        rel, scaled = _errs(p.cpu().numpy(), p_ref, inst.d)
+        accuracy = {"rel_err": rel, "scaled_err": scaled}
+        cpu_baseline = {"value": 1.0 / t_oracle, "unit": "steps/s", "cores": _cpu_threads(), "kind": "oracle",
+                        "sample": "one structured float64 oracle solve of the full workload (B assembled dense, "
+                                  "per-block LAPACK QR, LAPACK QR of the reduced rows); %.2f s" % t_oracle}
+    out = {"metric": "LM step solves/sec, camera columns at bundle-adjustment size", "value": 1000.0 / ms,
+           "unit": "steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32" if mode == "plain" else "bf16x3", "data": "synthetic",
+           "config": {"workload": "camera columns: 22,106 points seen by 2..6 of 14 cameras of 9 parameters, "
+                                  "176,844 rows, B compressed, float32, lambda 1e-2, one float64 sweep",
+                      "points": K, "rows": M, "cameras": inst.ncam, "camera_width": cw, "dense_cols": nB,
+                      "refine_sweeps": 1, "refine_dtype": "f64"},
+           "ms_per_step_dense_B": ms_dense, "bit_identical_to_dense_B": same,
+           "B_bytes_compressed": Bc, "B_bytes_dense": M * nB * es,
+           "phases": phases, "accuracy": accuracy, "roofline": roofline, "cpu_baseline": cpu_baseline}
+    print(json.dumps(out))
+    return 0
+
+
 def _errs(p, p_ref, d):
     """(2-norm relative error, largest column-scaled componentwise error) of p against p_ref."""
     import numpy as np
@@ -826,6 +929,8 @@ def main():
         return run_new_rhs(args)
     if args.workload == "configs":
         return run_configs(args)
+    if args.workload == "camera":
+        return run_camera(args)
     if args.workload != "scale":
         return run_batch(args)
     import numpy as np
