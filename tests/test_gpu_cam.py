@@ -9,7 +9,8 @@ matrix; the assembly is pinned in test_oracle_cam.py).  Configurations:
   * float32 with fp32 and BF16x3 dense-part updates, and float64.
 Bounds: unrefined as for dense-B problems (float32 1e-5 at cond <= 1e3, scaled by cond / 1e3
 above it; float64 1e-12), 1e-10 after two sweeps.  The camera handle is also compared bit for
-bit with a dense-B handle given the assembled B: the kernels read the same values."""
+bit with a dense-B handle given the assembled B: the kernels read the same values.  The
+autotuner and HIP-graph replay of the step read the camera rows as eager calls do."""
 import numpy as np
 import pytest
 
@@ -183,3 +184,44 @@ def test_cam_bundle_adjustment_size():
     e1 = p_err(p1, p_ref, inst.d)
     log(f"  one sweep: {e1:.2e}")
     assert e1 <= 1e-10
+
+
+def test_cam_autotune_and_graph_replay():
+    """The autotuner's trial factors and a captured factor + solve read the camera rows as an
+    eager call does: after autotuning p still matches the oracle, and every graph replay (with
+    eager work between replays) gives p bit for bit equal to the eager step."""
+    import torch
+    inst = _instance(51, K=2000, obs=(np.arange(2000) % 5) + 2, prior_rows=1)
+    p_ref, _ = structured.solve_blockangular(dense.blockangular_from_cam(inst))
+    s = _solver(inst, "bf16x3")
+    A, Bv, cam, b, d = _device(inst)
+    s.factor(A, Bv, cam, b, d, inst.lam)
+    s.autotune()
+    s.factor(A, Bv, cam, b, d, inst.lam)
+    p = torch.empty(inst.N, dtype=torch.float64, device="cuda")
+    s.solve(sweeps=2, out=p)
+    torch.cuda.synchronize()
+    e = p_err(p.cpu().numpy(), p_ref, inst.d)
+    log(f"cam after autotune: {e:.2e}")
+    assert e <= 1e-10
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # warm-up off the default stream before capture
+        s.factor(A, Bv, cam, b, d, inst.lam)
+        s.solve(sweeps=1, out=p)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    eager = p.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        s.factor(A, Bv, cam, b, d, inst.lam)
+        s.solve(sweeps=1, out=p)
+    for r in range(3):
+        p.fill_(float("nan"))
+        x = torch.ones(1 << 20, device="cuda").cumsum(0)  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(p, eager), f"replay {r}"
+        assert float(x[-1]) == float(1 << 20)
+    assert s.status()[0] == 0
