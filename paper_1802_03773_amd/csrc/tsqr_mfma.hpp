@@ -241,6 +241,34 @@ struct Tri {
   static constexpr int idx(int p, int q) { return p * NCB - (p * (p - 1)) / 2 + (q - p); }
 };
 
+// A running triangle whose block rows from RL on live in the wave's LDS (block t at
+// rl + (t - first) * 256, lane-major like a stored triangle) while its first RL block rows stay
+// in registers; RL = NCB keeps all of it in registers.  A panel reads and writes only its own
+// block row, so the LDS rows cost one load and one store per block and panel.
+template <int NCB, int RL>
+struct TriSplit {
+  static constexpr int first = Tri<NCB>::idx(RL, RL);  // first block kept in LDS (count if none)
+  static constexpr int lds_blocks = Tri<NCB>::count - first;
+};
+
+template <int NCB, int RL, int P, int Q>
+__device__ __forceinline__ f4 tri_get(const f4 (&R)[Tri<NCB>::count], const float* rl, int lane) {
+  constexpr int t = Tri<NCB>::idx(P, Q);
+  if constexpr (P < RL)
+    return R[t];
+  else
+    return *reinterpret_cast<const f4*>(rl + (t - TriSplit<NCB, RL>::first) * 256 + lane * 4);
+}
+
+template <int NCB, int RL, int P, int Q>
+__device__ __forceinline__ void tri_put(f4 (&R)[Tri<NCB>::count], float* rl, int lane, const f4& v) {
+  constexpr int t = Tri<NCB>::idx(P, Q);
+  if constexpr (P < RL)
+    R[t] = v;
+  else
+    *reinterpret_cast<f4*>(rl + (t - TriSplit<NCB, RL>::first) * 256 + lane * 4) = v;
+}
+
 // Merge the tile X (NRB block rows) into the running triangle R.
 //   TRI = false: a dense tile of 16*NRB rows; panels before pstart are skipped (their
 //                tile columns are known to be zero).
@@ -255,9 +283,12 @@ struct Tri {
 // KEEPQ: the panels' compact-WY factors (T, the scales and the raw reflector blocks,
 // qrk_batch.hpp) are stored at qkeep for a later Q^T: panel P at P * tile_panel_floats for a
 // dense tile, at TreeKeep<NCB>::off(P) for a triangle.
-template <int NCB, int NRB, bool TRI, bool BF = false, int NPANEL = NCB, bool FUSE = false, bool KEEPQ = false>
+// RL < NCB: R's block rows from RL on are in LDS at rl (TriSplit).
+template <int NCB, int NRB, bool TRI, bool BF = false, int NPANEL = NCB, bool FUSE = false, bool KEEPQ = false,
+          int RL = NCB>
 __device__ __forceinline__ void merge_tile(f4 (&R)[Tri<NCB>::count], f4 (&X)[NRB][NCB], int pstart,
-                                           float* __restrict__ lds, int lane, float* __restrict__ qkeep = nullptr) {
+                                           float* __restrict__ lds, int lane, float* __restrict__ qkeep = nullptr,
+                                           float* __restrict__ rl = nullptr) {
   const int g = lane >> 4;
   const int c = lane & 15;
   float* Tl = lds;            // [16][16]
@@ -278,7 +309,13 @@ __device__ __forceinline__ void merge_tile(f4 (&R)[Tri<NCB>::count], f4 (&X)[NRB
       f4 Xp[RBN];
 #pragma unroll
       for (int rb = 0; rb < RBN; ++rb) Xp[rb] = X[rb][P];
-      panel_factor<RBN, FUSE>(R[rp], Xp, trow, sc, lane);
+      if constexpr (RL == NCB) {
+        panel_factor<RBN, FUSE>(R[rp], Xp, trow, sc, lane);
+      } else {
+        f4 Rd = tri_get<NCB, RL, P, P>(R, rl, lane);
+        panel_factor<RBN, FUSE>(Rd, Xp, trow, sc, lane);
+        tri_put<NCB, RL, P, P>(R, rl, lane, Rd);
+      }
 #pragma unroll
       for (int rb = 0; rb < RBN; ++rb) X[rb][P] = Xp[rb];
     }
@@ -385,11 +422,19 @@ __device__ __forceinline__ void merge_tile(f4 (&R)[Tri<NCB>::count], f4 (&X)[NRB
               Y0 = mfma4(X[rb][P][v], X[rb][q][v], Y0);
           }
       }
-      const f4 Z = R[rq] + srow * (Y0 + Y1);
+      f4 Rq;
+      if constexpr (RL == NCB)
+        Rq = R[rq];
+      else
+        Rq = tri_get<NCB, RL, P, q>(R, rl, lane);
+      const f4 Z = Rq + srow * (Y0 + Y1);
       f4 Zp = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int v = 0; v < 4; ++v) Zp = mfma4(Td[v], Z[v], Zp);
-      R[rq] -= Zp;
+      if constexpr (RL == NCB)
+        R[rq] -= Zp;
+      else
+        tri_put<NCB, RL, P, q>(R, rl, lane, Rq - Zp);
       const f4 Zs = srow * Zp;
       if constexpr (BF) {
         float t[8];
@@ -416,25 +461,36 @@ __device__ __forceinline__ void merge_tile(f4 (&R)[Tri<NCB>::count], f4 (&X)[NRB
 }
 
 // A stored triangle is its NCB(NCB+1)/2 blocks, 1 KiB each, lane-contiguous.
-template <int NCB>
+// RL < NCB: the blocks from TriSplit<NCB, RL>::first on are read from / written to the LDS rows.
+template <int NCB, int RL = NCB>
 __device__ __forceinline__ void store_tri(float* __restrict__ dst, const f4 (&R)[Tri<NCB>::count],
-                                          int lane) {
-#pragma unroll
-  for (int t = 0; t < Tri<NCB>::count; ++t) *reinterpret_cast<f4*>(dst + t * 256 + lane * 4) = R[t];
-}
-
-template <int NCB>
-__device__ __forceinline__ void load_tri(const float* __restrict__ src, f4 (&R)[Tri<NCB>::count],
-                                         int lane) {
+                                          int lane, const float* __restrict__ rl = nullptr) {
+  constexpr int first = TriSplit<NCB, RL>::first;
 #pragma unroll
   for (int t = 0; t < Tri<NCB>::count; ++t)
-    R[t] = __builtin_nontemporal_load(reinterpret_cast<const f4*>(src + t * 256 + lane * 4));
+    *reinterpret_cast<f4*>(dst + t * 256 + lane * 4) =
+        t < first ? R[t] : *reinterpret_cast<const f4*>(rl + (t - first) * 256 + lane * 4);
+}
+
+template <int NCB, int RL = NCB>
+__device__ __forceinline__ void load_tri(const float* __restrict__ src, f4 (&R)[Tri<NCB>::count],
+                                         int lane, float* __restrict__ rl = nullptr) {
+  constexpr int first = TriSplit<NCB, RL>::first;
+#pragma unroll
+  for (int t = 0; t < Tri<NCB>::count; ++t) {
+    const f4 v = __builtin_nontemporal_load(reinterpret_cast<const f4*>(src + t * 256 + lane * 4));
+    if (t < first)
+      R[t] = v;
+    else
+      *reinterpret_cast<f4*>(rl + (t - first) * 256 + lane * 4) = v;
+  }
 }
 
 // R <- triangle of QR([R; stored triangle at src]).
-template <int NCB, bool BF = false, bool KEEPQ = false>
+template <int NCB, bool BF = false, bool KEEPQ = false, int RL = NCB>
 __device__ __forceinline__ void merge_stored_tri(f4 (&R)[Tri<NCB>::count], const float* __restrict__ src,
-                                                 float* lds, int lane, float* __restrict__ qkeep = nullptr) {
+                                                 float* lds, int lane, float* __restrict__ qkeep = nullptr,
+                                                 float* __restrict__ rl = nullptr) {
   f4 X[NCB][NCB];
   static_for<0, NCB>([&](auto RB) {
     constexpr int rb = decltype(RB)::value;
@@ -447,7 +503,7 @@ __device__ __forceinline__ void merge_stored_tri(f4 (&R)[Tri<NCB>::count], const
         X[rb][q] = f4{0.f, 0.f, 0.f, 0.f};
     });
   });
-  merge_tile<NCB, NCB, true, BF, NCB, false, KEEPQ>(R, X, 0, lds, lane, qkeep);
+  merge_tile<NCB, NCB, true, BF, NCB, false, KEEPQ, RL>(R, X, 0, lds, lane, qkeep, rl);
 }
 
 // One leaf of the dense part, by one wave: leaf li of problem p streams rows
@@ -459,12 +515,15 @@ __device__ __forceinline__ void merge_stored_tri(f4 (&R)[Tri<NCB>::count], const
 // tiles per leaf) and those of its merges to qs.qn (at qn0, one TreeKeep per merge node, numbered
 // level by level from the leaves up as the separate merge tree numbers its nodes).  A separate
 // instantiation, so that the kernels without it are compiled as if it did not exist.
-template <int NCB, int NRB, bool BF, bool KEEP = false>
+// RL < NCB: the running triangle's block rows from RL on are kept in the wave's LDS at rl
+// (TriSplit) instead of registers.
+template <int NCB, int NRB, bool BF, bool KEEP = false, int RL = NCB>
 __device__ __forceinline__ void tsqr_leaf(int pi, int leaf, const ProbDesc* __restrict__ probs, int n,
                                           const float* __restrict__ Red, const double* __restrict__ d,
                                           const double* __restrict__ lamv, float* __restrict__ slots,
                                           int* __restrict__ counters, float* __restrict__ RBall, float* lds,
-                                          int lane, const QStore qs = QStore()) {
+                                          int lane, const QStore qs = QStore(), float* __restrict__ rl = nullptr) {
+  static_assert(!KEEP || RL == NCB, "the stored Q's leaves keep the triangle in registers");
   const ProbDesc& P = probs[pi];
   const float* Xg = Red + P.redoff;
   const int64_t ldx = P.ldr;
@@ -492,6 +551,11 @@ __device__ __forceinline__ void tsqr_leaf(int pi, int leaf, const ProbDesc* __re
         if (4 * g + v == c && col < L - 1) R[Tri<NCB>::idx(Q, Q)][v] = (float)(sqrt_lam * dB[col]);
     });
   }
+  if constexpr (RL < NCB) {  // the rows kept in LDS start from the values just set
+#pragma unroll
+    for (int t = TriSplit<NCB, RL>::first; t < Tri<NCB>::count; ++t)
+      *reinterpret_cast<f4*>(rl + (t - TriSplit<NCB, RL>::first) * 256 + lane * 4) = R[t];
+  }
 
   // ---- leaf: stream this wave's rows -------------------------------------------------------
   const int64_t r0 = (int64_t)leaf * rows_per_leaf;
@@ -514,14 +578,14 @@ __device__ __forceinline__ void tsqr_leaf(int pi, int leaf, const ProbDesc* __re
       float* qk = qs.qt + qs.qo[pi].qt0 + ((int64_t)leaf * qs.qo[pi].qtiles + tile) * (NCB * tile_panel_floats(NRB));
       merge_tile<NCB, NRB, false, BF, NCB, false, true>(R, X, 0, lds, lane, qk);
     } else {
-      merge_tile<NCB, NRB, false, BF>(R, X, 0, lds, lane);
+      merge_tile<NCB, NRB, false, BF, NCB, false, false, RL>(R, X, 0, lds, lane, nullptr, rl);
     }
   }
 
   // ---- pairwise merges up the problem's tree, in the same launch ----------------------------
   float* pslots = slots + P.slot0;
   if (P.tree_sep && nleaves > 1) {  // the merges are a separate, pipelined launch
-    store_tri<NCB>(pslots + (int64_t)leaf * SLOT, R, lane);
+    store_tri<NCB, RL>(pslots + (int64_t)leaf * SLOT, R, lane, rl);
     return;
   }
   int* pctr = counters + P.ctr0;
@@ -542,7 +606,7 @@ __device__ __forceinline__ void tsqr_leaf(int pi, int leaf, const ProbDesc* __re
       nl = nn;
       continue;
     }
-    store_tri<NCB>(pslots + (base + slot) * SLOT, R, lane);
+    store_tri<NCB, RL>(pslots + (base + slot) * SLOT, R, lane, rl);
     __threadfence();
     int old = 0;
     if (lane == 0) old = atomicAdd(&pctr[cbase + parent], 1);
@@ -550,12 +614,12 @@ __device__ __forceinline__ void tsqr_leaf(int pi, int leaf, const ProbDesc* __re
     if (old == 0) return;  // the sibling is still running; it will merge
     __threadfence();
     const int left = slot & ~1;
-    load_tri<NCB>(pslots + (base + left) * SLOT, R, lane);
+    load_tri<NCB, RL>(pslots + (base + left) * SLOT, R, lane, rl);
     if constexpr (KEEP)
       merge_stored_tri<NCB, BF, true>(R, pslots + (base + left + 1) * SLOT, lds, lane,
                                       qs.qn + qs.qo[pi].qn0 + (mbase + parent) * TreeKeep<NCB>::total);
     else
-      merge_stored_tri<NCB, BF>(R, pslots + (base + left + 1) * SLOT, lds, lane);
+      merge_stored_tri<NCB, BF, false, RL>(R, pslots + (base + left + 1) * SLOT, lds, lane, nullptr, rl);
     base += nl;
     cbase += nn;
     if constexpr (KEEP) mbase += nl >> 1;
@@ -574,12 +638,16 @@ __device__ __forceinline__ void tsqr_leaf(int pi, int leaf, const ProbDesc* __re
         const int row = 16 * Q + 4 * g + v;
         const int col = 16 * q + c;
         float val = 0.f;
-        if constexpr (q >= Q) val = (col >= row) ? R[Tri<NCB>::idx(Q, q)][v] : 0.f;
+        if constexpr (q >= Q) val = (col >= row) ? tri_get<NCB, RL, Q, q>(R, rl, lane)[v] : 0.f;
         if (row < L && col < L) Rout[(int64_t)row * L + col] = val;
       }
     });
   });
 }
+
+// Block rows of the running triangle the plain leaf keeps in registers: all up to 6 column
+// blocks; at 7 none and at 8 the first (the rest in LDS, 28 blocks either way).
+constexpr int leaf_lds_rows(int ncb) { return ncb <= 6 ? ncb : (ncb == 7 ? 0 : 1); }
 
 // One launch per column-block count NCB: wave w is global leaf leaf_begin + w.  The launch
 // that stores Q is a kernel of its own with one more argument; the one without it keeps the
@@ -595,8 +663,17 @@ k_tsqr_mfma(int leaf_begin, int nleaves_cls, const int32_t* __restrict__ leaf_pr
   const int wv = threadIdx.x >> 6;
   const int wl = blockIdx.x * 4 + wv;
   if (wl >= nleaves_cls) return;
-  tsqr_leaf<NCB, NRB, BF>(leaf_prob[leaf_begin + wl], leaf_idx[leaf_begin + wl], probs, n, Red, d, lamv, slots,
-                          counters, RBall, lds_all[wv], lane);
+  if constexpr (leaf_lds_rows(NCB) < NCB) {
+    // 7 and 8 column blocks: the triangle's later block rows in LDS (28 KiB per wave, 152 KiB
+    // per workgroup with the staging), which frees the registers the tile needs
+    constexpr int RL = leaf_lds_rows(NCB);
+    __shared__ float rl_all[4][TriSplit<NCB, RL>::lds_blocks * 256];
+    tsqr_leaf<NCB, NRB, BF, false, RL>(leaf_prob[leaf_begin + wl], leaf_idx[leaf_begin + wl], probs, n, Red, d,
+                                       lamv, slots, counters, RBall, lds_all[wv], lane, QStore(), rl_all[wv]);
+  } else {
+    tsqr_leaf<NCB, NRB, BF>(leaf_prob[leaf_begin + wl], leaf_idx[leaf_begin + wl], probs, n, Red, d, lamv, slots,
+                            counters, RBall, lds_all[wv], lane);
+  }
 }
 template <int NCB, int NRB, bool BF>
 __global__ void __launch_bounds__(256)

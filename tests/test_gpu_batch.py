@@ -104,7 +104,9 @@ def test_batch_autotune_keeps_results():
 def test_autotune_cache_file_round_trip(tmp_path):
     """The autotuner's choice is written to the cache file under the batch's shape key, and a new
     handle of the same shape starts from it (in a process that reads the file afresh the key
-    and the file are the same; here the file is re-read into the process map)."""
+    and the file are the same; here the file is re-read into the process map).  The file also
+    holds whatever the process tuned before (the process map is written out whole), so the
+    batch's entry is looked up by its key."""
     import json
     import torch
     from paper_1802_03773_amd import BlockAngularBatch, qrkit
@@ -122,9 +124,9 @@ def test_autotune_cache_file_round_trip(tmp_path):
         assert chosen["leaf_scale"] == scale
         data = json.loads(path.read_text())
         entries = data["entries"]
-        assert len(entries) == 1
-        (key, rec), = entries.items()
-        assert key.startswith("gfx950/f32/plain/P8/n3/")
+        mine = [k for k in entries if k.startswith("gfx950/f32/plain/P8/n3/")]
+        assert len(mine) == 1, entries
+        rec = entries[mine[0]]
         assert rec["leaf_scale"] == chosen["leaf_scale"] and rec["refine_scale"] == chosen["refine_scale"]
         assert rec["leaf_queue"] == chosen["leaf_queue"]
         qrkit.set_tune_cache(path)  # reload
