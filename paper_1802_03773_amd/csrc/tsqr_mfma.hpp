@@ -645,9 +645,11 @@ __device__ __forceinline__ void tsqr_leaf(int pi, int leaf, const ProbDesc* __re
   });
 }
 
-// Block rows of the running triangle the plain leaf keeps in registers: all up to 6 column
-// blocks; at 7 none and at 8 the first (the rest in LDS, 28 blocks either way).
-constexpr int leaf_lds_rows(int ncb) { return ncb <= 6 ? ncb : (ncb == 7 ? 0 : 1); }
+// Block rows of the running triangle the plain leaf keeps in registers (the rest in LDS): all
+// up to 5 column blocks; at 6 the first three (the other 6 blocks in LDS free the registers the
+// BF16x3 leaf spilled; 2 or 3 rows in registers measured alike, 4 slower); at 7 none and at 8
+// the first (28 blocks in LDS either way).
+constexpr int leaf_lds_rows(int ncb) { return ncb <= 5 ? ncb : (ncb == 6 ? 3 : (ncb == 7 ? 0 : 1)); }
 
 // One launch per column-block count NCB: wave w is global leaf leaf_begin + w.  The launch
 // that stores Q is a kernel of its own with one more argument; the one without it keeps the
@@ -664,8 +666,9 @@ k_tsqr_mfma(int leaf_begin, int nleaves_cls, const int32_t* __restrict__ leaf_pr
   const int wl = blockIdx.x * 4 + wv;
   if (wl >= nleaves_cls) return;
   if constexpr (leaf_lds_rows(NCB) < NCB) {
-    // 7 and 8 column blocks: the triangle's later block rows in LDS (28 KiB per wave, 152 KiB
-    // per workgroup with the staging), which frees the registers the tile needs
+    // 6..8 column blocks: the triangle's later block rows in LDS (6 KiB per wave at 6, 28 KiB
+    // at 7 and 8: 152 KiB per workgroup with the staging), which frees the registers the tile
+    // needs
     constexpr int RL = leaf_lds_rows(NCB);
     __shared__ float rl_all[4][TriSplit<NCB, RL>::lds_blocks * 256];
     tsqr_leaf<NCB, NRB, BF, false, RL>(leaf_prob[leaf_begin + wl], leaf_idx[leaf_begin + wl], probs, n, Red, d,
@@ -713,8 +716,9 @@ __device__ __noinline__ void tsqr_leaf_call(int pi, int leaf, const ProbDesc* __
                                             const float* __restrict__ Red, const double* __restrict__ d,
                                             const double* __restrict__ lamv, float* __restrict__ slots,
                                             int* __restrict__ counters, float* __restrict__ RBall, float* lds,
-                                            int lane) {
-  tsqr_leaf<NCB, LeafTile<NCB>::nrb, BF>(pi, leaf, probs, n, Red, d, lamv, slots, counters, RBall, lds, lane);
+                                            int lane, float* rl) {
+  tsqr_leaf<NCB, LeafTile<NCB>::nrb, BF, false, leaf_lds_rows(NCB)>(pi, leaf, probs, n, Red, d, lamv, slots,
+                                                                     counters, RBall, lds, lane, QStore(), rl);
 }
 template <int NCB, bool BF>
 __device__ __noinline__ void tsqr_leaf_call_keep(int pi, int leaf, const ProbDesc* __restrict__ probs, int n,
@@ -748,10 +752,15 @@ __device__ __forceinline__ void tsqr_queue_loop(int nitems, const int32_t* __res
     switch ((probs[pi].L + 15) >> 4) {
 #define QRK_QLEAF(C)                                                                                          \
   case C:                                                                                                     \
-    if constexpr (KEEP)                                                                                       \
+    if constexpr (KEEP) {                                                                                     \
       tsqr_leaf_call_keep<C, BF>(pi, leaf, probs, n, Red, d, lamv, slots, counters, RBall, lds, lane, qs);    \
-    else                                                                                                      \
-      tsqr_leaf_call<C, BF>(pi, leaf, probs, n, Red, d, lamv, slots, counters, RBall, lds, lane);             \
+    } else if constexpr (leaf_lds_rows(C) < C) {                                                              \
+      __shared__ float rl_all[4][TriSplit<C, leaf_lds_rows(C)>::lds_blocks * 256];                            \
+      tsqr_leaf_call<C, BF>(pi, leaf, probs, n, Red, d, lamv, slots, counters, RBall, lds, lane,              \
+                            rl_all[threadIdx.x >> 6]);                                                        \
+    } else {                                                                                                  \
+      tsqr_leaf_call<C, BF>(pi, leaf, probs, n, Red, d, lamv, slots, counters, RBall, lds, lane, nullptr);    \
+    }                                                                                                         \
     break;
       QRK_QLEAF(1) QRK_QLEAF(2) QRK_QLEAF(3) QRK_QLEAF(4) QRK_QLEAF(5) QRK_QLEAF(6)
 #undef QRK_QLEAF
