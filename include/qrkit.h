@@ -336,7 +336,10 @@ qrk_status qrk_factor_vcat(qrk_handle h, qrk_handle h2, void* stream);
  *   and the panels (T, scales and reflector blocks) of every merge of two triangles.  Together
  *   about 1.4 times the reduced rows' bytes.  The storage is allocated here and when the leaf
  *   layout changes (qrk_set_tsqr_shape, autotuning); the factor calls stay capturable.  An LM
- *   driver graph captured before the call is captured again at its next qrk_lm_run.
+ *   driver graph captured before the call is captured again at its next qrk_lm_run.  A factor
+ *   that stores Q gives the same per-block factor, bit for bit, as one that does not; its dense
+ *   part may take tiles of another height (64 rows at 6 column blocks instead of 128), so R_B |
+ *   c_B agree up to row signs and rounding.
  *   keep == 0: later factor calls store nothing (the storage is kept until qrk_destroy).
  *   QRK_EINVAL: NULL handle; keep != 0 on a banded or float64 handle, or with a block of
  *   fewer rows than columns.  QRK_ENOMEM if the storage cannot be allocated.

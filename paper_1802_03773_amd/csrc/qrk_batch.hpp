@@ -17,13 +17,17 @@ constexpr int kMaxDense = 128;  // nB + 1 <= 128
 // (a device work queue of leaves, widest problems first); wider ones have a launch per width.
 constexpr int kQueueNCB = 6;
 
-// Dense-part leaves stream tiles of this many rows: 128 up to 4 column blocks, 64 beyond (taller
-// tiles no longer fit the register file there).
-constexpr int leaf_tile_rows(int ncb) { return ncb <= 4 ? 128 : 64; }
+// Dense-part leaves stream tiles of this many rows: 128 up to 4 column blocks and at 6 (there with
+// the running triangle's block rows 1..5 in LDS), 64 at 5, 7 and 8 (a taller tile does not fit
+// the register file there, at 5 not even with the triangle in LDS).  The leaves that store Q keep
+// the triangle in registers and use leaf_tile_rows_keep (the stored tile panels are laid out by
+// it).
+constexpr int leaf_tile_rows(int ncb) { return ncb <= 4 || ncb == 6 ? 128 : 64; }
+constexpr int leaf_tile_rows_keep(int ncb) { return ncb <= 4 ? 128 : 64; }
 
 // Stored Q of the float32 dense part: per 16-column panel, T (16 x 16, row-major), the column
 // scales (16, padded to 64) and the raw reflector blocks W (16 x 16 each, row-major, block row
-// rb at float 320 + 256 rb).  A tile merged into a leaf keeps nrb = leaf_tile_rows / 16 blocks
+// rb at float 320 + 256 rb).  A tile merged into a leaf keeps nrb = leaf_tile_rows_keep / 16 blocks
 // per panel (tile_panel_floats each, panel p at p * tile_panel_floats); a merge of two
 // triangles keeps p + 1 blocks for panel p (the rows of the right triangle it touches), panel p
 // at node_panel_off(p), a node of ncb column blocks taking node_panel_off(ncb).

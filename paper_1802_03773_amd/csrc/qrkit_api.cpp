@@ -418,9 +418,9 @@ qrk_status assign_leaves(qrk_handle h) {
       const ProbDesc& D = pd[(size_t)q];
       QOff& O = h->qoff_h[(size_t)q];
       const int ncb = (D.L + 15) / 16;
-      O.qtiles = ceil_div(D.rows_per_leaf, (int64_t)leaf_tile_rows(ncb));
+      O.qtiles = ceil_div(D.rows_per_leaf, (int64_t)leaf_tile_rows_keep(ncb));
       O.qt0 = qt;
-      qt += (int64_t)D.leaves * O.qtiles * ncb * tile_panel_floats(leaf_tile_rows(ncb) / 16);
+      qt += (int64_t)D.leaves * O.qtiles * ncb * tile_panel_floats(leaf_tile_rows_keep(ncb) / 16);
       O.qn0 = qn;
       qn += (int64_t)(D.leaves - 1) * node_panel_off(ncb);
       O.qc0 = qu;

@@ -149,7 +149,7 @@ k_qt_leaves(int leaf_begin, int nleaves_cls, const int32_t* __restrict__ leaf_pr
             const int32_t* __restrict__ leaf_idx, const ProbDesc* __restrict__ probs, int n,
             const QStore qs, const float* __restrict__ xr, float* __restrict__ uslots, int* __restrict__ counters,
             double* __restrict__ c) {
-  constexpr int KT = leaf_tile_rows(NCB);
+  constexpr int KT = leaf_tile_rows_keep(NCB);
   constexpr int RPL = KT / 64;                // tile rows per lane
   constexpr int RPM = (16 * NCB + 63) / 64;   // triangle rows per lane in a merge
   constexpr int64_t TPF = tile_panel_floats(KT / 16);

@@ -646,10 +646,10 @@ __device__ __forceinline__ void tsqr_leaf(int pi, int leaf, const ProbDesc* __re
 }
 
 // Block rows of the running triangle the plain leaf keeps in registers (the rest in LDS): all
-// up to 5 column blocks; at 6 the first three (the other 6 blocks in LDS free the registers the
-// BF16x3 leaf spilled; 2 or 3 rows in registers measured alike, 4 slower); at 7 none and at 8
-// the first (28 blocks in LDS either way).
-constexpr int leaf_lds_rows(int ncb) { return ncb <= 5 ? ncb : (ncb == 6 ? 3 : (ncb == 7 ? 0 : 1)); }
+// up to 5 column blocks; at 6 the first (15 blocks in LDS free the registers of its 128-row
+// tiles: 64-row tiles with three rows in registers measured 9% slower on the scale workload); at
+// 7 none and at 8 the first (28 blocks in LDS either way).
+constexpr int leaf_lds_rows(int ncb) { return ncb <= 5 ? ncb : (ncb == 6 ? 1 : (ncb == 7 ? 0 : 1)); }
 
 // One launch per column-block count NCB: wave w is global leaf leaf_begin + w.  The launch
 // that stores Q is a kernel of its own with one more argument; the one without it keeps the
@@ -666,7 +666,7 @@ k_tsqr_mfma(int leaf_begin, int nleaves_cls, const int32_t* __restrict__ leaf_pr
   const int wl = blockIdx.x * 4 + wv;
   if (wl >= nleaves_cls) return;
   if constexpr (leaf_lds_rows(NCB) < NCB) {
-    // 6..8 column blocks: the triangle's later block rows in LDS (6 KiB per wave at 6, 28 KiB
+    // 6..8 column blocks: the triangle's later block rows in LDS (15 KiB per wave at 6, 28 KiB
     // at 7 and 8: 152 KiB per workgroup with the staging), which frees the registers the tile
     // needs
     constexpr int RL = leaf_lds_rows(NCB);
@@ -697,6 +697,7 @@ k_tsqr_mfma_keep(int leaf_begin, int nleaves_cls, const int32_t* __restrict__ le
 template <int NCB>
 struct LeafTile {
   static constexpr int nrb = leaf_tile_rows(NCB) / 16;
+  static constexpr int nrb_keep = leaf_tile_rows_keep(NCB) / 16;
 };
 
 // The leaves of every problem with at most kQueueNCB column blocks in one persistent launch:
@@ -726,7 +727,7 @@ __device__ __noinline__ void tsqr_leaf_call_keep(int pi, int leaf, const ProbDes
                                                  const double* __restrict__ lamv, float* __restrict__ slots,
                                                  int* __restrict__ counters, float* __restrict__ RBall, float* lds,
                                                  int lane, const QStore qs) {
-  tsqr_leaf<NCB, LeafTile<NCB>::nrb, BF, true>(pi, leaf, probs, n, Red, d, lamv, slots, counters, RBall, lds, lane,
+  tsqr_leaf<NCB, LeafTile<NCB>::nrb_keep, BF, true>(pi, leaf, probs, n, Red, d, lamv, slots, counters, RBall, lds, lane,
                                                qs);
 }
 
@@ -793,15 +794,17 @@ hipError_t launch_tsqr_mfma_ncb(bool bf16x3, int leaf_begin, int nleaves_cls, co
                                 const int32_t* leaf_idx, const ProbDesc* probs, int n, const float* Red, const double* d,
                                 const double* lam, float* slots, int* counters, float* RB, const QStore& qs,
                                 hipStream_t st) {
-  // the stored Q's tile count per leaf assumes these tiles
+  // the plain leaves stream tiles of leaf_tile_rows rows, the leaves that store Q those of
+  // leaf_tile_rows_keep (the stored Q's tile count per leaf)
   static_assert(16 * NRB == leaf_tile_rows(NCB), "leaf tile height");
+  constexpr int NRBK = LeafTile<NCB>::nrb_keep;  // the leaves that store Q
   const int grid = (nleaves_cls + 3) / 4;
   if (qs.qt != nullptr) {
     if (bf16x3)
-      hipLaunchKernelGGL((k_tsqr_mfma_keep<NCB, NRB, true>), dim3(grid), dim3(256), 0, st, leaf_begin, nleaves_cls,
+      hipLaunchKernelGGL((k_tsqr_mfma_keep<NCB, NRBK, true>), dim3(grid), dim3(256), 0, st, leaf_begin, nleaves_cls,
                          leaf_prob, leaf_idx, probs, n, Red, d, lam, slots, counters, RB, qs);
     else
-      hipLaunchKernelGGL((k_tsqr_mfma_keep<NCB, NRB, false>), dim3(grid), dim3(256), 0, st, leaf_begin, nleaves_cls,
+      hipLaunchKernelGGL((k_tsqr_mfma_keep<NCB, NRBK, false>), dim3(grid), dim3(256), 0, st, leaf_begin, nleaves_cls,
                          leaf_prob, leaf_idx, probs, n, Red, d, lam, slots, counters, RB, qs);
   } else {
     if (bf16x3)

@@ -81,8 +81,10 @@ def test_apply_qt_single_problem(mode, leaves):
 
 @pytest.mark.parametrize("mode", ["plain", "bf16x3"])
 def test_apply_qt_own_rhs_is_the_factor_c(mode):
-    """Q^T b for the factor call's own b reproduces the c the factorisation carried as a column,
-    and storing Q leaves the factor bit for bit as it is without."""
+    """Q^T b for the factor call's own b reproduces the c the factorisation carried as a column.
+    Storing Q leaves the per-block factor bit for bit as it is without; at 6 column blocks the
+    leaves that store Q stream 64-row tiles where the others stream 128, so R_B | c_B agrees up to
+    row signs and rounding."""
     import torch
     from paper_1802_03773_amd import BlockAngularSolver
     inst = gen.make_blockangular(1011, K=1500, m=(np.arange(1500) % 5) + 8, n=3, nB=90, lam=1e-2,
@@ -94,8 +96,12 @@ def test_apply_qt_own_rhs_is_the_factor_c(mode):
     ref.factor(A, B, b, d, inst.lam)
     fk = s.get_factor()
     fr = ref.get_factor()
-    for x, y in zip(fk, fr):
-        assert torch.equal(x, y)
+    assert torch.equal(fk[0], fr[0]) and torch.equal(fk[1], fr[1])
+    RBk = sign_fix_rows(fk[2].cpu().numpy())[0]
+    RBr = sign_fix_rows(fr[2].cpu().numpy())[0]
+    eRB = np.abs(RBk - RBr).max() / np.abs(RBr).max()
+    log(f"R_B | c_B with and without the stored Q ({mode}): {eRB:.2e}")
+    assert eRB <= (1e-5 if mode == "plain" else 1e-4)
     c = s.apply_qt(b).cpu().numpy()
     _, S, RB = [t.cpu().numpy().astype(np.float64) for t in fk]
     K, n, nB = inst.K, inst.n, inst.nB
