@@ -59,7 +59,8 @@ hipError_t launch_zero_ints(int* p, int64_t n, hipStream_t st);
 
 // Pipelined merge tree of a single problem whose leaves stored their triangles (tree_sep):
 // nnodes inner nodes in level order (node_l / node_r child references, r < 0 leaf -1 - r),
-// flags[nnodes * ncb] cleared beforehand; ncb <= 6.  The root writes R_B | c_B.
+// flags[nnodes * ncb] cleared beforehand; ncb <= kTreeMaxNCB.  The root writes R_B | c_B.
+constexpr int kTreeMaxNCB = 8;
 hipError_t launch_tsqr_tree(int ncb, const ProbDesc* probs, const int32_t* node_l, const int32_t* node_r,
                             int nnodes, float* slots, int* flags, float* RB, int* status, const QStore& qs,
                             hipStream_t st);

@@ -377,10 +377,10 @@ qrk_status assign_leaves(qrk_handle h) {
           }
       h->cls_count[c] = (int)lp.size() - h->cls_begin[c];
     }
-    // a single problem of at most 6 column blocks merges its leaves in a separate launch,
-    // pipelined over column blocks; otherwise the merges run inside the leaf launch
+    // a single problem of at most kTreeMaxNCB column blocks merges its leaves in a separate
+    // launch, pipelined over column blocks; otherwise the merges run inside the leaf launch
     std::vector<int32_t> nl, nr;
-    const bool sep = P == 1 && pd[0].leaves > 1 && (pd[0].L + 15) / 16 <= 6;
+    const bool sep = P == 1 && pd[0].leaves > 1 && (pd[0].L + 15) / 16 <= kTreeMaxNCB;
     if (sep) {
       std::vector<int32_t> items((size_t)pd[0].leaves);
       for (int i = 0; i < pd[0].leaves; ++i) items[(size_t)i] = -1 - i;

@@ -159,14 +159,19 @@ __device__ __forceinline__ bool tree_wait2(const int* fa, const int* fb, int lan
 // q of a node's output as published above the diagonal, flags[(node * NCB + q) * 2 + 1] its
 // diagonal block.  The root (the last node) writes R_B | c_B row-major.  KEEP (the stored Q):
 // node w's kept panels are written to qs.qn + qn0 + w * TreeKeep<NCB>::total at its end.
+// Waves (nodes) per workgroup: four, or three at 8 column blocks, whose kept panels (46 KiB per
+// wave) fit the 160 KiB of LDS only three at a time.
+constexpr int tree_waves(int ncb) { return ncb <= 7 ? 4 : 3; }
+
 template <int NCB, bool KEEP>
 __device__ __forceinline__ void tsqr_tree_node(const ProbDesc* probs, const int32_t* node_l, const int32_t* node_r,
                                                int nnodes, float* slots, int* flags, float* RBall, int* status,
                                                const QStore& qs) {
-  __shared__ float keep_all[4][TreeKeep<NCB>::total];
+  constexpr int WPG = tree_waves(NCB);
+  __shared__ float keep_all[WPG][TreeKeep<NCB>::total];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int node = blockIdx.x * 4 + wv;
+  const int node = blockIdx.x * WPG + wv;
   if (node >= nnodes) return;
   const ProbDesc& P = probs[0];
   const int L = P.L;
