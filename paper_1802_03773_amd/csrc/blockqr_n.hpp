@@ -67,6 +67,14 @@ __device__ __forceinline__ void st_row(T* base, uint32_t off, T v) {
   asm("" : "+v"(off));
   *reinterpret_cast<QRK_GLOBAL T*>(pin_uniform(base) + off) = v;
 }
+// st_row for the reduced rows, the largest output: they are read once, by the dense part's
+// leaves, and are stored streaming so they do not push A and B out of the last-level cache,
+// from which the refinement pass that follows the solve reads them again
+template <typename T>
+__device__ __forceinline__ void st_row_stream(T* base, uint32_t off, T v) {
+  asm("" : "+v"(off));
+  __builtin_nontemporal_store(v, reinterpret_cast<QRK_GLOBAL T*>(pin_uniform(base) + off));
+}
 
 // Raw buffer access: the descriptor holds the (wave-uniform) base, the row offset goes in the
 // scalar offset and the lane's column offset in the vector offset, so a row costs no vector
@@ -260,9 +268,9 @@ __device__ __forceinline__ void block_qr_wave_n(int nB, int m, int ldb, int ldr,
       asm("" : "+s"(ms));
 #pragma unroll
       for (int r = N; r < RD; ++r)
-        if (r < ms) st_row(red + (int64_t)(r - N) * ldr, co, c[s][r]);
+        if (r < ms) st_row_stream(red + (int64_t)(r - N) * ldr, co, c[s][r]);
 #pragma unroll
-      for (int j = 0; j < N; ++j) st_row(red + (int64_t)(m - N + j) * ldr, co, c[s][RD + j]);
+      for (int j = 0; j < N; ++j) st_row_stream(red + (int64_t)(m - N + j) * ldr, co, c[s][RD + j]);
     }
   }
 }
