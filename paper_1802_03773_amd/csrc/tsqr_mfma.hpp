@@ -570,7 +570,9 @@ __device__ __forceinline__ void tsqr_leaf(int pi, int leaf, const ProbDesc* __re
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int64_t row = t + rb * 16 + 4 * g + v;
-          X[rb][q][v] = (row < r1 && col < L) ? Xg[row * ldx + col] : 0.f;
+          // read once: streaming, so the reduced rows do not displace A and B in the last-level
+          // cache, where the next block QR and refinement pass find them
+          X[rb][q][v] = (row < r1 && col < L) ? __builtin_nontemporal_load(Xg + row * ldx + col) : 0.f;
         }
       }
     if constexpr (KEEP) {
